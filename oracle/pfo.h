@@ -1,0 +1,135 @@
+/*
+ * pfo.h -- serial FP64 CPU oracle for the Poisson-Fermi hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that tests, the smoke
+ * check and the CPU-baseline leg of the benchmark can compare the GPU
+ * library against a plain, slow, obviously correct implementation.  The
+ * product path never links, loads or calls it.  It shares no code, header,
+ * table or constant with the GPU library.
+ *
+ * What it computes (citations are to the paper, arXiv:1711.04060):
+ *   - the 7-point finite-difference operator  -div(eps grad) + sigma
+ *     (Sec. 3, the FD discretisation of Eqs. (7), (12), (13)), assembled
+ *     explicitly as the seven diagonals A0..A6 of Sec. 4 (diagonal storage
+ *     without offset arrays: A0 centre, A1 east i+1, A2 west i-1, A3 south
+ *     i-nx, A4 north i+nx, A5 down i-nx*ny, A6 up i+nx*ny);
+ *   - Jacobi-preconditioned BiCGSTAB (Sec. 4, Table 3), right-preconditioned
+ *     with M = diag(A);
+ *   - the Fermi-like concentrations and steric potential (Sec. 2, Eq. (1))
+ *     by bisection on the void-fraction equation;
+ *   - the sequential nonlinear solver of Sec. 4, Table 2 (initial PF2 solve,
+ *     then PF1 / PF2 / relaxation until the max-norm update is small).
+ *
+ * Units: potentials are phi-hat = e*phi/(kB*T); lengths in the grid's unit;
+ * concentrations per cubed length unit; lambda = e^2/(eps0*kB*T) in the
+ * same length unit.  All arrays are host memory, x-fastest layout
+ * idx = i + nx*(j + ny*k).
+ */
+#ifndef PFO_H
+#define PFO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { PFO_DIRICHLET = 0, PFO_NEUMANN = 1 };
+enum { PFO_SOLVENT = 0, PFO_SOLUTE = 1, PFO_FIXED = 2 };
+
+/* return codes */
+enum { PFO_OK = 0, PFO_EARG = -1, PFO_ENOMEM = -2, PFO_ENOCONV = -4,
+       PFO_EBREAKDOWN = -5, PFO_ENONFINITE = -6 };
+
+typedef struct {
+    int nx, ny, nz;               /* >= 3 each */
+    double h;                     /* uniform spacing, > 0 */
+    const double *eps;            /* [N] nodal dielectric, > 0 */
+    const unsigned char *type;    /* [N] PFO_SOLVENT/SOLUTE/FIXED, or NULL = all solvent */
+    const double *fixed_value;    /* [N] phi-hat at FIXED nodes, or NULL = 0 */
+    int bc[6];                    /* faces -x,+x,-y,+y,-z,+z: PFO_DIRICHLET / PFO_NEUMANN */
+    double bc_value[6];           /* Dirichlet value per face */
+} pfo_grid;
+
+/* Which rows are Dirichlet (identity rows) and their values.
+ * system 0: the potential (bc, bc_value, FIXED nodes take fixed_value);
+ * system 1: the PF1 density Psi (bc given in bc_psi, value 0, every
+ *           non-solvent node is Dirichlet 0 -- Eq. (14)). */
+int pfo_dirichlet(const pfo_grid *g, int system, const int *bc_psi,
+                  unsigned char *is_dir, double *value);
+
+/* Assemble the seven diagonals A[0..6][N] (A must hold 7*N doubles) of
+ *   (-div_h coef grad_h + sigma) on free rows, identity on Dirichlet rows.
+ * coef: nodal coefficient field (eps, or a constant for PF1); sigma may be NULL. */
+int pfo_assemble(int nx, int ny, int nz, double h, const double *coef,
+                 const double *sigma, const int *bc, const unsigned char *is_dir,
+                 double *A);
+
+/* y = A x with the seven diagonals. */
+void pfo_dia_matvec(int nx, int ny, int nz, const double *A, const double *x, double *y);
+
+typedef struct {
+    int iters;          /* BiCGSTAB iterations */
+    int restarts;       /* shadow-residual restarts */
+    double rel_res;     /* final true ||b - A x||_2 / ||b_lifted||_2 */
+    double bnorm;       /* ||b_lifted||_2 */
+} pfo_lin_info;
+
+/* Right-Jacobi BiCGSTAB on A x = b.  x: in = initial guess, out = solution;
+ * Dirichlet rows of x are set to `value` before iterating.  b is read on
+ * free rows only.  Stops when the true relative residual <= tol. */
+int pfo_bicgstab(int nx, int ny, int nz, const double *A, const unsigned char *is_dir,
+                 const double *value, const double *b, double *x, double tol,
+                 int maxit, pfo_lin_info *info);
+
+/* Assemble + solve for system 0 of g: (-div eps grad + sigma) x = b. */
+int pfo_linear_solve(const pfo_grid *g, const double *sigma, const double *b,
+                     double *x, double tol, int maxit, pfo_lin_info *info);
+
+typedef struct {
+    int nsp;                  /* K+1 species, water last */
+    const double *z;          /* [nsp] valences */
+    const double *v;          /* [nsp] volumes 4*pi*a^3/3 */
+    const double *cb;         /* [nsp] bath concentrations (> 0) */
+    int steric;               /* 0: S == 0 (Boltzmann), 1: Fermi with steric potential */
+    double lambda;            /* e^2/(eps0 kB T) in grid length units */
+} pfo_species;
+
+/* Eq. (1) at every node of type SOLVENT (or every node if type == NULL).
+ * Outputs (each may be NULL): rho_hat = lambda*sum z_i C_i,
+ * sigma = lambda*sum z_i^2 C_i, conc[nsp*N] (species-major), S[N]. */
+int pfo_fermi(size_t N, const double *phi, const unsigned char *type,
+              const pfo_species *sp, double *rho_hat, double *sigma,
+              double *conc, double *S);
+
+/* Root S of Gamma_B e^S + sum v_i c_i^B exp(-z_i phi + p_i S) = 1 at a single node. */
+double pfo_steric_root(double phi, const pfo_species *sp);
+
+typedef struct {
+    double eps_s;             /* solvent dielectric */
+    double lc;                /* correlation length (grid units); 0 = no PF1 solve */
+    double omega;             /* relaxation weight on the old iterate */
+    double outer_tol;         /* max-norm stop on the relaxed update */
+    int max_outer;
+    double lin_tol;           /* relative residual for every linear solve */
+    int lin_maxit;
+    int warm_start;           /* 1: phi holds the initial phi_0, skip the initial PF2 solve */
+    int bc_psi[6];            /* Psi boundary kinds (Dirichlet value 0) */
+} pfo_nl_opts;
+
+typedef struct {
+    int outer_iters;
+    int total_lin_iters;
+    double last_delta;
+} pfo_nl_info;
+
+/* Table 2 of the paper.  fixed_charge: [N] charge (units of e) per node or
+ * NULL.  phi: in (warm start) / out.  conc/S optional outputs at the final phi. */
+int pfo_nonlinear_solve(const pfo_grid *g, const double *fixed_charge,
+                        const pfo_species *sp, const pfo_nl_opts *o, double *phi,
+                        double *conc, double *S, pfo_nl_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
