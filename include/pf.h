@@ -1,0 +1,220 @@
+/*
+ * pf.h -- C-ABI of the MI355X (gfx950) Poisson-Fermi hot path.
+ *
+ * Method: arXiv:1711.04060 (Chen, Chen, Liu, "A GPU Poisson-Fermi Solver for
+ * Ion Channel Simulations").  The library solves the 7-point finite-difference
+ * systems of Sec. 3 with Jacobi-preconditioned BiCGSTAB (Sec. 4, Table 3) and
+ * runs the nonlinear Poisson-Fermi loop of Sec. 4 (Tables 2 and 4) with the
+ * Fermi-like concentrations and steric potential of Sec. 2, Eq. (1).
+ *
+ * Conventions shared by every entry point
+ *   - Grid: nx*ny*nz nodes, uniform spacing h, x-fastest layout
+ *     idx = i + nx*(j + ny*k).  Neighbour naming follows the seven-diagonal
+ *     description of Sec. 4 (east i+1, west i-1, south i-nx, north i+nx,
+ *     down i-nx*ny, up i+nx*ny).  nx, ny, nz >= 3.
+ *   - Faces are numbered -x,+x,-y,+y,-z,+z.  Dirichlet faces hold a value;
+ *     Neumann faces (zero normal derivative, Eq. (4)) use a node-centred
+ *     mirror ghost.  A node on a Dirichlet face is Dirichlet even when it also
+ *     lies on a Neumann face; on several Dirichlet faces the face that comes
+ *     last in the order above sets its value; PF_NODE_FIXED nodes are interior
+ *     Dirichlet nodes with their own value.
+ *   - Operator: (A x)_i = sum over the six faces f of eps_f (x_i - x_j) / h^2
+ *     + sigma_i x_i on free rows, with eps_f = 2 eps_i eps_j / (eps_i + eps_j)
+ *     (harmonic mean of nodal values; it replaces the SMIB interface rows of
+ *     Eqs. (17)-(18)).  Dirichlet rows are identity rows.
+ *   - Potentials are phi-hat = e phi / (kB T).  Lengths are in the grid's unit;
+ *     lambda = e^2 / (eps0 kB T) and concentrations use the same unit.
+ *   - Pointers named "device" must be device memory of the current HIP device
+ *     (hipMalloc or torch CUDA tensors).  Pointers named "host" are host memory.
+ *   - Every call is synchronous with respect to the stream given at
+ *     pf_grid_create: it returns after the work has finished, so outputs and
+ *     info structs are valid on return.
+ *   - No exception crosses the ABI.  Each call returns a pf_status; on failure
+ *     pf_last_error() returns a thread-local message.  Invalid arguments are
+ *     rejected with PF_ERR_ARG before any device work.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PF_OK = 0,
+    PF_ERR_ARG = -1,        /* invalid argument (shape, pointer, value)          */
+    PF_ERR_ALLOC = -2,      /* device allocation failed                          */
+    PF_ERR_DEVICE = -3,     /* a HIP call failed                                 */
+    PF_ERR_NOCONV = -4,     /* iteration limit reached; best iterate written     */
+    PF_ERR_BREAKDOWN = -5,  /* BiCGSTAB breakdown that restarting did not cure   */
+    PF_ERR_NONFINITE = -6   /* NaN or Inf met in the iteration                   */
+} pf_status;
+
+typedef enum { PF_BC_DIRICHLET = 0, PF_BC_NEUMANN = 1 } pf_bc;
+
+/* Node kinds.  SOLVENT nodes carry ions (Omega_s of Sec. 2); SOLUTE nodes are
+ * the biomolecule/membrane (Omega_m); FIXED nodes are interior Dirichlet nodes
+ * (e.g. a filter region whose potential comes from an atomic model, Sec. 2). */
+typedef enum { PF_NODE_SOLVENT = 0, PF_NODE_SOLUTE = 1, PF_NODE_FIXED = 2 } pf_node;
+
+typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;
+
+typedef struct pf_grid pf_grid;   /* opaque; owns device copies of its fields */
+
+typedef struct {
+    int32_t nx, ny, nz;            /* nodes per axis, each >= 3                       */
+    double h;                      /* spacing, > 0                                    */
+    const double *eps;             /* device [N]: nodal dielectric, finite, > 0       */
+    const uint8_t *node_type;      /* device [N]: pf_node values, or NULL = solvent   */
+    const double *fixed_charge;    /* device [N]: charge (units of e) spread to nodes,
+                                      or NULL = none (used by pf_nonlinear_solve)     */
+    const double *fixed_value;     /* device [N]: phi-hat at FIXED nodes, or NULL = 0 */
+    int32_t bc_phi[6];             /* pf_bc per face for the potential                */
+    double bc_value[6];            /* phi-hat on Dirichlet faces                      */
+    int32_t bc_psi[6];             /* pf_bc per face for the PF1 density Psi; its
+                                      Dirichlet value is 0 (Eq. (14))                 */
+    void *stream;                  /* hipStream_t to run on; NULL = default stream    */
+} pf_grid_desc;
+
+/* Copy the fields of *desc into a new grid handle (the caller may free its
+ * arrays afterwards).  Validates shapes and values (eps finite and > 0,
+ * node types in range, fixed data finite).  Sec. 4, Table 4 step 1. */
+pf_status pf_grid_create(const pf_grid_desc *desc, pf_grid **out);
+
+/* Release the handle and all device memory it owns.  NULL is accepted. */
+void pf_grid_destroy(pf_grid *g);
+
+typedef struct {
+    double rel_tol;        /* stop when ||b - A x||_2 <= rel_tol * ||b_lift||_2, where
+                              b_lift is b on free rows minus the Dirichlet couplings  */
+    int32_t max_iter;      /* BiCGSTAB iterations (all refinements together), > 0    */
+    int32_t precision;     /* pf_precision: PF_FP64, or PF_MIXED = FP32 inner BiCGSTAB
+                              (FP32 eps, iterates and stencil; FP64 reductions and
+                              scalars) inside FP64 iterative refinement               */
+    double inner_tol;      /* PF_MIXED: relative residual target of each inner solve */
+    int32_t max_refine;    /* PF_MIXED: maximum refinement steps                     */
+    int32_t check_every;   /* iterations per device-side chunk between host checks;
+                              0 = library default                                     */
+} pf_lin_opts;
+
+typedef struct {
+    int32_t iters;         /* BiCGSTAB iterations performed                          */
+    int32_t refinements;   /* PF_MIXED refinement steps (0 for PF_FP64)              */
+    int32_t restarts;      /* shadow-residual restarts                               */
+    double rel_res;        /* final true relative residual                           */
+    double seconds;        /* wall time of the call                                  */
+    int32_t status;        /* pf_status of the call                                  */
+} pf_lin_info;
+
+/* Fill *o with defaults: rel_tol 1e-10, max_iter 20000, PF_FP64,
+ * inner_tol 1e-5, max_refine 30, check_every 0. */
+void pf_lin_opts_default(pf_lin_opts *o);
+
+/* Solve (-div eps grad + sigma) x = b on grid g (potential boundary data:
+ * bc_phi, bc_value, FIXED nodes).  sigma: device [N] >= 0 or NULL (= 0).
+ * b: device [N], read on free rows.  x: device [N], in = initial guess,
+ * out = solution (Dirichlet entries are overwritten with their values).
+ * Jacobi-BiCGSTAB, Sec. 4 Table 3; right preconditioning with M = diag(A).
+ * On PF_ERR_NOCONV the last iterate is written to x. */
+pf_status pf_linear_solve(pf_grid *g, const double *sigma, const double *b, double *x,
+                          const pf_lin_opts *opts, pf_lin_info *info);
+
+/* True residual of the linear system of pf_linear_solve.
+ * rel_res: host, receives ||b - A x||_2 / ||b_lift||_2 (0 when b_lift = 0 and
+ * the residual vanishes).  r: device [N] receives b - A x (0 on Dirichlet
+ * rows), or NULL.  x is read as given (Dirichlet entries included). */
+pf_status pf_residual(pf_grid *g, const double *sigma, const double *b, const double *x,
+                      double *rel_res, double *r);
+
+/* Stencil operator application y = A x (jacobi = 0) or y = A M^-1 x
+ * (jacobi = 1, M = diag(A), identity on Dirichlet rows) with the operator of
+ * pf_linear_solve.  x, y: device [N], distinct.  The FP64 form is the
+ * matrix-vector product of Table 3 steps 11 and 14, matrix-free. */
+pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, int32_t jacobi);
+
+/* Same in FP32 (the inner operator of PF_MIXED): FP32 eps and vectors.
+ * Only jacobi = 1 is supported (the form the inner solver applies). */
+pf_status pf_spmv_f32(pf_grid *g, const double *sigma, const float *x, float *y, int32_t jacobi);
+
+typedef struct {
+    int32_t n_species;        /* K+1 species, water last (valence 0), 1..16      */
+    const double *valence;    /* host [n_species]: z_i                           */
+    const double *radius;     /* host [n_species]: a_i in Angstrom               */
+    const double *bath_molar; /* host [n_species]: C_i^B in mol/L, > 0           */
+    int32_t steric;           /* 1: Fermi distribution with steric potential
+                                 (Eq. (1)); 0: Boltzmann (S == 0)                */
+    double lc;                /* correlation length l_c in grid units (Eq. (2));
+                                 0 = no PF1 solve (Psi = -rho/eps_s)              */
+    double eps_s;             /* solvent dielectric eps_s                        */
+    double kB, T, e, eps0;    /* Table 1: J/K, K, C, F/cm                        */
+    double NA;                /* Avogadro's number (not in Table 1)              */
+    double length_unit_A;     /* grid length unit in Angstrom (1 = Angstrom)     */
+    double omega;             /* relaxation weight omega_PF on the old iterate   */
+    double outer_tol;         /* stop when ||Phi - Phi_0||_inf <= outer_tol
+                                 after relaxation (Table 2 step 5)               */
+    int32_t max_outer;        /* outer iterations, > 0                           */
+    int32_t warm_start;       /* 1: phi holds Phi_0 (skip Table 2 step 2)        */
+    pf_lin_opts lin;          /* options of every PF1 / PF2 linear solve         */
+} pf_pf_params;
+
+typedef struct {
+    int32_t outer_iters;
+    int32_t total_lin_iters;
+    double last_delta;        /* last ||Phi - Phi_0||_inf                         */
+    double seconds;
+    int32_t status;
+} pf_nl_info;
+
+/* Fill *p with Table 1 constants, omega 0.3, outer_tol 1e-8, max_outer 5000,
+ * eps_s 78.45, lc 0, steric 1, lin = pf_lin_opts_default(); species fields are
+ * left empty for the caller. */
+void pf_pf_params_default(pf_pf_params *p);
+
+/* Nonlinear Poisson-Fermi solve (Sec. 4, Tables 2 and 4) on grid g.
+ *   step 2  PF2 with rho' = Psi = 0: -div eps grad phi = lambda q / h^3;
+ *   loop    Fermi update at Phi_0 (Eq. (1)) -> rho_hat, sigma = -rho_hat';
+ *           PF1 (Eq. (12), (14)): eps_s (1 - lc^2 Lap) Psi = -rho_hat on
+ *           solvent nodes, Psi = 0 elsewhere and on Dirichlet bc_psi faces;
+ *           PF2 (Eq. (13)): -div eps grad phi + sigma phi
+ *                           = -eps_s Psi + sigma Phi_0 + lambda q / h^3;
+ *           relax Phi := omega Phi_0 + (1 - omega) Phi; test the max norm.
+ * phi: device [N], in (warm start) / out.  conc: device [n_species * N]
+ * (species-major) or NULL; steric: device [N] or NULL -- both evaluated at the
+ * returned phi (zero off the solvent).  On PF_ERR_NOCONV the last relaxed
+ * iterate is returned. */
+pf_status pf_nonlinear_solve(pf_grid *g, const pf_pf_params *p, double *phi, double *conc,
+                             double *steric, pf_nl_info *info);
+
+/* Fermi update alone (Eq. (1)) at potential phi (device [N]): writes
+ * rho_hat = lambda sum_i z_i C_i and sigma = lambda sum_i z_i^2 C_i (device
+ * [N] each, or NULL), conc (device [n_species * N] or NULL) and the steric
+ * potential S (device [N] or NULL).  Non-solvent nodes get zeros. */
+pf_status pf_fermi(pf_grid *g, const pf_pf_params *p, const double *phi, double *rho_hat,
+                   double *sigma, double *conc, double *steric);
+
+/* Batched linear solves: n independent systems (grids may differ in size),
+ * each as pf_linear_solve with the shared opts.  info: host [n] or NULL. */
+pf_status pf_linear_solve_batch(int32_t n, pf_grid *const *g, const double *const *sigma,
+                                const double *const *b, double *const *x,
+                                const pf_lin_opts *opts, pf_lin_info *info);
+
+/* Batched nonlinear solves: n independent problems, each as
+ * pf_nonlinear_solve.  p: host [n] pointers; info: host [n] or NULL. */
+pf_status pf_nonlinear_solve_batch(int32_t n, pf_grid *const *g, const pf_pf_params *const *p,
+                                   double *const *phi, pf_nl_info *info);
+
+/* Thread-local description of the last error (empty string if none). */
+const char *pf_last_error(void);
+
+/* Launch-shape override for tests and tuning: points per workgroup strip,
+ * z-planes per workgroup, threads per workgroup.  0 = autotuned/default.
+ * Applies to grids created afterwards.  Returns PF_ERR_ARG for unsupported
+ * shapes. */
+pf_status pf_set_launch(int32_t strip, int32_t zdepth, int32_t threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

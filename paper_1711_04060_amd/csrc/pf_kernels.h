@@ -1,0 +1,716 @@
+// pf_kernels.h -- gfx950 device kernels of the Poisson-Fermi hot path.
+//
+// Operator (Sec. 3: 7-point FD of Eqs. (7), (12), (13)):
+//   (A x)_i = sum_f c_f (x_i - x_j) + sigma_i x_i,  c_f = 2 e_i e_j / (e_i + e_j) / h^2
+// evaluated matrix-free from the nodal coefficient field e (or a constant for
+// the PF1 operator), never stored as the seven diagonals of Sec. 4.
+//
+// Jacobi preconditioning (Sec. 4, Table 3, right-preconditioned) enters
+// through dinv: dinv_i = 1 / A_ii on free rows and -1 on Dirichlet rows (the
+// identity row's inverse diagonal is 1; the sign marks the row).  Since
+// A_ii * dinv_i = 1, (A M^-1 x)_i = x_i - sum_f c_f |dinv_j| x_j on free rows:
+// sigma appears only inside dinv, so the shifted PF2 operator costs no more
+// bytes per point than the Poisson one.
+//
+// Stencil kernels march along z.  A workgroup owns a strip of S consecutive
+// nodes of the flattened xy plane (m = i + nx*j) and a chunk of z planes.
+// For each plane it stages the strip plus one row of halo on each side
+// ([m0 - nx, m0 + S + nx)) in LDS; x and y neighbours are read from LDS, the
+// z neighbours of the thread's own nodes stay in registers.  Node loads are
+// coalesced along x.  Values that depend only on a node (the BiCGSTAB vector
+// updates) are computed once per staged node, so the update and the stencil
+// fuse into one pass.
+//
+// Reductions: each workgroup reduces its products in FP64 (wave shuffles,
+// then LDS), writes one partial per quantity, and the last workgroup to take
+// a ticket sums the partials in a fixed order and updates the BiCGSTAB
+// scalars on the device: deterministic, no floating-point atomics, no host
+// round trip inside an iteration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfk {
+
+// node flag bits (one byte per node)
+enum : uint8_t { F_DIR_PHI = 1, F_DIR_PSI = 2, F_SOLVENT = 4 };
+
+// device-side BiCGSTAB state (FP64 even when the vectors are FP32)
+struct Scalars {
+    double rho;        // shadow . r of the current iterate
+    double alpha, omega, beta;
+    double rr;         // ||r||^2 (recurrence)
+    double tol2;       // (rel_tol * ||b_lift||)^2
+    double rt2;        // ||r_shadow||^2 at the last (re)start
+    double red[4];     // raw sums of the last reduction
+    int iter, maxit, status, pad;
+};
+enum { ST_RUN = 0, ST_CONV = 1, ST_HALF = 2, ST_RESTART = 3, ST_NONFINITE = 4, ST_MAXIT = 5 };
+
+// stencil operation selector
+enum { OP_SPMV = 0, OP_SPMV_JAC = 1, OP_RESID = 2, OP_BA = 3, OP_BB = 4 };
+
+template <typename T>
+struct ZArgs {
+    int nx, ny, nz, P;          // P = nx*ny
+    int S, KZ, nstrips, G;      // strip length, z planes per workgroup, strips, workgroups
+    int lmax;                   // LDS elements per array (>= S + 2*nx)
+    T ih2;                      // 1/h^2
+    T ceps;                     // constant face coefficient (already / h^2), CEPS form
+    const T *eps;               // nodal coefficient field (non-CEPS)
+    const T *dinv;              // inverse diagonal, -1 on Dirichlet rows
+    const T *x;                 // SPMV*/RESID operand; BA/BB: r
+    const T *y0;                // BA: p (previous); BB: v
+    const T *y1;                // BA: v (previous)
+    const T *rt;                // BA: shadow residual
+    T *out;                     // SPMV*: y; RESID: r; BA: v (new); BB: t
+    T *out_aux;                 // BA: p (new); BB: s
+    // residual extras (FP64 only)
+    const double *b;            // right-hand side
+    const double *sigma;        // diagonal shift or null
+    double sig_const;           // used when sigma is null
+    const double *dval;         // Dirichlet values (lift form)
+    int lift;                   // RESID: use x = Dirichlet values on Dirichlet rows, 0 elsewhere
+    float *r32;                 // RESID: optional FP32 copy of r
+    double *rt64;               // RESID: optional shadow copy (FP64)
+    float *rt32;                // RESID: optional shadow copy (FP32)
+    // reduction and scalars
+    Scalars *sc;
+    double *partials;           // [G][4]
+    unsigned *ticket;
+};
+
+// ------------------------------------------------------------- helpers
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Remap so that each XCD receives a contiguous range of logical
+// tiles: neighbouring strips then share that XCD's L2 for their halos.
+__device__ __forceinline__ int xcd_remap(int b, int G)
+{
+    const int X = 8;
+    const int per = G / X, rem = G % X;
+    const int xcd = b % X, idx = b / X;
+    return (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+template <typename T>
+__device__ __forceinline__ T face(T a, T b, T ih2)
+{
+    return (T(2) * a * b) / (a + b) * ih2;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// Reduce NQ per-thread values over the workgroup; thread 0 gets the result.
+template <int NQ, int NT, bool MAX = false>
+__device__ __forceinline__ void block_reduce(double (&v)[NQ])
+{
+    __shared__ double red[NT / 64][NQ];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s = MAX ? wave_max(v[q]) : wave_sum(v[q]);
+        if (lane == 0) red[w][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double s = red[0][q];
+            for (int i = 1; i < NT / 64; ++i) s = MAX ? fmax(s, red[i][q]) : s + red[i][q];
+            v[q] = s;
+        }
+    }
+}
+
+// Store the workgroup partials and take a ticket; returns true in every
+// thread of the last workgroup, which then sees all partials.
+template <int NQ>
+__device__ __forceinline__ bool publish_partials(const double (&v)[NQ], double *partials,
+                                                 unsigned *ticket, int G)
+{
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) partials[blockIdx.x * 4 + q] = v[q];
+        unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (t == (unsigned)(G - 1));
+    }
+    __syncthreads();
+    if (is_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return is_last;
+}
+
+// Fixed-order sum (or max) of the G partials, run by the last workgroup.
+template <int NQ, int NT, bool MAX = false>
+__device__ __forceinline__ void final_reduce(double (&v)[NQ], const double *partials, int G)
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+    for (int i = threadIdx.x; i < G; i += NT) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double p = partials[i * 4 + q];
+            v[q] = MAX ? fmax(v[q], p) : v[q] + p;
+        }
+    }
+    __syncthreads();
+    block_reduce<NQ, NT, MAX>(v);
+}
+
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+// --------------------------------------------------- z-marching stencil
+
+template <typename T>
+__device__ __forceinline__ T absT(T x) { return x < T(0) ? -x : x; }
+
+// Per-node quantities of the staged plane for each operation:
+//   val: the value the stencil reads at neighbours;
+//   aux: the node's own unscaled value (BA: new p, BB: s, SPMV_JAC: x);
+//   d:   dinv at the node (row mask and Jacobi scale).
+template <int OP, typename T>
+__device__ __forceinline__ void stage_node(const ZArgs<T> &a, size_t g, T &val, T &aux, T &d,
+                                           double alpha, double omega, double beta, bool own)
+{
+    d = a.dinv[g];
+    if constexpr (OP == OP_SPMV) {
+        val = a.x[g];
+        aux = val;
+    } else if constexpr (OP == OP_SPMV_JAC) {
+        aux = a.x[g];
+        val = absT(d) * aux;
+    } else if constexpr (OP == OP_RESID) {
+        if (a.lift) val = (d < T(0) && a.dval) ? (T)a.dval[g] : T(0);
+        else val = a.x[g];
+        aux = val;
+    } else if constexpr (OP == OP_BA) {
+        // p = r + beta (p - omega v)   (Table 3 step 9)
+        const T r = a.x[g], p = a.y0[g], v = a.y1[g];
+        aux = r + (T)beta * (p - (T)omega * v);
+        val = absT(d) * aux;
+        if (own) a.out_aux[g] = aux;
+    } else {  // OP_BB
+        // s = r - alpha v   (Table 3 step 13)
+        const T r = a.x[g], v = a.y0[g];
+        aux = r - (T)alpha * v;
+        val = absT(d) * aux;
+        if (own) a.out_aux[g] = aux;
+    }
+}
+
+template <int OP, typename T, bool CEPS, int NT, int PPT>
+__global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int NQ = (OP == OP_BB) ? 3 : 1;
+    double alpha = 0, omega = 0, beta = 0;
+    if constexpr (OP == OP_BA || OP == OP_BB) {
+        if (a.sc->status != ST_RUN) return;
+        alpha = a.sc->alpha;
+        omega = a.sc->omega;
+        beta = a.sc->beta;
+    }
+    T *lval = reinterpret_cast<T *>(smem_raw);
+    T *leps = lval + a.lmax;
+
+    const int lb = xcd_remap(blockIdx.x, a.G);
+    const int strip = lb % a.nstrips, zc = lb / a.nstrips;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, P = a.P;
+    const int m0 = strip * a.S;
+    const int k0 = zc * a.KZ, k1 = min(nz, k0 + a.KZ);
+    const int lo = max(0, m0 - nx), hi = min(P, m0 + a.S + nx);
+    const int mend = min(P, m0 + a.S);
+    const int nhl = m0 - lo, nhalo = nhl + (hi - mend);
+    const T ih2 = a.ih2;
+
+    // own nodes and their LDS neighbour offsets (mirror ghosts at the faces;
+    // rows on Dirichlet faces are masked, so the mirror only matters on
+    // Neumann faces)
+    int om[PPT], ox[PPT], oxm[PPT], oxp[PPT], oym[PPT], oyp[PPT];
+    bool ok[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int m = m0 + threadIdx.x + q * NT;
+        ok[q] = m < mend;
+        const int mm = ok[q] ? m : m0;
+        const int j = mm / nx, i = mm - j * nx;
+        om[q] = mm;
+        ox[q] = mm - lo;
+        oxm[q] = ((i > 0) ? mm - 1 : mm + 1) - lo;
+        oxp[q] = ((i < nx - 1) ? mm + 1 : mm - 1) - lo;
+        oym[q] = ((j > 0) ? mm - nx : mm + nx) - lo;
+        oyp[q] = ((j < ny - 1) ? mm + nx : mm - nx) - lo;
+    }
+
+    T vp[PPT], vc[PPT], vn[PPT];   // staged value, planes k-1, k, k+1
+    T ep[PPT], ec[PPT], en[PPT];   // coefficient field
+    T ac[PPT], an[PPT];            // aux, planes k, k+1
+    T dc[PPT], dn[PPT];            // dinv, planes k, k+1
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+
+    const size_t Ps = (size_t)P;
+    // ---- prologue: plane k0 (own in registers, window in LDS), plane k0-1 own
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        vc[q] = ac[q] = dc[q] = ec[q] = T(0);
+        vp[q] = ep[q] = T(0);
+        if (ok[q]) {
+            const size_t g = (size_t)om[q] + Ps * k0;
+            stage_node<OP, T>(a, g, vc[q], ac[q], dc[q], alpha, omega, beta, true);
+            if constexpr (!CEPS) ec[q] = a.eps[g];
+            if (k0 > 0) {
+                T ax, dx;
+                const size_t gd = g - Ps;
+                stage_node<OP, T>(a, gd, vp[q], ax, dx, alpha, omega, beta, false);
+                if constexpr (!CEPS) ep[q] = a.eps[gd];
+            }
+            lval[ox[q]] = vc[q];
+            if constexpr (!CEPS) leps[ox[q]] = ec[q];
+        }
+    }
+    for (int hI = threadIdx.x; hI < nhalo; hI += NT) {
+        const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
+        const size_t g = (size_t)m + Ps * k0;
+        T v, ax, dx;
+        stage_node<OP, T>(a, g, v, ax, dx, alpha, omega, beta, false);
+        lval[m - lo] = v;
+        if constexpr (!CEPS) leps[m - lo] = a.eps[g];
+    }
+    __syncthreads();
+
+    for (int k = k0; k < k1; ++k) {
+        const bool has_up = (k + 1) < nz;
+        // (1) own nodes of plane k+1 into registers (loads in flight during (2))
+        if (has_up) {
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                if (ok[q]) {
+                    const size_t g = (size_t)om[q] + Ps * (k + 1);
+                    stage_node<OP, T>(a, g, vn[q], an[q], dn[q], alpha, omega, beta, k + 1 < k1);
+                    if constexpr (!CEPS) en[q] = a.eps[g];
+                }
+            }
+        }
+        // (2) output for plane k
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            if (!ok[q]) continue;
+            const size_t g = (size_t)om[q] + Ps * k;
+            const T vu = has_up ? vn[q] : vp[q];
+            const T vd = (k > 0) ? vp[q] : vn[q];
+            T sum, csum = T(0);
+            if constexpr (CEPS) {
+                const T c = a.ceps;
+                sum = c * (lval[oxm[q]] + lval[oxp[q]] + lval[oym[q]] + lval[oyp[q]] + vu + vd);
+                csum = T(6) * c;
+            } else {
+                const T e = ec[q];
+                const T eu = has_up ? en[q] : ep[q];
+                const T ed = (k > 0) ? ep[q] : en[q];
+                const T c0 = face(e, leps[oxm[q]], ih2), c1 = face(e, leps[oxp[q]], ih2);
+                const T c2 = face(e, leps[oym[q]], ih2), c3 = face(e, leps[oyp[q]], ih2);
+                const T c4 = face(e, ed, ih2), c5 = face(e, eu, ih2);
+                sum = c0 * lval[oxm[q]] + c1 * lval[oxp[q]] + c2 * lval[oym[q]] + c3 * lval[oyp[q]] +
+                      c4 * vd + c5 * vu;
+                csum = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
+            }
+            const bool freerow = dc[q] > T(0);
+            if constexpr (OP == OP_SPMV) {
+                const double sg = a.sigma ? a.sigma[g] : a.sig_const;
+                const T D = csum + (T)sg;
+                a.out[g] = freerow ? D * vc[q] - sum : vc[q];
+            } else if constexpr (OP == OP_SPMV_JAC) {
+                a.out[g] = freerow ? ac[q] - sum : ac[q];
+            } else if constexpr (OP == OP_RESID) {
+                const double sg = a.sigma ? a.sigma[g] : a.sig_const;
+                const double D = (double)csum + sg;
+                const double Ax = D * (double)vc[q] - (double)sum;
+                const double r = freerow ? a.b[g] - Ax : 0.0;
+                a.out[g] = (T)r;
+                if (a.r32) a.r32[g] = (float)r;
+                if (a.rt64) a.rt64[g] = r;
+                if (a.rt32) a.rt32[g] = (float)r;
+                acc[0] += r * r;
+            } else if constexpr (OP == OP_BA) {
+                // v = A M^-1 p  (Table 3 step 11), then shadow . v (step 12)
+                const T v = freerow ? ac[q] - sum : T(0);
+                a.out[g] = v;
+                acc[0] += (double)a.rt[g] * (double)v;
+            } else {
+                // t = A M^-1 s  (step 14); t.s, t.t (step 15), s.s
+                const T t = freerow ? ac[q] - sum : T(0);
+                const double s = (double)ac[q];
+                a.out[g] = t;
+                acc[0] += (double)t * s;
+                acc[1] += (double)t * (double)t;
+                acc[2] += s * s;
+            }
+        }
+        if (k + 1 >= k1) break;   // the next plane belongs to another workgroup
+        // (3) all reads of plane k done
+        __syncthreads();
+        // (4) stage plane k+1 in LDS
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            if (ok[q]) {
+                lval[ox[q]] = vn[q];
+                if constexpr (!CEPS) leps[ox[q]] = en[q];
+            }
+        }
+        for (int hI = threadIdx.x; hI < nhalo; hI += NT) {
+            const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
+            const size_t g = (size_t)m + Ps * (k + 1);
+            T v, ax, dx;
+            stage_node<OP, T>(a, g, v, ax, dx, alpha, omega, beta, false);
+            lval[m - lo] = v;
+            if constexpr (!CEPS) leps[m - lo] = a.eps[g];
+        }
+        __syncthreads();
+        // (6) rotate
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            vp[q] = vc[q]; vc[q] = vn[q];
+            ep[q] = ec[q]; ec[q] = en[q];
+            ac[q] = an[q]; dc[q] = dn[q];
+        }
+    }
+
+    if constexpr (OP == OP_RESID || OP == OP_BA || OP == OP_BB) {
+        block_reduce<NQ, NT>(acc);
+        if (publish_partials<NQ>(acc, a.partials, a.ticket, a.G)) {
+            double tot[NQ];
+            final_reduce<NQ, NT>(tot, a.partials, a.G);
+            if (threadIdx.x == 0) {
+                Scalars *sc = a.sc;
+                *a.ticket = 0u;
+                for (int q = 0; q < NQ; ++q) sc->red[q] = tot[q];
+                if constexpr (OP == OP_BA) {
+                    const double rtv = tot[0];
+                    if (!finite(rtv)) sc->status = ST_NONFINITE;
+                    else if (rtv == 0.0) sc->status = ST_RESTART;
+                    else sc->alpha = sc->rho / rtv;          // Table 3 step 12
+                } else if constexpr (OP == OP_BB) {
+                    const double ts = tot[0], tt = tot[1], ss = tot[2];
+                    if (!finite(ts) || !finite(tt) || !finite(ss)) {
+                        sc->status = ST_NONFINITE;
+                    } else if (ss <= sc->tol2) {
+                        // half-step convergence: x += alpha p_hat only
+                        sc->omega = 0.0;
+                        sc->status = ST_HALF;
+                    } else if (tt == 0.0) {
+                        sc->status = ST_RESTART;
+                    } else {
+                        sc->omega = ts / tt;                  // Table 3 step 15
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------- BiCGSTAB step C (pointwise, fused)
+
+// x += alpha M^-1 p + omega M^-1 s (step 16); r = s - omega t (step 17);
+// then shadow . r and r . r for the next beta (step 8) and the stop test.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_bicg_c(size_t N, T *__restrict__ x, T *__restrict__ r,
+                                               const T *__restrict__ p, const T *__restrict__ s,
+                                               const T *__restrict__ t, const T *__restrict__ dinv,
+                                               const T *__restrict__ rt, Scalars *sc,
+                                               double *partials, unsigned *ticket, int G)
+{
+    const int st = sc->status;
+    if (st != ST_RUN && st != ST_HALF) return;
+    const T alpha = (T)sc->alpha, omega = (T)sc->omega;
+    double acc[2] = {0.0, 0.0};
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < N; i += stride) {
+        const T d = absT(dinv[i]);
+        const T si = s[i], ti = t[i];
+        x[i] = x[i] + alpha * (d * p[i]) + omega * (d * si);
+        const T ri = si - omega * ti;
+        r[i] = ri;
+        acc[0] += (double)rt[i] * (double)ri;
+        acc[1] += (double)ri * (double)ri;
+    }
+    block_reduce<2, NT>(acc);
+    if (publish_partials<2>(acc, partials, ticket, G)) {
+        double tot[2];
+        final_reduce<2, NT>(tot, partials, G);
+        if (threadIdx.x == 0) {
+            *ticket = 0u;
+            const double rho_new = tot[0], rr = tot[1];
+            sc->red[0] = rho_new;
+            sc->red[1] = rr;
+            sc->rr = rr;
+            sc->iter += 1;
+            const int was = sc->status;
+            if (!finite(rho_new) || !finite(rr)) {
+                sc->status = ST_NONFINITE;
+            } else if (was == ST_HALF || rr <= sc->tol2) {
+                sc->status = ST_CONV;
+            } else if (sc->iter >= sc->maxit) {
+                sc->status = ST_MAXIT;
+            } else if (sc->omega == 0.0 || fabs(rho_new) < 1e-300 ||
+                       rho_new * rho_new < 1e-28 * sc->rt2 * rr) {
+                sc->status = ST_RESTART;   // shadow residual nearly orthogonal to r
+            } else {
+                sc->beta = (rho_new / sc->rho) * (sc->alpha / sc->omega);   // step 8
+                sc->rho = rho_new;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- small kernels
+
+struct Faces { double v[6]; };
+
+// Classify nodes: flag bits and Dirichlet values of the potential system.
+// bcphi/bcpsi: bit f set = face f is Neumann.
+__global__ void k_classify(int nx, int ny, int nz, const uint8_t *type, const double *fixed_value,
+                           int bcphi, Faces bcval, int bcpsi, uint8_t *flags, double *dval)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(n % nx), j = (int)((n / nx) % ny), k = (int)(n / ((size_t)nx * ny));
+        const int on[6] = {i == 0, i == nx - 1, j == 0, j == ny - 1, k == 0, k == nz - 1};
+        bool dphi = false, dpsi = false;
+        double v = 0.0;
+        for (int f = 0; f < 6; ++f) {
+            if (on[f] && !((bcphi >> f) & 1)) { dphi = true; v = bcval.v[f]; }
+            if (on[f] && !((bcpsi >> f) & 1)) dpsi = true;
+        }
+        const uint8_t t = type ? type[n] : 0;
+        if (t == 2) { dphi = true; v = fixed_value ? fixed_value[n] : 0.0; }
+        if (t != 0) dpsi = true;
+        flags[n] = (dphi ? F_DIR_PHI : 0) | (dpsi ? F_DIR_PSI : 0) | (t == 0 ? F_SOLVENT : 0);
+        dval[n] = dphi ? v : 0.0;
+    }
+}
+
+// Count invalid inputs: eps not finite or <= 0, type > 2, fixed data not finite.
+__global__ void k_validate(size_t N, const double *eps, const uint8_t *type, const double *q,
+                           const double *fv, unsigned *bad)
+{
+    unsigned b = 0;
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        const double e = eps[n];
+        if (!(e > 0.0) || !finite(e)) b |= 1u;
+        if (type && type[n] > 2) b |= 2u;
+        if (q && !finite(q[n])) b |= 4u;
+        if (fv && !finite(fv[n])) b |= 8u;
+    }
+    if (b) atomicOr(bad, b);
+}
+
+template <typename T>
+__global__ void k_convert(size_t N, const double *src, T *dst)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x)
+        dst[n] = (T)src[n];
+}
+
+template <typename T>
+__global__ void k_fill(size_t N, T *dst, T v)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x)
+        dst[n] = v;
+}
+
+// Inverse diagonal of the operator: 1 / (sum_f c_f + sigma) on free rows,
+// -1 on Dirichlet rows.  Computed in FP64 and rounded to T.
+template <typename T, bool CEPS>
+__global__ void k_dinv(int nx, int ny, int nz, double ih2, double ceps, const double *eps,
+                       const double *sigma, double sig_const, const uint8_t *flags, uint8_t dirbit,
+                       T *dinv)
+{
+    const size_t N = (size_t)nx * ny * nz, P = (size_t)nx * ny;
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        if (flags[n] & dirbit) { dinv[n] = T(-1); continue; }
+        const int i = (int)(n % nx), j = (int)((n / nx) % ny), k = (int)(n / P);
+        double D;
+        if (CEPS) {
+            D = 6.0 * ceps;
+        } else {
+            const double e = eps[n];
+            const size_t nb[6] = {i > 0 ? n - 1 : n + 1, i < nx - 1 ? n + 1 : n - 1,
+                                  j > 0 ? n - nx : n + nx, j < ny - 1 ? n + nx : n - nx,
+                                  k > 0 ? n - P : n + P, k < nz - 1 ? n + P : n - P};
+            D = 0.0;
+            for (int f = 0; f < 6; ++f) D += (2.0 * e * eps[nb[f]]) / (e + eps[nb[f]]) * ih2;
+        }
+        D += sigma ? sigma[n] : sig_const;
+        dinv[n] = (T)(1.0 / D);
+    }
+}
+
+// x_i := Dirichlet value on Dirichlet rows (potential system) or 0 (PF1).
+__global__ void k_set_dirichlet(size_t N, double *x, const uint8_t *flags, uint8_t dirbit,
+                                const double *dval)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x)
+        if (flags[n] & dirbit) x[n] = dval ? dval[n] : 0.0;
+}
+
+// x64 += d32 on free rows (iterative-refinement correction).
+__global__ void k_correct(size_t N, double *x, const float *d, const uint8_t *flags, uint8_t dirbit)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x)
+        if (!(flags[n] & dirbit)) x[n] += (double)d[n];
+}
+
+}  // namespace pfk
+
+namespace pfk {
+
+// ------------------------------------------------------------ Fermi, Eq. (1)
+
+constexpr int MAXSP = 16;
+struct SpeciesDev {
+    int nsp, steric;
+    double lam;              // e^2/(eps0 kB T) in grid units
+    double lnGB;             // ln(bulk void fraction), 0 when steric is off
+    double z[MAXSP];         // valences
+    double lncb[MAXSP];      // ln C_i^B
+    double lnvcb[MAXSP];     // ln(v_i C_i^B)
+    double p[MAXSP];         // v_i / v_0
+};
+
+// Steric potential S at potential phi: root of
+//   L(S) = ln( Gamma_B e^S + sum_i v_i C_i^B e^{-z_i phi + p_i S} ) = 0,
+// the void-fraction identity Gamma = Gamma_B e^S = 1 - sum_i v_i C_i.
+// L is convex and increasing in S; Newton's method started at the upper
+// bracket S = -ln Gamma_B (where L >= 0) descends monotonically to the root.
+// Everything stays in the log domain: |z_i phi| reaches 10^3 at charged nodes.
+__device__ __forceinline__ double steric_root(double phi, const SpeciesDev &sp)
+{
+    double S = -sp.lnGB;
+    for (int it = 0; it < 200; ++it) {
+        double m = sp.lnGB + S;
+        for (int i = 0; i < sp.nsp; ++i) m = fmax(m, sp.lnvcb[i] - sp.z[i] * phi + sp.p[i] * S);
+        double w0 = exp(sp.lnGB + S - m);
+        double sum = w0, dsum = w0;
+        for (int i = 0; i < sp.nsp; ++i) {
+            const double w = exp(sp.lnvcb[i] - sp.z[i] * phi + sp.p[i] * S - m);
+            sum += w;
+            dsum += sp.p[i] * w;
+        }
+        const double L = m + log(sum);
+        const double step = L * sum / dsum;
+        const double Sn = S - step;
+        if (!(fabs(Sn - S) > 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(S)))) return Sn;
+        S = Sn;
+    }
+    return S;
+}
+
+// Fermi update at every node; zeros off the solvent.  Writes any of:
+// rhs1 = -rho_hat (the PF1 right-hand side), rho = rho_hat,
+// sigma = lambda sum z_i^2 C_i (= -rho_hat' of Eq. (11)), conc[i*N + n], S.
+__global__ void k_fermi(size_t N, const double *phi, const uint8_t *flags, SpeciesDev sp,
+                        double *rhs1, double *rho, double *sigma, double *conc, double *Sout)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        double rh = 0.0, sg = 0.0, S = 0.0;
+        const bool solvent = flags[n] & F_SOLVENT;
+        if (solvent) {
+            const double ph = phi[n];
+            if (sp.steric) S = steric_root(ph, sp);
+            for (int i = 0; i < sp.nsp; ++i) {
+                const double C = exp(sp.lncb[i] - sp.z[i] * ph + sp.p[i] * S);
+                rh += sp.z[i] * C;
+                sg += sp.z[i] * sp.z[i] * C;
+                if (conc) conc[(size_t)i * N + n] = C;
+            }
+            rh *= sp.lam;
+            sg *= sp.lam;
+        } else if (conc) {
+            for (int i = 0; i < sp.nsp; ++i) conc[(size_t)i * N + n] = 0.0;
+        }
+        if (rhs1) rhs1[n] = -rh;
+        if (rho) rho[n] = rh;
+        if (sigma) sigma[n] = sg;
+        if (Sout) Sout[n] = S;
+    }
+}
+
+// Fixed-charge source lambda q / h^3.
+__global__ void k_source(size_t N, const double *q, double scale, double *src)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x)
+        src[n] = q ? scale * q[n] : 0.0;
+}
+
+// PF1 with l_c = 0: Psi = -rho_hat / eps_s on free Psi rows, 0 elsewhere.
+__global__ void k_psi_local(size_t N, const double *rhs1, const uint8_t *flags, double inv_eps_s,
+                            double *psi)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x)
+        psi[n] = (flags[n] & F_DIR_PSI) ? 0.0 : rhs1[n] * inv_eps_s;
+}
+
+// PF2 right-hand side (Eq. (13) scaled): -eps_s Psi + sigma Phi_0 + lambda q / h^3.
+__global__ void k_rhs_pf2(size_t N, const double *psi, const double *sigma, const double *phi0,
+                          const double *src, double eps_s, double *b)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x)
+        b[n] = -eps_s * psi[n] + sigma[n] * phi0[n] + src[n];
+}
+
+// Relaxation (Table 2 step 5): Phi := omega Phi_0 + (1 - omega) Phi; the max
+// norm of the change; Phi_0 := Phi.  Result in sc->red[0].
+template <int NT>
+__global__ __launch_bounds__(NT) void k_relax(size_t N, double *phi0, double *phi, double omega,
+                                              Scalars *sc, double *partials, unsigned *ticket, int G)
+{
+    double acc[1] = {0.0};
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t n = (size_t)blockIdx.x * NT + threadIdx.x; n < N; n += stride) {
+        const double old = phi0[n];
+        const double nv = omega * old + (1.0 - omega) * phi[n];
+        double d = fabs(nv - old);
+        if (d != d) d = __builtin_inf();   // keep a NaN visible through fmax
+        acc[0] = fmax(acc[0], d);
+        phi0[n] = nv;
+        phi[n] = nv;
+    }
+    block_reduce<1, NT, true>(acc);
+    if (publish_partials<1>(acc, partials, ticket, G)) {
+        double tot[1];
+        final_reduce<1, NT, true>(tot, partials, G);
+        if (threadIdx.x == 0) {
+            *ticket = 0u;
+            sc->red[0] = tot[0];
+        }
+    }
+}
+
+}  // namespace pfk
