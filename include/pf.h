@@ -205,6 +205,19 @@ pf_status pf_linear_solve_batch(int32_t n, pf_grid *const *g, const double *cons
 pf_status pf_nonlinear_solve_batch(int32_t n, pf_grid *const *g, const pf_pf_params *const *p,
                                    double *const *phi, pf_nl_info *info);
 
+/* Kernel timing for measurement: while enabled, one chunk in every `sample`
+ * records HIP events (as graph nodes, on the library's stream) around each
+ * launch of the BiCGSTAB step-A stencil kernel (the update of p fused with
+ * v = A M^-1 p, the kernel that moves the most bytes per iteration).
+ * enable = 1 clears the accumulators and starts; 0 stops.  Process-wide. */
+pf_status pf_timing_enable(int32_t enable, int32_t sample);
+
+/* Accumulated step-A timings for one precision (PF_FP64 or PF_MIXED = the
+ * FP32 inner kernel): launches timed and their mean duration in ms; bytes is
+ * the algorithmic HBM traffic of those launches (8 vectors of N elements per
+ * launch: r, p, v, dinv, eps, shadow read; p, v written). */
+pf_status pf_timing_read(int32_t precision, int64_t *launches, double *mean_ms, double *bytes);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *pf_last_error(void);
 

@@ -53,33 +53,59 @@ pf_status fail(pf_status st, const char *fmt, ...)
 constexpr int NT = 256;          // threads per workgroup of every kernel
 constexpr int PW_MAX_G = 1024;   // workgroups of the pointwise kernels
 
-// launch override (pf_set_launch)
-int g_ppt_override = 0, g_kz_override = 0;
+// launch override (pf_set_launch): threads, points per thread, z-planes
+int g_nt_override = 0, g_ppt_override = 0, g_kz_override = 0;
 
+// step-A kernel timing (pf_timing_enable / pf_timing_read)
+struct Timing {
+    bool enabled = false;
+    int sample = 8;
+    long chunk = 0;
+    long long launches[2] = {0, 0};
+    double ms[2] = {0, 0}, bytes[2] = {0, 0};
+} g_timing;
+
+constexpr size_t LDS_MAX = 152 * 1024;   // dynamic LDS per workgroup (gfx950 has 160 KB; static arrays use the rest)
+
+// Launch shape of the z-marching stencil kernels: NTZ threads per
+// workgroup, PPT nodes per thread (strip S = NTZ*PPT), KZ planes per
+// workgroup.
 struct ZCfg {
-    int PPT = 2, S = 512, KZ = 8, nstrips = 1, nzc = 1, G = 1, lmax = 0;
+    int NTZ = 256, PPT = 2, S = 512, KZ = 8, nstrips = 1, nzc = 1, G = 1, lmax = 0;
     size_t lds = 0;
 };
 
-ZCfg make_cfg(int nx, int ny, int nz, size_t elem)
+ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz)
 {
     ZCfg c;
     const int P = nx * ny;
-    c.PPT = g_ppt_override ? g_ppt_override : (elem == 8 ? 2 : 4);
-    c.S = NT * c.PPT;
+    c.NTZ = ntz;
+    c.PPT = ppt;
+    c.S = ntz * ppt;
     c.nstrips = (P + c.S - 1) / c.S;
-    if (g_kz_override) {
-        c.KZ = g_kz_override;
-    } else {
-        // aim at ~8 workgroups per CU (256 CUs) with at least 4 planes each
-        const long work = (long)c.nstrips * nz;
-        c.KZ = (int)std::max<long>(4, (work + 2047) / 2048);
-    }
-    c.KZ = std::min(c.KZ, nz);
+    c.KZ = std::max(1, std::min(kz, nz));
     c.nzc = (nz + c.KZ - 1) / c.KZ;
     c.G = c.nstrips * c.nzc;
     c.lmax = std::min(P, c.S + 2 * nx);
-    c.lds = 2 * (size_t)c.lmax * elem;
+    c.lds = 4 * (size_t)c.lmax * elem;   // two planes of (value, coefficient)
+    return c;
+}
+
+// Shape used before (or without) tuning: long strips for wide planes,
+// z-chunks sized for several workgroups per CU.
+ZCfg default_cfg(int nx, int ny, int nz, size_t elem)
+{
+    const int P = nx * ny;
+    int ntz = g_nt_override ? g_nt_override : (P >= 16384 ? 1024 : 512);
+    int ppt = g_ppt_override ? g_ppt_override : (P >= 16384 ? 2 : 1);
+    int kz = g_kz_override;
+    if (!kz) {
+        const long strips = (P + (long)ntz * ppt - 1) / ((long)ntz * ppt);
+        kz = (int)std::max<long>(4, std::min<long>(16, strips * nz / 1024));
+    }
+    ZCfg c = make_cfg(nx, ny, nz, elem, ntz, ppt, kz);
+    while (c.lds > LDS_MAX && c.PPT > 1) c = make_cfg(nx, ny, nz, elem, c.NTZ, c.PPT - 1, c.KZ);
+    while (c.lds > LDS_MAX && c.NTZ > 256) c = make_cfg(nx, ny, nz, elem, c.NTZ / 2, c.PPT, c.KZ);
     return c;
 }
 
@@ -124,6 +150,8 @@ struct pf_grid {
     double *partials = nullptr;
     unsigned *ticket = nullptr;
     std::map<long, hipGraphExec_t> graphs;
+    std::vector<hipEvent_t> tev;       // timing events (2 per iteration of a chunk)
+    bool last_timed = false;
 
     // nonlinear state
     double *phi0 = nullptr, *phi = nullptr, *psi = nullptr, *rhs1 = nullptr, *sig = nullptr,
@@ -170,6 +198,9 @@ pf_status sync(pf_grid *g)
 }
 
 template <typename T>
+pf_status tune(pf_grid *g);
+
+template <typename T>
 pf_status ensure_work(pf_grid *g)
 {
     if constexpr (sizeof(T) == 8) {
@@ -181,6 +212,7 @@ pf_status ensure_work(pf_grid *g)
         for (double **p : {&w.x, &w.r, &w.rt, &w.p[0], &w.p[1], &w.v[0], &w.v[1], &w.s, &w.t})
             PFCHK(dalloc(g, p, g->N));
         g->have64 = true;
+        PFCHK(tune<double>(g));
     } else {
         if (g->have32) return PF_OK;
         PFCHK(ensure_work<double>(g));
@@ -194,31 +226,54 @@ pf_status ensure_work(pf_grid *g)
                            g->N, (const double *)g->eps64, g->eps32);
         HIPCHK(hipGetLastError());
         g->have32 = true;
+        PFCHK(tune<float>(g));
     }
     return PF_OK;
 }
 
 // --------------------------------------------------------------- launches
 
+template <int OP, typename T, bool CEPS, int NTZ, int PPT>
+hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
+{
+    auto kern = pfk::k_zmarch<OP, T, CEPS, NTZ, PPT>;
+    if (c.lds > 64 * 1024) {
+        static size_t granted = 0;   // per instantiation
+        if (c.lds > granted) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)c.lds);
+            if (e != hipSuccess) return e;
+            granted = c.lds;
+        }
+    }
+    hipLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), c.lds, s, a);
+    return hipGetLastError();
+}
+
 template <int OP, typename T, bool CEPS>
 hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
 {
-    switch (c.PPT) {
-    case 1:
-        hipLaunchKernelGGL((pfk::k_zmarch<OP, T, CEPS, NT, 1>), dim3(c.G), dim3(NT), c.lds, s, a);
-        break;
-    case 2:
-        hipLaunchKernelGGL((pfk::k_zmarch<OP, T, CEPS, NT, 2>), dim3(c.G), dim3(NT), c.lds, s, a);
-        break;
-    default:
-        hipLaunchKernelGGL((pfk::k_zmarch<OP, T, CEPS, NT, 4>), dim3(c.G), dim3(NT), c.lds, s, a);
-        break;
+    const int key = c.NTZ * 10 + c.PPT;
+    switch (key) {
+    case 2561: return launch_zk<OP, T, CEPS, 256, 1>(c, a, s);
+    case 2562: return launch_zk<OP, T, CEPS, 256, 2>(c, a, s);
+    case 5121: return launch_zk<OP, T, CEPS, 512, 1>(c, a, s);
+    case 5122: return launch_zk<OP, T, CEPS, 512, 2>(c, a, s);
+    case 10241: return launch_zk<OP, T, CEPS, 1024, 1>(c, a, s);
+    case 10242: return launch_zk<OP, T, CEPS, 1024, 2>(c, a, s);
+    default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <typename T>
 const ZCfg &cfg_of(const pf_grid *g)
+{
+    if constexpr (sizeof(T) == 8) return g->c64;
+    else return g->c32;
+}
+
+template <typename T>
+ZCfg &cfg_ref(pf_grid *g)
 {
     if constexpr (sizeof(T) == 8) return g->c64;
     else return g->c32;
@@ -324,7 +379,8 @@ pf_status write_scalars(pf_grid *g)
 // One BiCGSTAB iteration: stencil step A (p, v), stencil step B (s, t),
 // pointwise step C (x, r).  parity selects the p/v ping-pong buffers.
 template <typename T>
-pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity)
+pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     pfk::ZArgs<T> a = zbase<T>(g, op, dinv);
     a.x = w.r;
@@ -333,7 +389,9 @@ pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
     a.rt = w.rt;
     a.out = w.v[parity ^ 1];
     a.out_aux = w.p[parity ^ 1];
+    if (e0) HIPCHK(hipEventRecord(e0, g->stream));
     PFCHK((zlaunch<pfk::OP_BA, T>(g, op, a)));
+    if (e1) HIPCHK(hipEventRecord(e1, g->stream));
     pfk::ZArgs<T> b = zbase<T>(g, op, dinv);
     b.x = w.r;
     b.y0 = w.v[parity ^ 1];
@@ -353,7 +411,21 @@ pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
 template <typename T>
 pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m)
 {
-    const long key = (long)m * 8 + (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0) + (dinv == nullptr ? 4 : 0);
+    const bool timed = g_timing.enabled && (g_timing.chunk++ % g_timing.sample) == 0;
+    g->last_timed = timed;
+    if (timed && (int)g->tev.size() < 2 * m) {
+        while ((int)g->tev.size() < 2 * m) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            g->tev.push_back(e);
+        }
+    }
+    if (timed) {
+        // sampled chunk: direct launches with HIP events around step A
+        for (int i = 0; i < m; ++i) PFCHK(iteration<T>(g, op, dinv, w, i & 1, g->tev[2 * i], g->tev[2 * i + 1]));
+        return PF_OK;
+    }
+    const long key = (long)m * 16 + (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0);
     auto it = g->graphs.find(key);
     if (it == g->graphs.end()) {
         hipGraph_t graph;
@@ -370,6 +442,99 @@ pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
         it = g->graphs.emplace(key, exec).first;
     }
     HIPCHK(hipGraphLaunch(it->second, g->stream));
+    return PF_OK;
+}
+
+// ---------------------------------------------------------------- tuner
+
+// Launch shapes chosen per (grid shape, precision) for this process.
+std::map<std::tuple<int, int, int, int>, ZCfg> g_tuned;
+
+bool tuning_enabled()
+{
+    const char *e = getenv("PF_TUNE");
+    if (e && e[0] == '0') return false;
+    return !g_nt_override && !g_ppt_override && !g_kz_override;
+}
+
+// Time the BiCGSTAB step-A kernel (the kernel with the most traffic per
+// iteration) for each candidate shape on this grid and keep the fastest.
+// Runs once per grid shape and precision; the grid's workspace holds
+// synthetic vectors meanwhile (every solve reinitialises it).
+template <typename T>
+pf_status tune(pf_grid *g)
+{
+    if (!tuning_enabled()) return PF_OK;
+    const auto key = std::make_tuple(g->nx, g->ny, g->nz, (int)sizeof(T));
+    auto found = g_tuned.find(key);
+    if (found != g_tuned.end()) {
+        cfg_ref<T>(g) = found->second;
+        return PF_OK;
+    }
+    Work<T> &w = [&]() -> Work<T> & {
+        if constexpr (sizeof(T) == 8) return g->w64;
+        else return g->w32;
+    }();
+    T *dinv = nullptr;
+    if constexpr (sizeof(T) == 8) dinv = g->dinv64;
+    else dinv = g->dinv32;
+    PFCHK(fill<T>(g, w.r, T(1), g->N));
+    PFCHK(fill<T>(g, w.rt, T(1), g->N));
+    PFCHK(fill<T>(g, w.p[0], T(0), g->N));
+    PFCHK(fill<T>(g, w.v[0], T(0), g->N));
+    PFCHK(fill<T>(g, dinv, T(0.1), g->N));
+    Scalars &h = *g->hsc;
+    h = Scalars{};
+    h.rho = 1.0; h.alpha = 1.0; h.omega = 1.0; h.beta = 0.5; h.status = pfk::ST_RUN;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const ZCfg saved = cfg_ref<T>(g);
+    ZCfg best = saved;
+    float best_ms = 1e30f;
+    const int shapes[6][2] = {{256, 1}, {256, 2}, {512, 1}, {512, 2}, {1024, 1}, {1024, 2}};
+    OpDesc op;
+    pf_status st = PF_OK;
+    for (auto &sh : shapes) {
+        for (int kz : {2, 4, 8, 16, 32}) {
+            ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), sh[0], sh[1], kz);
+            if (c.lds > LDS_MAX || c.G > g->Gmax || kz > g->nz) continue;
+            cfg_ref<T>(g) = c;
+            pfk::ZArgs<T> a = zbase<T>(g, op, dinv);
+            a.x = w.r; a.y0 = w.p[0]; a.y1 = w.v[0]; a.rt = w.rt;
+            a.out = w.v[1]; a.out_aux = w.p[1];
+            float tot = 0;
+            for (int rep = 0; rep < 4 && st == PF_OK; ++rep) {
+                if ((st = write_scalars(g)) != PF_OK) break;
+                if (hipEventRecord(e0, g->stream) != hipSuccess) { st = fail(PF_ERR_DEVICE, "event record failed"); break; }
+                if (zlaunch<pfk::OP_BA, T>(g, op, a) != PF_OK) {
+                    // shape not launchable here: skip it
+                    (void)hipGetLastError();
+                    g_err.clear();
+                    tot = 1e30f;
+                    break;
+                }
+                if (hipEventRecord(e1, g->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    st = fail(PF_ERR_DEVICE, "event timing failed");
+                    break;
+                }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) tot += ms;
+            }
+            if (st != PF_OK) break;
+            if (tot < best_ms) { best_ms = tot; best = c; }
+        }
+        if (st != PF_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cfg_ref<T>(g) = (st == PF_OK) ? best : saved;
+    if (st != PF_OK) return st;
+    g_tuned[key] = best;
+    if (getenv("PF_LOG"))
+        fprintf(stderr, "[pf] tuned %dx%dx%d %s: threads %d, strip %d, z-planes %d, step A %.1f us\n", g->nx, g->ny,
+                g->nz, sizeof(T) == 8 ? "fp64" : "fp32", best.NTZ, best.S, best.KZ, best_ms / 3 * 1e3);
     return PF_OK;
 }
 
@@ -407,8 +572,21 @@ template <typename T>
 pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m, int *status)
 {
     for (;;) {
+        const int before = g->hsc->iter;
         PFCHK(run_chunk<T>(g, op, dinv, w, m));
         PFCHK(read_scalars(g));
+        if (g->last_timed && !op.psi) {
+            // iterations whose step A ran in full (later ones exit at once)
+            const int ran = std::min(m, g->hsc->iter - before);
+            const int pi = sizeof(T) == 8 ? 0 : 1;
+            for (int i = 0; i < ran; ++i) {
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, g->tev[2 * i], g->tev[2 * i + 1]));
+                g_timing.ms[pi] += ms;
+                g_timing.launches[pi] += 1;
+                g_timing.bytes[pi] += 8.0 * (double)g->N * sizeof(T);
+            }
+        }
         if (g->hsc->status != pfk::ST_RUN) {
             *status = g->hsc->status;
             return PF_OK;
@@ -556,13 +734,35 @@ void pf_lin_opts_default(pf_lin_opts *o)
     o->check_every = 0;
 }
 
+pf_status pf_timing_enable(int32_t enable, int32_t sample)
+{
+    if (sample <= 0) return fail(PF_ERR_ARG, "sample must be > 0");
+    g_timing = Timing{};
+    g_timing.enabled = enable != 0;
+    g_timing.sample = sample;
+    return PF_OK;
+}
+
+pf_status pf_timing_read(int32_t precision, int64_t *launches, double *mean_ms, double *bytes)
+{
+    if (precision != PF_FP64 && precision != PF_MIXED) return fail(PF_ERR_ARG, "unknown precision");
+    const int i = precision == PF_FP64 ? 0 : 1;
+    if (launches) *launches = g_timing.launches[i];
+    if (mean_ms) *mean_ms = g_timing.launches[i] ? g_timing.ms[i] / g_timing.launches[i] : 0.0;
+    if (bytes) *bytes = g_timing.bytes[i];
+    return PF_OK;
+}
+
 pf_status pf_set_launch(int32_t strip, int32_t zdepth, int32_t threads)
 {
-    if (threads != 0 && threads != NT) return fail(PF_ERR_ARG, "threads must be 0 or %d", NT);
-    if (strip != 0 && strip != NT && strip != 2 * NT && strip != 4 * NT)
-        return fail(PF_ERR_ARG, "strip must be 0, %d, %d or %d", NT, 2 * NT, 4 * NT);
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(PF_ERR_ARG, "threads must be 0, 256, 512 or 1024");
+    const int nt = threads ? threads : 256;
+    if (strip != 0 && strip != nt && strip != 2 * nt)
+        return fail(PF_ERR_ARG, "strip must be 0, threads or 2*threads");
     if (zdepth < 0) return fail(PF_ERR_ARG, "zdepth must be >= 0");
-    g_ppt_override = strip / NT;
+    g_nt_override = threads ? threads : (strip ? 256 : 0);
+    g_ppt_override = strip ? strip / nt : 0;
     g_kz_override = zdepth;
     return PF_OK;
 }
@@ -590,13 +790,14 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     g->bcphi_mask = bp; g->bcpsi_mask = bs;
     for (int f = 0; f < 6; ++f) g->bcval[f] = d->bc_value[f];
     g->ustream = (hipStream_t)d->stream;
-    g->c64 = make_cfg(d->nx, d->ny, d->nz, 8);
-    g->c32 = make_cfg(d->nx, d->ny, d->nz, 4);
-    if (g->c64.lds > 64 * 1024 || g->c32.lds > 64 * 1024) {
+    g->c64 = default_cfg(d->nx, d->ny, d->nz, 8);
+    g->c32 = default_cfg(d->nx, d->ny, d->nz, 4);
+    if (g->c64.lds > LDS_MAX || g->c32.lds > LDS_MAX) {
         delete g;
-        return fail(PF_ERR_ARG, "nx too large for the LDS strip (nx <= ~1500)");
+        return fail(PF_ERR_ARG, "nx too large for the LDS strip (nx <= ~4800)");
     }
-    g->Gmax = std::max({g->c64.G, g->c32.G, PW_MAX_G});
+    // partials must cover every launch shape the tuner may pick (KZ >= 1)
+    g->Gmax = std::max({(int)(((size_t)d->nx * d->ny + 255) / 256) * d->nz, g->c64.G, g->c32.G, PW_MAX_G});
     auto cleanup = [&](pf_status st) {
         pf_grid_destroy(g);
         return st;
@@ -650,6 +851,7 @@ void pf_grid_destroy(pf_grid *g)
     if (!g) return;
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     for (auto &kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : g->tev) (void)hipEventDestroy(e);
     for (void *p : g->allocs) (void)hipFree(p);
     if (g->hsc) (void)hipHostFree(g->hsc);
     if (g->ev) (void)hipEventDestroy(g->ev);

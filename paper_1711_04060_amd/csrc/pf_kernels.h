@@ -94,10 +94,28 @@ __device__ __forceinline__ int xcd_remap(int b, int G)
     return (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+// 1/d for d > 0: the hardware reciprocal estimate refined by two Newton steps
+// (FP64; within an ulp or so of the correctly rounded quotient) or the
+// hardware FP32 reciprocal (1 ulp).
+__device__ __forceinline__ double rcp_pos(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_pos(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// Face coefficient: harmonic mean of the two nodal values, divided by h^2.
 template <typename T>
 __device__ __forceinline__ T face(T a, T b, T ih2)
 {
+#ifdef PF_FACE_IEEE
     return (T(2) * a * b) / (a + b) * ih2;
+#else
+    return (T(2) * a * b * ih2) * rcp_pos(a + b);
+#endif
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -182,39 +200,77 @@ __device__ __forceinline__ T absT(T x) { return x < T(0) ? -x : x; }
 //   val: the value the stencil reads at neighbours;
 //   aux: the node's own unscaled value (BA: new p, BB: s, SPMV_JAC: x);
 //   d:   dinv at the node (row mask and Jacobi scale).
-template <int OP, typename T>
-__device__ __forceinline__ void stage_node(const ZArgs<T> &a, size_t g, T &val, T &aux, T &d,
-                                           double alpha, double omega, double beta, bool own)
+// Loading (raw) and staging are split so that the loads of a plane can be
+// issued one march step before their values are needed.
+template <typename T>
+struct Raw {
+    T d, e, x0, x1, x2;
+};
+
+template <int OP, typename T, bool CEPS>
+__device__ __forceinline__ void load_raw(const ZArgs<T> &a, size_t g, Raw<T> &w)
 {
-    d = a.dinv[g];
+    w.d = a.dinv[g];
+    if constexpr (!CEPS) w.e = a.eps[g];
+    if constexpr (OP == OP_SPMV || OP == OP_SPMV_JAC) {
+        w.x0 = a.x[g];
+    } else if constexpr (OP == OP_RESID) {
+        if (a.lift) w.x0 = a.dval ? (T)a.dval[g] : T(0);
+        else w.x0 = a.x[g];
+    } else if constexpr (OP == OP_BA) {
+        w.x0 = a.x[g];    // r
+        w.x1 = a.y0[g];   // p (previous)
+        w.x2 = a.y1[g];   // v (previous)
+    } else {
+        w.x0 = a.x[g];    // r
+        w.x1 = a.y0[g];   // v
+    }
+}
+
+template <int OP, typename T>
+__device__ __forceinline__ void stage_raw(const ZArgs<T> &a, const Raw<T> &w, size_t g, T &val, T &aux,
+                                          double alpha, double omega, double beta, bool own)
+{
+    const T d = w.d;
     if constexpr (OP == OP_SPMV) {
-        val = a.x[g];
+        val = w.x0;
         aux = val;
     } else if constexpr (OP == OP_SPMV_JAC) {
-        aux = a.x[g];
+        aux = w.x0;
         val = absT(d) * aux;
     } else if constexpr (OP == OP_RESID) {
-        if (a.lift) val = (d < T(0) && a.dval) ? (T)a.dval[g] : T(0);
-        else val = a.x[g];
+        val = (a.lift && !(d < T(0))) ? T(0) : w.x0;
         aux = val;
     } else if constexpr (OP == OP_BA) {
         // p = r + beta (p - omega v)   (Table 3 step 9)
-        const T r = a.x[g], p = a.y0[g], v = a.y1[g];
-        aux = r + (T)beta * (p - (T)omega * v);
+        aux = w.x0 + (T)beta * (w.x1 - (T)omega * w.x2);
         val = absT(d) * aux;
         if (own) a.out_aux[g] = aux;
     } else {  // OP_BB
         // s = r - alpha v   (Table 3 step 13)
-        const T r = a.x[g], v = a.y0[g];
-        aux = r - (T)alpha * v;
+        aux = w.x0 - (T)alpha * w.x1;
         val = absT(d) * aux;
         if (own) a.out_aux[g] = aux;
     }
 }
 
+template <int OP, typename T, bool CEPS>
+__device__ __forceinline__ void stage_node(const ZArgs<T> &a, size_t g, T &val, T &aux, T &d, T &e,
+                                           double alpha, double omega, double beta, bool own)
+{
+    Raw<T> w;
+    load_raw<OP, T, CEPS>(a, g, w);
+    stage_raw<OP, T>(a, w, g, val, aux, alpha, omega, beta, own);
+    d = w.d;
+    if constexpr (!CEPS) e = w.e;
+}
+
 template <int OP, typename T, bool CEPS, int NT, int PPT>
 __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
 {
+    // halo nodes per thread kept in registers; more than HMAX*NT halo nodes
+    // (nx > HMAX*NT/2) are handled by a slower loop
+    constexpr int HMAX = 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int NQ = (OP == OP_BB) ? 3 : 1;
     double alpha = 0, omega = 0, beta = 0;
@@ -224,8 +280,11 @@ __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
         omega = a.sc->omega;
         beta = a.sc->beta;
     }
-    T *lval = reinterpret_cast<T *>(smem_raw);
-    T *leps = lval + a.lmax;
+    // two LDS planes (double buffer) of staged values and coefficients
+    T *lval0 = reinterpret_cast<T *>(smem_raw);
+    T *leps0 = lval0 + a.lmax;
+    T *lval1 = leps0 + a.lmax;
+    T *leps1 = lval1 + a.lmax;
 
     const int lb = xcd_remap(blockIdx.x, a.G);
     const int strip = lb % a.nstrips, zc = lb / a.nstrips;
@@ -255,78 +314,133 @@ __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
         oym[q] = ((j > 0) ? mm - nx : mm + nx) - lo;
         oyp[q] = ((j < ny - 1) ? mm + nx : mm - nx) - lo;
     }
+    // halo nodes of this thread (plane-local index)
+    int hm[HMAX];
+    bool hok[HMAX];
+#pragma unroll
+    for (int u = 0; u < HMAX; ++u) {
+        const int hI = threadIdx.x + u * NT;
+        hok[u] = hI < nhalo;
+        hm[u] = (hI < nhl) ? lo + hI : mend + (hI - nhl);
+    }
 
     T vp[PPT], vc[PPT], vn[PPT];   // staged value, planes k-1, k, k+1
     T ep[PPT], ec[PPT], en[PPT];   // coefficient field
     T ac[PPT], an[PPT];            // aux, planes k, k+1
     T dc[PPT], dn[PPT];            // dinv, planes k, k+1
+    Raw<T> ro[PPT], rh[HMAX];      // raw loads of the plane after next
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 
     const size_t Ps = (size_t)P;
-    // ---- prologue: plane k0 (own in registers, window in LDS), plane k0-1 own
+    // ---- prologue: plane k0 (own in registers, window in LDS buffer 0),
+    //      plane k0-1 own values, raw loads of plane k0+1
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         vc[q] = ac[q] = dc[q] = ec[q] = T(0);
-        vp[q] = ep[q] = T(0);
+        vp[q] = ep[q] = vn[q] = en[q] = an[q] = dn[q] = T(0);
         if (ok[q]) {
             const size_t g = (size_t)om[q] + Ps * k0;
-            stage_node<OP, T>(a, g, vc[q], ac[q], dc[q], alpha, omega, beta, true);
-            if constexpr (!CEPS) ec[q] = a.eps[g];
+            stage_node<OP, T, CEPS>(a, g, vc[q], ac[q], dc[q], ec[q], alpha, omega, beta, true);
             if (k0 > 0) {
                 T ax, dx;
-                const size_t gd = g - Ps;
-                stage_node<OP, T>(a, gd, vp[q], ax, dx, alpha, omega, beta, false);
-                if constexpr (!CEPS) ep[q] = a.eps[gd];
+                stage_node<OP, T, CEPS>(a, g - Ps, vp[q], ax, dx, ep[q], alpha, omega, beta, false);
             }
-            lval[ox[q]] = vc[q];
-            if constexpr (!CEPS) leps[ox[q]] = ec[q];
+            lval0[ox[q]] = vc[q];
+            if constexpr (!CEPS) leps0[ox[q]] = ec[q];
         }
     }
     for (int hI = threadIdx.x; hI < nhalo; hI += NT) {
         const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
-        const size_t g = (size_t)m + Ps * k0;
-        T v, ax, dx;
-        stage_node<OP, T>(a, g, v, ax, dx, alpha, omega, beta, false);
-        lval[m - lo] = v;
-        if constexpr (!CEPS) leps[m - lo] = a.eps[g];
+        T v, ax, dx, e;
+        stage_node<OP, T, CEPS>(a, (size_t)m + Ps * k0, v, ax, dx, e, alpha, omega, beta, false);
+        lval0[m - lo] = v;
+        if constexpr (!CEPS) leps0[m - lo] = e;
+    }
+    if (k0 + 1 < nz) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q)
+            if (ok[q]) load_raw<OP, T, CEPS>(a, (size_t)om[q] + Ps * (k0 + 1), ro[q]);
+    }
+    if (k0 + 1 < k1) {
+#pragma unroll
+        for (int u = 0; u < HMAX; ++u)
+            if (hok[u]) load_raw<OP, T, CEPS>(a, (size_t)hm[u] + Ps * (k0 + 1), rh[u]);
     }
     __syncthreads();
 
+    int cur = 0;
+    T hv[HMAX], he[HMAX];
     for (int k = k0; k < k1; ++k) {
         const bool has_up = (k + 1) < nz;
-        // (1) own nodes of plane k+1 into registers (loads in flight during (2))
+        const bool stage_next = (k + 1) < k1;
+        T *lv = cur ? lval1 : lval0;
+        T *le = cur ? leps1 : leps0;
+        // (1) stage plane k+1 from the raw loads issued one step ago
         if (has_up) {
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
                 if (ok[q]) {
                     const size_t g = (size_t)om[q] + Ps * (k + 1);
-                    stage_node<OP, T>(a, g, vn[q], an[q], dn[q], alpha, omega, beta, k + 1 < k1);
-                    if constexpr (!CEPS) en[q] = a.eps[g];
+                    stage_raw<OP, T>(a, ro[q], g, vn[q], an[q], alpha, omega, beta, stage_next);
+                    dn[q] = ro[q].d;
+                    if constexpr (!CEPS) en[q] = ro[q].e;
                 }
             }
         }
-        // (2) output for plane k
+        if (stage_next) {
+#pragma unroll
+            for (int u = 0; u < HMAX; ++u) {
+                if (hok[u]) {
+                    T ax;
+                    stage_raw<OP, T>(a, rh[u], 0, hv[u], ax, alpha, omega, beta, false);
+                    if constexpr (!CEPS) he[u] = rh[u].e;
+                }
+            }
+        }
+        // (2) issue the loads of plane k+2; they arrive during this step
+        if (k + 2 < nz && k + 2 <= k1) {
+#pragma unroll
+            for (int q = 0; q < PPT; ++q)
+                if (ok[q]) load_raw<OP, T, CEPS>(a, (size_t)om[q] + Ps * (k + 2), ro[q]);
+        }
+        if (k + 2 < k1) {
+#pragma unroll
+            for (int u = 0; u < HMAX; ++u)
+                if (hok[u]) load_raw<OP, T, CEPS>(a, (size_t)hm[u] + Ps * (k + 2), rh[u]);
+        }
+        // mirror ghosts across the z faces, written into the register planes
+        // (uniform branches, static indices: selecting between the arrays
+        // themselves would force them out of registers)
+        if (!has_up) {
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) { vn[q] = vp[q]; en[q] = ep[q]; }
+        }
+        if (k == 0) {
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) { vp[q] = vn[q]; ep[q] = en[q]; }
+        }
+        // (3) output for plane k
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             if (!ok[q]) continue;
             const size_t g = (size_t)om[q] + Ps * k;
-            const T vu = has_up ? vn[q] : vp[q];
-            const T vd = (k > 0) ? vp[q] : vn[q];
+            const T vu = vn[q];
+            const T vd = vp[q];
             T sum, csum = T(0);
             if constexpr (CEPS) {
                 const T c = a.ceps;
-                sum = c * (lval[oxm[q]] + lval[oxp[q]] + lval[oym[q]] + lval[oyp[q]] + vu + vd);
+                sum = c * (lv[oxm[q]] + lv[oxp[q]] + lv[oym[q]] + lv[oyp[q]] + vu + vd);
                 csum = T(6) * c;
             } else {
                 const T e = ec[q];
-                const T eu = has_up ? en[q] : ep[q];
-                const T ed = (k > 0) ? ep[q] : en[q];
-                const T c0 = face(e, leps[oxm[q]], ih2), c1 = face(e, leps[oxp[q]], ih2);
-                const T c2 = face(e, leps[oym[q]], ih2), c3 = face(e, leps[oyp[q]], ih2);
+                const T eu = en[q];
+                const T ed = ep[q];
+                const T c0 = face(e, le[oxm[q]], ih2), c1 = face(e, le[oxp[q]], ih2);
+                const T c2 = face(e, le[oym[q]], ih2), c3 = face(e, le[oyp[q]], ih2);
                 const T c4 = face(e, ed, ih2), c5 = face(e, eu, ih2);
-                sum = c0 * lval[oxm[q]] + c1 * lval[oxp[q]] + c2 * lval[oym[q]] + c3 * lval[oyp[q]] +
+                sum = c0 * lv[oxm[q]] + c1 * lv[oxp[q]] + c2 * lv[oym[q]] + c3 * lv[oyp[q]] +
                       c4 * vd + c5 * vu;
                 csum = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
             }
@@ -362,27 +476,36 @@ __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
                 acc[2] += s * s;
             }
         }
-        if (k + 1 >= k1) break;   // the next plane belongs to another workgroup
-        // (3) all reads of plane k done
-        __syncthreads();
-        // (4) stage plane k+1 in LDS
+        if (!stage_next) break;   // the next plane belongs to another workgroup
+        // (4) stage plane k+1 in the other LDS buffer
+        T *nv = cur ? lval0 : lval1;
+        T *ne = cur ? leps0 : leps1;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             if (ok[q]) {
-                lval[ox[q]] = vn[q];
-                if constexpr (!CEPS) leps[ox[q]] = en[q];
+                nv[ox[q]] = vn[q];
+                if constexpr (!CEPS) ne[ox[q]] = en[q];
             }
         }
-        for (int hI = threadIdx.x; hI < nhalo; hI += NT) {
-            const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
-            const size_t g = (size_t)m + Ps * (k + 1);
-            T v, ax, dx;
-            stage_node<OP, T>(a, g, v, ax, dx, alpha, omega, beta, false);
-            lval[m - lo] = v;
-            if constexpr (!CEPS) leps[m - lo] = a.eps[g];
+#pragma unroll
+        for (int u = 0; u < HMAX; ++u) {
+            if (hok[u]) {
+                nv[hm[u] - lo] = hv[u];
+                if constexpr (!CEPS) ne[hm[u] - lo] = he[u];
+            }
         }
+        for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
+            const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
+            T v, ax, dx, e;
+            stage_node<OP, T, CEPS>(a, (size_t)m + Ps * (k + 1), v, ax, dx, e, alpha, omega, beta, false);
+            nv[m - lo] = v;
+            if constexpr (!CEPS) ne[m - lo] = e;
+        }
+        // one barrier per plane: the buffer written next step was last read
+        // before this barrier
         __syncthreads();
-        // (6) rotate
+        cur ^= 1;
+        // (5) rotate
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             vp[q] = vc[q]; vc[q] = vn[q];

@@ -24,7 +24,7 @@ PF_FP64, PF_MIXED = 0, 1
 EXPORTS = ("pf_grid_create", "pf_grid_destroy", "pf_lin_opts_default", "pf_linear_solve",
            "pf_residual", "pf_spmv", "pf_spmv_f32", "pf_pf_params_default", "pf_nonlinear_solve",
            "pf_fermi", "pf_linear_solve_batch", "pf_nonlinear_solve_batch", "pf_last_error",
-           "pf_set_launch")
+           "pf_set_launch", "pf_timing_enable", "pf_timing_read")
 
 
 class pf_grid_desc(C.Structure):
@@ -93,6 +93,8 @@ def load():
         lib.pf_last_error.argtypes = []
         lib.pf_last_error.restype = C.c_char_p
         lib.pf_set_launch.argtypes = [I32, I32, I32]
+        lib.pf_timing_enable.argtypes = [I32, I32]
+        lib.pf_timing_read.argtypes = [I32, C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]
         for name in EXPORTS:
             if name not in ("pf_grid_destroy", "pf_lin_opts_default", "pf_pf_params_default", "pf_last_error"):
                 getattr(lib, name).restype = C.c_int32
@@ -293,6 +295,16 @@ def pf_nonlinear_solve_batch(grids, params, phis, check=True):
 
 def pf_set_launch(strip=0, zdepth=0, threads=0):
     _check(load().pf_set_launch(int(strip), int(zdepth), int(threads)), "pf_set_launch")
+
+
+def pf_timing_enable(enable=1, sample=8):
+    _check(load().pf_timing_enable(int(enable), int(sample)), "pf_timing_enable")
+
+
+def pf_timing_read(precision=PF_FP64):
+    n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+    _check(load().pf_timing_read(int(precision), C.byref(n), C.byref(ms), C.byref(by)), "pf_timing_read")
+    return dict(launches=n.value, mean_ms=ms.value, bytes=by.value)
 
 
 def grid_from_problem(prob, device="cuda", stream=None) -> Grid:
