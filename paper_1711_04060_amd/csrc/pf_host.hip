@@ -148,7 +148,6 @@ struct pf_grid {
     bool have64 = false, have32 = false;
     Scalars *sc = nullptr, *hsc = nullptr;
     double *partials = nullptr;
-    unsigned *ticket = nullptr;
     std::map<long, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> tev;       // timing events (2 per iteration of a chunk)
     bool last_timed = false;
@@ -265,6 +264,23 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
     }
 }
 
+template <int OP, typename T, bool CEPS>
+hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
+{
+    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, 512, 1>;
+    if (c.lds > 64 * 1024) {
+        static size_t granted = 0;
+        if (c.lds > granted) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)c.lds);
+            if (e != hipSuccess) return e;
+            granted = c.lds;
+        }
+    }
+    hipLaunchKernelGGL(kern, dim3(c.G), dim3(512), c.lds, s, args, start, n);
+    return hipGetLastError();
+}
+
 template <typename T>
 const ZCfg &cfg_of(const pf_grid *g)
 {
@@ -291,9 +307,8 @@ struct OpDesc {
 uint8_t dirbit(const OpDesc &op) { return op.psi ? pfk::F_DIR_PSI : pfk::F_DIR_PHI; }
 
 template <typename T>
-pfk::ZArgs<T> zbase(pf_grid *g, const OpDesc &op, const T *dinv)
+pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const T *dinv, const ZCfg &c)
 {
-    const ZCfg &c = cfg_of<T>(g);
     pfk::ZArgs<T> a{};
     a.nx = g->nx; a.ny = g->ny; a.nz = g->nz; a.P = g->nx * g->ny;
     a.S = c.S; a.KZ = c.KZ; a.nstrips = c.nstrips; a.G = c.G; a.lmax = c.lmax;
@@ -308,8 +323,13 @@ pfk::ZArgs<T> zbase(pf_grid *g, const OpDesc &op, const T *dinv)
     a.dval = g->dval;
     a.sc = g->sc;
     a.partials = g->partials;
-    a.ticket = g->ticket;
     return a;
+}
+
+template <typename T>
+pfk::ZArgs<T> zbase(pf_grid *g, const OpDesc &op, const T *dinv)
+{
+    return zbase_cfg<T>(g, op, dinv, cfg_of<T>(g));
 }
 
 template <int OP, typename T>
@@ -318,6 +338,15 @@ pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a)
     const ZCfg &c = cfg_of<T>(g);
     hipError_t e = op.psi ? launch_z<OP, T, true>(c, a, g->stream) : launch_z<OP, T, false>(c, a, g->stream);
     if (e != hipSuccess) return fail(PF_ERR_DEVICE, "stencil kernel launch failed: %s", hipGetErrorString(e));
+    return PF_OK;
+}
+
+template <int KIND>
+pf_status finalize(pf_grid *g, int G)
+{
+    pfk::FinArgs f{g->sc, g->partials, G};
+    hipLaunchKernelGGL((pfk::k_finalize<KIND>), dim3(1), dim3(256), 0, g->stream, f);
+    HIPCHK(hipGetLastError());
     return PF_OK;
 }
 
@@ -361,7 +390,8 @@ pf_status residual64(pf_grid *g, const OpDesc &op, const double *dinv, const dou
         a.lift = 1;
         a.dval = nullptr;
     }
-    return zlaunch<pfk::OP_RESID, double>(g, op, a);
+    PFCHK((zlaunch<pfk::OP_RESID, double>(g, op, a)));
+    return finalize<pfk::FIN_SUM>(g, a.G);
 }
 
 pf_status read_scalars(pf_grid *g)
@@ -376,34 +406,67 @@ pf_status write_scalars(pf_grid *g)
     return PF_OK;
 }
 
-// One BiCGSTAB iteration: stencil step A (p, v), stencil step B (s, t),
-// pointwise step C (x, r).  parity selects the p/v ping-pong buffers.
+// Arguments of the three kernels of one BiCGSTAB iteration.  parity selects
+// the p/v ping-pong buffers.
 template <typename T>
-pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity,
-                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c)
 {
-    pfk::ZArgs<T> a = zbase<T>(g, op, dinv);
+    pfk::ZArgs<T> a = zbase_cfg<T>(g, op, dinv, c);
     a.x = w.r;
     a.y0 = w.p[parity];
     a.y1 = w.v[parity];
     a.rt = w.rt;
     a.out = w.v[parity ^ 1];
     a.out_aux = w.p[parity ^ 1];
-    if (e0) HIPCHK(hipEventRecord(e0, g->stream));
-    PFCHK((zlaunch<pfk::OP_BA, T>(g, op, a)));
-    if (e1) HIPCHK(hipEventRecord(e1, g->stream));
-    pfk::ZArgs<T> b = zbase<T>(g, op, dinv);
+    return a;
+}
+
+template <typename T>
+pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c)
+{
+    pfk::ZArgs<T> b = zbase_cfg<T>(g, op, dinv, c);
     b.x = w.r;
     b.y0 = w.v[parity ^ 1];
     b.out = w.t;
     b.out_aux = w.s;
-    PFCHK((zlaunch<pfk::OP_BB, T>(g, op, b)));
-    const int G = pw_blocks(g->N);
-    hipLaunchKernelGGL((pfk::k_bicg_c<T, NT>), dim3(G), dim3(NT), 0, g->stream, g->N, w.x, w.r,
-                       (const T *)w.p[parity ^ 1], (const T *)w.s, (const T *)w.t, dinv,
-                       (const T *)w.rt, g->sc, g->partials, g->ticket, G);
+    return b;
+}
+
+template <typename T>
+pfk::CArgs<T> args_c(pf_grid *g, const T *dinv, Work<T> &w, int parity)
+{
+    pfk::CArgs<T> c{};
+    c.N = g->N;
+    c.x = w.x;
+    c.r = w.r;
+    c.p = w.p[parity ^ 1];
+    c.s = w.s;
+    c.t = w.t;
+    c.dinv = dinv;
+    c.rt = w.rt;
+    c.sc = g->sc;
+    c.partials = g->partials;
+    c.G = pw_blocks(g->N);
+    return c;
+}
+
+// One BiCGSTAB iteration: stencil step A (p, v), stencil step B (s, t),
+// pointwise step C (x, r).
+template <typename T>
+pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+{
+    const ZCfg &cfg = cfg_of<T>(g);
+    if (e0) HIPCHK(hipEventRecord(e0, g->stream));
+    PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, dinv, w, parity, cfg))));
+    if (e1) HIPCHK(hipEventRecord(e1, g->stream));
+    PFCHK(finalize<pfk::FIN_A>(g, cfg.G));
+    PFCHK((zlaunch<pfk::OP_BB, T>(g, op, args_b<T>(g, op, dinv, w, parity, cfg))));
+    PFCHK(finalize<pfk::FIN_B>(g, cfg.G));
+    const pfk::CArgs<T> c = args_c<T>(g, dinv, w, parity);
+    hipLaunchKernelGGL((pfk::k_bicg_c<T, NT>), dim3(c.G), dim3(NT), 0, g->stream, c);
     HIPCHK(hipGetLastError());
-    return PF_OK;
+    return finalize<pfk::FIN_C>(g, c.G);
 }
 
 // Chunk of m iterations (m even) captured once per (precision, system) and
@@ -546,7 +609,7 @@ int chunk_len(const pf_grid *g, const pf_lin_opts *o)
 }
 
 // Reset the Krylov state from a residual already in w.r / w.rt with
-// ||r||^2 = rr.  Keeps the cumulative iteration count.
+// ||r||^2 = rr.  Keeps the cumulative iteration count.  Asynchronous.
 template <typename T>
 pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter, int maxit)
 {
@@ -606,101 +669,352 @@ pf_status check_opts(const pf_lin_opts *o)
     return PF_OK;
 }
 
-// The linear solve on grid-owned buffers: g->b64 holds b, g->w64.x the
-// initial guess; on return g->w64.x holds the solution.
-pf_status solve_internal(pf_grid *g, const OpDesc &op, const pf_lin_opts *o, pf_lin_info *info)
+// State of one linear solve on grid-owned buffers (g->b64 holds b, g->w64.x
+// the initial guess and, at the end, the solution).  The same steps drive a
+// single solve and every member of a batch:
+//   ls_init        dinv, Dirichlet values, ||b_lift|| (read back);
+//   ls_round_*     true FP64 residual (read back), then either finish or
+//                  start a Krylov run (FP64 restart, or FP32 correction);
+//   ls_after       account for the run (FP32: x += d).
+struct LinSolve {
+    pf_grid *g = nullptr;
+    OpDesc op;
+    const pf_lin_opts *o = nullptr;
+    bool mixed = false;
+    double *dinv64 = nullptr;
+    float *dinv32 = nullptr;
+    double bnorm = 0, tol2 = 0, rr = 0;
+    int iter = 0, restarts = 0, refinements = 0;
+    bool started = false, done = false;
+    pf_status result = PF_OK;
+};
+
+pf_status ls_init_launch(LinSolve &L)
 {
-    PFCHK(check_opts(o));
+    pf_grid *g = L.g;
+    PFCHK(check_opts(L.o));
     PFCHK(ensure_work<double>(g));
-    if (o->precision == PF_MIXED) PFCHK(ensure_work<float>(g));
-    const uint8_t db = dirbit(op);
-    Work<double> &w = g->w64;
-    double *dinv = op.psi ? g->dinv64_psi : g->dinv64;
-    PFCHK(compute_dinv<double>(g, op, dinv));
-    hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.x,
-                       (const uint8_t *)g->flags, db, op.psi ? nullptr : (const double *)g->dval);
-    HIPCHK(hipGetLastError());
-    // ||b_lift||
-    PFCHK(residual64(g, op, dinv, g->b64, nullptr, w.r, true, nullptr, nullptr, nullptr));
-    PFCHK(read_scalars(g));
-    const double bnorm = std::sqrt(g->hsc->red[0]);
-    pf_lin_info li{};
-    li.status = PF_OK;
-    if (!std::isfinite(bnorm)) {
-        li.status = PF_ERR_NONFINITE;
-        if (info) *info = li;
-        return fail(PF_ERR_NONFINITE, "right-hand side is not finite");
+    L.mixed = L.o->precision == PF_MIXED;
+    if (L.mixed) PFCHK(ensure_work<float>(g));
+    L.dinv64 = L.op.psi ? g->dinv64_psi : g->dinv64;
+    PFCHK(compute_dinv<double>(g, L.op, L.dinv64));
+    if (L.mixed) {
+        L.dinv32 = L.op.psi ? g->dinv32_psi : g->dinv32;
+        PFCHK(compute_dinv<float>(g, L.op, L.dinv32));
     }
-    if (bnorm == 0.0) {
-        // homogeneous problem: x = Dirichlet values, 0 on free rows
-        PFCHK(fill<double>(g, w.x, 0.0, g->N));
-        hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.x,
-                           (const uint8_t *)g->flags, db, op.psi ? nullptr : (const double *)g->dval);
-        HIPCHK(hipGetLastError());
-        if (info) *info = li;
+    hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
+                       (const uint8_t *)g->flags, dirbit(L.op), L.op.psi ? nullptr : (const double *)g->dval);
+    HIPCHK(hipGetLastError());
+    PFCHK(residual64(g, L.op, L.dinv64, g->b64, nullptr, g->w64.r, true, nullptr, nullptr, nullptr));
+    HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
+    return PF_OK;
+}
+
+// After the stream has synchronised.
+pf_status ls_init_decide(LinSolve &L)
+{
+    pf_grid *g = L.g;
+    L.bnorm = std::sqrt(g->hsc->red[0]);
+    if (!std::isfinite(L.bnorm)) {
+        L.done = true;
+        L.result = PF_ERR_NONFINITE;
         return PF_OK;
     }
-    const double tol2 = o->rel_tol * o->rel_tol * bnorm * bnorm;
-    const int m = chunk_len(g, o);
-    int iter = 0, restarts = 0, refinements = 0;
-    pf_status result = PF_OK;
-    double rr = 0;
-
-    if (o->precision == PF_FP64) {
-        bool started = false;
-        for (;;) {
-            // true residual; also the shadow residual of a (re)start
-            PFCHK(residual64(g, op, dinv, g->b64, w.x, w.r, false, w.rt, nullptr, nullptr));
-            PFCHK(read_scalars(g));
-            rr = g->hsc->red[0];
-            if (!std::isfinite(rr)) { result = PF_ERR_NONFINITE; break; }
-            if (rr <= tol2) break;
-            if (iter >= o->max_iter) { result = PF_ERR_NOCONV; break; }
-            if (started) ++restarts;
-            if (restarts > 1000) { result = PF_ERR_BREAKDOWN; break; }
-            started = true;
-            PFCHK(krylov_start<double>(g, w, rr, tol2, iter, o->max_iter));
-            int st = 0;
-            PFCHK(krylov_run<double>(g, op, dinv, w, m, &st));
-            iter = g->hsc->iter;
-            if (st == pfk::ST_NONFINITE) { result = PF_ERR_NONFINITE; break; }
-            // ST_CONV, ST_MAXIT and ST_RESTART all go back to the true residual
-        }
-    } else {
-        // Mixed precision: FP64 residual -> FP32 BiCGSTAB correction -> FP64 update.
-        Work<float> &v = g->w32;
-        float *dinv32 = op.psi ? g->dinv32_psi : g->dinv32;
-        PFCHK(compute_dinv<float>(g, op, dinv32));
-        const double itol2 = o->inner_tol * o->inner_tol;
-        for (;;) {
-            PFCHK(residual64(g, op, dinv, g->b64, w.x, w.r, false, nullptr, v.r, v.rt));
-            PFCHK(read_scalars(g));
-            rr = g->hsc->red[0];
-            if (!std::isfinite(rr)) { result = PF_ERR_NONFINITE; break; }
-            if (rr <= tol2) break;
-            if (refinements >= o->max_refine || iter >= o->max_iter) { result = PF_ERR_NOCONV; break; }
-            ++refinements;
-            PFCHK(fill<float>(g, v.x, 0.0f, g->N));
-            PFCHK(krylov_start<float>(g, v, rr, std::max(itol2 * rr, tol2), iter, o->max_iter));
-            int st = 0;
-            PFCHK(krylov_run<float>(g, op, dinv32, v, m, &st));
-            iter = g->hsc->iter;
-            if (st == pfk::ST_NONFINITE) { result = PF_ERR_NONFINITE; break; }
-            if (st == pfk::ST_RESTART) ++restarts;
-            hipLaunchKernelGGL(pfk::k_correct, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.x,
-                               (const float *)v.x, (const uint8_t *)g->flags, db);
-            HIPCHK(hipGetLastError());
-        }
+    if (L.bnorm == 0.0) {
+        // homogeneous problem: x = Dirichlet values, 0 on free rows
+        PFCHK(fill<double>(g, g->w64.x, 0.0, g->N));
+        hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
+                           (const uint8_t *)g->flags, dirbit(L.op), L.op.psi ? nullptr : (const double *)g->dval);
+        HIPCHK(hipGetLastError());
+        L.done = true;
+        return PF_OK;
     }
-    li.iters = iter;
-    li.refinements = refinements;
-    li.restarts = restarts;
-    li.rel_res = std::sqrt(rr) / bnorm;
-    li.status = result;
+    L.tol2 = L.o->rel_tol * L.o->rel_tol * L.bnorm * L.bnorm;
+    return PF_OK;
+}
+
+pf_status ls_round_launch(LinSolve &L)
+{
+    pf_grid *g = L.g;
+    if (L.mixed)
+        PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, nullptr, g->w32.r, g->w32.rt));
+    else
+        PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, g->w64.rt, nullptr, nullptr));
+    HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
+    return PF_OK;
+}
+
+// After the stream has synchronised: finish, or start a Krylov run (*run).
+pf_status ls_round_decide(LinSolve &L, bool *run)
+{
+    pf_grid *g = L.g;
+    *run = false;
+    L.rr = g->hsc->red[0];
+    if (!std::isfinite(L.rr)) { L.result = PF_ERR_NONFINITE; L.done = true; return PF_OK; }
+    if (L.rr <= L.tol2) { L.done = true; return PF_OK; }
+    if (!L.mixed) {
+        if (L.iter >= L.o->max_iter) { L.result = PF_ERR_NOCONV; L.done = true; return PF_OK; }
+        if (L.started) ++L.restarts;
+        if (L.restarts > 1000) { L.result = PF_ERR_BREAKDOWN; L.done = true; return PF_OK; }
+        L.started = true;
+        PFCHK(krylov_start<double>(g, g->w64, L.rr, L.tol2, L.iter, L.o->max_iter));
+    } else {
+        if (L.refinements >= L.o->max_refine || L.iter >= L.o->max_iter) {
+            L.result = PF_ERR_NOCONV;
+            L.done = true;
+            return PF_OK;
+        }
+        ++L.refinements;
+        PFCHK(fill<float>(g, g->w32.x, 0.0f, g->N));
+        const double itol2 = L.o->inner_tol * L.o->inner_tol;
+        PFCHK(krylov_start<float>(g, g->w32, L.rr, std::max(itol2 * L.rr, L.tol2), L.iter, L.o->max_iter));
+    }
+    *run = true;
+    return PF_OK;
+}
+
+// After a Krylov run that ended with device status st (g->hsc is current).
+pf_status ls_after(LinSolve &L, int st)
+{
+    pf_grid *g = L.g;
+    L.iter = g->hsc->iter;
+    if (st == pfk::ST_NONFINITE) { L.result = PF_ERR_NONFINITE; L.done = true; return PF_OK; }
+    if (L.mixed) {
+        if (st == pfk::ST_RESTART) ++L.restarts;
+        hipLaunchKernelGGL(pfk::k_correct, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
+                           (const float *)g->w32.x, (const uint8_t *)g->flags, dirbit(L.op));
+        HIPCHK(hipGetLastError());
+    }
+    // FP64: CONV, MAXIT and RESTART all return to the true residual
+    return PF_OK;
+}
+
+pf_status ls_finish(const LinSolve &L, pf_lin_info *info)
+{
+    pf_lin_info li{};
+    li.iters = L.iter;
+    li.refinements = L.refinements;
+    li.restarts = L.restarts;
+    li.rel_res = L.bnorm > 0 ? std::sqrt(L.rr) / L.bnorm : 0.0;
+    li.status = L.result;
     if (info) *info = li;
-    if (result == PF_ERR_NOCONV) return fail(result, "no convergence: rel_res %.3e after %d iterations", li.rel_res, iter);
-    if (result == PF_ERR_NONFINITE) return fail(result, "non-finite value in the iteration");
-    if (result == PF_ERR_BREAKDOWN) return fail(result, "repeated BiCGSTAB breakdown");
+    if (L.result == PF_ERR_NOCONV)
+        return fail(L.result, "no convergence: rel_res %.3e after %d iterations", li.rel_res, L.iter);
+    if (L.result == PF_ERR_NONFINITE) return fail(L.result, "non-finite value in the iteration");
+    if (L.result == PF_ERR_BREAKDOWN) return fail(L.result, "repeated BiCGSTAB breakdown");
+    return PF_OK;
+}
+
+pf_status solve_internal(pf_grid *g, const OpDesc &op, const pf_lin_opts *o, pf_lin_info *info)
+{
+    LinSolve L;
+    L.g = g;
+    L.op = op;
+    L.o = o;
+    PFCHK(ls_init_launch(L));
+    PFCHK(sync(g));
+    PFCHK(ls_init_decide(L));
+    const int m = chunk_len(g, o);
+    while (!L.done) {
+        PFCHK(ls_round_launch(L));
+        PFCHK(sync(g));
+        bool run = false;
+        PFCHK(ls_round_decide(L, &run));
+        if (!run) break;
+        int st = 0;
+        if (L.mixed) PFCHK(krylov_run<float>(g, op, L.dinv32, g->w32, m, &st));
+        else PFCHK(krylov_run<double>(g, op, L.dinv64, g->w64, m, &st));
+        PFCHK(ls_after(L, st));
+    }
+    return ls_finish(L, info);
+}
+
+// ------------------------------------------------------------------ batch
+
+// Device tables of a batched Krylov run: kernel arguments per system, block
+// offsets, scalar pointers and a gather buffer.  Grows on demand; one batch
+// runs at a time per process.
+struct BatchBuf {
+    void *dev = nullptr;
+    size_t bytes = 0;
+    Scalars *hsc = nullptr;
+    int hcap = 0;
+} g_batch;
+
+// Shape shared by every member of a batched launch (one kernel instance):
+// 512 threads, one node per thread, z-chunks sized per grid.
+ZCfg batch_cfg(const pf_grid *g, size_t elem)
+{
+    const int P = g->nx * g->ny;
+    const long strips = (P + 511) / 512;
+    const int kz = (int)std::max<long>(2, std::min<long>(16, strips * g->nz / 256));
+    return make_cfg(g->nx, g->ny, g->nz, elem, 512, 1, kz);
+}
+
+// Run the Krylov iterations of all listed systems (same precision, same
+// operator kind) together: one launch per kernel per iteration covers every
+// system, captured as a graph chunk and replayed until no system is RUN.
+template <typename T>
+pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int m, std::vector<int> &status)
+{
+    const int n = (int)act.size();
+    const bool psi = act[0]->op.psi;
+    std::vector<pfk::ZArgs<T>> za[2], zb[2];
+    std::vector<pfk::CArgs<T>> zc[2];
+    std::vector<int> zstart(n + 1, 0), cstart(n + 1, 0);
+    std::vector<const Scalars *> scp(n);
+    std::vector<pfk::FinArgs> fz(n), fc(n);
+    size_t lds = 0;
+    for (int par = 0; par < 2; ++par) { za[par].resize(n); zb[par].resize(n); zc[par].resize(n); }
+    for (int i = 0; i < n; ++i) {
+        LinSolve &L = *act[i];
+        pf_grid *g = L.g;
+        const ZCfg c = batch_cfg(g, sizeof(T));
+        Work<T> *w;
+        const T *dinv;
+        if constexpr (sizeof(T) == 8) { w = &g->w64; dinv = L.dinv64; }
+        else { w = &g->w32; dinv = L.dinv32; }
+        for (int par = 0; par < 2; ++par) {
+            za[par][i] = args_a<T>(g, L.op, dinv, *w, par, c);
+            zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, c);
+            zc[par][i] = args_c<T>(g, dinv, *w, par);
+        }
+        zstart[i + 1] = zstart[i] + c.G;
+        cstart[i + 1] = cstart[i] + zc[0][i].G;
+        fz[i] = pfk::FinArgs{g->sc, g->partials, c.G};
+        fc[i] = pfk::FinArgs{g->sc, g->partials, zc[0][i].G};
+        lds = std::max(lds, c.lds);
+        scp[i] = g->sc;
+    }
+    if (lds > LDS_MAX) return fail(PF_ERR_ARG, "batch member too wide for the LDS strip");
+    // device tables
+    const size_t szZ = sizeof(pfk::ZArgs<T>) * n, szC = sizeof(pfk::CArgs<T>) * n;
+    const size_t szI = sizeof(int) * (n + 1), szP = sizeof(void *) * n, szS = sizeof(Scalars) * n;
+    const size_t szF = sizeof(pfk::FinArgs) * n;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t need = 4 * al(szZ) + 2 * al(szC) + 2 * al(szI) + al(szP) + al(szS) + 2 * al(szF);
+    if (need > g_batch.bytes) {
+        if (g_batch.dev) (void)hipFree(g_batch.dev);
+        g_batch.dev = nullptr;
+        g_batch.bytes = 0;
+        if (hipMalloc(&g_batch.dev, need) != hipSuccess) return fail(PF_ERR_ALLOC, "batch table allocation failed");
+        g_batch.bytes = need;
+    }
+    if (n > g_batch.hcap) {
+        if (g_batch.hsc) (void)hipHostFree(g_batch.hsc);
+        g_batch.hsc = nullptr;
+        g_batch.hcap = 0;
+        if (hipHostMalloc((void **)&g_batch.hsc, szS, hipHostMallocDefault) != hipSuccess)
+            return fail(PF_ERR_ALLOC, "batch pinned allocation failed");
+        g_batch.hcap = n;
+    }
+    char *base = (char *)g_batch.dev;
+    size_t off = 0;
+    auto take = [&](size_t sz) { char *p = base + off; off += al(sz); return p; };
+    pfk::ZArgs<T> *dA[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
+    pfk::ZArgs<T> *dB[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
+    pfk::CArgs<T> *dC[2] = {(pfk::CArgs<T> *)take(szC), (pfk::CArgs<T> *)take(szC)};
+    int *dzs = (int *)take(szI), *dcs = (int *)take(szI);
+    const Scalars **dscp = (const Scalars **)take(szP);
+    Scalars *dgather = (Scalars *)take(szS);
+    pfk::FinArgs *dfz = (pfk::FinArgs *)take(szF), *dfc = (pfk::FinArgs *)take(szF);
+    for (int par = 0; par < 2; ++par) {
+        HIPCHK(hipMemcpyAsync(dA[par], za[par].data(), szZ, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(dB[par], zb[par].data(), szZ, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(dC[par], zc[par].data(), szC, hipMemcpyHostToDevice, stream));
+    }
+    HIPCHK(hipMemcpyAsync(dzs, zstart.data(), szI, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dcs, cstart.data(), szI, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dscp, scp.data(), szP, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dfz, fz.data(), szF, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dfc, fc.data(), szF, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+
+    const int GZ = zstart[n], GC = cstart[n];
+    auto launch_iter = [&](int par) -> pf_status {
+        ZCfg c{};
+        c.NTZ = 512; c.PPT = 1; c.G = GZ; c.lds = lds;
+        hipError_t e;
+        if (psi) e = launch_batch<pfk::OP_BA, T, true>(c, dA[par], dzs, n, stream);
+        else e = launch_batch<pfk::OP_BA, T, false>(c, dA[par], dzs, n, stream);
+        if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
+        hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_A>), dim3(n), dim3(256), 0, stream,
+                           (const pfk::FinArgs *)dfz);
+        if (psi) e = launch_batch<pfk::OP_BB, T, true>(c, dB[par], dzs, n, stream);
+        else e = launch_batch<pfk::OP_BB, T, false>(c, dB[par], dzs, n, stream);
+        if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
+        hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_B>), dim3(n), dim3(256), 0, stream,
+                           (const pfk::FinArgs *)dfz);
+        hipLaunchKernelGGL((pfk::k_bicg_c_batch<T, NT>), dim3(GC), dim3(NT), 0, stream,
+                           (const pfk::CArgs<T> *)dC[par], (const int *)dcs, n);
+        hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_C>), dim3(n), dim3(256), 0, stream,
+                           (const pfk::FinArgs *)dfc);
+        HIPCHK(hipGetLastError());
+        return PF_OK;
+    };
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+    pf_status st = PF_OK;
+    for (int i = 0; i < m && st == PF_OK; ++i) st = launch_iter(i & 1);
+    hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
+    hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (st != PF_OK) return st;
+    if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
+    status.assign(n, pfk::ST_RUN);
+    for (;;) {
+        e = hipGraphLaunch(exec, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(g_batch.hsc, dgather, szS, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            return fail(PF_ERR_DEVICE, "batched chunk failed: %s", hipGetErrorString(e));
+        }
+        bool any = false;
+        for (int i = 0; i < n; ++i) {
+            status[i] = g_batch.hsc[i].status;
+            any |= status[i] == pfk::ST_RUN;
+        }
+        if (!any) break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    for (int i = 0; i < n; ++i) *act[i]->g->hsc = g_batch.hsc[i];
+    return PF_OK;
+}
+
+// Solve several systems (same operator kind and options) as one batch.
+pf_status solve_batch(std::vector<LinSolve> &Ls)
+{
+    const int n = (int)Ls.size();
+    if (n == 0) return PF_OK;
+    for (auto &L : Ls) PFCHK(ls_init_launch(L));
+    for (auto &L : Ls) PFCHK(sync(L.g));
+    for (auto &L : Ls) PFCHK(ls_init_decide(L));
+    hipStream_t bs = Ls[0].g->stream;
+    int m = 16;
+    for (auto &L : Ls) m = std::max(m, chunk_len(L.g, L.o));
+    for (;;) {
+        for (auto &L : Ls)
+            if (!L.done) PFCHK(ls_round_launch(L));
+        for (auto &L : Ls) PFCHK(sync(L.g));
+        std::vector<LinSolve *> act;
+        for (auto &L : Ls) {
+            if (L.done) continue;
+            bool run = false;
+            PFCHK(ls_round_decide(L, &run));
+            if (run) act.push_back(&L);
+        }
+        if (act.empty()) break;
+        for (LinSolve *L : act) PFCHK(sync(L->g));   // Krylov starts written
+        std::vector<int> st;
+        if (act[0]->mixed) PFCHK(batch_krylov_run<float>(act, bs, m, st));
+        else PFCHK(batch_krylov_run<double>(act, bs, m, st));
+        for (size_t i = 0; i < act.size(); ++i) PFCHK(ls_after(*act[i], st[i]));
+    }
+    for (auto &L : Ls) PFCHK(sync(L.g));
     return PF_OK;
 }
 
@@ -811,14 +1125,12 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     if ((st = dalloc(g, &g->dval, N)) != PF_OK) return cleanup(st);
     if ((st = dalloc(g, &g->sc, 1)) != PF_OK) return cleanup(st);
     if ((st = dalloc(g, &g->partials, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
-    if ((st = dalloc(g, &g->ticket, 1)) != PF_OK) return cleanup(st);
     if (hipHostMalloc((void **)&g->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(PF_ERR_ALLOC, "pinned host allocation failed"));
     if (d->fixed_charge && (st = dalloc(g, &g->q, N)) != PF_OK) return cleanup(st);
     unsigned *bad = nullptr;
     if ((st = dalloc(g, &bad, 1)) != PF_OK) return cleanup(st);
     if (hipMemsetAsync(bad, 0, sizeof(unsigned), g->stream) != hipSuccess ||
-        hipMemsetAsync(g->ticket, 0, sizeof(unsigned), g->stream) != hipSuccess ||
         hipMemsetAsync(g->sc, 0, sizeof(Scalars), g->stream) != hipSuccess)
         return cleanup(fail(PF_ERR_DEVICE, "hipMemsetAsync failed"));
     hipLaunchKernelGGL(pfk::k_validate, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, N, d->eps, d->node_type,
@@ -1020,20 +1332,6 @@ pf_status ensure_nl(pf_grid *g)
     return PF_OK;
 }
 
-// Linear solve on grid buffers: b in src_b, initial guess / result in xio.
-pf_status nl_solve(pf_grid *g, const OpDesc &op, const double *src_b, double *xio, const pf_lin_opts *o,
-                   int *iters)
-{
-    HIPCHK(hipMemcpyAsync(g->b64, src_b, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
-    HIPCHK(hipMemcpyAsync(g->w64.x, xio, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
-    pf_lin_info li{};
-    pf_status st = solve_internal(g, op, o, &li);
-    *iters += li.iters;
-    if (st != PF_OK) return st;
-    HIPCHK(hipMemcpyAsync(xio, g->w64.x, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
-    return PF_OK;
-}
-
 }  // namespace
 
 pf_status pf_fermi(pf_grid *g, const pf_pf_params *p, const double *phi, double *rho_hat, double *sigma,
@@ -1050,124 +1348,317 @@ pf_status pf_fermi(pf_grid *g, const pf_pf_params *p, const double *phi, double 
     return sync(g);
 }
 
+}  // extern "C"
+
+namespace {
+
+// One nonlinear problem of a (possibly batched) Table 2 / Table 4 run.
+struct NlSys {
+    pf_grid *g = nullptr;
+    const pf_pf_params *p = nullptr;
+    pfk::SpeciesDev sp{};
+    double *phi_out = nullptr, *conc = nullptr, *steric = nullptr;
+    int it = 0, lin_iters = 0;
+    double delta = INFINITY;
+    pf_status st = PF_OK;
+    bool done = false;
+    std::chrono::steady_clock::time_point t0;
+};
+
+// Linear solves of one phase of the outer loop: system i solves ops[i] with
+// right-hand side bs[i] and initial guess / result xs[i] (grid buffers).
+// Batched phases run every member's Krylov iterations in shared launches.
+pf_status nl_linear_phase(std::vector<NlSys *> &sys, const std::vector<OpDesc> &ops,
+                          const std::vector<const double *> &bs, const std::vector<double *> &xs, bool batched)
+{
+    const size_t n = sys.size();
+    for (size_t i = 0; i < n; ++i) {
+        pf_grid *g = sys[i]->g;
+        HIPCHK(hipMemcpyAsync(g->b64, bs[i], g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+        HIPCHK(hipMemcpyAsync(g->w64.x, xs[i], g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    }
+    bool same_prec = true;
+    for (size_t i = 1; i < n; ++i) same_prec &= sys[i]->p->lin.precision == sys[0]->p->lin.precision;
+    std::vector<pf_lin_info> li(n);
+    std::vector<pf_status> st(n, PF_OK);
+    if (batched && n > 1 && same_prec) {
+        std::vector<LinSolve> Ls(n);
+        for (size_t i = 0; i < n; ++i) {
+            Ls[i].g = sys[i]->g;
+            Ls[i].op = ops[i];
+            Ls[i].o = &sys[i]->p->lin;
+        }
+        PFCHK(solve_batch(Ls));
+        for (size_t i = 0; i < n; ++i) st[i] = ls_finish(Ls[i], &li[i]);
+    } else {
+        for (size_t i = 0; i < n; ++i) {
+            st[i] = solve_internal(sys[i]->g, ops[i], &sys[i]->p->lin, &li[i]);
+            if (st[i] == PF_ERR_DEVICE || st[i] == PF_ERR_ALLOC || st[i] == PF_ERR_ARG) return st[i];
+        }
+    }
+    for (size_t i = 0; i < n; ++i) {
+        pf_grid *g = sys[i]->g;
+        sys[i]->lin_iters += li[i].iters;
+        if (st[i] != PF_OK) {
+            sys[i]->st = st[i];
+            sys[i]->done = true;
+            continue;
+        }
+        HIPCHK(hipMemcpyAsync(xs[i], g->w64.x, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    }
+    return PF_OK;
+}
+
+// Table 2 (sequential algorithm) with the device-resident steps of Table 4:
+//   step 2   PF2 with rho' = Psi = 0 (fixed charges only), unless warm-started;
+//   step 3   Fermi update at Phi_0 (Eq. (1)) and PF1 (Eq. (12), (14));
+//   step 4   PF2 (Eq. (13)) warm-started from Phi_0;
+//   step 5   Phi := omega Phi_0 + (1 - omega) Phi, stop on the max norm.
+pf_status nl_drive(std::vector<NlSys> &S, bool batched)
+{
+    for (auto &s : S) {
+        pf_grid *g = s.g;
+        PFCHK(begin(g));
+        PFCHK(ensure_work<double>(g));
+        PFCHK(ensure_nl(g));
+        const int B = pw_blocks(g->N);
+        const double h3 = g->h * g->h * g->h;
+        hipLaunchKernelGGL(pfk::k_source, dim3(B), dim3(NT), 0, g->stream, g->N, (const double *)g->q,
+                           s.sp.lam / h3, g->src);
+        HIPCHK(hipGetLastError());
+        if (!s.p->warm_start) {
+            PFCHK(fill<double>(g, g->phi0, 0.0, g->N));
+        } else {
+            HIPCHK(hipMemcpyAsync(g->phi0, s.phi_out, g->N * sizeof(double), hipMemcpyDefault, g->stream));
+            hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(B), dim3(NT), 0, g->stream, g->N, g->phi0,
+                               (const uint8_t *)g->flags, (uint8_t)pfk::F_DIR_PHI, (const double *)g->dval);
+            HIPCHK(hipGetLastError());
+        }
+        PFCHK(fill<double>(g, g->psi, 0.0, g->N));
+    }
+    {   // step 2
+        std::vector<NlSys *> cold;
+        std::vector<OpDesc> ops;
+        std::vector<const double *> bs;
+        std::vector<double *> xs;
+        for (auto &s : S) {
+            if (s.p->warm_start) continue;
+            cold.push_back(&s);
+            ops.push_back(OpDesc{});
+            bs.push_back(s.g->src);
+            xs.push_back(s.g->phi0);
+        }
+        if (!cold.empty()) PFCHK(nl_linear_phase(cold, ops, bs, xs, batched));
+    }
+    for (;;) {
+        std::vector<NlSys *> act;
+        for (auto &s : S)
+            if (!s.done && s.it < s.p->max_outer) act.push_back(&s);
+        if (act.empty()) break;
+        // Fermi update at Phi_0: rhs1 = -rho_hat, sig = -rho_hat'  (Eq. (1), (11))
+        for (NlSys *s : act) {
+            pf_grid *g = s->g;
+            ++s->it;
+            hipLaunchKernelGGL(pfk::k_fermi, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
+                               (const double *)g->phi0, (const uint8_t *)g->flags, s->sp, g->rhs1, (double *)nullptr,
+                               g->sig, (double *)nullptr, (double *)nullptr);
+            HIPCHK(hipGetLastError());
+        }
+        // PF1
+        {
+            std::vector<NlSys *> pf1;
+            std::vector<OpDesc> ops;
+            std::vector<const double *> bs;
+            std::vector<double *> xs;
+            for (NlSys *s : act) {
+                pf_grid *g = s->g;
+                if (s->p->lc > 0) {
+                    OpDesc op;
+                    op.psi = true;
+                    op.ceps = s->p->eps_s * s->p->lc * s->p->lc;
+                    op.sig_const = s->p->eps_s;
+                    pf1.push_back(s);
+                    ops.push_back(op);
+                    bs.push_back(g->rhs1);
+                    xs.push_back(g->psi);
+                } else {
+                    hipLaunchKernelGGL(pfk::k_psi_local, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
+                                       (const double *)g->rhs1, (const uint8_t *)g->flags, 1.0 / s->p->eps_s, g->psi);
+                    HIPCHK(hipGetLastError());
+                }
+            }
+            if (!pf1.empty()) PFCHK(nl_linear_phase(pf1, ops, bs, xs, batched));
+        }
+        // PF2
+        {
+            std::vector<NlSys *> pf2;
+            std::vector<OpDesc> ops;
+            std::vector<const double *> bs;
+            std::vector<double *> xs;
+            for (NlSys *s : act) {
+                if (s->done) continue;
+                pf_grid *g = s->g;
+                hipLaunchKernelGGL(pfk::k_rhs_pf2, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
+                                   (const double *)g->psi, (const double *)g->sig, (const double *)g->phi0,
+                                   (const double *)g->src, s->p->eps_s, g->rhs2);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipMemcpyAsync(g->phi, g->phi0, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+                OpDesc op;
+                op.sigma = g->sig;
+                pf2.push_back(s);
+                ops.push_back(op);
+                bs.push_back(g->rhs2);
+                xs.push_back(g->phi);
+            }
+            if (!pf2.empty()) PFCHK(nl_linear_phase(pf2, ops, bs, xs, batched));
+        }
+        // relaxation and max-norm test (Table 2 step 5)
+        for (NlSys *s : act) {
+            if (s->done) continue;
+            pf_grid *g = s->g;
+            const int B = pw_blocks(g->N);
+            hipLaunchKernelGGL((pfk::k_relax<NT>), dim3(B), dim3(NT), 0, g->stream, g->N, g->phi0, g->phi,
+                               s->p->omega, g->partials);
+            HIPCHK(hipGetLastError());
+            PFCHK(finalize<pfk::FIN_MAX>(g, B));
+            HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
+        }
+        for (NlSys *s : act) {
+            if (s->done) continue;
+            PFCHK(sync(s->g));
+            s->delta = s->g->hsc->red[0];
+            if (!std::isfinite(s->delta)) { s->st = PF_ERR_NONFINITE; s->done = true; }
+            else if (s->delta <= s->p->outer_tol) s->done = true;
+        }
+    }
+    for (auto &s : S) {
+        pf_grid *g = s.g;
+        if (s.st == PF_OK && !(s.delta <= s.p->outer_tol)) s.st = PF_ERR_NOCONV;
+        HIPCHK(hipMemcpyAsync(s.phi_out, g->phi0, g->N * sizeof(double), hipMemcpyDefault, g->stream));
+        if (s.conc || s.steric) {
+            hipLaunchKernelGGL(pfk::k_fermi, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
+                               (const double *)g->phi0, (const uint8_t *)g->flags, s.sp, (double *)nullptr,
+                               (double *)nullptr, (double *)nullptr, s.conc, s.steric);
+            HIPCHK(hipGetLastError());
+        }
+    }
+    for (auto &s : S) PFCHK(sync(s.g));
+    return PF_OK;
+}
+
+void nl_info(const NlSys &s, pf_nl_info *info)
+{
+    if (!info) return;
+    info->outer_iters = s.it;
+    info->total_lin_iters = s.lin_iters;
+    info->last_delta = s.delta;
+    info->seconds = secs_since(s.t0);
+    info->status = s.st;
+}
+
+pf_status nl_status_message(const NlSys &s)
+{
+    if (s.st == PF_ERR_NOCONV)
+        return fail(s.st, "outer loop: delta %.3e after %d iterations", s.delta, s.it);
+    if (s.st == PF_ERR_NONFINITE) return fail(s.st, "non-finite value in the outer loop");
+    return s.st;
+}
+
+}  // namespace
+
+extern "C" {
+
 pf_status pf_nonlinear_solve(pf_grid *g, const pf_pf_params *p, double *phi, double *conc, double *steric,
                              pf_nl_info *info)
 {
-    auto t0 = std::chrono::steady_clock::now();
+    g_err.clear();
     PFCHK(check_grid(g));
     if (!phi) return fail(PF_ERR_ARG, "phi is required");
     PFCHK(check_pf(p));
-    pfk::SpeciesDev sp;
-    PFCHK(species_dev(p, &sp));
-    PFCHK(begin(g));
-    PFCHK(ensure_work<double>(g));
-    PFCHK(ensure_nl(g));
-    const size_t N = g->N;
-    const int B = pw_blocks(N);
-    const double h3 = g->h * g->h * g->h;
-    pf_nl_info ni{};
-    int lin_iters = 0;
-    pf_status st = PF_OK;
-
-    hipLaunchKernelGGL(pfk::k_source, dim3(B), dim3(NT), 0, g->stream, N, (const double *)g->q, sp.lam / h3, g->src);
-    HIPCHK(hipGetLastError());
-
-    OpDesc phi_op;                      // potential system, sigma set per iteration
-    OpDesc psi_op;                      // PF1: eps_s (1 - lc^2 Lap)
-    psi_op.psi = true;
-    psi_op.ceps = p->eps_s * p->lc * p->lc;
-    psi_op.sig_const = p->eps_s;
-
-    if (!p->warm_start) {
-        // Table 2 step 2: PF2 with rho' = Psi = 0 (fixed charges only)
-        PFCHK(fill<double>(g, g->phi0, 0.0, N));
-        st = nl_solve(g, phi_op, g->src, g->phi0, &p->lin, &lin_iters);
-    } else {
-        HIPCHK(hipMemcpyAsync(g->phi0, phi, N * sizeof(double), hipMemcpyDefault, g->stream));
-        hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(B), dim3(NT), 0, g->stream, N, g->phi0,
-                           (const uint8_t *)g->flags, (uint8_t)pfk::F_DIR_PHI, (const double *)g->dval);
-        HIPCHK(hipGetLastError());
-    }
-    PFCHK(fill<double>(g, g->psi, 0.0, N));
-    double delta = INFINITY;
-    int it = 0;
-    while (st == PF_OK && it < p->max_outer) {
-        ++it;
-        // Fermi update at Phi_0: rhs1 = -rho_hat, sig = -rho_hat'  (Eq. (1), (11))
-        hipLaunchKernelGGL(pfk::k_fermi, dim3(B), dim3(NT), 0, g->stream, N, (const double *)g->phi0,
-                           (const uint8_t *)g->flags, sp, g->rhs1, (double *)nullptr, g->sig,
-                           (double *)nullptr, (double *)nullptr);
-        HIPCHK(hipGetLastError());
-        // PF1 (Eq. (12), (14))
-        if (p->lc > 0) {
-            st = nl_solve(g, psi_op, g->rhs1, g->psi, &p->lin, &lin_iters);
-            if (st != PF_OK) break;
-        } else {
-            hipLaunchKernelGGL(pfk::k_psi_local, dim3(B), dim3(NT), 0, g->stream, N, (const double *)g->rhs1,
-                               (const uint8_t *)g->flags, 1.0 / p->eps_s, g->psi);
-            HIPCHK(hipGetLastError());
-        }
-        // PF2 (Eq. (13)), warm-started from Phi_0
-        hipLaunchKernelGGL(pfk::k_rhs_pf2, dim3(B), dim3(NT), 0, g->stream, N, (const double *)g->psi,
-                           (const double *)g->sig, (const double *)g->phi0, (const double *)g->src, p->eps_s,
-                           g->rhs2);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(g->phi, g->phi0, N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
-        phi_op.sigma = g->sig;
-        st = nl_solve(g, phi_op, g->rhs2, g->phi, &p->lin, &lin_iters);
-        if (st != PF_OK) break;
-        // relaxation and max-norm test (Table 2 step 5)
-        hipLaunchKernelGGL((pfk::k_relax<NT>), dim3(B), dim3(NT), 0, g->stream, N, g->phi0, g->phi, p->omega,
-                           g->sc, g->partials, g->ticket, B);
-        HIPCHK(hipGetLastError());
-        PFCHK(read_scalars(g));
-        delta = g->hsc->red[0];
-        if (!std::isfinite(delta)) { st = PF_ERR_NONFINITE; break; }
-        if (delta <= p->outer_tol) break;
-    }
-    if (st == PF_OK && !(delta <= p->outer_tol)) st = PF_ERR_NOCONV;
-    HIPCHK(hipMemcpyAsync(phi, g->phi0, N * sizeof(double), hipMemcpyDefault, g->stream));
-    if (conc || steric) {
-        hipLaunchKernelGGL(pfk::k_fermi, dim3(B), dim3(NT), 0, g->stream, N, (const double *)g->phi0,
-                           (const uint8_t *)g->flags, sp, (double *)nullptr, (double *)nullptr,
-                           (double *)nullptr, conc, steric);
-        HIPCHK(hipGetLastError());
-    }
-    PFCHK(sync(g));
-    ni.outer_iters = it;
-    ni.total_lin_iters = lin_iters;
-    ni.last_delta = delta;
-    ni.seconds = secs_since(t0);
-    ni.status = st;
-    if (info) *info = ni;
-    if (st == PF_ERR_NOCONV && g_err.empty()) return fail(st, "outer loop: delta %.3e after %d iterations", delta, it);
-    return st;
+    std::vector<NlSys> S(1);
+    S[0].t0 = std::chrono::steady_clock::now();
+    S[0].g = g;
+    S[0].p = p;
+    S[0].phi_out = phi;
+    S[0].conc = conc;
+    S[0].steric = steric;
+    PFCHK(species_dev(p, &S[0].sp));
+    PFCHK(nl_drive(S, false));
+    nl_info(S[0], info);
+    return nl_status_message(S[0]);
 }
 
 pf_status pf_linear_solve_batch(int32_t n, pf_grid *const *g, const double *const *sigma,
                                 const double *const *b, double *const *x, const pf_lin_opts *opts,
                                 pf_lin_info *info)
 {
+    auto t0 = std::chrono::steady_clock::now();
+    g_err.clear();
     if (n < 0 || (n > 0 && (!g || !b || !x))) return fail(PF_ERR_ARG, "bad batch arguments");
-    pf_status worst = PF_OK;
+    pf_lin_opts o;
+    if (opts) o = *opts; else pf_lin_opts_default(&o);
+    PFCHK(check_opts(&o));
     for (int i = 0; i < n; ++i) {
-        pf_status st = pf_linear_solve(g[i], sigma ? sigma[i] : nullptr, b[i], x[i], opts, info ? &info[i] : nullptr);
-        if (st != PF_OK && worst == PF_OK) worst = st;
-        if (st == PF_ERR_ARG || st == PF_ERR_DEVICE || st == PF_ERR_ALLOC) return st;
+        if (!g[i] || !b[i] || !x[i]) return fail(PF_ERR_ARG, "batch member %d: null grid, b or x", i);
+        for (int j = 0; j < i; ++j)
+            if (g[j] == g[i]) return fail(PF_ERR_ARG, "batch members %d and %d share a grid", j, i);
     }
+    std::vector<LinSolve> Ls(n);
+    for (int i = 0; i < n; ++i) {
+        PFCHK(begin(g[i]));
+        PFCHK(ensure_work<double>(g[i]));
+        HIPCHK(hipMemcpyAsync(g[i]->b64, b[i], g[i]->N * sizeof(double), hipMemcpyDefault, g[i]->stream));
+        HIPCHK(hipMemcpyAsync(g[i]->w64.x, x[i], g[i]->N * sizeof(double), hipMemcpyDefault, g[i]->stream));
+        Ls[i].g = g[i];
+        Ls[i].op.sigma = sigma ? sigma[i] : nullptr;
+        Ls[i].o = &o;
+    }
+    PFCHK(solve_batch(Ls));
+    pf_status worst = PF_OK;
+    std::string first_err;
+    for (int i = 0; i < n; ++i) {
+        pf_lin_info li{};
+        pf_status st = ls_finish(Ls[i], &li);
+        if (st != PF_OK && worst == PF_OK) { worst = st; first_err = g_err; }
+        if (st == PF_OK || st == PF_ERR_NOCONV)
+            HIPCHK(hipMemcpyAsync(x[i], g[i]->w64.x, g[i]->N * sizeof(double), hipMemcpyDefault, g[i]->stream));
+        li.status = st;
+        if (info) info[i] = li;
+    }
+    for (int i = 0; i < n; ++i) PFCHK(sync(g[i]));
+    const double secs = secs_since(t0);
+    if (info)
+        for (int i = 0; i < n; ++i) info[i].seconds = secs;
+    g_err = first_err;
     return worst;
 }
 
 pf_status pf_nonlinear_solve_batch(int32_t n, pf_grid *const *g, const pf_pf_params *const *p,
                                    double *const *phi, pf_nl_info *info)
 {
+    g_err.clear();
     if (n < 0 || (n > 0 && (!g || !p || !phi))) return fail(PF_ERR_ARG, "bad batch arguments");
-    pf_status worst = PF_OK;
+    std::vector<NlSys> S(n);
     for (int i = 0; i < n; ++i) {
-        pf_status st = pf_nonlinear_solve(g[i], p[i], phi[i], nullptr, nullptr, info ? &info[i] : nullptr);
-        if (st != PF_OK && worst == PF_OK) worst = st;
-        if (st == PF_ERR_ARG || st == PF_ERR_DEVICE || st == PF_ERR_ALLOC) return st;
+        if (!g[i] || !phi[i]) return fail(PF_ERR_ARG, "batch member %d: null grid or phi", i);
+        for (int j = 0; j < i; ++j)
+            if (g[j] == g[i]) return fail(PF_ERR_ARG, "batch members %d and %d share a grid", j, i);
+        PFCHK(check_pf(p[i]));
+        S[i].t0 = std::chrono::steady_clock::now();
+        S[i].g = g[i];
+        S[i].p = p[i];
+        S[i].phi_out = phi[i];
+        PFCHK(species_dev(p[i], &S[i].sp));
     }
+    PFCHK(nl_drive(S, true));
+    pf_status worst = PF_OK;
+    std::string first_err;
+    for (int i = 0; i < n; ++i) {
+        nl_info(S[i], info ? &info[i] : nullptr);
+        pf_status st = nl_status_message(S[i]);
+        if (st != PF_OK && worst == PF_OK) { worst = st; first_err = g_err; }
+    }
+    g_err = first_err;
     return worst;
 }
 

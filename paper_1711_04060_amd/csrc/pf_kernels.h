@@ -22,10 +22,13 @@
 // fuse into one pass.
 //
 // Reductions: each workgroup reduces its products in FP64 (wave shuffles,
-// then LDS), writes one partial per quantity, and the last workgroup to take
-// a ticket sums the partials in a fixed order and updates the BiCGSTAB
-// scalars on the device: deterministic, no floating-point atomics, no host
-// round trip inside an iteration.
+// then LDS) and stores one partial per quantity.  A one-workgroup finalize
+// kernel launched right after sums the partials in a fixed order and updates
+// the BiCGSTAB scalars on the device: deterministic, no floating-point
+// atomics, no host round trip inside an iteration.  (Taking a completion
+// ticket inside the producer instead would need an agent-scope release per
+// workgroup, which writes back the XCD's L2 each time; the kernel boundary
+// provides that visibility once.)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -78,7 +81,6 @@ struct ZArgs {
     // reduction and scalars
     Scalars *sc;
     double *partials;           // [G][4]
-    unsigned *ticket;
 };
 
 // ------------------------------------------------------------- helpers
@@ -154,25 +156,17 @@ __device__ __forceinline__ void block_reduce(double (&v)[NQ])
     }
 }
 
-// Store the workgroup partials and take a ticket; returns true in every
-// thread of the last workgroup, which then sees all partials.
+// Store the workgroup partials (thread 0 holds the reduced values).
 template <int NQ>
-__device__ __forceinline__ bool publish_partials(const double (&v)[NQ], double *partials,
-                                                 unsigned *ticket, int G)
+__device__ __forceinline__ void store_partials(const double (&v)[NQ], double *partials, int slot)
 {
-    __shared__ int is_last;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) partials[blockIdx.x * 4 + q] = v[q];
-        unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (t == (unsigned)(G - 1));
+        for (int q = 0; q < NQ; ++q) partials[slot * 4 + q] = v[q];
     }
-    __syncthreads();
-    if (is_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return is_last;
 }
 
-// Fixed-order sum (or max) of the G partials, run by the last workgroup.
+// Fixed-order sum (or max) of the G partials, run by a finalize workgroup.
 template <int NQ, int NT, bool MAX = false>
 __device__ __forceinline__ void final_reduce(double (&v)[NQ], const double *partials, int G)
 {
@@ -265,8 +259,10 @@ __device__ __forceinline__ void stage_node(const ZArgs<T> &a, size_t g, T &val, 
     if constexpr (!CEPS) e = w.e;
 }
 
+// One workgroup's tile: logical tile index lb (strip, z-chunk) and partial
+// slot `slot` of the system described by a.
 template <int OP, typename T, bool CEPS, int NT, int PPT>
-__global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
+__device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, const int slot)
 {
     // halo nodes per thread kept in registers; more than HMAX*NT halo nodes
     // (nx > HMAX*NT/2) are handled by a slower loop
@@ -286,7 +282,6 @@ __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
     T *lval1 = leps0 + a.lmax;
     T *leps1 = lval1 + a.lmax;
 
-    const int lb = xcd_remap(blockIdx.x, a.G);
     const int strip = lb % a.nstrips, zc = lb / a.nstrips;
     const int nx = a.nx, ny = a.ny, nz = a.nz, P = a.P;
     const int m0 = strip * a.S;
@@ -516,54 +511,71 @@ __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
 
     if constexpr (OP == OP_RESID || OP == OP_BA || OP == OP_BB) {
         block_reduce<NQ, NT>(acc);
-        if (publish_partials<NQ>(acc, a.partials, a.ticket, a.G)) {
-            double tot[NQ];
-            final_reduce<NQ, NT>(tot, a.partials, a.G);
-            if (threadIdx.x == 0) {
-                Scalars *sc = a.sc;
-                *a.ticket = 0u;
-                for (int q = 0; q < NQ; ++q) sc->red[q] = tot[q];
-                if constexpr (OP == OP_BA) {
-                    const double rtv = tot[0];
-                    if (!finite(rtv)) sc->status = ST_NONFINITE;
-                    else if (rtv == 0.0) sc->status = ST_RESTART;
-                    else sc->alpha = sc->rho / rtv;          // Table 3 step 12
-                } else if constexpr (OP == OP_BB) {
-                    const double ts = tot[0], tt = tot[1], ss = tot[2];
-                    if (!finite(ts) || !finite(tt) || !finite(ss)) {
-                        sc->status = ST_NONFINITE;
-                    } else if (ss <= sc->tol2) {
-                        // half-step convergence: x += alpha p_hat only
-                        sc->omega = 0.0;
-                        sc->status = ST_HALF;
-                    } else if (tt == 0.0) {
-                        sc->status = ST_RESTART;
-                    } else {
-                        sc->omega = ts / tt;                  // Table 3 step 15
-                    }
-                }
-            }
-        }
+        store_partials<NQ>(acc, a.partials, slot);
     }
+}
+
+template <int OP, typename T, bool CEPS, int NT, int PPT>
+__global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
+{
+    zmarch_tile<OP, T, CEPS, NT, PPT>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
+}
+
+// System owning global block b: start[s] <= b < start[s+1].
+__device__ __forceinline__ int batch_system(const int *start, int nsys, int b)
+{
+    int lo = 0, hi = nsys;   // invariant: start[lo] <= b < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Batched form: one launch covers the tiles of nsys systems (grids of any
+// size); each system keeps its own scalars, partials and status.
+template <int OP, typename T, bool CEPS, int NT, int PPT>
+__global__ __launch_bounds__(NT) void k_zmarch_batch(const ZArgs<T> *__restrict__ args,
+                                                     const int *__restrict__ start, int nsys)
+{
+    const int s = batch_system(start, nsys, blockIdx.x);
+    const int lb = blockIdx.x - start[s];
+    const ZArgs<T> a = args[s];   // private copy: stores cannot alias it
+    zmarch_tile<OP, T, CEPS, NT, PPT>(a, lb, lb);
 }
 
 // ------------------------------------- BiCGSTAB step C (pointwise, fused)
 
 // x += alpha M^-1 p + omega M^-1 s (step 16); r = s - omega t (step 17);
 // then shadow . r and r . r for the next beta (step 8) and the stop test.
+template <typename T>
+struct CArgs {
+    size_t N;
+    T *x, *r;
+    const T *p, *s, *t, *dinv, *rt;
+    Scalars *sc;
+    double *partials;
+    int G;
+};
+
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_bicg_c(size_t N, T *__restrict__ x, T *__restrict__ r,
-                                               const T *__restrict__ p, const T *__restrict__ s,
-                                               const T *__restrict__ t, const T *__restrict__ dinv,
-                                               const T *__restrict__ rt, Scalars *sc,
-                                               double *partials, unsigned *ticket, int G)
+__device__ __forceinline__ void bicg_c_block(const CArgs<T> &a, const int b)
 {
+    Scalars *sc = a.sc;
     const int st = sc->status;
     if (st != ST_RUN && st != ST_HALF) return;
     const T alpha = (T)sc->alpha, omega = (T)sc->omega;
     double acc[2] = {0.0, 0.0};
-    const size_t stride = (size_t)gridDim.x * NT;
-    for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < N; i += stride) {
+    const size_t N = a.N;
+    T *__restrict__ x = a.x;
+    T *__restrict__ r = a.r;
+    const T *__restrict__ p = a.p;
+    const T *__restrict__ s = a.s;
+    const T *__restrict__ t = a.t;
+    const T *__restrict__ dinv = a.dinv;
+    const T *__restrict__ rt = a.rt;
+    const size_t stride = (size_t)a.G * NT;
+    for (size_t i = (size_t)b * NT + threadIdx.x; i < N; i += stride) {
         const T d = absT(dinv[i]);
         const T si = s[i], ti = t[i];
         x[i] = x[i] + alpha * (d * p[i]) + omega * (d * si);
@@ -573,32 +585,109 @@ __global__ __launch_bounds__(NT) void k_bicg_c(size_t N, T *__restrict__ x, T *_
         acc[1] += (double)ri * (double)ri;
     }
     block_reduce<2, NT>(acc);
-    if (publish_partials<2>(acc, partials, ticket, G)) {
-        double tot[2];
-        final_reduce<2, NT>(tot, partials, G);
-        if (threadIdx.x == 0) {
-            *ticket = 0u;
-            const double rho_new = tot[0], rr = tot[1];
-            sc->red[0] = rho_new;
-            sc->red[1] = rr;
-            sc->rr = rr;
-            sc->iter += 1;
-            const int was = sc->status;
-            if (!finite(rho_new) || !finite(rr)) {
-                sc->status = ST_NONFINITE;
-            } else if (was == ST_HALF || rr <= sc->tol2) {
-                sc->status = ST_CONV;
-            } else if (sc->iter >= sc->maxit) {
-                sc->status = ST_MAXIT;
-            } else if (sc->omega == 0.0 || fabs(rho_new) < 1e-300 ||
-                       rho_new * rho_new < 1e-28 * sc->rt2 * rr) {
-                sc->status = ST_RESTART;   // shadow residual nearly orthogonal to r
-            } else {
-                sc->beta = (rho_new / sc->rho) * (sc->alpha / sc->omega);   // step 8
-                sc->rho = rho_new;
-            }
+    store_partials<2>(acc, a.partials, b);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_bicg_c(CArgs<T> a)
+{
+    bicg_c_block<T, NT>(a, blockIdx.x);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_bicg_c_batch(const CArgs<T> *__restrict__ args,
+                                                     const int *__restrict__ start, int nsys)
+{
+    const int s = batch_system(start, nsys, blockIdx.x);
+    const CArgs<T> a = args[s];
+    bicg_c_block<T, NT>(a, blockIdx.x - start[s]);
+}
+
+// ------------------------------------------------------------ finalize
+
+enum { FIN_A = 0, FIN_B = 1, FIN_C = 2, FIN_SUM = 3, FIN_MAX = 4 };
+
+struct FinArgs {
+    Scalars *sc;
+    const double *partials;
+    int G;
+};
+
+// Sum the partials of the kernel that just ran and apply the BiCGSTAB
+// scalar recurrences (Table 3) on the device.
+template <int KIND>
+__device__ __forceinline__ void finalize_block(const FinArgs &f)
+{
+    constexpr int NQ = (KIND == FIN_B) ? 3 : (KIND == FIN_C) ? 2 : 1;
+    constexpr int NTF = 256;
+    Scalars *sc = f.sc;
+    if constexpr (KIND == FIN_A || KIND == FIN_B) {
+        if (sc->status != ST_RUN) return;          // the producer did not run
+    } else if constexpr (KIND == FIN_C) {
+        const int st = sc->status;
+        if (st != ST_RUN && st != ST_HALF) return;
+    }
+    double tot[NQ];
+    final_reduce<NQ, NTF, KIND == FIN_MAX>(tot, f.partials, f.G);
+    if (threadIdx.x != 0) return;
+    for (int q = 0; q < NQ; ++q) sc->red[q] = tot[q];
+    if constexpr (KIND == FIN_A) {
+        const double rtv = tot[0];
+        if (!finite(rtv)) sc->status = ST_NONFINITE;
+        else if (rtv == 0.0) sc->status = ST_RESTART;
+        else sc->alpha = sc->rho / rtv;                          // Table 3 step 12
+    } else if constexpr (KIND == FIN_B) {
+        const double ts = tot[0], tt = tot[1], ss = tot[2];
+        if (!finite(ts) || !finite(tt) || !finite(ss)) {
+            sc->status = ST_NONFINITE;
+        } else if (ss <= sc->tol2) {
+            sc->omega = 0.0;                                     // half-step convergence
+            sc->status = ST_HALF;
+        } else if (tt == 0.0) {
+            sc->status = ST_RESTART;
+        } else {
+            sc->omega = ts / tt;                                  // Table 3 step 15
+        }
+    } else if constexpr (KIND == FIN_C) {
+        const double rho_new = tot[0], rr = tot[1];
+        sc->rr = rr;
+        sc->iter += 1;
+        const int was = sc->status;
+        if (!finite(rho_new) || !finite(rr)) {
+            sc->status = ST_NONFINITE;
+        } else if (was == ST_HALF || rr <= sc->tol2) {
+            sc->status = ST_CONV;
+        } else if (sc->iter >= sc->maxit) {
+            sc->status = ST_MAXIT;
+        } else if (sc->omega == 0.0 || fabs(rho_new) < 1e-300 ||
+                   rho_new * rho_new < 1e-28 * sc->rt2 * rr) {
+            sc->status = ST_RESTART;   // shadow residual nearly orthogonal to r
+        } else {
+            sc->beta = (rho_new / sc->rho) * (sc->alpha / sc->omega);   // step 8
+            sc->rho = rho_new;
         }
     }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_finalize(FinArgs f)
+{
+    finalize_block<KIND>(f);
+}
+
+// One workgroup per system.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_finalize_batch(const FinArgs *__restrict__ f)
+{
+    const FinArgs a = f[blockIdx.x];
+    finalize_block<KIND>(a);
+}
+
+// Copy the scalar blocks of n systems into one array (one host read per chunk).
+__global__ void k_gather_scalars(const Scalars *const *src, Scalars *dst, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = *src[i];
 }
 
 // ------------------------------------------------------- small kernels
@@ -811,8 +900,7 @@ __global__ void k_rhs_pf2(size_t N, const double *psi, const double *sigma, cons
 // Relaxation (Table 2 step 5): Phi := omega Phi_0 + (1 - omega) Phi; the max
 // norm of the change; Phi_0 := Phi.  Result in sc->red[0].
 template <int NT>
-__global__ __launch_bounds__(NT) void k_relax(size_t N, double *phi0, double *phi, double omega,
-                                              Scalars *sc, double *partials, unsigned *ticket, int G)
+__global__ __launch_bounds__(NT) void k_relax(size_t N, double *phi0, double *phi, double omega, double *partials)
 {
     double acc[1] = {0.0};
     const size_t stride = (size_t)gridDim.x * NT;
@@ -826,14 +914,7 @@ __global__ __launch_bounds__(NT) void k_relax(size_t N, double *phi0, double *ph
         phi[n] = nv;
     }
     block_reduce<1, NT, true>(acc);
-    if (publish_partials<1>(acc, partials, ticket, G)) {
-        double tot[1];
-        final_reduce<1, NT, true>(tot, partials, G);
-        if (threadIdx.x == 0) {
-            *ticket = 0u;
-            sc->red[0] = tot[0];
-        }
-    }
+    store_partials<1>(acc, partials, blockIdx.x);
 }
 
 }  // namespace pfk

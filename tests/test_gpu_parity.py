@@ -300,3 +300,53 @@ def test_nonlinear_bias_and_warm_start():
     prm2 = pf.params_for(prob, outer_tol=1e-8, warm_start=1, lin={"rel_tol": 1e-13})
     info = pf.pf_nonlinear_solve(g, prm2, phi)
     assert info["outer_iters"] == 1
+
+
+# ------------------------------------------------------------------- batch
+
+def test_linear_batch_matches_single_solves():
+    """Batched launches (one kernel launch per BiCGSTAB step for all members)
+    give each member the answer of its standalone solve (FP64: 1e-9 against
+    the oracle; mixed: residual 1e-10 and 1e-8)."""
+    pf = _pf()
+    probs = inputs.batch_systems(n_sys=6, seed_base=4000)
+    probs = [p for p in probs if p.nx <= 65][:3] + [inputs.sphere_poisson(33)]
+    grids = [pf.grid_from_problem(p) for p in probs]
+    bs = [dev(p.b) for p in probs]
+    sg = [None if p.sigma is None else dev(p.sigma) for p in probs]
+    refs = [oracle.linear_solve(p, p.sigma, p.b, tol=1e-13)[0] for p in probs]
+    for prec, tol, bar in ((0, 1e-12, 1e-9), (1, 1e-10, 1e-8)):
+        xs = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
+        infos = pf.pf_linear_solve_batch(grids, sg, bs, xs, pf.pf_lin_opts_default(rel_tol=tol, precision=prec))
+        for p, g, s, b, x, ref, info in zip(probs, grids, sg, bs, xs, refs, infos):
+            assert info["status"] == 0 and info["rel_res"] <= tol
+            assert pf.pf_residual(g, s, b, x) <= tol
+            assert _rel(host(x), ref) <= bar, (p.name, prec)
+
+
+def test_linear_batch_rejects_shared_grid():
+    pf = _pf()
+    p = inputs.sphere_poisson(33)
+    g = pf.grid_from_problem(p)
+    b = dev(p.b)
+    xs = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for _ in range(2)]
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_linear_solve_batch([g, g], None, [b, b], xs)
+    assert e.value.code == pf.PF_ERR_ARG
+
+
+def test_nonlinear_batch_bias_sweep_matches_oracle():
+    """Three bias voltages solved as one batch match their oracle solves."""
+    pf = _pf()
+    vt = inputs.thermal_voltage_mV()
+    probs = [inputs.membrane_pore(17, n_charges=40, bias_phi=v / vt) for v in (-150.0, 0.0, 150.0)]
+    grids = [pf.grid_from_problem(p) for p in probs]
+    prms = [pf.params_for(p, outer_tol=1e-11, lin={"rel_tol": 1e-13}) for p in probs]
+    phis = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
+    infos = pf.pf_nonlinear_solve_batch(grids, prms, phis)
+    ms = probs[0].meta["species"]
+    sp = oracle.species_from_molar(ms["valence"], ms["radius_A"], ms["bath_M"])
+    for p, phi, info in zip(probs, phis, infos):
+        ref, _, _, _ = oracle.nonlinear_solve(p, p.fixed_charge, sp, 78.45, 1.9, outer_tol=1e-11, lin_tol=1e-13)
+        assert info["status"] == 0
+        assert _rel(host(phi), ref) <= 1e-9
