@@ -37,9 +37,8 @@ def log(*a):
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("pf_kernels.h", "pf_host.hip"):
-        h.update(open(os.path.join(ROOT, "paper_1711_04060_amd", "csrc", f), "rb").read())
+    """Hash of the device source: traffic counters stay valid while it is unchanged."""
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_1711_04060_amd", "csrc", "pf_kernels.h"), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -60,7 +59,7 @@ def traffic_from_profiles(workload):
 
 def run_nonlinear(pf, torch, prob, prm):
     phi = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
-    info = pf.pf_nonlinear_solve(g_cache[prob.name], prm, phi)
+    info = pf.pf_nonlinear_solve(g_cache[prob.name], prm, phi, check=prm.c.max_outer >= 5000)
     return info, phi
 
 
@@ -105,33 +104,123 @@ def forms_linear(pf, torch, inputs, timing_sample):
 
 
 def forms_batch(pf, torch, inputs):
-    """64 linearised-PB systems (33^3..129^3): sequential FP64 vs batched mixed."""
+    """64 linearised-PB systems (33^3..129^3), each to rel. res. 1e-10:
+    sequential FP64 solves vs one batched launch sequence (FP64 and mixed)."""
     probs = inputs.batch_systems()
     grids = [pf.grid_from_problem(p) for p in probs]
     bs = [torch.as_tensor(p.b, device="cuda") for p in probs]
     sg = [torch.as_tensor(p.sigma, device="cuda") for p in probs]
     xs = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
     res = {}
-    for name, prec in (("sequential_fp64", pf.PF_FP64), ("batched_mixed", pf.PF_MIXED)):
+    for name, prec, batched in (("sequential_fp64", pf.PF_FP64, False), ("batched_fp64", pf.PF_FP64, True),
+                                ("batched_mixed", pf.PF_MIXED, True)):
         opts = pf.pf_lin_opts_default(precision=prec)
-        for x in xs:
-            x.zero_()
-        pf.pf_linear_solve_batch(grids, sg, bs, xs, opts)    # warm-up (graphs, workspaces)
-        for x in xs:
-            x.zero_()
+        times = []
+        for rep in range(2):                       # first pass: tuning, workspaces
+            for x in xs:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if batched:
+                infos = pf.pf_linear_solve_batch(grids, sg, bs, xs, opts)
+            else:
+                infos = [pf.pf_linear_solve(gr, s, b, x, opts) for gr, s, b, x in zip(grids, sg, bs, xs)]
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        res[name] = dict(seconds=times[-1], total_iters=sum(i["iters"] for i in infos),
+                         max_rel_res=max(pf.pf_residual(gr, s, b, x) for gr, s, b, x in zip(grids, sg, bs, xs)))
+    res["unknowns"] = sum(p.N for p in probs)
+    res["batched_fp64_speedup"] = res["sequential_fp64"]["seconds"] / res["batched_fp64"]["seconds"]
+    res["batched_mixed_speedup"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
+    return res
+
+
+def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400):
+    """Configuration 5: 16 bias voltages on the membrane workload, full PF
+    nonlinear solves, batched (shared launches, mixed-precision linear
+    solves) vs 16 sequential FP64 solves.  Each run is driven in chunks of
+    `chunk` outer iterations (warm-started from the last iterate, which is the
+    whole state of the outer loop) so that progress is printed."""
+    vt = inputs.thermal_voltage_mV()
+    probs = [inputs.membrane_pore(n, bias_phi=v / vt) for v in inputs.bias_sweep_mV()]
+    grids = [pf.grid_from_problem(p) for p in probs]
+    res = {}
+    for name, prec, batched in (("batched_mixed", pf.PF_MIXED, True), ("sequential_fp64", pf.PF_FP64, False)):
+        prms = [pf.params_for(p, outer_tol=1e-8, max_outer=chunk, lin={"rel_tol": 1e-10, "precision": prec})
+                for p in probs]
+        phis = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
+        outer = [0] * len(probs)
+        lin = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if name == "sequential_fp64":
-            infos = [pf.pf_linear_solve(gr, s, b, x, opts) for gr, s, b, x in zip(grids, sg, bs, xs)]
-        else:
-            infos = pf.pf_linear_solve_batch(grids, sg, bs, xs, opts)
+        groups = [list(range(len(probs)))] if batched else [[i] for i in range(len(probs))]
+        for grp in groups:
+            todo = list(grp)
+            while todo:
+                if len(todo) > 1 or batched:
+                    infos = pf.pf_nonlinear_solve_batch([grids[i] for i in todo], [prms[i] for i in todo],
+                                                        [phis[i] for i in todo], check=False)
+                else:
+                    infos = [pf.pf_nonlinear_solve(grids[todo[0]], prms[todo[0]], phis[todo[0]], check=False)]
+                nxt = []
+                for i, info in zip(todo, infos):
+                    outer[i] += info["outer_iters"]
+                    lin += info["total_lin_iters"]
+                    prms[i].c.warm_start = 1
+                    if info["status"] == pf.PF_ERR_NOCONV and outer[i] < 20000:
+                        nxt.append(i)
+                    elif info["status"] != 0:
+                        raise RuntimeError(f"bias {i}: status {info['status']}")
+                todo = nxt
+                log(f"[bench]   {name}: {len(todo)} of {len(grp)} still running, "
+                    f"{time.perf_counter() - t0:.1f} s")
         torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        res[name] = dict(seconds=t, total_iters=sum(i["iters"] for i in infos),
-                         max_rel_res=max(i["rel_res"] for i in infos))
-    res["unknowns"] = sum(p.N for p in probs)
-    res["batched_speedup"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
+        res[name] = dict(seconds=time.perf_counter() - t0, outer_iters=outer, total_lin_iters=lin)
+        log(f"[bench] bias sweep {name}: {res[name]['seconds']:.1f} s")
+    res["speedup"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
+    res["workload"] = f"membrane_pore {n}^3, 16 biases -150..+150 mV on -z, outer 1e-8, BiCGSTAB 1e-10"
     return res
+
+
+def copy_reference(torch, mib=512):
+    """A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE give the
+    counters' scale (bytes per reported KiB) for the traffic figure."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return n * 8
+
+
+def pmc_summary(fetch_csv, write_csv, workload, copy_bytes):
+    """Per-launch HBM traffic of step A from two rocprofv3 --pmc runs (CSV),
+    each counter scaled by its reading on the copy kernel of known size."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return vals
+
+    out = {"workload": workload, "source_hash": kernel_source_hash(), "copy_bytes": copy_bytes}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        v = per_kernel(path, counter)
+        copy = [x for k, xs in v.items() if "copy" in k.lower() for x in xs]
+        copy_read = max(copy) if copy else None
+        step_a = [x for k, xs in v.items() if "k_zmarch<3, double, false" in k for x in xs]
+        big = sorted(step_a)[len(step_a) // 2:] if step_a else []   # launches that ran (not early exits)
+        mean = sum(big) / len(big) if big else None
+        scale = (copy_bytes / copy_read) if copy_read else None
+        out[counter] = dict(step_a_raw_bytes=mean, copy_raw_bytes=copy_read, scale=scale,
+                            step_a_bytes=(mean * scale) if (mean and scale) else None, launches=len(step_a))
+    f, w = out["FETCH_SIZE"]["step_a_bytes"], out["WRITE_SIZE"]["step_a_bytes"]
+    out["hbm_bytes_per_launch"] = (f + w) if (f is not None and w is not None) else None
+    return out
 
 
 def cpu_baseline(prob, lin_iters_full, budget_outer=2):
@@ -161,7 +250,16 @@ def main():
     ap.add_argument("--forms", type=int, default=1)
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--n", type=int, default=97)
+    ap.add_argument("--bias-sweep", type=int, default=0, help="also run configuration 5 (16 biases, 129^3)")
+    ap.add_argument("--max-outer", type=int, default=0, help="bounded outer loop (profiler runs only)")
+    ap.add_argument("--copy-ref", type=int, default=0, help="run the copy reference kernel (counter scale)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc CSVs into the traffic file and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], f"membrane_pore_{args.n}",
+                                     512 * (1 << 20)), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path "
               "is a design note, not part of this build.", file=sys.stderr)
@@ -172,9 +270,12 @@ def main():
     pf.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.copy_ref:
+        copy_reference(torch)
     prob = inputs.membrane_pore(args.n)
     g_cache[prob.name] = pf.grid_from_problem(prob)
-    prm = pf.params_for(prob, outer_tol=1e-8, lin={"rel_tol": 1e-10})
+    extra = {"max_outer": args.max_outer} if args.max_outer else {}
+    prm = pf.params_for(prob, outer_tol=1e-8, lin={"rel_tol": 1e-10}, **extra)
     log(f"[bench] workload {prob.name}: N={prob.N}, warmup {args.warmup}, steps {args.steps}")
     for w in range(args.warmup):
         info, _ = run_nonlinear(pf, torch, prob, prm)
@@ -238,6 +339,9 @@ def main():
         result["forms"] = {"linear_193": forms_linear(pf, torch, inputs, args.sample)}
         log("[bench] forms: 64-system batch")
         result["forms"]["batch_64"] = forms_batch(pf, torch, inputs)
+    if args.bias_sweep:
+        log("[bench] forms: 16-bias sweep at 129^3")
+        result.setdefault("forms", {})["bias_sweep_129"] = forms_bias_sweep(pf, torch, inputs)
     if args.cpu:
         log("[bench] cpu baseline (oracle sample)")
         result["cpu_baseline"] = cpu_baseline(prob, lin_iters)

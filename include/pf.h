@@ -215,7 +215,9 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample);
 /* Accumulated step-A timings for one precision (PF_FP64 or PF_MIXED = the
  * FP32 inner kernel): launches timed and their mean duration in ms; bytes is
  * the algorithmic HBM traffic of those launches (8 vectors of N elements per
- * launch: r, p, v, dinv, eps, shadow read; p, v written). */
+ * launch: r, p, v, dinv, eps, shadow read; p, v written).  The mean excludes
+ * the event-bracket latency (dispatch and completion of the launch), which
+ * pf_timing_enable measures around an empty one-workgroup kernel. */
 pf_status pf_timing_read(int32_t precision, int64_t *launches, double *mean_ms, double *bytes);
 
 /* Thread-local description of the last error (empty string if none). */

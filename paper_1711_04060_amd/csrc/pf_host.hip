@@ -63,6 +63,7 @@ struct Timing {
     long chunk = 0;
     long long launches[2] = {0, 0};
     double ms[2] = {0, 0}, bytes[2] = {0, 0};
+    double bracket_ms = 0;   // latency of an event bracket around an empty kernel
 } g_timing;
 
 constexpr size_t LDS_MAX = 152 * 1024;   // dynamic LDS per workgroup (gfx950 has 160 KB; static arrays use the rest)
@@ -151,6 +152,7 @@ struct pf_grid {
     std::map<long, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> tev;       // timing events (2 per iteration of a chunk)
     bool last_timed = false;
+    int last_run[4] = {0, 0, 0, 0};    // iterations of the last Krylov run per (precision, system)
 
     // nonlinear state
     double *phi0 = nullptr, *phi = nullptr, *psi = nullptr, *rhs1 = nullptr, *sig = nullptr,
@@ -630,11 +632,30 @@ pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter,
     return write_scalars(g);
 }
 
-// Iterate until the device reports a state other than RUN.
+// Iterate until the device reports a state other than RUN.  The first chunk
+// is sized from the previous run on the same grid and operator (the outer
+// loop repeats similar solves), later chunks are short, so few iterations
+// run past convergence as no-ops; a fixed check_every overrides this.
 template <typename T>
-pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m, int *status)
+pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m_fixed, int *status,
+                     bool adaptive)
 {
-    for (;;) {
+    const int slot = (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0);
+    const int start_iter = g->hsc->iter;
+    int chunk = 0;
+    for (;; ++chunk) {
+        int m = m_fixed;
+        if (adaptive) {
+            const int expect = g->last_run[slot];
+            if (chunk == 0 && expect >= 8) {
+                m = 4;
+                while (m * 2 <= expect && m < 128) m *= 2;
+            } else if (chunk == 0) {
+                m = m_fixed;
+            } else {
+                m = 8;
+            }
+        }
         const int before = g->hsc->iter;
         PFCHK(run_chunk<T>(g, op, dinv, w, m));
         PFCHK(read_scalars(g));
@@ -652,6 +673,7 @@ pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
         }
         if (g->hsc->status != pfk::ST_RUN) {
             *status = g->hsc->status;
+            g->last_run[slot] = g->hsc->iter - start_iter;
             return PF_OK;
         }
     }
@@ -822,8 +844,9 @@ pf_status solve_internal(pf_grid *g, const OpDesc &op, const pf_lin_opts *o, pf_
         PFCHK(ls_round_decide(L, &run));
         if (!run) break;
         int st = 0;
-        if (L.mixed) PFCHK(krylov_run<float>(g, op, L.dinv32, g->w32, m, &st));
-        else PFCHK(krylov_run<double>(g, op, L.dinv64, g->w64, m, &st));
+        const bool adaptive = o->check_every == 0;
+        if (L.mixed) PFCHK(krylov_run<float>(g, op, L.dinv32, g->w32, m, &st, adaptive));
+        else PFCHK(krylov_run<double>(g, op, L.dinv64, g->w64, m, &st, adaptive));
         PFCHK(ls_after(L, st));
     }
     return ls_finish(L, info);
@@ -1054,6 +1077,30 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample)
     g_timing = Timing{};
     g_timing.enabled = enable != 0;
     g_timing.sample = sample;
+    if (!g_timing.enabled) return PF_OK;
+    // An event pair around a launch also times the dispatch of the kernel
+    // packet and its completion signal.  Measure that bracket around an empty
+    // one-workgroup kernel launched the same way; pf_timing_read subtracts it.
+    hipStream_t st;
+    hipEvent_t e0, e1;
+    HIPCHK(hipStreamCreate(&st));
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    std::vector<float> v;
+    for (int i = 0; i < 25; ++i) {
+        if (hipEventRecord(e0, st) != hipSuccess) break;
+        hipLaunchKernelGGL(pfk::k_fill<double>, dim3(1), dim3(NT), 0, st, (size_t)0, (double *)nullptr, 0.0);
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && i >= 5) v.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (!v.empty()) {
+        std::sort(v.begin(), v.end());
+        g_timing.bracket_ms = v[v.size() / 2];
+    }
     return PF_OK;
 }
 
@@ -1062,7 +1109,10 @@ pf_status pf_timing_read(int32_t precision, int64_t *launches, double *mean_ms, 
     if (precision != PF_FP64 && precision != PF_MIXED) return fail(PF_ERR_ARG, "unknown precision");
     const int i = precision == PF_FP64 ? 0 : 1;
     if (launches) *launches = g_timing.launches[i];
-    if (mean_ms) *mean_ms = g_timing.launches[i] ? g_timing.ms[i] / g_timing.launches[i] : 0.0;
+    if (mean_ms)
+        *mean_ms = g_timing.launches[i]
+                       ? std::max(0.0, g_timing.ms[i] / g_timing.launches[i] - g_timing.bracket_ms)
+                       : 0.0;
     if (bytes) *bytes = g_timing.bytes[i];
     return PF_OK;
 }
