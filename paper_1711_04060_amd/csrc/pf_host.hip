@@ -148,7 +148,8 @@ struct pf_grid {
     Work<float> w32;
     bool have64 = false, have32 = false;
     Scalars *sc = nullptr, *hsc = nullptr;
-    double *partials = nullptr;
+    double *partials = nullptr;                                // standalone reductions
+    double *partA = nullptr, *partB = nullptr, *partC = nullptr;   // BiCGSTAB steps A, B, C
     std::map<long, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> tev;       // timing events (2 per iteration of a chunk)
     bool last_timed = false;
@@ -420,6 +421,10 @@ pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
     a.rt = w.rt;
     a.out = w.v[parity ^ 1];
     a.out_aux = w.p[parity ^ 1];
+    a.partials = g->partA;
+    a.pin = g->partC;
+    a.Gin = pw_blocks(g->N);
+    a.parity = parity;
     return a;
 }
 
@@ -431,11 +436,15 @@ pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
     b.y0 = w.v[parity ^ 1];
     b.out = w.t;
     b.out_aux = w.s;
+    b.partials = g->partB;
+    b.pin = g->partA;
+    b.Gin = c.G;
+    b.parity = parity;
     return b;
 }
 
 template <typename T>
-pfk::CArgs<T> args_c(pf_grid *g, const T *dinv, Work<T> &w, int parity)
+pfk::CArgs<T> args_c(pf_grid *g, const T *dinv, Work<T> &w, int parity, const ZCfg &cz)
 {
     pfk::CArgs<T> c{};
     c.N = g->N;
@@ -447,8 +456,11 @@ pfk::CArgs<T> args_c(pf_grid *g, const T *dinv, Work<T> &w, int parity)
     c.dinv = dinv;
     c.rt = w.rt;
     c.sc = g->sc;
-    c.partials = g->partials;
+    c.partials = g->partC;
+    c.pin = g->partB;
+    c.Gin = cz.G;
     c.G = pw_blocks(g->N);
+    c.parity = parity;
     return c;
 }
 
@@ -462,13 +474,20 @@ pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
     if (e0) HIPCHK(hipEventRecord(e0, g->stream));
     PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, dinv, w, parity, cfg))));
     if (e1) HIPCHK(hipEventRecord(e1, g->stream));
-    PFCHK(finalize<pfk::FIN_A>(g, cfg.G));
     PFCHK((zlaunch<pfk::OP_BB, T>(g, op, args_b<T>(g, op, dinv, w, parity, cfg))));
-    PFCHK(finalize<pfk::FIN_B>(g, cfg.G));
-    const pfk::CArgs<T> c = args_c<T>(g, dinv, w, parity);
+    const pfk::CArgs<T> c = args_c<T>(g, dinv, w, parity, cfg);
     hipLaunchKernelGGL((pfk::k_bicg_c<T, NT>), dim3(c.G), dim3(NT), 0, g->stream, c);
     HIPCHK(hipGetLastError());
-    return finalize<pfk::FIN_C>(g, c.G);
+    return PF_OK;
+}
+
+// Close a chunk: finish step C of its last iteration for the host to read.
+pf_status chunk_end(pf_grid *g)
+{
+    pfk::FinArgs f{g->sc, g->partC, pw_blocks(g->N)};
+    hipLaunchKernelGGL((pfk::k_finalize<pfk::FIN_C>), dim3(1), dim3(256), 0, g->stream, f);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
 }
 
 // Chunk of m iterations (m even) captured once per (precision, system) and
@@ -488,7 +507,7 @@ pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
     if (timed) {
         // sampled chunk: direct launches with HIP events around step A
         for (int i = 0; i < m; ++i) PFCHK(iteration<T>(g, op, dinv, w, i & 1, g->tev[2 * i], g->tev[2 * i + 1]));
-        return PF_OK;
+        return chunk_end(g);
     }
     const long key = (long)m * 16 + (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0);
     auto it = g->graphs.find(key);
@@ -497,6 +516,7 @@ pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
         HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
         pf_status st = PF_OK;
         for (int i = 0; i < m && st == PF_OK; ++i) st = iteration<T>(g, op, dinv, w, i & 1);
+        if (st == PF_OK) st = chunk_end(g);
         hipError_t e = hipStreamEndCapture(g->stream, &graph);
         if (st != PF_OK) return st;
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -550,7 +570,8 @@ pf_status tune(pf_grid *g)
     PFCHK(fill<T>(g, dinv, T(0.1), g->N));
     Scalars &h = *g->hsc;
     h = Scalars{};
-    h.rho = 1.0; h.alpha = 1.0; h.omega = 1.0; h.beta = 0.5; h.status = pfk::ST_RUN;
+    h.rho[0] = h.rho[1] = 1.0; h.alpha[1] = 1.0; h.omega[1] = 1.0; h.stop = pfk::ST_RUN; h.fresh = 1;
+    h.maxit = 1 << 30;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -565,9 +586,7 @@ pf_status tune(pf_grid *g)
             ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), sh[0], sh[1], kz);
             if (c.lds > LDS_MAX || c.G > g->Gmax || kz > g->nz) continue;
             cfg_ref<T>(g) = c;
-            pfk::ZArgs<T> a = zbase<T>(g, op, dinv);
-            a.x = w.r; a.y0 = w.p[0]; a.y1 = w.v[0]; a.rt = w.rt;
-            a.out = w.v[1]; a.out_aux = w.p[1];
+            pfk::ZArgs<T> a = args_a<T>(g, op, dinv, w, 0, c);
             float tot = 0;
             for (int rep = 0; rep < 4 && st == PF_OK; ++rep) {
                 if ((st = write_scalars(g)) != PF_OK) break;
@@ -619,16 +638,17 @@ pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter,
     PFCHK(fill<T>(g, w.v[0], T(0), g->N));
     Scalars &h = *g->hsc;
     h = Scalars{};
-    h.rho = rr;
-    h.alpha = 1.0;
-    h.omega = 1.0;
-    h.beta = 0.0;
+    h.rho[0] = rr;            // shadow = r, so rho_0 = ||r||^2
+    h.alpha[1] = 1.0;
+    h.omega[1] = 1.0;
     h.rr = rr;
     h.tol2 = tol2;
     h.rt2 = rr;
-    h.iter = iter;
+    h.iter[0] = iter;
+    h.iter_done = iter;
     h.maxit = maxit;
-    h.status = pfk::ST_RUN;
+    h.stop = pfk::ST_RUN;
+    h.fresh = 1;
     return write_scalars(g);
 }
 
@@ -641,7 +661,7 @@ pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
                      bool adaptive)
 {
     const int slot = (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0);
-    const int start_iter = g->hsc->iter;
+    const int start_iter = g->hsc->iter_done;
     int chunk = 0;
     for (;; ++chunk) {
         int m = m_fixed;
@@ -656,12 +676,12 @@ pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
                 m = 8;
             }
         }
-        const int before = g->hsc->iter;
+        const int before = g->hsc->iter_done;
         PFCHK(run_chunk<T>(g, op, dinv, w, m));
         PFCHK(read_scalars(g));
         if (g->last_timed && !op.psi) {
             // iterations whose step A ran in full (later ones exit at once)
-            const int ran = std::min(m, g->hsc->iter - before);
+            const int ran = std::min(m, g->hsc->iter_done - before);
             const int pi = sizeof(T) == 8 ? 0 : 1;
             for (int i = 0; i < ran; ++i) {
                 float ms = 0;
@@ -671,9 +691,9 @@ pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
                 g_timing.bytes[pi] += 8.0 * (double)g->N * sizeof(T);
             }
         }
-        if (g->hsc->status != pfk::ST_RUN) {
-            *status = g->hsc->status;
-            g->last_run[slot] = g->hsc->iter - start_iter;
+        if (g->hsc->stop != pfk::ST_RUN) {
+            *status = g->hsc->stop;
+            g->last_run[slot] = g->hsc->iter_done - start_iter;
             return PF_OK;
         }
     }
@@ -799,7 +819,7 @@ pf_status ls_round_decide(LinSolve &L, bool *run)
 pf_status ls_after(LinSolve &L, int st)
 {
     pf_grid *g = L.g;
-    L.iter = g->hsc->iter;
+    L.iter = g->hsc->iter_done;
     if (st == pfk::ST_NONFINITE) { L.result = PF_ERR_NONFINITE; L.done = true; return PF_OK; }
     if (L.mixed) {
         if (st == pfk::ST_RESTART) ++L.restarts;
@@ -886,7 +906,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     std::vector<pfk::CArgs<T>> zc[2];
     std::vector<int> zstart(n + 1, 0), cstart(n + 1, 0);
     std::vector<const Scalars *> scp(n);
-    std::vector<pfk::FinArgs> fz(n), fc(n);
+    std::vector<pfk::FinArgs> fc(n);
     size_t lds = 0;
     for (int par = 0; par < 2; ++par) { za[par].resize(n); zb[par].resize(n); zc[par].resize(n); }
     for (int i = 0; i < n; ++i) {
@@ -900,12 +920,11 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         for (int par = 0; par < 2; ++par) {
             za[par][i] = args_a<T>(g, L.op, dinv, *w, par, c);
             zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, c);
-            zc[par][i] = args_c<T>(g, dinv, *w, par);
+            zc[par][i] = args_c<T>(g, dinv, *w, par, c);
         }
         zstart[i + 1] = zstart[i] + c.G;
         cstart[i + 1] = cstart[i] + zc[0][i].G;
-        fz[i] = pfk::FinArgs{g->sc, g->partials, c.G};
-        fc[i] = pfk::FinArgs{g->sc, g->partials, zc[0][i].G};
+        fc[i] = pfk::FinArgs{g->sc, g->partC, zc[0][i].G};
         lds = std::max(lds, c.lds);
         scp[i] = g->sc;
     }
@@ -915,7 +934,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     const size_t szI = sizeof(int) * (n + 1), szP = sizeof(void *) * n, szS = sizeof(Scalars) * n;
     const size_t szF = sizeof(pfk::FinArgs) * n;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t need = 4 * al(szZ) + 2 * al(szC) + 2 * al(szI) + al(szP) + al(szS) + 2 * al(szF);
+    const size_t need = 4 * al(szZ) + 2 * al(szC) + 2 * al(szI) + al(szP) + al(szS) + al(szF);
     if (need > g_batch.bytes) {
         if (g_batch.dev) (void)hipFree(g_batch.dev);
         g_batch.dev = nullptr;
@@ -940,7 +959,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     int *dzs = (int *)take(szI), *dcs = (int *)take(szI);
     const Scalars **dscp = (const Scalars **)take(szP);
     Scalars *dgather = (Scalars *)take(szS);
-    pfk::FinArgs *dfz = (pfk::FinArgs *)take(szF), *dfc = (pfk::FinArgs *)take(szF);
+    pfk::FinArgs *dfc = (pfk::FinArgs *)take(szF);
     for (int par = 0; par < 2; ++par) {
         HIPCHK(hipMemcpyAsync(dA[par], za[par].data(), szZ, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(dB[par], zb[par].data(), szZ, hipMemcpyHostToDevice, stream));
@@ -949,7 +968,6 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     HIPCHK(hipMemcpyAsync(dzs, zstart.data(), szI, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dcs, cstart.data(), szI, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dscp, scp.data(), szP, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(dfz, fz.data(), szF, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dfc, fc.data(), szF, hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
 
@@ -961,17 +979,11 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         if (psi) e = launch_batch<pfk::OP_BA, T, true>(c, dA[par], dzs, n, stream);
         else e = launch_batch<pfk::OP_BA, T, false>(c, dA[par], dzs, n, stream);
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
-        hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_A>), dim3(n), dim3(256), 0, stream,
-                           (const pfk::FinArgs *)dfz);
         if (psi) e = launch_batch<pfk::OP_BB, T, true>(c, dB[par], dzs, n, stream);
         else e = launch_batch<pfk::OP_BB, T, false>(c, dB[par], dzs, n, stream);
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
-        hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_B>), dim3(n), dim3(256), 0, stream,
-                           (const pfk::FinArgs *)dfz);
         hipLaunchKernelGGL((pfk::k_bicg_c_batch<T, NT>), dim3(GC), dim3(NT), 0, stream,
                            (const pfk::CArgs<T> *)dC[par], (const int *)dcs, n);
-        hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_C>), dim3(n), dim3(256), 0, stream,
-                           (const pfk::FinArgs *)dfc);
         HIPCHK(hipGetLastError());
         return PF_OK;
     };
@@ -979,6 +991,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
     pf_status st = PF_OK;
     for (int i = 0; i < m && st == PF_OK; ++i) st = launch_iter(i & 1);
+    hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_C>), dim3(n), dim3(256), 0, stream, (const pfk::FinArgs *)dfc);
     hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
     hipError_t e = hipStreamEndCapture(stream, &graph);
     if (st != PF_OK) return st;
@@ -998,7 +1011,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         }
         bool any = false;
         for (int i = 0; i < n; ++i) {
-            status[i] = g_batch.hsc[i].status;
+            status[i] = g_batch.hsc[i].stop;
             any |= status[i] == pfk::ST_RUN;
         }
         if (!any) break;
@@ -1175,6 +1188,9 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     if ((st = dalloc(g, &g->dval, N)) != PF_OK) return cleanup(st);
     if ((st = dalloc(g, &g->sc, 1)) != PF_OK) return cleanup(st);
     if ((st = dalloc(g, &g->partials, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
+    if ((st = dalloc(g, &g->partA, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
+    if ((st = dalloc(g, &g->partB, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
+    if ((st = dalloc(g, &g->partC, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
     if (hipHostMalloc((void **)&g->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(PF_ERR_ALLOC, "pinned host allocation failed"));
     if (d->fixed_charge && (st = dalloc(g, &g->q, N)) != PF_OK) return cleanup(st);

@@ -39,15 +39,25 @@ namespace pfk {
 // node flag bits (one byte per node)
 enum : uint8_t { F_DIR_PHI = 1, F_DIR_PSI = 2, F_SOLVENT = 4 };
 
-// device-side BiCGSTAB state (FP64 even when the vectors are FP32)
+// Device-side BiCGSTAB state (FP64 even when the vectors are FP32).  Values
+// produced inside an iteration are kept per iteration parity q = i & 1: a
+// kernel of iteration i reads the slots of iteration i-1 (or of its own
+// iteration written by an earlier kernel) and its leading workgroup writes
+// slot q, so no workgroup reads a slot that its own kernel writes.
 struct Scalars {
-    double rho;        // shadow . r of the current iterate
-    double alpha, omega, beta;
-    double rr;         // ||r||^2 (recurrence)
+    double rho[2];     // shadow . r at the start of iteration i
+    double alpha[2];   // alpha_i
+    double omega[2];   // omega_i
+    double rr;         // ||r||^2 of the recurrence, last completed iteration
     double tol2;       // (rel_tol * ||b_lift||)^2
     double rt2;        // ||r_shadow||^2 at the last (re)start
-    double red[4];     // raw sums of the last reduction
-    int iter, maxit, status, pad;
+    double red[4];     // sums of the last standalone reduction (residual, relaxation)
+    int iter[2];       // iterations completed when iteration i starts
+    int iter_done;     // iterations completed (host view)
+    int maxit;
+    int stop;          // ST_RUN while iterating, ST_HALF between steps B and C of a
+                       // half-step convergence, else the terminal state
+    int fresh;         // 1 from a (re)start until step B of the first iteration
 };
 enum { ST_RUN = 0, ST_CONV = 1, ST_HALF = 2, ST_RESTART = 3, ST_NONFINITE = 4, ST_MAXIT = 5 };
 
@@ -80,7 +90,10 @@ struct ZArgs {
     float *rt32;                // RESID: optional shadow copy (FP32)
     // reduction and scalars
     Scalars *sc;
-    double *partials;           // [G][4]
+    double *partials;           // [G][4] partials written by this kernel
+    const double *pin;          // partials of the previous phase (BA: step C, BB: step A)
+    int Gin;                    // their count
+    int parity;                 // iteration parity q
 };
 
 // ------------------------------------------------------------- helpers
@@ -185,6 +198,80 @@ __device__ __forceinline__ void final_reduce(double (&v)[NQ], const double *part
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
+// Sum of NQ quantities over G partials in one fixed order whatever the
+// workgroup size (lanes 0..255 sum strided subsets, then a fixed tree), so
+// every workgroup of a consumer kernel and the one-workgroup finalize kernel
+// obtain identical bits.  Every thread receives the result.
+template <int NQ>
+__device__ __forceinline__ void sum_partials(double (&tot)[NQ], const double *partials, int G)
+{
+    __shared__ double sred[4][NQ];
+    __shared__ double sout[NQ];
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+    if (threadIdx.x < 256) {
+        for (int i = threadIdx.x; i < G; i += 256) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[q] += partials[i * 4 + q];
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double sw = wave_sum(v[q]);
+        if (lane == 0 && w < 4) sred[w][q] = sw;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sout[q] = ((sred[0][q] + sred[1][q]) + sred[2][q]) + sred[3][q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tot[q] = sout[q];
+}
+
+// End of step C of iteration i-1 (Table 3 steps 4, 8 and the stop test):
+// rho_i = shadow . r, ||r||^2, the stop state and beta_i.  q is the parity of
+// iteration i.
+struct FinC {
+    double rho, rr, beta;
+    int iter, stop;
+};
+
+__device__ __forceinline__ FinC fin_c(const Scalars *sc, const double (&tot)[2], int q)
+{
+    const int qp = q ^ 1;
+    FinC f;
+    f.rho = tot[0];
+    f.rr = tot[1];
+    f.iter = sc->iter[qp] + 1;
+    f.beta = 0.0;
+    if (!finite(f.rho) || !finite(f.rr)) {
+        f.stop = ST_NONFINITE;
+    } else if (sc->stop == ST_HALF || f.rr <= sc->tol2) {
+        f.stop = ST_CONV;
+    } else if (f.iter >= sc->maxit) {
+        f.stop = ST_MAXIT;
+    } else if (sc->omega[qp] == 0.0 || fabs(f.rho) < 1e-300 || f.rho * f.rho < 1e-28 * sc->rt2 * f.rr) {
+        f.stop = ST_RESTART;   // shadow residual nearly orthogonal to r
+    } else {
+        f.stop = ST_RUN;
+        f.beta = (f.rho / sc->rho[qp]) * (sc->alpha[qp] / sc->omega[qp]);   // step 8
+    }
+    return f;
+}
+
+__device__ __forceinline__ void fin_c_store(Scalars *sc, const FinC &f, int q)
+{
+    sc->rho[q] = f.rho;
+    sc->iter[q] = f.iter;
+    sc->iter_done = f.iter;
+    sc->rr = f.rr;
+    if (f.stop != ST_RUN) sc->stop = f.stop;
+}
+
 // --------------------------------------------------- z-marching stencil
 
 template <typename T>
@@ -270,11 +357,37 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int NQ = (OP == OP_BB) ? 3 : 1;
     double alpha = 0, omega = 0, beta = 0;
-    if constexpr (OP == OP_BA || OP == OP_BB) {
-        if (a.sc->status != ST_RUN) return;
-        alpha = a.sc->alpha;
-        omega = a.sc->omega;
-        beta = a.sc->beta;
+    if constexpr (OP == OP_BA) {
+        // finish step C of the previous iteration (or start fresh)
+        Scalars *sc = a.sc;
+        const int stop = sc->stop;
+        if (stop != ST_RUN && stop != ST_HALF) return;
+        if (!sc->fresh) {
+            double tot[2];
+            sum_partials<2>(tot, a.pin, a.Gin);
+            const FinC f = fin_c(sc, tot, a.parity);
+            if (lb == 0 && threadIdx.x == 0) fin_c_store(sc, f, a.parity);
+            if (f.stop != ST_RUN) return;
+            beta = f.beta;
+            omega = sc->omega[a.parity ^ 1];
+        }
+    } else if constexpr (OP == OP_BB) {
+        // finish step A: alpha_i = rho_i / (shadow . v)   (Table 3 step 12)
+        Scalars *sc = a.sc;
+        if (sc->stop != ST_RUN) return;
+        double tot[1];
+        sum_partials<1>(tot, a.pin, a.Gin);
+        const double rtv = tot[0];
+        int st = ST_RUN;
+        if (!finite(rtv)) st = ST_NONFINITE;
+        else if (rtv == 0.0) st = ST_RESTART;
+        else alpha = sc->rho[a.parity] / rtv;
+        if (lb == 0 && threadIdx.x == 0) {
+            sc->alpha[a.parity] = alpha;
+            sc->fresh = 0;
+            if (st != ST_RUN) sc->stop = st;
+        }
+        if (st != ST_RUN) return;
     }
     // two LDS planes (double buffer) of staged values and coefficients
     T *lval0 = reinterpret_cast<T *>(smem_raw);
@@ -554,17 +667,36 @@ struct CArgs {
     T *x, *r;
     const T *p, *s, *t, *dinv, *rt;
     Scalars *sc;
-    double *partials;
+    double *partials;        // written: shadow . r, r . r
+    const double *pin;       // step B partials: t.s, t.t, s.s
+    int Gin;
     int G;
+    int parity;
 };
 
 template <typename T, int NT>
 __device__ __forceinline__ void bicg_c_block(const CArgs<T> &a, const int b)
 {
     Scalars *sc = a.sc;
-    const int st = sc->status;
-    if (st != ST_RUN && st != ST_HALF) return;
-    const T alpha = (T)sc->alpha, omega = (T)sc->omega;
+    const int stop = sc->stop;
+    if (stop != ST_RUN && stop != ST_HALF) return;
+    // finish step B: omega_i = t.s / t.t (Table 3 step 15), or the half-step
+    // exit when ||s|| already meets the tolerance
+    double tot[3];
+    sum_partials<3>(tot, a.pin, a.Gin);
+    const double ts = tot[0], tt = tot[1], ss = tot[2];
+    int st = ST_RUN;
+    double om = 0.0;
+    if (!finite(ts) || !finite(tt) || !finite(ss)) st = ST_NONFINITE;
+    else if (ss <= sc->tol2) st = ST_HALF;
+    else if (tt == 0.0) st = ST_RESTART;
+    else om = ts / tt;
+    if (b == 0 && threadIdx.x == 0) {
+        sc->omega[a.parity] = om;
+        if (st != ST_RUN) sc->stop = st;
+    }
+    if (st == ST_NONFINITE || st == ST_RESTART) return;
+    const T alpha = (T)sc->alpha[a.parity], omega = (T)om;
     double acc[2] = {0.0, 0.0};
     const size_t N = a.N;
     T *__restrict__ x = a.x;
@@ -578,8 +710,8 @@ __device__ __forceinline__ void bicg_c_block(const CArgs<T> &a, const int b)
     for (size_t i = (size_t)b * NT + threadIdx.x; i < N; i += stride) {
         const T d = absT(dinv[i]);
         const T si = s[i], ti = t[i];
-        x[i] = x[i] + alpha * (d * p[i]) + omega * (d * si);
-        const T ri = si - omega * ti;
+        x[i] = x[i] + alpha * (d * p[i]) + omega * (d * si);   // step 16
+        const T ri = si - omega * ti;                           // step 17
         r[i] = ri;
         acc[0] += (double)rt[i] * (double)ri;
         acc[1] += (double)ri * (double)ri;
@@ -605,7 +737,7 @@ __global__ __launch_bounds__(NT) void k_bicg_c_batch(const CArgs<T> *__restrict_
 
 // ------------------------------------------------------------ finalize
 
-enum { FIN_A = 0, FIN_B = 1, FIN_C = 2, FIN_SUM = 3, FIN_MAX = 4 };
+enum { FIN_C = 2, FIN_SUM = 3, FIN_MAX = 4 };
 
 struct FinArgs {
     Scalars *sc;
@@ -613,59 +745,25 @@ struct FinArgs {
     int G;
 };
 
-// Sum the partials of the kernel that just ran and apply the BiCGSTAB
-// scalar recurrences (Table 3) on the device.
+// FIN_C closes a graph chunk: it finishes step C of the chunk's last
+// iteration exactly as the next step A would (same sums, same bits), so the
+// host can read the stop state.  FIN_SUM / FIN_MAX finish the standalone
+// residual and relaxation reductions into red[0].
 template <int KIND>
 __device__ __forceinline__ void finalize_block(const FinArgs &f)
 {
-    constexpr int NQ = (KIND == FIN_B) ? 3 : (KIND == FIN_C) ? 2 : 1;
-    constexpr int NTF = 256;
     Scalars *sc = f.sc;
-    if constexpr (KIND == FIN_A || KIND == FIN_B) {
-        if (sc->status != ST_RUN) return;          // the producer did not run
-    } else if constexpr (KIND == FIN_C) {
-        const int st = sc->status;
-        if (st != ST_RUN && st != ST_HALF) return;
-    }
-    double tot[NQ];
-    final_reduce<NQ, NTF, KIND == FIN_MAX>(tot, f.partials, f.G);
-    if (threadIdx.x != 0) return;
-    for (int q = 0; q < NQ; ++q) sc->red[q] = tot[q];
-    if constexpr (KIND == FIN_A) {
-        const double rtv = tot[0];
-        if (!finite(rtv)) sc->status = ST_NONFINITE;
-        else if (rtv == 0.0) sc->status = ST_RESTART;
-        else sc->alpha = sc->rho / rtv;                          // Table 3 step 12
-    } else if constexpr (KIND == FIN_B) {
-        const double ts = tot[0], tt = tot[1], ss = tot[2];
-        if (!finite(ts) || !finite(tt) || !finite(ss)) {
-            sc->status = ST_NONFINITE;
-        } else if (ss <= sc->tol2) {
-            sc->omega = 0.0;                                     // half-step convergence
-            sc->status = ST_HALF;
-        } else if (tt == 0.0) {
-            sc->status = ST_RESTART;
-        } else {
-            sc->omega = ts / tt;                                  // Table 3 step 15
-        }
-    } else if constexpr (KIND == FIN_C) {
-        const double rho_new = tot[0], rr = tot[1];
-        sc->rr = rr;
-        sc->iter += 1;
-        const int was = sc->status;
-        if (!finite(rho_new) || !finite(rr)) {
-            sc->status = ST_NONFINITE;
-        } else if (was == ST_HALF || rr <= sc->tol2) {
-            sc->status = ST_CONV;
-        } else if (sc->iter >= sc->maxit) {
-            sc->status = ST_MAXIT;
-        } else if (sc->omega == 0.0 || fabs(rho_new) < 1e-300 ||
-                   rho_new * rho_new < 1e-28 * sc->rt2 * rr) {
-            sc->status = ST_RESTART;   // shadow residual nearly orthogonal to r
-        } else {
-            sc->beta = (rho_new / sc->rho) * (sc->alpha / sc->omega);   // step 8
-            sc->rho = rho_new;
-        }
+    if constexpr (KIND == FIN_C) {
+        const int stop = sc->stop;
+        if ((stop != ST_RUN && stop != ST_HALF) || sc->fresh) return;
+        double tot[2];
+        sum_partials<2>(tot, f.partials, f.G);
+        const FinC c = fin_c(sc, tot, 0);   // chunks hold an even number of iterations
+        if (threadIdx.x == 0) fin_c_store(sc, c, 0);
+    } else {
+        double tot[1];
+        final_reduce<1, 256, KIND == FIN_MAX>(tot, f.partials, f.G);
+        if (threadIdx.x == 0) sc->red[0] = tot[0];
     }
 }
 
