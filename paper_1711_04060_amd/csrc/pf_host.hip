@@ -73,8 +73,13 @@ constexpr size_t LDS_MAX = 152 * 1024;   // dynamic LDS per workgroup (gfx950 ha
 // workgroup.
 struct ZCfg {
     int NTZ = 256, PPT = 2, S = 512, KZ = 8, nstrips = 1, nzc = 1, G = 1, lmax = 0;
+    bool wide = false;   // halo rows exceed the registers' halo slots (WIDE kernel form)
     size_t lds = 0;
 };
+
+// Halo slots per thread of the z-march kernels (both halo rows, 2 nx nodes,
+// fit in registers when 2 nx <= halo_slots(NT) * NT).
+constexpr int halo_slots(int ntz) { return ntz >= 512 ? 1 : 2; }
 
 ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz)
 {
@@ -89,6 +94,7 @@ ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz)
     c.G = c.nstrips * c.nzc;
     c.lmax = std::min(P, c.S + 2 * nx);
     c.lds = 4 * (size_t)c.lmax * elem;   // two planes of (value, coefficient)
+    c.wide = 2 * nx > halo_slots(ntz) * ntz;
     return c;
 }
 
@@ -107,10 +113,18 @@ ZCfg default_cfg(int nx, int ny, int nz, size_t elem)
     ZCfg c = make_cfg(nx, ny, nz, elem, ntz, ppt, kz);
     while (c.lds > LDS_MAX && c.PPT > 1) c = make_cfg(nx, ny, nz, elem, c.NTZ, c.PPT - 1, c.KZ);
     while (c.lds > LDS_MAX && c.NTZ > 256) c = make_cfg(nx, ny, nz, elem, c.NTZ / 2, c.PPT, c.KZ);
+    // very wide planes: only the 1024-thread, one-node-per-thread shape has a WIDE form
+    if (c.wide && (c.NTZ != 1024 || c.PPT != 1)) c = make_cfg(nx, ny, nz, elem, 1024, 1, c.KZ);
     return c;
 }
 
 int pw_blocks(size_t N) { return (int)std::min<size_t>(PW_MAX_G, (N + NT - 1) / NT); }
+// workgroups of BiCGSTAB step C (each covers NT * C_UNROLL elements per round)
+int c_blocks(size_t N)
+{
+    const size_t span = (size_t)NT * pfk::C_UNROLL;
+    return (int)std::max<size_t>(1, std::min<size_t>(PW_MAX_G, (N + span - 1) / span));
+}
 
 template <typename T>
 struct Work {
@@ -235,10 +249,10 @@ pf_status ensure_work(pf_grid *g)
 
 // --------------------------------------------------------------- launches
 
-template <int OP, typename T, bool CEPS, int NTZ, int PPT>
+template <int OP, typename T, bool CEPS, int NTZ, int PPT, bool WIDE = false>
 hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
 {
-    auto kern = pfk::k_zmarch<OP, T, CEPS, NTZ, PPT>;
+    auto kern = pfk::k_zmarch<OP, T, CEPS, NTZ, PPT, WIDE>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;   // per instantiation
         if (c.lds > granted) {
@@ -255,6 +269,10 @@ hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
 template <int OP, typename T, bool CEPS>
 hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
 {
+    if (c.wide) {
+        if (c.NTZ == 1024 && c.PPT == 1) return launch_zk<OP, T, CEPS, 1024, 1, true>(c, a, s);
+        return hipErrorInvalidValue;
+    }
     const int key = c.NTZ * 10 + c.PPT;
     switch (key) {
     case 2561: return launch_zk<OP, T, CEPS, 256, 1>(c, a, s);
@@ -267,10 +285,10 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
     }
 }
 
-template <int OP, typename T, bool CEPS>
-hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
+template <int OP, typename T, bool CEPS, bool WIDE>
+hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
 {
-    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, 512, 1>;
+    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, 512, 1, WIDE>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;
         if (c.lds > granted) {
@@ -282,6 +300,14 @@ hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *sta
     }
     hipLaunchKernelGGL(kern, dim3(c.G), dim3(512), c.lds, s, args, start, n);
     return hipGetLastError();
+}
+
+// c: the batch's combined shape (G = all tiles, lds and wide = the maxima)
+template <int OP, typename T, bool CEPS>
+hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
+{
+    return c.wide ? launch_batch_k<OP, T, CEPS, true>(c, args, start, n, s)
+                  : launch_batch_k<OP, T, CEPS, false>(c, args, start, n, s);
 }
 
 template <typename T>
@@ -423,7 +449,7 @@ pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
     a.out_aux = w.p[parity ^ 1];
     a.partials = g->partA;
     a.pin = g->partC;
-    a.Gin = pw_blocks(g->N);
+    a.Gin = c_blocks(g->N);
     a.parity = parity;
     return a;
 }
@@ -459,7 +485,7 @@ pfk::CArgs<T> args_c(pf_grid *g, const T *dinv, Work<T> &w, int parity, const ZC
     c.partials = g->partC;
     c.pin = g->partB;
     c.Gin = cz.G;
-    c.G = pw_blocks(g->N);
+    c.G = c_blocks(g->N);
     c.parity = parity;
     return c;
 }
@@ -484,7 +510,7 @@ pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
 // Close a chunk: finish step C of its last iteration for the host to read.
 pf_status chunk_end(pf_grid *g)
 {
-    pfk::FinArgs f{g->sc, g->partC, pw_blocks(g->N)};
+    pfk::FinArgs f{g->sc, g->partC, c_blocks(g->N)};
     hipLaunchKernelGGL((pfk::k_finalize<pfk::FIN_C>), dim3(1), dim3(256), 0, g->stream, f);
     HIPCHK(hipGetLastError());
     return PF_OK;
@@ -584,7 +610,7 @@ pf_status tune(pf_grid *g)
     for (auto &sh : shapes) {
         for (int kz : {2, 4, 8, 16, 32}) {
             ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), sh[0], sh[1], kz);
-            if (c.lds > LDS_MAX || c.G > g->Gmax || kz > g->nz) continue;
+            if (c.lds > LDS_MAX || c.G > g->Gmax || kz > g->nz || (c.wide && (c.NTZ != 1024 || c.PPT != 1))) continue;
             cfg_ref<T>(g) = c;
             pfk::ZArgs<T> a = args_a<T>(g, op, dinv, w, 0, c);
             float tot = 0;
@@ -908,6 +934,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     std::vector<const Scalars *> scp(n);
     std::vector<pfk::FinArgs> fc(n);
     size_t lds = 0;
+    bool wide = false;
     for (int par = 0; par < 2; ++par) { za[par].resize(n); zb[par].resize(n); zc[par].resize(n); }
     for (int i = 0; i < n; ++i) {
         LinSolve &L = *act[i];
@@ -926,6 +953,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         cstart[i + 1] = cstart[i] + zc[0][i].G;
         fc[i] = pfk::FinArgs{g->sc, g->partC, zc[0][i].G};
         lds = std::max(lds, c.lds);
+        wide = wide || c.wide;
         scp[i] = g->sc;
     }
     if (lds > LDS_MAX) return fail(PF_ERR_ARG, "batch member too wide for the LDS strip");
@@ -974,7 +1002,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     const int GZ = zstart[n], GC = cstart[n];
     auto launch_iter = [&](int par) -> pf_status {
         ZCfg c{};
-        c.NTZ = 512; c.PPT = 1; c.G = GZ; c.lds = lds;
+        c.NTZ = 512; c.PPT = 1; c.G = GZ; c.lds = lds; c.wide = wide;
         hipError_t e;
         if (psi) e = launch_batch<pfk::OP_BA, T, true>(c, dA[par], dzs, n, stream);
         else e = launch_batch<pfk::OP_BA, T, false>(c, dA[par], dzs, n, stream);

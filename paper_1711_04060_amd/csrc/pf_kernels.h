@@ -199,11 +199,36 @@ __device__ __forceinline__ void final_reduce(double (&v)[NQ], const double *part
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
 // Sum of NQ quantities over G partials in one fixed order whatever the
-// workgroup size (lanes 0..255 sum strided subsets, then a fixed tree), so
-// every workgroup of a consumer kernel and the one-workgroup finalize kernel
-// obtain identical bits.  Every thread receives the result.
+// workgroup size (lanes 0..255 each add the partials lane, lane + 256, ...
+// in increasing order, then a fixed tree), so every workgroup of a consumer
+// kernel and the one-workgroup finalize kernel obtain identical bits.  The
+// loads are split from the sum so that a kernel can issue them together with
+// its first data loads: the first PJ*256 partials are loaded without a loop
+// (indices past G load slot 0 and are not added).
+constexpr int PJ = 4;
+
 template <int NQ>
-__device__ __forceinline__ void sum_partials(double (&tot)[NQ], const double *partials, int G)
+struct PartLoad {
+    double l[PJ][NQ];
+};
+
+template <int NQ>
+__device__ __forceinline__ void load_partials(PartLoad<NQ> &pl, const double *partials, int G)
+{
+    const int lane = threadIdx.x & 255;
+#pragma unroll
+    for (int j = 0; j < PJ; ++j) {
+        const int i = lane + 256 * j;
+        const int ic = i < G ? i : 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) pl.l[j][q] = partials[ic * 4 + q];
+    }
+}
+
+// Every thread receives the result.
+template <int NQ>
+__device__ __forceinline__ void sum_loaded_partials(double (&tot)[NQ], const PartLoad<NQ> &pl,
+                                                    const double *partials, int G)
 {
     __shared__ double sred[4][NQ];
     __shared__ double sout[NQ];
@@ -211,7 +236,15 @@ __device__ __forceinline__ void sum_partials(double (&tot)[NQ], const double *pa
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] = 0.0;
     if (threadIdx.x < 256) {
-        for (int i = threadIdx.x; i < G; i += 256) {
+        const int lane = threadIdx.x;
+#pragma unroll
+        for (int j = 0; j < PJ; ++j) {
+            if (lane + 256 * j < G) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) v[q] += pl.l[j][q];
+            }
+        }
+        for (int i = lane + 256 * PJ; i < G; i += 256) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) v[q] += partials[i * 4 + q];
         }
@@ -230,6 +263,14 @@ __device__ __forceinline__ void sum_partials(double (&tot)[NQ], const double *pa
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NQ; ++q) tot[q] = sout[q];
+}
+
+template <int NQ>
+__device__ __forceinline__ void sum_partials(double (&tot)[NQ], const double *partials, int G)
+{
+    PartLoad<NQ> pl;
+    load_partials<NQ>(pl, partials, G);
+    sum_loaded_partials<NQ>(tot, pl, partials, G);
 }
 
 // End of step C of iteration i-1 (Table 3 steps 4, 8 and the stop test):
@@ -282,13 +323,14 @@ __device__ __forceinline__ T absT(T x) { return x < T(0) ? -x : x; }
 //   aux: the node's own unscaled value (BA: new p, BB: s, SPMV_JAC: x);
 //   d:   dinv at the node (row mask and Jacobi scale).
 // Loading (raw) and staging are split so that the loads of a plane can be
-// issued one march step before their values are needed.
+// issued two march steps before their values are needed.  OWN loads add what
+// only the node's own output reads (BA: the shadow residual).
 template <typename T>
 struct Raw {
-    T d, e, x0, x1, x2;
+    T d, e, x0, x1, x2, t;
 };
 
-template <int OP, typename T, bool CEPS>
+template <int OP, typename T, bool CEPS, bool OWN>
 __device__ __forceinline__ void load_raw(const ZArgs<T> &a, size_t g, Raw<T> &w)
 {
     w.d = a.dinv[g];
@@ -302,6 +344,7 @@ __device__ __forceinline__ void load_raw(const ZArgs<T> &a, size_t g, Raw<T> &w)
         w.x0 = a.x[g];    // r
         w.x1 = a.y0[g];   // p (previous)
         w.x2 = a.y1[g];   // v (previous)
+        if constexpr (OWN) w.t = a.rt[g];
     } else {
         w.x0 = a.x[g];    // r
         w.x1 = a.y0[g];   // v
@@ -309,91 +352,80 @@ __device__ __forceinline__ void load_raw(const ZArgs<T> &a, size_t g, Raw<T> &w)
 }
 
 template <int OP, typename T>
-__device__ __forceinline__ void stage_raw(const ZArgs<T> &a, const Raw<T> &w, size_t g, T &val, T &aux,
-                                          double alpha, double omega, double beta, bool own)
+__device__ __forceinline__ void stage_raw(const Raw<T> &w, T &val, T &aux, double alpha, double omega,
+                                          double beta)
 {
     const T d = w.d;
-    if constexpr (OP == OP_SPMV) {
+    if constexpr (OP == OP_SPMV || OP == OP_RESID) {
         val = w.x0;
         aux = val;
     } else if constexpr (OP == OP_SPMV_JAC) {
         aux = w.x0;
         val = absT(d) * aux;
-    } else if constexpr (OP == OP_RESID) {
-        val = (a.lift && !(d < T(0))) ? T(0) : w.x0;
-        aux = val;
     } else if constexpr (OP == OP_BA) {
         // p = r + beta (p - omega v)   (Table 3 step 9)
         aux = w.x0 + (T)beta * (w.x1 - (T)omega * w.x2);
         val = absT(d) * aux;
-        if (own) a.out_aux[g] = aux;
     } else {  // OP_BB
         // s = r - alpha v   (Table 3 step 13)
         aux = w.x0 - (T)alpha * w.x1;
         val = absT(d) * aux;
-        if (own) a.out_aux[g] = aux;
     }
 }
 
-template <int OP, typename T, bool CEPS>
-__device__ __forceinline__ void stage_node(const ZArgs<T> &a, size_t g, T &val, T &aux, T &d, T &e,
-                                           double alpha, double omega, double beta, bool own)
+// The residual form stages Dirichlet rows of the lifted operand as zero.
+template <int OP, typename T>
+__device__ __forceinline__ T resid_val(const ZArgs<T> &a, const Raw<T> &w, T val)
 {
-    Raw<T> w;
-    load_raw<OP, T, CEPS>(a, g, w);
-    stage_raw<OP, T>(a, w, g, val, aux, alpha, omega, beta, own);
-    d = w.d;
-    if constexpr (!CEPS) e = w.e;
+    if constexpr (OP == OP_RESID) return (a.lift && !(w.d < T(0))) ? T(0) : val;
+    else return val;
+}
+
+
+// A staged value materialised in a register of its own at this point of the
+// step.  Without it the compiler keeps a staged value in the register its
+// load wrote, or sinks its arithmetic to the value's first use (after the
+// next loads were issued); either way the load register set stays live
+// across the refill, the refill needs other registers, and the loop latch
+// then waits for every load in flight to move them back.  The volatile asm
+// is kept in program order with the scheduling barrier that follows it.
+template <typename T>
+__device__ __forceinline__ T own_reg(T x)
+{
+    T y;
+    if constexpr (sizeof(T) == 8) asm volatile("v_mov_b64 %0, %1" : "=v"(y) : "v"(x));
+    else asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    return y;
 }
 
 // One workgroup's tile: logical tile index lb (strip, z-chunk) and partial
 // slot `slot` of the system described by a.
-template <int OP, typename T, bool CEPS, int NT, int PPT>
+//
+// Memory pipeline: the raw loads of plane k+1 and k+2 are in flight while
+// plane k is computed, in two register sets used alternately (the march is
+// unrolled by two so that each set keeps fixed registers).  Every load is
+// issued unconditionally with its plane clamped into the tile's range and
+// its node clamped into the strip, so the number of loads per step is fixed
+// and the wait before staging a plane covers only that plane's loads.
+template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE>
 __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, const int slot)
 {
-    // halo nodes per thread kept in registers; more than HMAX*NT halo nodes
-    // (nx > HMAX*NT/2) are handled by a slower loop
-    constexpr int HMAX = 2;
+    // halo nodes per thread kept in registers (both halo rows fit when
+    // 2 nx <= HMAX*NT); the WIDE form stages the rest in a slower
+    // synchronous loop, for planes wider than that
+    constexpr int HMAX = (NT >= 512) ? 1 : 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int NQ = (OP == OP_BB) ? 3 : 1;
-    double alpha = 0, omega = 0, beta = 0;
-    if constexpr (OP == OP_BA) {
-        // finish step C of the previous iteration (or start fresh)
-        Scalars *sc = a.sc;
+    constexpr int NQP = (OP == OP_BB) ? 1 : 2;   // quantities of the previous phase's partials
+    constexpr bool SCAL = (OP == OP_BA || OP == OP_BB);
+
+    Scalars *sc = a.sc;
+    int fresh = 0;
+    if constexpr (SCAL) {
         const int stop = sc->stop;
-        if (stop != ST_RUN && stop != ST_HALF) return;
-        if (!sc->fresh) {
-            double tot[2];
-            sum_partials<2>(tot, a.pin, a.Gin);
-            const FinC f = fin_c(sc, tot, a.parity);
-            if (lb == 0 && threadIdx.x == 0) fin_c_store(sc, f, a.parity);
-            if (f.stop != ST_RUN) return;
-            beta = f.beta;
-            omega = sc->omega[a.parity ^ 1];
-        }
-    } else if constexpr (OP == OP_BB) {
-        // finish step A: alpha_i = rho_i / (shadow . v)   (Table 3 step 12)
-        Scalars *sc = a.sc;
-        if (sc->stop != ST_RUN) return;
-        double tot[1];
-        sum_partials<1>(tot, a.pin, a.Gin);
-        const double rtv = tot[0];
-        int st = ST_RUN;
-        if (!finite(rtv)) st = ST_NONFINITE;
-        else if (rtv == 0.0) st = ST_RESTART;
-        else alpha = sc->rho[a.parity] / rtv;
-        if (lb == 0 && threadIdx.x == 0) {
-            sc->alpha[a.parity] = alpha;
-            sc->fresh = 0;
-            if (st != ST_RUN) sc->stop = st;
-        }
-        if (st != ST_RUN) return;
+        if (OP == OP_BA ? (stop != ST_RUN && stop != ST_HALF) : (stop != ST_RUN)) return;
+        if constexpr (OP == OP_BA) fresh = sc->fresh;
     }
-    // two LDS planes (double buffer) of staged values and coefficients
-    T *lval0 = reinterpret_cast<T *>(smem_raw);
-    T *leps0 = lval0 + a.lmax;
-    T *lval1 = leps0 + a.lmax;
-    T *leps1 = lval1 + a.lmax;
 
     const int strip = lb % a.nstrips, zc = lb / a.nstrips;
     const int nx = a.nx, ny = a.ny, nz = a.nz, P = a.P;
@@ -402,11 +434,14 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     const int lo = max(0, m0 - nx), hi = min(P, m0 + a.S + nx);
     const int mend = min(P, m0 + a.S);
     const int nhl = m0 - lo, nhalo = nhl + (hi - mend);
+    const int kown_hi = min(k1, nz - 1);   // own planes loaded: k0-1 .. k1 (within the grid)
+    const int khal_hi = k1 - 1;            // halo planes loaded: k0 .. k1-1
     const T ih2 = a.ih2;
+    const size_t Ps = (size_t)P;
 
     // own nodes and their LDS neighbour offsets (mirror ghosts at the faces;
     // rows on Dirichlet faces are masked, so the mirror only matters on
-    // Neumann faces)
+    // Neumann faces); nodes past the strip end stand in for node m0
     int om[PPT], ox[PPT], oxm[PPT], oxp[PPT], oym[PPT], oyp[PPT];
     bool ok[PPT];
 #pragma unroll
@@ -422,105 +457,173 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         oym[q] = ((j > 0) ? mm - nx : mm + nx) - lo;
         oyp[q] = ((j < ny - 1) ? mm + nx : mm - nx) - lo;
     }
-    // halo nodes of this thread (plane-local index)
+    // halo nodes of this thread (plane-local index; unused slots repeat lo)
     int hm[HMAX];
     bool hok[HMAX];
 #pragma unroll
     for (int u = 0; u < HMAX; ++u) {
         const int hI = threadIdx.x + u * NT;
         hok[u] = hI < nhalo;
-        hm[u] = (hI < nhl) ? lo + hI : mend + (hI - nhl);
+        hm[u] = !hok[u] ? lo : (hI < nhl) ? lo + hI : mend + (hI - nhl);
     }
+    auto gown = [&](int q, int k) { return (size_t)om[q] + Ps * min(k, kown_hi); };
+    auto ghal = [&](int u, int k) { return (size_t)hm[u] + Ps * min(k, khal_hi); };
+
+    // ---- prologue loads: the previous phase's partials, then planes k0-1,
+    //      k0 (own), k0 (halo), and the raw sets of planes k0+1 and k0+2
+    PartLoad<NQP> pl;
+    if constexpr (SCAL) load_partials<NQP>(pl, a.pin, a.Gin);
+    Raw<T> rp[PPT], rc[PPT], hc[HMAX];
+    Raw<T> rA[PPT], hA[HMAX], rB[PPT], hB[HMAX];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        load_raw<OP, T, CEPS, true>(a, gown(q, k0), rc[q]);
+        load_raw<OP, T, CEPS, false>(a, gown(q, max(k0 - 1, 0)), rp[q]);
+    }
+#pragma unroll
+    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k0), hc[u]);
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        load_raw<OP, T, CEPS, true>(a, gown(q, k0 + 1), rA[q]);
+        load_raw<OP, T, CEPS, true>(a, gown(q, k0 + 2), rB[q]);
+    }
+#pragma unroll
+    for (int u = 0; u < HMAX; ++u) {
+        load_raw<OP, T, CEPS, false>(a, ghal(u, k0 + 1), hA[u]);
+        load_raw<OP, T, CEPS, false>(a, ghal(u, k0 + 2), hB[u]);
+    }
+
+    // ---- scalars of this step (while the plane loads are in flight)
+    double alpha = 0, omega = 0, beta = 0;
+    if constexpr (OP == OP_BA) {
+        // finish step C of the previous iteration (or start fresh)
+        if (!fresh) {
+            double tot[2];
+            sum_loaded_partials<2>(tot, pl, a.pin, a.Gin);
+            const FinC f = fin_c(sc, tot, a.parity);
+            if (lb == 0 && threadIdx.x == 0) fin_c_store(sc, f, a.parity);
+            if (f.stop != ST_RUN) return;
+            beta = f.beta;
+            omega = sc->omega[a.parity ^ 1];
+        }
+    } else if constexpr (OP == OP_BB) {
+        // finish step A: alpha_i = rho_i / (shadow . v)   (Table 3 step 12)
+        double tot[1];
+        sum_loaded_partials<1>(tot, pl, a.pin, a.Gin);
+        const double rtv = tot[0];
+        int st = ST_RUN;
+        if (!finite(rtv)) st = ST_NONFINITE;
+        else if (rtv == 0.0) st = ST_RESTART;
+        else alpha = sc->rho[a.parity] / rtv;
+        if (lb == 0 && threadIdx.x == 0) {
+            sc->alpha[a.parity] = alpha;
+            sc->fresh = 0;
+            if (st != ST_RUN) sc->stop = st;
+        }
+        if (st != ST_RUN) return;
+    }
+
+    // two LDS planes (double buffer) of staged values and coefficients
+    T *lval0 = reinterpret_cast<T *>(smem_raw);
+    T *leps0 = lval0 + a.lmax;
+    T *lval1 = leps0 + a.lmax;
+    T *leps1 = lval1 + a.lmax;
 
     T vp[PPT], vc[PPT], vn[PPT];   // staged value, planes k-1, k, k+1
     T ep[PPT], ec[PPT], en[PPT];   // coefficient field
     T ac[PPT], an[PPT];            // aux, planes k, k+1
     T dc[PPT], dn[PPT];            // dinv, planes k, k+1
-    Raw<T> ro[PPT], rh[HMAX];      // raw loads of the plane after next
+    T tc[PPT], tn[PPT];            // shadow residual (BA), planes k, k+1
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 
-    const size_t Ps = (size_t)P;
-    // ---- prologue: plane k0 (own in registers, window in LDS buffer 0),
-    //      plane k0-1 own values, raw loads of plane k0+1
+    // ---- stage plane k0 (registers + LDS buffer 0) and plane k0-1 (registers)
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        vc[q] = ac[q] = dc[q] = ec[q] = T(0);
-        vp[q] = ep[q] = vn[q] = en[q] = an[q] = dn[q] = T(0);
+        stage_raw<OP, T>(rc[q], vc[q], ac[q], alpha, omega, beta);
+        vc[q] = resid_val<OP, T>(a, rc[q], vc[q]);
+        dc[q] = rc[q].d;
+        ec[q] = CEPS ? T(0) : rc[q].e;
+        tc[q] = (OP == OP_BA) ? rc[q].t : T(0);
+        T ax;
+        stage_raw<OP, T>(rp[q], vp[q], ax, alpha, omega, beta);
+        vp[q] = resid_val<OP, T>(a, rp[q], vp[q]);
+        ep[q] = CEPS ? T(0) : rp[q].e;
+        vn[q] = en[q] = an[q] = dn[q] = tn[q] = T(0);
         if (ok[q]) {
-            const size_t g = (size_t)om[q] + Ps * k0;
-            stage_node<OP, T, CEPS>(a, g, vc[q], ac[q], dc[q], ec[q], alpha, omega, beta, true);
-            if (k0 > 0) {
-                T ax, dx;
-                stage_node<OP, T, CEPS>(a, g - Ps, vp[q], ax, dx, ep[q], alpha, omega, beta, false);
-            }
+            if constexpr (OP == OP_BA || OP == OP_BB) a.out_aux[gown(q, k0)] = ac[q];
             lval0[ox[q]] = vc[q];
             if constexpr (!CEPS) leps0[ox[q]] = ec[q];
         }
     }
-    for (int hI = threadIdx.x; hI < nhalo; hI += NT) {
-        const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
-        T v, ax, dx, e;
-        stage_node<OP, T, CEPS>(a, (size_t)m + Ps * k0, v, ax, dx, e, alpha, omega, beta, false);
-        lval0[m - lo] = v;
-        if constexpr (!CEPS) leps0[m - lo] = e;
-    }
-    if (k0 + 1 < nz) {
 #pragma unroll
-        for (int q = 0; q < PPT; ++q)
-            if (ok[q]) load_raw<OP, T, CEPS>(a, (size_t)om[q] + Ps * (k0 + 1), ro[q]);
+    for (int u = 0; u < HMAX; ++u) {
+        if (hok[u]) {
+            T v, ax;
+            stage_raw<OP, T>(hc[u], v, ax, alpha, omega, beta);
+            lval0[hm[u] - lo] = resid_val<OP, T>(a, hc[u], v);
+            if constexpr (!CEPS) leps0[hm[u] - lo] = hc[u].e;
+        }
     }
-    if (k0 + 1 < k1) {
-#pragma unroll
-        for (int u = 0; u < HMAX; ++u)
-            if (hok[u]) load_raw<OP, T, CEPS>(a, (size_t)hm[u] + Ps * (k0 + 1), rh[u]);
+    if (WIDE && nhalo > HMAX * NT) {
+        for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
+            const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
+            Raw<T> w;
+            load_raw<OP, T, CEPS, false>(a, (size_t)m + Ps * k0, w);
+            T v, ax;
+            stage_raw<OP, T>(w, v, ax, alpha, omega, beta);
+            lval0[m - lo] = resid_val<OP, T>(a, w, v);
+            if constexpr (!CEPS) leps0[m - lo] = w.e;
+        }
     }
     __syncthreads();
 
     int cur = 0;
     T hv[HMAX], he[HMAX];
-    for (int k = k0; k < k1; ++k) {
+    // One march step: output plane k from LDS buffer `cur`; ro / rh hold the
+    // raw loads of plane k+1 and are refilled with plane k+3.  The march runs
+    // in pairs of steps; a step past the tile's last plane (odd plane count)
+    // computes but stores nothing.
+    auto step = [&](const int k, Raw<T>(&ro)[PPT], Raw<T>(&rh)[HMAX]) {
+        const bool live = k < k1;
         const bool has_up = (k + 1) < nz;
         const bool stage_next = (k + 1) < k1;
-        T *lv = cur ? lval1 : lval0;
-        T *le = cur ? leps1 : leps0;
-        // (1) stage plane k+1 from the raw loads issued one step ago
-        if (has_up) {
+        // (1) stage plane k+1 from the raw loads issued two steps ago
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                if (ok[q]) {
-                    const size_t g = (size_t)om[q] + Ps * (k + 1);
-                    stage_raw<OP, T>(a, ro[q], g, vn[q], an[q], alpha, omega, beta, stage_next);
-                    dn[q] = ro[q].d;
-                    if constexpr (!CEPS) en[q] = ro[q].e;
-                }
-            }
+        for (int q = 0; q < PPT; ++q) {
+            stage_raw<OP, T>(ro[q], vn[q], an[q], alpha, omega, beta);
+            vn[q] = own_reg(resid_val<OP, T>(a, ro[q], vn[q]));
+            an[q] = own_reg(an[q]);
+            dn[q] = own_reg(ro[q].d);
+            if constexpr (!CEPS) en[q] = own_reg(ro[q].e);
+            if constexpr (OP == OP_BA) tn[q] = own_reg(ro[q].t);
         }
+#pragma unroll
+        for (int u = 0; u < HMAX; ++u) {
+            T ax;
+            stage_raw<OP, T>(rh[u], hv[u], ax, alpha, omega, beta);
+            hv[u] = own_reg(resid_val<OP, T>(a, rh[u], hv[u]));
+            if constexpr (!CEPS) he[u] = own_reg(rh[u].e);
+        }
+        // (2) refill the set with plane k+3 (clamped: re-reads of a plane
+        //     already loaded near the tile's end hit the cache).  The
+        //     scheduling barrier keeps the refill after the reads of the set
+        //     above, so the loads can reuse its registers.
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, true>(a, gown(q, k + 3), ro[q]);
+#pragma unroll
+        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k + 3), rh[u]);
         if (stage_next) {
+            if constexpr (OP == OP_BA || OP == OP_BB) {
 #pragma unroll
-            for (int u = 0; u < HMAX; ++u) {
-                if (hok[u]) {
-                    T ax;
-                    stage_raw<OP, T>(a, rh[u], 0, hv[u], ax, alpha, omega, beta, false);
-                    if constexpr (!CEPS) he[u] = rh[u].e;
-                }
+                for (int q = 0; q < PPT; ++q)
+                    if (ok[q]) a.out_aux[gown(q, k + 1)] = an[q];
             }
-        }
-        // (2) issue the loads of plane k+2; they arrive during this step
-        if (k + 2 < nz && k + 2 <= k1) {
-#pragma unroll
-            for (int q = 0; q < PPT; ++q)
-                if (ok[q]) load_raw<OP, T, CEPS>(a, (size_t)om[q] + Ps * (k + 2), ro[q]);
-        }
-        if (k + 2 < k1) {
-#pragma unroll
-            for (int u = 0; u < HMAX; ++u)
-                if (hok[u]) load_raw<OP, T, CEPS>(a, (size_t)hm[u] + Ps * (k + 2), rh[u]);
         }
         // mirror ghosts across the z faces, written into the register planes
-        // (uniform branches, static indices: selecting between the arrays
-        // themselves would force them out of registers)
+        // (uniform branches, static indices)
         if (!has_up) {
 #pragma unroll
             for (int q = 0; q < PPT; ++q) { vn[q] = vp[q]; en[q] = ep[q]; }
@@ -529,10 +632,11 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
             for (int q = 0; q < PPT; ++q) { vp[q] = vn[q]; ep[q] = en[q]; }
         }
-        // (3) output for plane k
+        // (3) output for plane k (live: uniform)
+        const T *lv = cur ? lval1 : lval0;
+        const T *le = cur ? leps1 : leps0;
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-            if (!ok[q]) continue;
             const size_t g = (size_t)om[q] + Ps * k;
             const T vu = vn[q];
             const T vd = vp[q];
@@ -543,49 +647,55 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                 csum = T(6) * c;
             } else {
                 const T e = ec[q];
-                const T eu = en[q];
-                const T ed = ep[q];
                 const T c0 = face(e, le[oxm[q]], ih2), c1 = face(e, le[oxp[q]], ih2);
                 const T c2 = face(e, le[oym[q]], ih2), c3 = face(e, le[oyp[q]], ih2);
-                const T c4 = face(e, ed, ih2), c5 = face(e, eu, ih2);
+                const T c4 = face(e, ep[q], ih2), c5 = face(e, en[q], ih2);
                 sum = c0 * lv[oxm[q]] + c1 * lv[oxp[q]] + c2 * lv[oym[q]] + c3 * lv[oyp[q]] +
                       c4 * vd + c5 * vu;
                 csum = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
             }
             const bool freerow = dc[q] > T(0);
             if constexpr (OP == OP_SPMV) {
-                const double sg = a.sigma ? a.sigma[g] : a.sig_const;
-                const T D = csum + (T)sg;
-                a.out[g] = freerow ? D * vc[q] - sum : vc[q];
+                if (live && ok[q]) {
+                    const double sg = a.sigma ? a.sigma[g] : a.sig_const;
+                    const T D = csum + (T)sg;
+                    a.out[g] = freerow ? D * vc[q] - sum : vc[q];
+                }
             } else if constexpr (OP == OP_SPMV_JAC) {
-                a.out[g] = freerow ? ac[q] - sum : ac[q];
+                if (live && ok[q]) a.out[g] = freerow ? ac[q] - sum : ac[q];
             } else if constexpr (OP == OP_RESID) {
-                const double sg = a.sigma ? a.sigma[g] : a.sig_const;
-                const double D = (double)csum + sg;
-                const double Ax = D * (double)vc[q] - (double)sum;
-                const double r = freerow ? a.b[g] - Ax : 0.0;
-                a.out[g] = (T)r;
-                if (a.r32) a.r32[g] = (float)r;
-                if (a.rt64) a.rt64[g] = r;
-                if (a.rt32) a.rt32[g] = (float)r;
-                acc[0] += r * r;
+                if (live && ok[q]) {
+                    const double sg = a.sigma ? a.sigma[g] : a.sig_const;
+                    const double D = (double)csum + sg;
+                    const double Ax = D * (double)vc[q] - (double)sum;
+                    const double r = freerow ? a.b[g] - Ax : 0.0;
+                    a.out[g] = (T)r;
+                    if (a.r32) a.r32[g] = (float)r;
+                    if (a.rt64) a.rt64[g] = r;
+                    if (a.rt32) a.rt32[g] = (float)r;
+                    acc[0] += r * r;
+                }
             } else if constexpr (OP == OP_BA) {
                 // v = A M^-1 p  (Table 3 step 11), then shadow . v (step 12)
                 const T v = freerow ? ac[q] - sum : T(0);
-                a.out[g] = v;
-                acc[0] += (double)a.rt[g] * (double)v;
+                if (live && ok[q]) {
+                    a.out[g] = v;
+                    acc[0] += (double)tc[q] * (double)v;
+                }
             } else {
                 // t = A M^-1 s  (step 14); t.s, t.t (step 15), s.s
                 const T t = freerow ? ac[q] - sum : T(0);
                 const double s = (double)ac[q];
-                a.out[g] = t;
-                acc[0] += (double)t * s;
-                acc[1] += (double)t * (double)t;
-                acc[2] += s * s;
+                if (live && ok[q]) {
+                    a.out[g] = t;
+                    acc[0] += (double)t * s;
+                    acc[1] += (double)t * (double)t;
+                    acc[2] += s * s;
+                }
             }
         }
-        if (!stage_next) break;   // the next plane belongs to another workgroup
-        // (4) stage plane k+1 in the other LDS buffer
+        // (4) stage plane k+1 in the other LDS buffer (unused after the last
+        //     plane of the tile)
         T *nv = cur ? lval0 : lval1;
         T *ne = cur ? leps0 : leps1;
 #pragma unroll
@@ -602,12 +712,16 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                 if constexpr (!CEPS) ne[hm[u] - lo] = he[u];
             }
         }
-        for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
-            const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
-            T v, ax, dx, e;
-            stage_node<OP, T, CEPS>(a, (size_t)m + Ps * (k + 1), v, ax, dx, e, alpha, omega, beta, false);
-            nv[m - lo] = v;
-            if constexpr (!CEPS) ne[m - lo] = e;
+        if (WIDE && nhalo > HMAX * NT) {
+            for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
+                const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
+                Raw<T> w;
+                load_raw<OP, T, CEPS, false>(a, (size_t)m + Ps * (k + 1), w);
+                T v, ax;
+                stage_raw<OP, T>(w, v, ax, alpha, omega, beta);
+                nv[m - lo] = resid_val<OP, T>(a, w, v);
+                if constexpr (!CEPS) ne[m - lo] = w.e;
+            }
         }
         // one barrier per plane: the buffer written next step was last read
         // before this barrier
@@ -618,8 +732,12 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         for (int q = 0; q < PPT; ++q) {
             vp[q] = vc[q]; vc[q] = vn[q];
             ep[q] = ec[q]; ec[q] = en[q];
-            ac[q] = an[q]; dc[q] = dn[q];
+            ac[q] = an[q]; dc[q] = dn[q]; tc[q] = tn[q];
         }
+    };
+    for (int k = k0; k < k1; k += 2) {
+        step(k, rA, hA);
+        step(k + 1, rB, hB);
     }
 
     if constexpr (OP == OP_RESID || OP == OP_BA || OP == OP_BB) {
@@ -628,10 +746,10 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     }
 }
 
-template <int OP, typename T, bool CEPS, int NT, int PPT>
+template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE>
 __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
 {
-    zmarch_tile<OP, T, CEPS, NT, PPT>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
+    zmarch_tile<OP, T, CEPS, NT, PPT, WIDE>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
 }
 
 // System owning global block b: start[s] <= b < start[s+1].
@@ -647,14 +765,14 @@ __device__ __forceinline__ int batch_system(const int *start, int nsys, int b)
 
 // Batched form: one launch covers the tiles of nsys systems (grids of any
 // size); each system keeps its own scalars, partials and status.
-template <int OP, typename T, bool CEPS, int NT, int PPT>
+template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE>
 __global__ __launch_bounds__(NT) void k_zmarch_batch(const ZArgs<T> *__restrict__ args,
                                                      const int *__restrict__ start, int nsys)
 {
     const int s = batch_system(start, nsys, blockIdx.x);
     const int lb = blockIdx.x - start[s];
     const ZArgs<T> a = args[s];   // private copy: stores cannot alias it
-    zmarch_tile<OP, T, CEPS, NT, PPT>(a, lb, lb);
+    zmarch_tile<OP, T, CEPS, NT, PPT, WIDE>(a, lb, lb);
 }
 
 // ------------------------------------- BiCGSTAB step C (pointwise, fused)
@@ -674,16 +792,51 @@ struct CArgs {
     int parity;
 };
 
+// Elements per thread per round of step C (a workgroup covers NT*C_UNROLL
+// consecutive elements per round).
+constexpr int C_UNROLL = 4;
+
 template <typename T, int NT>
 __device__ __forceinline__ void bicg_c_block(const CArgs<T> &a, const int b)
 {
+    constexpr int U = C_UNROLL;
     Scalars *sc = a.sc;
     const int stop = sc->stop;
     if (stop != ST_RUN && stop != ST_HALF) return;
+    const size_t N = a.N;
+    T *__restrict__ x = a.x;
+    T *__restrict__ r = a.r;
+    const T *__restrict__ p = a.p;
+    const T *__restrict__ s = a.s;
+    const T *__restrict__ t = a.t;
+    const T *__restrict__ dinv = a.dinv;
+    const T *__restrict__ rt = a.rt;
+    const size_t span = (size_t)NT * U;
+    const size_t stride = (size_t)a.G * span;
+    const size_t rounds = (N + stride - 1) / stride;
+    // the previous phase's partials and the first round's operands are
+    // loaded before the scalar work below (indices past N read element N-1)
+    PartLoad<3> pl;
+    load_partials<3>(pl, a.pin, a.Gin);
+    T vd[U], vs[U], vt[U], vp[U], vx[U], vr[U];
+    auto load_round = [&](size_t r0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = r0 + (size_t)b * span + (size_t)u * NT + threadIdx.x;
+            const size_t ic = i < N ? i : N - 1;
+            vd[u] = dinv[ic];
+            vs[u] = s[ic];
+            vt[u] = t[ic];
+            vp[u] = p[ic];
+            vx[u] = x[ic];
+            vr[u] = rt[ic];
+        }
+    };
+    load_round(0);
     // finish step B: omega_i = t.s / t.t (Table 3 step 15), or the half-step
     // exit when ||s|| already meets the tolerance
     double tot[3];
-    sum_partials<3>(tot, a.pin, a.Gin);
+    sum_loaded_partials<3>(tot, pl, a.pin, a.Gin);
     const double ts = tot[0], tt = tot[1], ss = tot[2];
     int st = ST_RUN;
     double om = 0.0;
@@ -698,23 +851,22 @@ __device__ __forceinline__ void bicg_c_block(const CArgs<T> &a, const int b)
     if (st == ST_NONFINITE || st == ST_RESTART) return;
     const T alpha = (T)sc->alpha[a.parity], omega = (T)om;
     double acc[2] = {0.0, 0.0};
-    const size_t N = a.N;
-    T *__restrict__ x = a.x;
-    T *__restrict__ r = a.r;
-    const T *__restrict__ p = a.p;
-    const T *__restrict__ s = a.s;
-    const T *__restrict__ t = a.t;
-    const T *__restrict__ dinv = a.dinv;
-    const T *__restrict__ rt = a.rt;
-    const size_t stride = (size_t)a.G * NT;
-    for (size_t i = (size_t)b * NT + threadIdx.x; i < N; i += stride) {
-        const T d = absT(dinv[i]);
-        const T si = s[i], ti = t[i];
-        x[i] = x[i] + alpha * (d * p[i]) + omega * (d * si);   // step 16
-        const T ri = si - omega * ti;                           // step 17
-        r[i] = ri;
-        acc[0] += (double)rt[i] * (double)ri;
-        acc[1] += (double)ri * (double)ri;
+    for (size_t rd = 0; rd < rounds; ++rd) {
+        const size_t r0 = rd * stride;
+        if (rd > 0) load_round(r0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = r0 + (size_t)b * span + (size_t)u * NT + threadIdx.x;
+            const T d = absT(vd[u]);
+            const T xi = vx[u] + alpha * (d * vp[u]) + omega * (d * vs[u]);   // step 16
+            const T ri = vs[u] - omega * vt[u];                                // step 17
+            if (i < N) {
+                x[i] = xi;
+                r[i] = ri;
+                acc[0] += (double)vr[u] * (double)ri;
+                acc[1] += (double)ri * (double)ri;
+            }
+        }
     }
     block_reduce<2, NT>(acc);
     store_partials<2>(acc, a.partials, b);
