@@ -8,10 +8,12 @@ every linear solve Jacobi-BiCGSTAB to relative residual 1e-10.  All inputs are
 resident in device memory before the timed region starts.
 
 The JSON line also carries:
-  roofline      the BiCGSTAB step-A stencil kernel (p update fused with
-                v = A M^-1 p), timed with HIP events on the library's stream
-                during the timed steps; algorithmic bytes = 8 vectors of N
-                doubles per launch;
+  roofline      the BiCGSTAB step-A stencil kernel (the previous iteration's
+                x, r update, the p update and v = A M^-1 p in one pass),
+                timed with HIP events on the library's stream during the
+                timed steps; algorithmic bytes = 12 vectors of N doubles per
+                launch (reads s, t, x, p, v, shadow, dinv, eps; writes x, r,
+                p, v);
   cpu_baseline  the serial FP64 oracle on a bounded sample of the same solve
                 (its first outer iterations), scaled to a whole solve by the
                 number of BiCGSTAB iterations the solve needs;
@@ -30,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "time to 1e-10 rel residual & HBM GB/s: FP64 vs mixed-precision vs batched"
+STEP_A_VECTORS = 12.0   # N-vectors step A reads and writes
 
 
 def log(*a):
@@ -91,7 +94,7 @@ def forms_linear(pf, torch, inputs, timing_sample):
         t = sorted(times)[1]
         rel = pf.pf_residual(g, None, b, x)
         xs[name] = x.cpu().numpy()
-        bpl = 8.0 * prob.N * (8 if prec == pf.PF_FP64 else 4)
+        bpl = STEP_A_VECTORS * prob.N * (8 if prec == pf.PF_FP64 else 4)
         out[name] = dict(seconds=t, iters=info["iters"], refinements=info["refinements"],
                          rel_res=rel, iters_per_s=info["iters"] / t,
                          step_a_mean_us=tm["mean_ms"] * 1e3,
@@ -295,7 +298,7 @@ def main():
     tm = pf.pf_timing_read(pf.PF_FP64)
     pf.pf_timing_enable(0, 1)
     sec_per_step = elapsed / args.steps
-    bytes_per_launch = 8.0 * prob.N * 8
+    bytes_per_launch = STEP_A_VECTORS * prob.N * 8
     achieved = bytes_per_launch / (tm["mean_ms"] * 1e-3) / 1e9 if tm["launches"] else 0.0
     traffic = traffic_from_profiles(prob.name)
     lin_iters = infos[-1]["total_lin_iters"]
@@ -323,7 +326,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "BiCGSTAB step A (fused p update + v = A M^-1 p), FP64",
+            "kernel": "BiCGSTAB step A (previous x, r update + p update + v = A M^-1 p + 2 dots), FP64",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",

@@ -11,7 +11,8 @@
  *   - Grid: nx*ny*nz nodes, uniform spacing h, x-fastest layout
  *     idx = i + nx*(j + ny*k).  Neighbour naming follows the seven-diagonal
  *     description of Sec. 4 (east i+1, west i-1, south i-nx, north i+nx,
- *     down i-nx*ny, up i+nx*ny).  nx, ny, nz >= 3.
+ *     down i-nx*ny, up i+nx*ny).  nx, ny, nz >= 3 and N = nx*ny*nz < 2^29
+ *     (byte offsets of FP64 vectors fit 32 bits).
  *   - Faces are numbered -x,+x,-y,+y,-z,+z.  Dirichlet faces hold a value;
  *     Neumann faces (zero normal derivative, Eq. (4)) use a node-centred
  *     mirror ghost.  A node on a Dirichlet face is Dirichlet even when it also
@@ -224,10 +225,12 @@ pf_status pf_timing_read(int32_t precision, int64_t *launches, double *mean_ms, 
 const char *pf_last_error(void);
 
 /* Launch-shape override for tests and tuning: points per workgroup strip,
- * z-planes per workgroup, threads per workgroup.  0 = autotuned/default.
- * Applies to grids created afterwards.  Returns PF_ERR_ARG for unsupported
- * shapes. */
-pf_status pf_set_launch(int32_t strip, int32_t zdepth, int32_t threads);
+ * z-planes per workgroup, threads per workgroup, and planes of loads kept in
+ * flight ahead of the plane being computed (pipeline 1 or 2).  0 =
+ * autotuned/default for each.  Applies to grids created afterwards (and
+ * turns the autotuner off while any override is set).  Returns PF_ERR_ARG
+ * for unsupported shapes. */
+pf_status pf_set_launch(int32_t strip, int32_t zdepth, int32_t threads, int32_t pipeline);
 
 #ifdef __cplusplus
 }

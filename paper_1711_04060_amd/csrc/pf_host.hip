@@ -54,7 +54,7 @@ constexpr int NT = 256;          // threads per workgroup of every kernel
 constexpr int PW_MAX_G = 1024;   // workgroups of the pointwise kernels
 
 // launch override (pf_set_launch): threads, points per thread, z-planes
-int g_nt_override = 0, g_ppt_override = 0, g_kz_override = 0;
+int g_nt_override = 0, g_ppt_override = 0, g_kz_override = 0, g_depth_override = 0;
 
 // step-A kernel timing (pf_timing_enable / pf_timing_read)
 struct Timing {
@@ -74,6 +74,7 @@ constexpr size_t LDS_MAX = 152 * 1024;   // dynamic LDS per workgroup (gfx950 ha
 struct ZCfg {
     int NTZ = 256, PPT = 2, S = 512, KZ = 8, nstrips = 1, nzc = 1, G = 1, lmax = 0;
     bool wide = false;   // halo rows exceed the registers' halo slots (WIDE kernel form)
+    int depth = 1;       // planes of loads in flight ahead of the plane computed
     size_t lds = 0;
 };
 
@@ -81,7 +82,11 @@ struct ZCfg {
 // fit in registers when 2 nx <= halo_slots(NT) * NT).
 constexpr int halo_slots(int ntz) { return ntz >= 512 ? 1 : 2; }
 
-ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz)
+// Load pipeline depth when none is given: two planes where the two register
+// sets still leave four waves per SIMD (FP32, one node per thread).
+int default_depth(size_t elem, int ppt) { return (elem == 4 && ppt == 1) ? 2 : 1; }
+
+ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz, int depth = 0)
 {
     ZCfg c;
     const int P = nx * ny;
@@ -95,6 +100,7 @@ ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz)
     c.lmax = std::min(P, c.S + 2 * nx);
     c.lds = 4 * (size_t)c.lmax * elem;   // two planes of (value, coefficient)
     c.wide = 2 * nx > halo_slots(ntz) * ntz;
+    c.depth = c.wide ? 1 : (depth ? depth : (g_depth_override ? g_depth_override : default_depth(elem, ppt)));
     return c;
 }
 
@@ -119,12 +125,6 @@ ZCfg default_cfg(int nx, int ny, int nz, size_t elem)
 }
 
 int pw_blocks(size_t N) { return (int)std::min<size_t>(PW_MAX_G, (N + NT - 1) / NT); }
-// workgroups of BiCGSTAB step C (each covers NT * C_UNROLL elements per round)
-int c_blocks(size_t N)
-{
-    const size_t span = (size_t)NT * pfk::C_UNROLL;
-    return (int)std::max<size_t>(1, std::min<size_t>(PW_MAX_G, (N + span - 1) / span));
-}
 
 template <typename T>
 struct Work {
@@ -163,7 +163,8 @@ struct pf_grid {
     bool have64 = false, have32 = false;
     Scalars *sc = nullptr, *hsc = nullptr;
     double *partials = nullptr;                                // standalone reductions
-    double *partA = nullptr, *partB = nullptr, *partC = nullptr;   // BiCGSTAB steps A, B, C
+    double *partA = nullptr, *partB = nullptr;   // BiCGSTAB steps A, B
+    double *sink = nullptr;            // target of the stencil kernels' masked stores
     std::map<long, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> tev;       // timing events (2 per iteration of a chunk)
     bool last_timed = false;
@@ -249,10 +250,10 @@ pf_status ensure_work(pf_grid *g)
 
 // --------------------------------------------------------------- launches
 
-template <int OP, typename T, bool CEPS, int NTZ, int PPT, bool WIDE = false>
+template <int OP, typename T, bool CEPS, int NTZ, int PPT, bool WIDE = false, int DEPTH = 1>
 hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
 {
-    auto kern = pfk::k_zmarch<OP, T, CEPS, NTZ, PPT, WIDE>;
+    auto kern = pfk::k_zmarch<OP, T, CEPS, NTZ, PPT, WIDE, DEPTH>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;   // per instantiation
         if (c.lds > granted) {
@@ -273,8 +274,21 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
         if (c.NTZ == 1024 && c.PPT == 1) return launch_zk<OP, T, CEPS, 1024, 1, true>(c, a, s);
         return hipErrorInvalidValue;
     }
-    const int key = c.NTZ * 10 + c.PPT;
-    switch (key) {
+    // the BiCGSTAB steps and the Jacobi-scaled product come in both pipeline
+    // depths; the residual and plain products (a few launches per solve) in one
+    constexpr bool PIPE = (OP == pfk::OP_BA || OP == pfk::OP_BB || OP == pfk::OP_SPMV_JAC);
+    if (PIPE && c.depth == 2) {
+        switch (c.NTZ * 10 + c.PPT) {
+        case 2561: return launch_zk<OP, T, CEPS, 256, 1, false, 2>(c, a, s);
+        case 2562: return launch_zk<OP, T, CEPS, 256, 2, false, 2>(c, a, s);
+        case 5121: return launch_zk<OP, T, CEPS, 512, 1, false, 2>(c, a, s);
+        case 5122: return launch_zk<OP, T, CEPS, 512, 2, false, 2>(c, a, s);
+        case 10241: return launch_zk<OP, T, CEPS, 1024, 1, false, 2>(c, a, s);
+        case 10242: return launch_zk<OP, T, CEPS, 1024, 2, false, 2>(c, a, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (c.NTZ * 10 + c.PPT) {
     case 2561: return launch_zk<OP, T, CEPS, 256, 1>(c, a, s);
     case 2562: return launch_zk<OP, T, CEPS, 256, 2>(c, a, s);
     case 5121: return launch_zk<OP, T, CEPS, 512, 1>(c, a, s);
@@ -285,10 +299,10 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
     }
 }
 
-template <int OP, typename T, bool CEPS, bool WIDE>
+template <int OP, typename T, bool CEPS, bool WIDE, int DEPTH>
 hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
 {
-    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, 512, 1, WIDE>;
+    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, 512, 1, WIDE, DEPTH>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;
         if (c.lds > granted) {
@@ -306,8 +320,9 @@ hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *s
 template <int OP, typename T, bool CEPS>
 hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
 {
-    return c.wide ? launch_batch_k<OP, T, CEPS, true>(c, args, start, n, s)
-                  : launch_batch_k<OP, T, CEPS, false>(c, args, start, n, s);
+    if (c.wide) return launch_batch_k<OP, T, CEPS, true, 1>(c, args, start, n, s);
+    return c.depth == 2 ? launch_batch_k<OP, T, CEPS, false, 2>(c, args, start, n, s)
+                        : launch_batch_k<OP, T, CEPS, false, 1>(c, args, start, n, s);
 }
 
 template <typename T>
@@ -352,6 +367,7 @@ pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const T *dinv, const ZCfg 
     a.dval = g->dval;
     a.sc = g->sc;
     a.partials = g->partials;
+    a.sink = reinterpret_cast<T *>(g->sink);
     return a;
 }
 
@@ -435,21 +451,25 @@ pf_status write_scalars(pf_grid *g)
     return PF_OK;
 }
 
-// Arguments of the three kernels of one BiCGSTAB iteration.  parity selects
-// the p/v ping-pong buffers.
+// Arguments of the two kernels of one BiCGSTAB iteration.  parity selects
+// the p/v ping-pong buffers: step A reads p[parity], v[parity] and writes
+// p[parity^1], v[parity^1].
 template <typename T>
 pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c)
 {
     pfk::ZArgs<T> a = zbase_cfg<T>(g, op, dinv, c);
-    a.x = w.r;
+    a.x = w.s;
     a.y0 = w.p[parity];
     a.y1 = w.v[parity];
+    a.y2 = w.t;
     a.rt = w.rt;
+    a.xio = w.x;
     a.out = w.v[parity ^ 1];
     a.out_aux = w.p[parity ^ 1];
+    a.out_r = w.r;
     a.partials = g->partA;
-    a.pin = g->partC;
-    a.Gin = c_blocks(g->N);
+    a.pin = g->partB;
+    a.Gin = c.G;
     a.parity = parity;
     return a;
 }
@@ -460,6 +480,7 @@ pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
     pfk::ZArgs<T> b = zbase_cfg<T>(g, op, dinv, c);
     b.x = w.r;
     b.y0 = w.v[parity ^ 1];
+    b.rt = w.rt;
     b.out = w.t;
     b.out_aux = w.s;
     b.partials = g->partB;
@@ -469,29 +490,8 @@ pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
     return b;
 }
 
-template <typename T>
-pfk::CArgs<T> args_c(pf_grid *g, const T *dinv, Work<T> &w, int parity, const ZCfg &cz)
-{
-    pfk::CArgs<T> c{};
-    c.N = g->N;
-    c.x = w.x;
-    c.r = w.r;
-    c.p = w.p[parity ^ 1];
-    c.s = w.s;
-    c.t = w.t;
-    c.dinv = dinv;
-    c.rt = w.rt;
-    c.sc = g->sc;
-    c.partials = g->partC;
-    c.pin = g->partB;
-    c.Gin = cz.G;
-    c.G = c_blocks(g->N);
-    c.parity = parity;
-    return c;
-}
-
-// One BiCGSTAB iteration: stencil step A (p, v), stencil step B (s, t),
-// pointwise step C (x, r).
+// One BiCGSTAB iteration: stencil step A (x, r of the previous iteration;
+// p, v), stencil step B (s, t).
 template <typename T>
 pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity,
                     hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
@@ -501,18 +501,6 @@ pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
     PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, dinv, w, parity, cfg))));
     if (e1) HIPCHK(hipEventRecord(e1, g->stream));
     PFCHK((zlaunch<pfk::OP_BB, T>(g, op, args_b<T>(g, op, dinv, w, parity, cfg))));
-    const pfk::CArgs<T> c = args_c<T>(g, dinv, w, parity, cfg);
-    hipLaunchKernelGGL((pfk::k_bicg_c<T, NT>), dim3(c.G), dim3(NT), 0, g->stream, c);
-    HIPCHK(hipGetLastError());
-    return PF_OK;
-}
-
-// Close a chunk: finish step C of its last iteration for the host to read.
-pf_status chunk_end(pf_grid *g)
-{
-    pfk::FinArgs f{g->sc, g->partC, c_blocks(g->N)};
-    hipLaunchKernelGGL((pfk::k_finalize<pfk::FIN_C>), dim3(1), dim3(256), 0, g->stream, f);
-    HIPCHK(hipGetLastError());
     return PF_OK;
 }
 
@@ -533,7 +521,7 @@ pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
     if (timed) {
         // sampled chunk: direct launches with HIP events around step A
         for (int i = 0; i < m; ++i) PFCHK(iteration<T>(g, op, dinv, w, i & 1, g->tev[2 * i], g->tev[2 * i + 1]));
-        return chunk_end(g);
+        return PF_OK;
     }
     const long key = (long)m * 16 + (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0);
     auto it = g->graphs.find(key);
@@ -542,7 +530,6 @@ pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
         HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
         pf_status st = PF_OK;
         for (int i = 0; i < m && st == PF_OK; ++i) st = iteration<T>(g, op, dinv, w, i & 1);
-        if (st == PF_OK) st = chunk_end(g);
         hipError_t e = hipStreamEndCapture(g->stream, &graph);
         if (st != PF_OK) return st;
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -565,11 +552,11 @@ bool tuning_enabled()
 {
     const char *e = getenv("PF_TUNE");
     if (e && e[0] == '0') return false;
-    return !g_nt_override && !g_ppt_override && !g_kz_override;
+    return !g_nt_override && !g_ppt_override && !g_kz_override && !g_depth_override;
 }
 
-// Time the BiCGSTAB step-A kernel (the kernel with the most traffic per
-// iteration) for each candidate shape on this grid and keep the fastest.
+// Time one BiCGSTAB iteration (steps A and B, which share the shape) for each
+// candidate shape on this grid and keep the fastest.
 // Runs once per grid shape and precision; the grid's workspace holds
 // synthetic vectors meanwhile (every solve reinitialises it).
 template <typename T>
@@ -590,6 +577,8 @@ pf_status tune(pf_grid *g)
     if constexpr (sizeof(T) == 8) dinv = g->dinv64;
     else dinv = g->dinv32;
     PFCHK(fill<T>(g, w.r, T(1), g->N));
+    PFCHK(fill<T>(g, w.s, T(1), g->N));
+    PFCHK(fill<T>(g, w.t, T(0), g->N));
     PFCHK(fill<T>(g, w.rt, T(1), g->N));
     PFCHK(fill<T>(g, w.p[0], T(0), g->N));
     PFCHK(fill<T>(g, w.v[0], T(0), g->N));
@@ -609,15 +598,19 @@ pf_status tune(pf_grid *g)
     pf_status st = PF_OK;
     for (auto &sh : shapes) {
         for (int kz : {2, 4, 8, 16, 32}) {
-            ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), sh[0], sh[1], kz);
+          for (int depth : {1, 2}) {
+            ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), sh[0], sh[1], kz, depth);
             if (c.lds > LDS_MAX || c.G > g->Gmax || kz > g->nz || (c.wide && (c.NTZ != 1024 || c.PPT != 1))) continue;
+            if (c.depth != depth) continue;
             cfg_ref<T>(g) = c;
             pfk::ZArgs<T> a = args_a<T>(g, op, dinv, w, 0, c);
+            a.xio = w.r;   // keep the caller's iterate: the timed launches update r in its place
+            const pfk::ZArgs<T> b = args_b<T>(g, op, dinv, w, 0, c);
             float tot = 0;
             for (int rep = 0; rep < 4 && st == PF_OK; ++rep) {
                 if ((st = write_scalars(g)) != PF_OK) break;
                 if (hipEventRecord(e0, g->stream) != hipSuccess) { st = fail(PF_ERR_DEVICE, "event record failed"); break; }
-                if (zlaunch<pfk::OP_BA, T>(g, op, a) != PF_OK) {
+                if (zlaunch<pfk::OP_BA, T>(g, op, a) != PF_OK || zlaunch<pfk::OP_BB, T>(g, op, b) != PF_OK) {
                     // shape not launchable here: skip it
                     (void)hipGetLastError();
                     g_err.clear();
@@ -634,6 +627,8 @@ pf_status tune(pf_grid *g)
             }
             if (st != PF_OK) break;
             if (tot < best_ms) { best_ms = tot; best = c; }
+          }
+          if (st != PF_OK) break;
         }
         if (st != PF_OK) break;
     }
@@ -643,8 +638,8 @@ pf_status tune(pf_grid *g)
     if (st != PF_OK) return st;
     g_tuned[key] = best;
     if (getenv("PF_LOG"))
-        fprintf(stderr, "[pf] tuned %dx%dx%d %s: threads %d, strip %d, z-planes %d, step A %.1f us\n", g->nx, g->ny,
-                g->nz, sizeof(T) == 8 ? "fp64" : "fp32", best.NTZ, best.S, best.KZ, best_ms / 3 * 1e3);
+        fprintf(stderr, "[pf] tuned %dx%dx%d %s: threads %d, strip %d, z-planes %d, depth %d, iteration %.1f us\n", g->nx, g->ny,
+                g->nz, sizeof(T) == 8 ? "fp64" : "fp32", best.NTZ, best.S, best.KZ, best.depth, best_ms / 3 * 1e3);
     return PF_OK;
 }
 
@@ -656,12 +651,15 @@ int chunk_len(const pf_grid *g, const pf_lin_opts *o)
 }
 
 // Reset the Krylov state from a residual already in w.r / w.rt with
-// ||r||^2 = rr.  Keeps the cumulative iteration count.  Asynchronous.
+// ||r||^2 = rr.  Keeps the cumulative iteration count.  Asynchronous.  The
+// first step A reads r from s (r = s - omega t with t = 0) and p = v = 0.
 template <typename T>
 pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter, int maxit)
 {
     PFCHK(fill<T>(g, w.p[0], T(0), g->N));
     PFCHK(fill<T>(g, w.v[0], T(0), g->N));
+    PFCHK(fill<T>(g, w.t, T(0), g->N));
+    HIPCHK(hipMemcpyAsync(w.s, w.r, g->N * sizeof(T), hipMemcpyDeviceToDevice, g->stream));
     Scalars &h = *g->hsc;
     h = Scalars{};
     h.rho[0] = rr;            // shadow = r, so rho_0 = ||r||^2
@@ -674,6 +672,7 @@ pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter,
     h.iter_done = iter;
     h.maxit = maxit;
     h.stop = pfk::ST_RUN;
+    h.stop_a = pfk::ST_RUN;
     h.fresh = 1;
     return write_scalars(g);
 }
@@ -714,7 +713,7 @@ pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
                 HIPCHK(hipEventElapsedTime(&ms, g->tev[2 * i], g->tev[2 * i + 1]));
                 g_timing.ms[pi] += ms;
                 g_timing.launches[pi] += 1;
-                g_timing.bytes[pi] += 8.0 * (double)g->N * sizeof(T);
+                g_timing.bytes[pi] += 12.0 * (double)g->N * sizeof(T);
             }
         }
         if (g->hsc->stop != pfk::ST_RUN) {
@@ -929,13 +928,11 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     const int n = (int)act.size();
     const bool psi = act[0]->op.psi;
     std::vector<pfk::ZArgs<T>> za[2], zb[2];
-    std::vector<pfk::CArgs<T>> zc[2];
-    std::vector<int> zstart(n + 1, 0), cstart(n + 1, 0);
+    std::vector<int> zstart(n + 1, 0);
     std::vector<const Scalars *> scp(n);
-    std::vector<pfk::FinArgs> fc(n);
     size_t lds = 0;
     bool wide = false;
-    for (int par = 0; par < 2; ++par) { za[par].resize(n); zb[par].resize(n); zc[par].resize(n); }
+    for (int par = 0; par < 2; ++par) { za[par].resize(n); zb[par].resize(n); }
     for (int i = 0; i < n; ++i) {
         LinSolve &L = *act[i];
         pf_grid *g = L.g;
@@ -947,22 +944,18 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         for (int par = 0; par < 2; ++par) {
             za[par][i] = args_a<T>(g, L.op, dinv, *w, par, c);
             zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, c);
-            zc[par][i] = args_c<T>(g, dinv, *w, par, c);
         }
         zstart[i + 1] = zstart[i] + c.G;
-        cstart[i + 1] = cstart[i] + zc[0][i].G;
-        fc[i] = pfk::FinArgs{g->sc, g->partC, zc[0][i].G};
         lds = std::max(lds, c.lds);
         wide = wide || c.wide;
         scp[i] = g->sc;
     }
     if (lds > LDS_MAX) return fail(PF_ERR_ARG, "batch member too wide for the LDS strip");
     // device tables
-    const size_t szZ = sizeof(pfk::ZArgs<T>) * n, szC = sizeof(pfk::CArgs<T>) * n;
+    const size_t szZ = sizeof(pfk::ZArgs<T>) * n;
     const size_t szI = sizeof(int) * (n + 1), szP = sizeof(void *) * n, szS = sizeof(Scalars) * n;
-    const size_t szF = sizeof(pfk::FinArgs) * n;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t need = 4 * al(szZ) + 2 * al(szC) + 2 * al(szI) + al(szP) + al(szS) + al(szF);
+    const size_t need = 4 * al(szZ) + al(szI) + al(szP) + al(szS);
     if (need > g_batch.bytes) {
         if (g_batch.dev) (void)hipFree(g_batch.dev);
         g_batch.dev = nullptr;
@@ -983,26 +976,21 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     auto take = [&](size_t sz) { char *p = base + off; off += al(sz); return p; };
     pfk::ZArgs<T> *dA[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
     pfk::ZArgs<T> *dB[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
-    pfk::CArgs<T> *dC[2] = {(pfk::CArgs<T> *)take(szC), (pfk::CArgs<T> *)take(szC)};
-    int *dzs = (int *)take(szI), *dcs = (int *)take(szI);
+    int *dzs = (int *)take(szI);
     const Scalars **dscp = (const Scalars **)take(szP);
     Scalars *dgather = (Scalars *)take(szS);
-    pfk::FinArgs *dfc = (pfk::FinArgs *)take(szF);
     for (int par = 0; par < 2; ++par) {
         HIPCHK(hipMemcpyAsync(dA[par], za[par].data(), szZ, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(dB[par], zb[par].data(), szZ, hipMemcpyHostToDevice, stream));
-        HIPCHK(hipMemcpyAsync(dC[par], zc[par].data(), szC, hipMemcpyHostToDevice, stream));
     }
     HIPCHK(hipMemcpyAsync(dzs, zstart.data(), szI, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(dcs, cstart.data(), szI, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dscp, scp.data(), szP, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(dfc, fc.data(), szF, hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
 
-    const int GZ = zstart[n], GC = cstart[n];
+    const int GZ = zstart[n];
     auto launch_iter = [&](int par) -> pf_status {
         ZCfg c{};
-        c.NTZ = 512; c.PPT = 1; c.G = GZ; c.lds = lds; c.wide = wide;
+        c.NTZ = 512; c.PPT = 1; c.G = GZ; c.lds = lds; c.wide = wide; c.depth = default_depth(sizeof(T), 1);
         hipError_t e;
         if (psi) e = launch_batch<pfk::OP_BA, T, true>(c, dA[par], dzs, n, stream);
         else e = launch_batch<pfk::OP_BA, T, false>(c, dA[par], dzs, n, stream);
@@ -1010,16 +998,12 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         if (psi) e = launch_batch<pfk::OP_BB, T, true>(c, dB[par], dzs, n, stream);
         else e = launch_batch<pfk::OP_BB, T, false>(c, dB[par], dzs, n, stream);
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
-        hipLaunchKernelGGL((pfk::k_bicg_c_batch<T, NT>), dim3(GC), dim3(NT), 0, stream,
-                           (const pfk::CArgs<T> *)dC[par], (const int *)dcs, n);
-        HIPCHK(hipGetLastError());
         return PF_OK;
     };
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
     pf_status st = PF_OK;
     for (int i = 0; i < m && st == PF_OK; ++i) st = launch_iter(i & 1);
-    hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_C>), dim3(n), dim3(256), 0, stream, (const pfk::FinArgs *)dfc);
     hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
     hipError_t e = hipStreamEndCapture(stream, &graph);
     if (st != PF_OK) return st;
@@ -1158,8 +1142,9 @@ pf_status pf_timing_read(int32_t precision, int64_t *launches, double *mean_ms, 
     return PF_OK;
 }
 
-pf_status pf_set_launch(int32_t strip, int32_t zdepth, int32_t threads)
+pf_status pf_set_launch(int32_t strip, int32_t zdepth, int32_t threads, int32_t pipeline)
 {
+    if (pipeline < 0 || pipeline > 2) return fail(PF_ERR_ARG, "pipeline must be 0, 1 or 2");
     if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
         return fail(PF_ERR_ARG, "threads must be 0, 256, 512 or 1024");
     const int nt = threads ? threads : 256;
@@ -1169,6 +1154,7 @@ pf_status pf_set_launch(int32_t strip, int32_t zdepth, int32_t threads)
     g_nt_override = threads ? threads : (strip ? 256 : 0);
     g_ppt_override = strip ? strip / nt : 0;
     g_kz_override = zdepth;
+    g_depth_override = pipeline;
     return PF_OK;
 }
 
@@ -1181,7 +1167,7 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     if (!(d->h > 0.0) || !std::isfinite(d->h)) return fail(PF_ERR_ARG, "h must be finite and > 0");
     if (!d->eps) return fail(PF_ERR_ARG, "eps is required");
     const size_t N = (size_t)d->nx * d->ny * d->nz;
-    if (N > (size_t)1 << 31) return fail(PF_ERR_ARG, "grid too large (N > 2^31)");
+    if (N >= (size_t)1 << 29) return fail(PF_ERR_ARG, "grid too large (N >= 2^29 nodes)");
     int bp = 0, bs = 0;
     for (int f = 0; f < 6; ++f) {
         if (d->bc_phi[f] != PF_BC_DIRICHLET && d->bc_phi[f] != PF_BC_NEUMANN) return fail(PF_ERR_ARG, "bad bc_phi");
@@ -1215,10 +1201,10 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     if ((st = dalloc(g, &g->flags, N)) != PF_OK) return cleanup(st);
     if ((st = dalloc(g, &g->dval, N)) != PF_OK) return cleanup(st);
     if ((st = dalloc(g, &g->sc, 1)) != PF_OK) return cleanup(st);
-    if ((st = dalloc(g, &g->partials, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
-    if ((st = dalloc(g, &g->partA, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
-    if ((st = dalloc(g, &g->partB, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
-    if ((st = dalloc(g, &g->partC, (size_t)g->Gmax * 4)) != PF_OK) return cleanup(st);
+    if ((st = dalloc(g, &g->partials, (size_t)g->Gmax * pfk::PSTRIDE)) != PF_OK) return cleanup(st);
+    if ((st = dalloc(g, &g->partA, (size_t)g->Gmax * pfk::PSTRIDE)) != PF_OK) return cleanup(st);
+    if ((st = dalloc(g, &g->partB, (size_t)g->Gmax * pfk::PSTRIDE)) != PF_OK) return cleanup(st);
+    if ((st = dalloc(g, &g->sink, (size_t)pfk::SINK_ELEMS)) != PF_OK) return cleanup(st);
     if (hipHostMalloc((void **)&g->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(PF_ERR_ALLOC, "pinned host allocation failed"));
     if (d->fixed_charge && (st = dalloc(g, &g->q, N)) != PF_OK) return cleanup(st);

@@ -21,14 +21,24 @@
 // updates) are computed once per staged node, so the update and the stencil
 // fuse into one pass.
 //
+// BiCGSTAB (Table 3, right Jacobi preconditioning) runs as two fused stencil
+// kernels per iteration i:
+//   step A: finishes iteration i-1 (x += alpha M^-1 p + omega M^-1 s,
+//           r = s - omega t), forms p = r + beta (p - omega v) and
+//           v = A M^-1 p, and sums shadow . v and r . r;
+//   step B: s = r - alpha v, t = A M^-1 s, and sums t.s, t.t, s.s,
+//           shadow . s and shadow . t.
+// beta needs rho_i = shadow . r_i before step A forms p; with r_i = s - omega t
+// it is shadow . s - omega shadow . t, known from step B's sums.
+//
 // Reductions: each workgroup reduces its products in FP64 (wave shuffles,
-// then LDS) and stores one partial per quantity.  A one-workgroup finalize
-// kernel launched right after sums the partials in a fixed order and updates
-// the BiCGSTAB scalars on the device: deterministic, no floating-point
-// atomics, no host round trip inside an iteration.  (Taking a completion
-// ticket inside the producer instead would need an agent-scope release per
-// workgroup, which writes back the XCD's L2 each time; the kernel boundary
-// provides that visibility once.)
+// then LDS) and stores one partial per quantity.  The next kernel sums the
+// partials in every workgroup, in one fixed order (identical bits
+// everywhere), and derives the BiCGSTAB scalars on the device before its own
+// loads are needed: deterministic, no floating-point atomics, no host round
+// trip inside an iteration.  (Taking a completion ticket inside the producer
+// instead would need an agent-scope release per workgroup, which writes back
+// the XCD's L2 each time; the kernel boundary provides that visibility once.)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,11 +65,11 @@ struct Scalars {
     int iter[2];       // iterations completed when iteration i starts
     int iter_done;     // iterations completed (host view)
     int maxit;
-    int stop;          // ST_RUN while iterating, ST_HALF between steps B and C of a
-                       // half-step convergence, else the terminal state
+    int stop;          // ST_RUN while iterating, else the terminal state
+    int stop_a;        // state decided by the last step A, published by the step B after it
     int fresh;         // 1 from a (re)start until step B of the first iteration
 };
-enum { ST_RUN = 0, ST_CONV = 1, ST_HALF = 2, ST_RESTART = 3, ST_NONFINITE = 4, ST_MAXIT = 5 };
+enum { ST_RUN = 0, ST_CONV = 1, ST_RESTART = 3, ST_NONFINITE = 4, ST_MAXIT = 5 };
 
 // stencil operation selector
 enum { OP_SPMV = 0, OP_SPMV_JAC = 1, OP_RESID = 2, OP_BA = 3, OP_BB = 4 };
@@ -73,12 +83,16 @@ struct ZArgs {
     T ceps;                     // constant face coefficient (already / h^2), CEPS form
     const T *eps;               // nodal coefficient field (non-CEPS)
     const T *dinv;              // inverse diagonal, -1 on Dirichlet rows
-    const T *x;                 // SPMV*/RESID operand; BA/BB: r
+    const T *x;                 // SPMV*/RESID operand; BA: s; BB: r
     const T *y0;                // BA: p (previous); BB: v
     const T *y1;                // BA: v (previous)
-    const T *rt;                // BA: shadow residual
+    const T *y2;                // BA: t
+    const T *rt;                // BA, BB: shadow residual
+    T *xio;                     // BA: iterate x (read and updated in place)
     T *out;                     // SPMV*: y; RESID: r; BA: v (new); BB: t
     T *out_aux;                 // BA: p (new); BB: s
+    T *out_r;                   // BA: r (new)
+    T *sink;                    // SINK_ELEMS doubles: target of masked stores (BA, BB)
     // residual extras (FP64 only)
     const double *b;            // right-hand side
     const double *sigma;        // diagonal shift or null
@@ -90,8 +104,8 @@ struct ZArgs {
     float *rt32;                // RESID: optional shadow copy (FP32)
     // reduction and scalars
     Scalars *sc;
-    double *partials;           // [G][4] partials written by this kernel
-    const double *pin;          // partials of the previous phase (BA: step C, BB: step A)
+    double *partials;           // [G][PSTRIDE] partials written by this kernel
+    const double *pin;          // partials of the previous phase (BA: step B, BB: step A)
     int Gin;                    // their count
     int parity;                 // iteration parity q
 };
@@ -147,6 +161,16 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Partials: PSTRIDE doubles per workgroup (up to PSTRIDE quantities).
+constexpr int PSTRIDE = 8;
+
+// The BiCGSTAB stencil steps issue every store unconditionally: a store whose
+// node is outside the tile (or a step past its last plane) goes to a sink
+// slot of the thread instead.  Stores count in the same wait counter as
+// loads, and a store under a branch would make the compiler assume the
+// shorter path and wait for loads still meant to be in flight.
+constexpr int SINK_ELEMS = 2048;   // >= threads * nodes per thread
+
 // Reduce NQ per-thread values over the workgroup; thread 0 gets the result.
 template <int NQ, int NT, bool MAX = false>
 __device__ __forceinline__ void block_reduce(double (&v)[NQ])
@@ -175,7 +199,7 @@ __device__ __forceinline__ void store_partials(const double (&v)[NQ], double *pa
 {
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) partials[slot * 4 + q] = v[q];
+        for (int q = 0; q < NQ; ++q) partials[slot * PSTRIDE + q] = v[q];
     }
 }
 
@@ -188,7 +212,7 @@ __device__ __forceinline__ void final_reduce(double (&v)[NQ], const double *part
     for (int i = threadIdx.x; i < G; i += NT) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const double p = partials[i * 4 + q];
+            const double p = partials[i * PSTRIDE + q];
             v[q] = MAX ? fmax(v[q], p) : v[q] + p;
         }
     }
@@ -221,7 +245,7 @@ __device__ __forceinline__ void load_partials(PartLoad<NQ> &pl, const double *pa
         const int i = lane + 256 * j;
         const int ic = i < G ? i : 0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) pl.l[j][q] = partials[ic * 4 + q];
+        for (int q = 0; q < NQ; ++q) pl.l[j][q] = partials[ic * PSTRIDE + q];
     }
 }
 
@@ -246,7 +270,7 @@ __device__ __forceinline__ void sum_loaded_partials(double (&tot)[NQ], const Par
         }
         for (int i = lane + 256 * PJ; i < G; i += 256) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) v[q] += partials[i * 4 + q];
+            for (int q = 0; q < NQ; ++q) v[q] += partials[i * PSTRIDE + q];
         }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -273,44 +297,75 @@ __device__ __forceinline__ void sum_partials(double (&tot)[NQ], const double *pa
     sum_loaded_partials<NQ>(tot, pl, partials, G);
 }
 
-// End of step C of iteration i-1 (Table 3 steps 4, 8 and the stop test):
-// rho_i = shadow . r, ||r||^2, the stop state and beta_i.  q is the parity of
-// iteration i.
-struct FinC {
-    double rho, rr, beta;
+// Start of step A of iteration i (parity q).  Step A also finishes iteration
+// i-1: its x, r update (Table 3 steps 16, 17) needs omega_{i-1} = t.s / t.t
+// (step 15), and the p update needs beta_i (step 8), i.e. rho_i = shadow . r_i
+// (step 4).  Since r_i = s - omega t, rho_i = shadow . s - omega shadow . t
+// from step B's sums, so no pass over r_i has to finish first; ||r_i||^2 for
+// the stop test is summed from r_i itself in this step and tested by step B.
+// tot: t.s, t.t, s.s, shadow . s, shadow . t of iteration i-1.
+struct FinB {
+    double alpha, omega, beta, rho, rr;
     int iter, stop;
+    bool update;   // apply the x, r update of iteration i-1
 };
 
-__device__ __forceinline__ FinC fin_c(const Scalars *sc, const double (&tot)[2], int q)
+__device__ __forceinline__ FinB fin_b(const Scalars *sc, const double (&tot)[5], int q)
 {
     const int qp = q ^ 1;
-    FinC f;
-    f.rho = tot[0];
-    f.rr = tot[1];
+    const double ts = tot[0], tt = tot[1], ss = tot[2], rs = tot[3], rtt = tot[4];
+    FinB f{};
+    f.alpha = sc->alpha[qp];
     f.iter = sc->iter[qp] + 1;
-    f.beta = 0.0;
-    if (!finite(f.rho) || !finite(f.rr)) {
+    f.stop = ST_RUN;
+    f.update = true;
+    if (!finite(ts) || !finite(tt) || !finite(ss) || !finite(rs) || !finite(rtt)) {
         f.stop = ST_NONFINITE;
-    } else if (sc->stop == ST_HALF || f.rr <= sc->tol2) {
-        f.stop = ST_CONV;
-    } else if (f.iter >= sc->maxit) {
-        f.stop = ST_MAXIT;
-    } else if (sc->omega[qp] == 0.0 || fabs(f.rho) < 1e-300 || f.rho * f.rho < 1e-28 * sc->rt2 * f.rr) {
-        f.stop = ST_RESTART;   // shadow residual nearly orthogonal to r
-    } else {
-        f.stop = ST_RUN;
-        f.beta = (f.rho / sc->rho[qp]) * (sc->alpha[qp] / sc->omega[qp]);   // step 8
+        f.update = false;
+        return f;
     }
+    if (ss <= sc->tol2) {
+        // ||s|| already meets the tolerance: x += alpha M^-1 p, r = s
+        f.omega = 0.0;
+        f.rho = rs;
+        f.rr = ss;
+        f.stop = ST_CONV;
+        return f;
+    }
+    if (tt == 0.0) {
+        f.stop = ST_RESTART;
+        f.update = false;
+        return f;
+    }
+    f.omega = ts / tt;
+    f.rho = rs - f.omega * rtt;
+    f.rr = fmax(0.0, ss - 2.0 * f.omega * ts + f.omega * f.omega * tt);
+    if (f.rr > sc->tol2) {   // otherwise step B decides on the summed ||r_i||^2
+        if (f.iter >= sc->maxit) {
+            f.stop = ST_MAXIT;
+            return f;
+        }
+        if (f.omega == 0.0 || fabs(f.rho) < 1e-300 || f.rho * f.rho < 1e-28 * sc->rt2 * f.rr) {
+            f.stop = ST_RESTART;   // shadow residual nearly orthogonal to r
+            return f;
+        }
+    }
+    if (f.omega != 0.0 && sc->rho[qp] != 0.0) f.beta = (f.rho / sc->rho[qp]) * (f.alpha / f.omega);
     return f;
 }
 
-__device__ __forceinline__ void fin_c_store(Scalars *sc, const FinC &f, int q)
+// Written by the leading workgroup.  The stop state goes to stop_a, not stop:
+// the other workgroups of this step A test stop on entry and must still apply
+// the x, r update when the state ends the run.
+__device__ __forceinline__ void fin_b_store(Scalars *sc, const FinB &f, int q)
 {
+    sc->stop_a = f.stop;
+    if (!f.update) return;
+    sc->omega[q ^ 1] = f.omega;
     sc->rho[q] = f.rho;
     sc->iter[q] = f.iter;
     sc->iter_done = f.iter;
     sc->rr = f.rr;
-    if (f.stop != ST_RUN) sc->stop = f.stop;
 }
 
 // --------------------------------------------------- z-marching stencil
@@ -324,30 +379,44 @@ __device__ __forceinline__ T absT(T x) { return x < T(0) ? -x : x; }
 //   d:   dinv at the node (row mask and Jacobi scale).
 // Loading (raw) and staging are split so that the loads of a plane can be
 // issued two march steps before their values are needed.  OWN loads add what
-// only the node's own output reads (BA: the shadow residual).
+// only the node's own outputs read (the shadow residual; BA: x).
 template <typename T>
 struct Raw {
-    T d, e, x0, x1, x2, t;
+    T d, e, x0, x1, x2, x3, x4, t;
 };
 
-template <int OP, typename T, bool CEPS, bool OWN>
-__device__ __forceinline__ void load_raw(const ZArgs<T> &a, size_t g, Raw<T> &w)
+// Load of element g (g < 2^29 nodes, so the byte offset fits 32 bits): the
+// array base stays in scalar registers and one 32-bit vector offset serves
+// every array of the node.
+template <typename U>
+__device__ __forceinline__ U ldx(const U *base, unsigned g)
 {
-    w.d = a.dinv[g];
-    if constexpr (!CEPS) w.e = a.eps[g];
+    return *reinterpret_cast<const U *>(reinterpret_cast<const char *>(base) + g * (unsigned)sizeof(U));
+}
+
+template <int OP, typename T, bool CEPS, bool OWN>
+__device__ __forceinline__ void load_raw(const ZArgs<T> &a, unsigned g, Raw<T> &w)
+{
+    w.d = ldx(a.dinv, g);
+    if constexpr (!CEPS) w.e = ldx(a.eps, g);
     if constexpr (OP == OP_SPMV || OP == OP_SPMV_JAC) {
-        w.x0 = a.x[g];
+        w.x0 = ldx(a.x, g);
     } else if constexpr (OP == OP_RESID) {
-        if (a.lift) w.x0 = a.dval ? (T)a.dval[g] : T(0);
-        else w.x0 = a.x[g];
+        if (a.lift) w.x0 = a.dval ? (T)ldx(a.dval, g) : T(0);
+        else w.x0 = ldx(a.x, g);
     } else if constexpr (OP == OP_BA) {
-        w.x0 = a.x[g];    // r
-        w.x1 = a.y0[g];   // p (previous)
-        w.x2 = a.y1[g];   // v (previous)
-        if constexpr (OWN) w.t = a.rt[g];
+        w.x0 = ldx(a.x, g);    // s
+        w.x1 = ldx(a.y0, g);   // p (previous)
+        w.x2 = ldx(a.y1, g);   // v (previous)
+        w.x3 = ldx(a.y2, g);   // t
+        if constexpr (OWN) {
+            w.x4 = ldx((const T *)a.xio, g);
+            w.t = ldx(a.rt, g);
+        }
     } else {
-        w.x0 = a.x[g];    // r
-        w.x1 = a.y0[g];   // v
+        w.x0 = ldx(a.x, g);    // r
+        w.x1 = ldx(a.y0, g);   // v
+        if constexpr (OWN) w.t = ldx(a.rt, g);
     }
 }
 
@@ -363,14 +432,59 @@ __device__ __forceinline__ void stage_raw(const Raw<T> &w, T &val, T &aux, doubl
         aux = w.x0;
         val = absT(d) * aux;
     } else if constexpr (OP == OP_BA) {
-        // p = r + beta (p - omega v)   (Table 3 step 9)
-        aux = w.x0 + (T)beta * (w.x1 - (T)omega * w.x2);
+        // r = s - omega t (Table 3 step 17 of the previous iteration), then
+        // p = r + beta (p - omega v)   (step 9)
+        const T r = w.x0 - (T)omega * w.x3;
+        aux = r + (T)beta * (w.x1 - (T)omega * w.x2);
         val = absT(d) * aux;
     } else {  // OP_BB
         // s = r - alpha v   (Table 3 step 13)
         aux = w.x0 - (T)alpha * w.x1;
         val = absT(d) * aux;
     }
+}
+
+// Store target chosen without a branch: the target is `real` plus a byte
+// offset (0, or the distance to the sink slot) that an empty asm hides from
+// the compiler, which would otherwise turn the choice back into two
+// conditional stores.  The base stays the global pointer, so the store stays
+// a global (not flat) store.
+template <typename T>
+__device__ __forceinline__ T *pick(bool keep, T *real, T *sink)
+{
+    long d = keep ? 0L : (long)(reinterpret_cast<char *>(sink) - reinterpret_cast<char *>(real));
+    asm volatile("" : "+v"(d));
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(real) + d);
+}
+
+// A workgroup-uniform double moved into scalar registers (it then takes no
+// vector registers in the march loop and carries no pending vector load).
+__device__ __forceinline__ double uniform(double x)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// A store to the thread's sink slot that the compiler can neither drop nor
+// merge with another (its address carries a hidden zero offset).
+template <typename T>
+__device__ __forceinline__ void sink_store(T *slot)
+{
+    long d = 0;
+    asm volatile("" : "+v"(d));
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(slot) + d) = T(0);
+}
+
+// Step A's own-node update of the previous iteration (Table 3 steps 16, 17):
+// x += alpha M^-1 p + omega M^-1 s, r = s - omega t.
+template <typename T>
+__device__ __forceinline__ void stage_xr(const Raw<T> &w, T &xn, T &rn, double alpha, double omega)
+{
+    const T d = absT(w.d);
+    rn = w.x0 - (T)omega * w.x3;
+    xn = w.x4 + (T)alpha * (d * w.x1) + (T)omega * (d * w.x0);
 }
 
 // The residual form stages Dirichlet rows of the lifted operand as zero.
@@ -401,13 +515,14 @@ __device__ __forceinline__ T own_reg(T x)
 // One workgroup's tile: logical tile index lb (strip, z-chunk) and partial
 // slot `slot` of the system described by a.
 //
-// Memory pipeline: the raw loads of plane k+1 and k+2 are in flight while
-// plane k is computed, in two register sets used alternately (the march is
-// unrolled by two so that each set keeps fixed registers).  Every load is
+// Memory pipeline: the raw loads of the next DEPTH planes are in flight
+// while plane k is computed, in DEPTH register sets used in turn (for
+// DEPTH = 2 the march is unrolled by two so that each set keeps fixed
+// registers; DEPTH = 1 needs half the registers).  Every load is
 // issued unconditionally with its plane clamped into the tile's range and
 // its node clamped into the strip, so the number of loads per step is fixed
 // and the wait before staging a plane covers only that plane's loads.
-template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE>
+template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE, int DEPTH>
 __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, const int slot)
 {
     // halo nodes per thread kept in registers (both halo rows fit when
@@ -415,15 +530,16 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     // synchronous loop, for planes wider than that
     constexpr int HMAX = (NT >= 512) ? 1 : 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int NQ = (OP == OP_BB) ? 3 : 1;
-    constexpr int NQP = (OP == OP_BB) ? 1 : 2;   // quantities of the previous phase's partials
+    // quantities this kernel sums (BA: shadow . v, r . r; BB: t.s, t.t, s.s,
+    // shadow . s, shadow . t) and those of the previous phase's partials
+    constexpr int NQ = (OP == OP_BB) ? 5 : (OP == OP_BA) ? 2 : 1;
+    constexpr int NQP = (OP == OP_BB) ? 2 : 5;
     constexpr bool SCAL = (OP == OP_BA || OP == OP_BB);
 
     Scalars *sc = a.sc;
     int fresh = 0;
     if constexpr (SCAL) {
-        const int stop = sc->stop;
-        if (OP == OP_BA ? (stop != ST_RUN && stop != ST_HALF) : (stop != ST_RUN)) return;
+        if (sc->stop != ST_RUN) return;
         if constexpr (OP == OP_BA) fresh = sc->fresh;
     }
 
@@ -466,13 +582,15 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         hok[u] = hI < nhalo;
         hm[u] = !hok[u] ? lo : (hI < nhl) ? lo + hI : mend + (hI - nhl);
     }
-    auto gown = [&](int q, int k) { return (size_t)om[q] + Ps * min(k, kown_hi); };
-    auto ghal = [&](int u, int k) { return (size_t)hm[u] + Ps * min(k, khal_hi); };
+    const unsigned Pu = (unsigned)P;
+    auto gown = [&](int q, int k) { return (unsigned)om[q] + Pu * (unsigned)min(k, kown_hi); };
+    auto ghal = [&](int u, int k) { return (unsigned)hm[u] + Pu * (unsigned)min(k, khal_hi); };
 
     // ---- prologue loads: the previous phase's partials, then planes k0-1,
     //      k0 (own), k0 (halo), and the raw sets of planes k0+1 and k0+2
     PartLoad<NQP> pl;
     if constexpr (SCAL) load_partials<NQP>(pl, a.pin, a.Gin);
+    __builtin_amdgcn_sched_barrier(0);
     Raw<T> rp[PPT], rc[PPT], hc[HMAX];
     Raw<T> rA[PPT], hA[HMAX], rB[PPT], hB[HMAX];
 #pragma unroll
@@ -482,46 +600,76 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     }
 #pragma unroll
     for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k0), hc[u]);
+    // The sets go out in the order of the march steps (own, halo, then as
+    // many stores as a step makes, here to the sink), so that at the loop's
+    // first wait the loads of each set are as far from the newest event as in
+    // every later step: the compiler takes the nearer of the two, and a
+    // nearer distance here would make every step wait for loads meant to
+    // stay in flight.
+    constexpr int NST = PPT * ((OP == OP_BA) ? 4 : (OP == OP_BB) ? 2 : (OP == OP_SPMV_JAC) ? 1 : 0);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        load_raw<OP, T, CEPS, true>(a, gown(q, k0 + 1), rA[q]);
-        load_raw<OP, T, CEPS, true>(a, gown(q, k0 + 2), rB[q]);
-    }
+    for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, true>(a, gown(q, k0 + 1), rA[q]);
 #pragma unroll
-    for (int u = 0; u < HMAX; ++u) {
-        load_raw<OP, T, CEPS, false>(a, ghal(u, k0 + 1), hA[u]);
-        load_raw<OP, T, CEPS, false>(a, ghal(u, k0 + 2), hB[u]);
+    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k0 + 1), hA[u]);
+#pragma unroll
+    for (int j = 0; j < NST; ++j) sink_store(a.sink + threadIdx.x);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (DEPTH == 2) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, true>(a, gown(q, k0 + 2), rB[q]);
+#pragma unroll
+        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k0 + 2), hB[u]);
+#pragma unroll
+        for (int j = 0; j < NST; ++j) sink_store(a.sink + threadIdx.x);
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---- scalars of this step (while the plane loads are in flight)
+    // alpha, omega: of the previous iteration in BA (its x, r update), of
+    // this iteration in BB
     double alpha = 0, omega = 0, beta = 0;
     if constexpr (OP == OP_BA) {
-        // finish step C of the previous iteration (or start fresh)
+        // finish step B of the previous iteration (a fresh start has r in s,
+        // t = 0, p = v = 0: with alpha = omega = beta = 0 the update keeps x
+        // and sets p = r)
         if (!fresh) {
-            double tot[2];
-            sum_loaded_partials<2>(tot, pl, a.pin, a.Gin);
-            const FinC f = fin_c(sc, tot, a.parity);
-            if (lb == 0 && threadIdx.x == 0) fin_c_store(sc, f, a.parity);
-            if (f.stop != ST_RUN) return;
-            beta = f.beta;
-            omega = sc->omega[a.parity ^ 1];
+            double tot[5];
+            sum_loaded_partials<5>(tot, pl, a.pin, a.Gin);
+            const FinB f = fin_b(sc, tot, a.parity);
+            if (lb == 0 && threadIdx.x == 0) fin_b_store(sc, f, a.parity);
+            if (!f.update) return;
+            alpha = f.alpha;
+            omega = f.omega;
+            beta = (f.stop == ST_RUN) ? f.beta : 0.0;
+        } else if (lb == 0 && threadIdx.x == 0) {
+            sc->stop_a = ST_RUN;
         }
     } else if constexpr (OP == OP_BB) {
-        // finish step A: alpha_i = rho_i / (shadow . v)   (Table 3 step 12)
-        double tot[1];
-        sum_loaded_partials<1>(tot, pl, a.pin, a.Gin);
-        const double rtv = tot[0];
-        int st = ST_RUN;
-        if (!finite(rtv)) st = ST_NONFINITE;
-        else if (rtv == 0.0) st = ST_RESTART;
-        else alpha = sc->rho[a.parity] / rtv;
+        // finish step A: the stop test on ||r_i||^2, then
+        // alpha_i = rho_i / (shadow . v)   (Table 3 step 12)
+        double tot[2];
+        sum_loaded_partials<2>(tot, pl, a.pin, a.Gin);
+        const double rtv = tot[0], rr = tot[1];
+        int st = sc->stop_a;
+        if (st == ST_RUN) {
+            if (!finite(rtv) || !finite(rr)) st = ST_NONFINITE;
+            else if (rr <= sc->tol2) st = ST_CONV;
+            else if (sc->iter[a.parity] >= sc->maxit) st = ST_MAXIT;
+            else if (rtv == 0.0) st = ST_RESTART;
+            else alpha = sc->rho[a.parity] / rtv;
+        }
         if (lb == 0 && threadIdx.x == 0) {
             sc->alpha[a.parity] = alpha;
+            sc->rr = rr;
             sc->fresh = 0;
             if (st != ST_RUN) sc->stop = st;
         }
         if (st != ST_RUN) return;
     }
+    alpha = uniform(alpha);
+    omega = uniform(omega);
+    beta = uniform(beta);
 
     // two LDS planes (double buffer) of staged values and coefficients
     T *lval0 = reinterpret_cast<T *>(smem_raw);
@@ -533,7 +681,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     T ep[PPT], ec[PPT], en[PPT];   // coefficient field
     T ac[PPT], an[PPT];            // aux, planes k, k+1
     T dc[PPT], dn[PPT];            // dinv, planes k, k+1
-    T tc[PPT], tn[PPT];            // shadow residual (BA), planes k, k+1
+    T tc[PPT], tn[PPT];            // shadow residual (BA, BB), planes k, k+1
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
@@ -545,14 +693,22 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         vc[q] = resid_val<OP, T>(a, rc[q], vc[q]);
         dc[q] = rc[q].d;
         ec[q] = CEPS ? T(0) : rc[q].e;
-        tc[q] = (OP == OP_BA) ? rc[q].t : T(0);
+        tc[q] = SCAL ? rc[q].t : T(0);
         T ax;
         stage_raw<OP, T>(rp[q], vp[q], ax, alpha, omega, beta);
         vp[q] = resid_val<OP, T>(a, rp[q], vp[q]);
         ep[q] = CEPS ? T(0) : rp[q].e;
         vn[q] = en[q] = an[q] = dn[q] = tn[q] = T(0);
         if (ok[q]) {
-            if constexpr (OP == OP_BA || OP == OP_BB) a.out_aux[gown(q, k0)] = ac[q];
+            const unsigned g0 = gown(q, k0);
+            if constexpr (SCAL) a.out_aux[g0] = ac[q];
+            if constexpr (OP == OP_BA) {
+                T xn, rn;
+                stage_xr<T>(rc[q], xn, rn, alpha, omega);
+                a.xio[g0] = xn;
+                a.out_r[g0] = rn;
+                acc[1] += (double)rn * (double)rn;
+            }
             lval0[ox[q]] = vc[q];
             if constexpr (!CEPS) leps0[ox[q]] = ec[q];
         }
@@ -570,7 +726,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
             const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
             Raw<T> w;
-            load_raw<OP, T, CEPS, false>(a, (size_t)m + Ps * k0, w);
+            load_raw<OP, T, CEPS, false>(a, (unsigned)m + Pu * (unsigned)k0, w);
             T v, ax;
             stage_raw<OP, T>(w, v, ax, alpha, omega, beta);
             lval0[m - lo] = resid_val<OP, T>(a, w, v);
@@ -582,14 +738,15 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     int cur = 0;
     T hv[HMAX], he[HMAX];
     // One march step: output plane k from LDS buffer `cur`; ro / rh hold the
-    // raw loads of plane k+1 and are refilled with plane k+3.  The march runs
+    // raw loads of plane k+1 and are refilled with plane k+1+DEPTH.  The march runs
     // in pairs of steps; a step past the tile's last plane (odd plane count)
     // computes but stores nothing.
     auto step = [&](const int k, Raw<T>(&ro)[PPT], Raw<T>(&rh)[HMAX]) {
         const bool live = k < k1;
         const bool has_up = (k + 1) < nz;
         const bool stage_next = (k + 1) < k1;
-        // (1) stage plane k+1 from the raw loads issued two steps ago
+        // (1) stage plane k+1 from the raw loads issued DEPTH steps ago
+        T xn[PPT], rn[PPT];   // BA: updated x, r of plane k+1
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             stage_raw<OP, T>(ro[q], vn[q], an[q], alpha, omega, beta);
@@ -597,7 +754,12 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             an[q] = own_reg(an[q]);
             dn[q] = own_reg(ro[q].d);
             if constexpr (!CEPS) en[q] = own_reg(ro[q].e);
-            if constexpr (OP == OP_BA) tn[q] = own_reg(ro[q].t);
+            if constexpr (SCAL) tn[q] = own_reg(ro[q].t);
+            if constexpr (OP == OP_BA) {
+                stage_xr<T>(ro[q], xn[q], rn[q], alpha, omega);
+                xn[q] = own_reg(xn[q]);
+                rn[q] = own_reg(rn[q]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < HMAX; ++u) {
@@ -606,20 +768,29 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             hv[u] = own_reg(resid_val<OP, T>(a, rh[u], hv[u]));
             if constexpr (!CEPS) he[u] = own_reg(rh[u].e);
         }
-        // (2) refill the set with plane k+3 (clamped: re-reads of a plane
+        // (2) refill the set with plane k+1+DEPTH (clamped: re-reads of a plane
         //     already loaded near the tile's end hit the cache).  The
         //     scheduling barrier keeps the refill after the reads of the set
         //     above, so the loads can reuse its registers.
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, true>(a, gown(q, k + 3), ro[q]);
+        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, true>(a, gown(q, k + 1 + DEPTH), ro[q]);
 #pragma unroll
-        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k + 3), rh[u]);
-        if (stage_next) {
-            if constexpr (OP == OP_BA || OP == OP_BB) {
+        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k + 1 + DEPTH), rh[u]);
+        if constexpr (SCAL) {
+            // own outputs of plane k+1 when the tile owns it (else the sink)
 #pragma unroll
-                for (int q = 0; q < PPT; ++q)
-                    if (ok[q]) a.out_aux[gown(q, k + 1)] = an[q];
+            for (int q = 0; q < PPT; ++q) {
+                const bool keep = stage_next && ok[q];
+                const unsigned g1 = gown(q, k + 1);
+                T *sk = a.sink + threadIdx.x + q * NT;
+                *pick(keep, a.out_aux + g1, sk) = an[q];
+                if constexpr (OP == OP_BA) {
+                    *pick(keep, a.xio + g1, sk) = xn[q];
+                    *pick(keep, a.out_r + g1, sk) = rn[q];
+                    const double r2 = (double)rn[q] * (double)rn[q];
+                    acc[1] += keep ? r2 : 0.0;
+                }
             }
         }
         // mirror ghosts across the z faces, written into the register planes
@@ -662,7 +833,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                     a.out[g] = freerow ? D * vc[q] - sum : vc[q];
                 }
             } else if constexpr (OP == OP_SPMV_JAC) {
-                if (live && ok[q]) a.out[g] = freerow ? ac[q] - sum : ac[q];
+                *pick(live && ok[q], a.out + g, a.sink + threadIdx.x + q * NT) = freerow ? ac[q] - sum : ac[q];
             } else if constexpr (OP == OP_RESID) {
                 if (live && ok[q]) {
                     const double sg = a.sigma ? a.sigma[g] : a.sig_const;
@@ -678,20 +849,23 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             } else if constexpr (OP == OP_BA) {
                 // v = A M^-1 p  (Table 3 step 11), then shadow . v (step 12)
                 const T v = freerow ? ac[q] - sum : T(0);
-                if (live && ok[q]) {
-                    a.out[g] = v;
-                    acc[0] += (double)tc[q] * (double)v;
-                }
+                const bool keep = live && ok[q];
+                *pick(keep, a.out + g, a.sink + threadIdx.x + q * NT) = v;
+                const double rv = (double)tc[q] * (double)v;
+                acc[0] += keep ? rv : 0.0;
             } else {
-                // t = A M^-1 s  (step 14); t.s, t.t (step 15), s.s
+                // t = A M^-1 s  (step 14); t.s, t.t (step 15), s.s (half-step
+                // test), shadow . s and shadow . t (rho of the next iteration)
                 const T t = freerow ? ac[q] - sum : T(0);
                 const double s = (double)ac[q];
-                if (live && ok[q]) {
-                    a.out[g] = t;
-                    acc[0] += (double)t * s;
-                    acc[1] += (double)t * (double)t;
-                    acc[2] += s * s;
-                }
+                const bool keep = live && ok[q];
+                *pick(keep, a.out + g, a.sink + threadIdx.x + q * NT) = t;
+                const double m = keep ? 1.0 : 0.0;
+                acc[0] += m * ((double)t * s);
+                acc[1] += m * ((double)t * (double)t);
+                acc[2] += m * (s * s);
+                acc[3] += m * ((double)tc[q] * s);
+                acc[4] += m * ((double)tc[q] * (double)t);
             }
         }
         // (4) stage plane k+1 in the other LDS buffer (unused after the last
@@ -716,7 +890,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
                 const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
                 Raw<T> w;
-                load_raw<OP, T, CEPS, false>(a, (size_t)m + Ps * (k + 1), w);
+                load_raw<OP, T, CEPS, false>(a, (unsigned)m + Pu * (unsigned)(k + 1), w);
                 T v, ax;
                 stage_raw<OP, T>(w, v, ax, alpha, omega, beta);
                 nv[m - lo] = resid_val<OP, T>(a, w, v);
@@ -735,9 +909,13 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             ac[q] = an[q]; dc[q] = dn[q]; tc[q] = tn[q];
         }
     };
-    for (int k = k0; k < k1; k += 2) {
-        step(k, rA, hA);
-        step(k + 1, rB, hB);
+    if constexpr (DEPTH == 2) {
+        for (int k = k0; k < k1; k += 2) {
+            step(k, rA, hA);
+            step(k + 1, rB, hB);
+        }
+    } else {
+        for (int k = k0; k < k1; ++k) step(k, rA, hA);
     }
 
     if constexpr (OP == OP_RESID || OP == OP_BA || OP == OP_BB) {
@@ -746,10 +924,10 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     }
 }
 
-template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE>
+template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
 {
-    zmarch_tile<OP, T, CEPS, NT, PPT, WIDE>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
+    zmarch_tile<OP, T, CEPS, NT, PPT, WIDE, DEPTH>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
 }
 
 // System owning global block b: start[s] <= b < start[s+1].
@@ -765,131 +943,19 @@ __device__ __forceinline__ int batch_system(const int *start, int nsys, int b)
 
 // Batched form: one launch covers the tiles of nsys systems (grids of any
 // size); each system keeps its own scalars, partials and status.
-template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE>
+template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch_batch(const ZArgs<T> *__restrict__ args,
                                                      const int *__restrict__ start, int nsys)
 {
     const int s = batch_system(start, nsys, blockIdx.x);
     const int lb = blockIdx.x - start[s];
     const ZArgs<T> a = args[s];   // private copy: stores cannot alias it
-    zmarch_tile<OP, T, CEPS, NT, PPT, WIDE>(a, lb, lb);
-}
-
-// ------------------------------------- BiCGSTAB step C (pointwise, fused)
-
-// x += alpha M^-1 p + omega M^-1 s (step 16); r = s - omega t (step 17);
-// then shadow . r and r . r for the next beta (step 8) and the stop test.
-template <typename T>
-struct CArgs {
-    size_t N;
-    T *x, *r;
-    const T *p, *s, *t, *dinv, *rt;
-    Scalars *sc;
-    double *partials;        // written: shadow . r, r . r
-    const double *pin;       // step B partials: t.s, t.t, s.s
-    int Gin;
-    int G;
-    int parity;
-};
-
-// Elements per thread per round of step C (a workgroup covers NT*C_UNROLL
-// consecutive elements per round).
-constexpr int C_UNROLL = 4;
-
-template <typename T, int NT>
-__device__ __forceinline__ void bicg_c_block(const CArgs<T> &a, const int b)
-{
-    constexpr int U = C_UNROLL;
-    Scalars *sc = a.sc;
-    const int stop = sc->stop;
-    if (stop != ST_RUN && stop != ST_HALF) return;
-    const size_t N = a.N;
-    T *__restrict__ x = a.x;
-    T *__restrict__ r = a.r;
-    const T *__restrict__ p = a.p;
-    const T *__restrict__ s = a.s;
-    const T *__restrict__ t = a.t;
-    const T *__restrict__ dinv = a.dinv;
-    const T *__restrict__ rt = a.rt;
-    const size_t span = (size_t)NT * U;
-    const size_t stride = (size_t)a.G * span;
-    const size_t rounds = (N + stride - 1) / stride;
-    // the previous phase's partials and the first round's operands are
-    // loaded before the scalar work below (indices past N read element N-1)
-    PartLoad<3> pl;
-    load_partials<3>(pl, a.pin, a.Gin);
-    T vd[U], vs[U], vt[U], vp[U], vx[U], vr[U];
-    auto load_round = [&](size_t r0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t i = r0 + (size_t)b * span + (size_t)u * NT + threadIdx.x;
-            const size_t ic = i < N ? i : N - 1;
-            vd[u] = dinv[ic];
-            vs[u] = s[ic];
-            vt[u] = t[ic];
-            vp[u] = p[ic];
-            vx[u] = x[ic];
-            vr[u] = rt[ic];
-        }
-    };
-    load_round(0);
-    // finish step B: omega_i = t.s / t.t (Table 3 step 15), or the half-step
-    // exit when ||s|| already meets the tolerance
-    double tot[3];
-    sum_loaded_partials<3>(tot, pl, a.pin, a.Gin);
-    const double ts = tot[0], tt = tot[1], ss = tot[2];
-    int st = ST_RUN;
-    double om = 0.0;
-    if (!finite(ts) || !finite(tt) || !finite(ss)) st = ST_NONFINITE;
-    else if (ss <= sc->tol2) st = ST_HALF;
-    else if (tt == 0.0) st = ST_RESTART;
-    else om = ts / tt;
-    if (b == 0 && threadIdx.x == 0) {
-        sc->omega[a.parity] = om;
-        if (st != ST_RUN) sc->stop = st;
-    }
-    if (st == ST_NONFINITE || st == ST_RESTART) return;
-    const T alpha = (T)sc->alpha[a.parity], omega = (T)om;
-    double acc[2] = {0.0, 0.0};
-    for (size_t rd = 0; rd < rounds; ++rd) {
-        const size_t r0 = rd * stride;
-        if (rd > 0) load_round(r0);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t i = r0 + (size_t)b * span + (size_t)u * NT + threadIdx.x;
-            const T d = absT(vd[u]);
-            const T xi = vx[u] + alpha * (d * vp[u]) + omega * (d * vs[u]);   // step 16
-            const T ri = vs[u] - omega * vt[u];                                // step 17
-            if (i < N) {
-                x[i] = xi;
-                r[i] = ri;
-                acc[0] += (double)vr[u] * (double)ri;
-                acc[1] += (double)ri * (double)ri;
-            }
-        }
-    }
-    block_reduce<2, NT>(acc);
-    store_partials<2>(acc, a.partials, b);
-}
-
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_bicg_c(CArgs<T> a)
-{
-    bicg_c_block<T, NT>(a, blockIdx.x);
-}
-
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_bicg_c_batch(const CArgs<T> *__restrict__ args,
-                                                     const int *__restrict__ start, int nsys)
-{
-    const int s = batch_system(start, nsys, blockIdx.x);
-    const CArgs<T> a = args[s];
-    bicg_c_block<T, NT>(a, blockIdx.x - start[s]);
+    zmarch_tile<OP, T, CEPS, NT, PPT, WIDE, DEPTH>(a, lb, lb);
 }
 
 // ------------------------------------------------------------ finalize
 
-enum { FIN_C = 2, FIN_SUM = 3, FIN_MAX = 4 };
+enum { FIN_SUM = 3, FIN_MAX = 4 };
 
 struct FinArgs {
     Scalars *sc;
@@ -897,40 +963,20 @@ struct FinArgs {
     int G;
 };
 
-// FIN_C closes a graph chunk: it finishes step C of the chunk's last
-// iteration exactly as the next step A would (same sums, same bits), so the
-// host can read the stop state.  FIN_SUM / FIN_MAX finish the standalone
-// residual and relaxation reductions into red[0].
+// FIN_SUM / FIN_MAX finish the standalone residual and relaxation reductions
+// into red[0] (the BiCGSTAB steps finish each other's sums themselves).
 template <int KIND>
 __device__ __forceinline__ void finalize_block(const FinArgs &f)
 {
-    Scalars *sc = f.sc;
-    if constexpr (KIND == FIN_C) {
-        const int stop = sc->stop;
-        if ((stop != ST_RUN && stop != ST_HALF) || sc->fresh) return;
-        double tot[2];
-        sum_partials<2>(tot, f.partials, f.G);
-        const FinC c = fin_c(sc, tot, 0);   // chunks hold an even number of iterations
-        if (threadIdx.x == 0) fin_c_store(sc, c, 0);
-    } else {
-        double tot[1];
-        final_reduce<1, 256, KIND == FIN_MAX>(tot, f.partials, f.G);
-        if (threadIdx.x == 0) sc->red[0] = tot[0];
-    }
+    double tot[1];
+    final_reduce<1, 256, KIND == FIN_MAX>(tot, f.partials, f.G);
+    if (threadIdx.x == 0) f.sc->red[0] = tot[0];
 }
 
 template <int KIND>
 __global__ __launch_bounds__(256) void k_finalize(FinArgs f)
 {
     finalize_block<KIND>(f);
-}
-
-// One workgroup per system.
-template <int KIND>
-__global__ __launch_bounds__(256) void k_finalize_batch(const FinArgs *__restrict__ f)
-{
-    const FinArgs a = f[blockIdx.x];
-    finalize_block<KIND>(a);
 }
 
 // Copy the scalar blocks of n systems into one array (one host read per chunk).

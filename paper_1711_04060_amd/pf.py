@@ -92,7 +92,7 @@ def load():
         lib.pf_nonlinear_solve_batch.argtypes = [I32, P, P, P, P]
         lib.pf_last_error.argtypes = []
         lib.pf_last_error.restype = C.c_char_p
-        lib.pf_set_launch.argtypes = [I32, I32, I32]
+        lib.pf_set_launch.argtypes = [I32, I32, I32, I32]
         lib.pf_timing_enable.argtypes = [I32, I32]
         lib.pf_timing_read.argtypes = [I32, C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]
         for name in EXPORTS:
@@ -293,8 +293,8 @@ def pf_nonlinear_solve_batch(grids, params, phis, check=True):
     return [_info(infos[i]) for i in range(n)]
 
 
-def pf_set_launch(strip=0, zdepth=0, threads=0):
-    _check(load().pf_set_launch(int(strip), int(zdepth), int(threads)), "pf_set_launch")
+def pf_set_launch(strip=0, zdepth=0, threads=0, pipeline=0):
+    _check(load().pf_set_launch(int(strip), int(zdepth), int(threads), int(pipeline)), "pf_set_launch")
 
 
 def pf_timing_enable(enable=1, sample=8):

@@ -167,6 +167,59 @@ def test_linear_solve_fp64_parity(name):
     assert _rel(host(x2), ref) <= 1e-7
 
 
+# (threads, nodes per thread, z-planes per workgroup, load pipeline depth):
+# odd plane counts run a step past the tile's last plane; every shape and
+# depth the autotuner may pick must give the same answers
+LAUNCHES = [(256, 1, 3, 1), (256, 2, 2, 2), (512, 1, 5, 2), (512, 2, 4, 1), (1024, 1, 3, 2), (1024, 1, 7, 1)]
+
+
+@pytest.mark.parametrize("launch", LAUNCHES, ids=lambda l: "t%d_p%d_kz%d_d%d" % l)
+def test_launch_shapes_and_pipeline_depths(launch):
+    pf = _pf()
+    nt, ppt, kz, depth = launch
+    p = _rand_problem(37, 23, 19, seed=11, bc=(NM, NM, D, D, D, NM), bcv=(0, 0, 0.3, -1.2, 0.7, 0), nfixed=7)
+    rng = np.random.default_rng(4)
+    sigma = np.where(rng.uniform(size=p.N) < 0.5, rng.uniform(0, 20, p.N), 0.0)
+    b = rng.normal(size=p.N) * 50
+    ref, _ = oracle.linear_solve(p, sigma, b, tol=1e-13)
+    A, isd, val = _oracle_A(p, sigma)
+    pf.pf_set_launch(nt * ppt, kz, nt, depth)
+    try:
+        g = pf.grid_from_problem(p)
+    finally:
+        pf.pf_set_launch(0, 0, 0, 0)
+    x = rng.normal(size=p.N)
+    y = torch.empty(p.N, dtype=torch.float64, device="cuda")
+    pf.pf_spmv(g, dev(sigma), dev(x), y, 1)
+    xm = x / A[0]
+    assert np.all(np.abs(host(y) - oracle.dia_matvec(p.nx, p.ny, p.nz, A, xm)) <= 16 * EPS64 * _abs_terms(p, A, xm))
+    xs = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    info = pf.pf_linear_solve(g, dev(sigma), dev(b), xs, pf.pf_lin_opts_default(rel_tol=1e-12))
+    assert info["status"] == 0 and _rel(host(xs), ref) <= 1e-9
+    xs.zero_()
+    info = pf.pf_linear_solve(g, dev(sigma), dev(b), xs, pf.pf_lin_opts_default(precision=pf.PF_MIXED))
+    assert info["status"] == 0 and info["rel_res"] <= 1e-10 and _rel(host(xs), ref) <= 1e-8
+
+
+def test_wide_planes():
+    """Planes wider than the register halo (2 nx > threads): the WIDE form."""
+    pf = _pf()
+    p = _rand_problem(521, 5, 6, seed=21, bc=(D, NM, NM, D, D, NM), bcv=(0.4, 0, 0, -0.3, 1.0, 0))
+    rng = np.random.default_rng(8)
+    b = rng.normal(size=p.N) * 20
+    A, isd, val = _oracle_A(p)
+    ref, _ = oracle.linear_solve(p, None, b, tol=1e-13)
+    g = pf.grid_from_problem(p)
+    x = rng.normal(size=p.N)
+    y = torch.empty(p.N, dtype=torch.float64, device="cuda")
+    pf.pf_spmv(g, None, dev(x), y, 1)
+    xm = x / A[0]
+    assert np.all(np.abs(host(y) - oracle.dia_matvec(p.nx, p.ny, p.nz, A, xm)) <= 16 * EPS64 * _abs_terms(p, A, xm))
+    xs = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    info = pf.pf_linear_solve(g, None, dev(b), xs, pf.pf_lin_opts_default(rel_tol=1e-12))
+    assert info["status"] == 0 and _rel(host(xs), ref) <= 1e-9
+
+
 def test_linear_solve_mixed_parity():
     pf = _pf()
     p = inputs.sphere_poisson(65)
