@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--sample", type=int, default=4, help="time step A in one chunk out of this many")
+    ap.add_argument("--sample", type=int, default=16, help="time step A in one batch of chunks out of this many")
     ap.add_argument("--forms", type=int, default=1)
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--n", type=int, default=97)

@@ -167,7 +167,7 @@ struct pf_grid {
     double *sink = nullptr;            // target of the stencil kernels' masked stores
     std::map<long, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> tev;       // timing events (2 per iteration of a chunk)
-    bool last_timed = false;
+    bool last_timed_first = false;   // the first chunk of the last batch ran timed
     int last_run[4] = {0, 0, 0, 0};    // iterations of the last Krylov run per (precision, system)
 
     // nonlinear state
@@ -387,9 +387,9 @@ pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a)
 }
 
 template <int KIND>
-pf_status finalize(pf_grid *g, int G)
+pf_status finalize(pf_grid *g, int G, int slot = 0)
 {
-    pfk::FinArgs f{g->sc, g->partials, G};
+    pfk::FinArgs f{g->sc, g->partials, G, slot};
     hipLaunchKernelGGL((pfk::k_finalize<KIND>), dim3(1), dim3(256), 0, g->stream, f);
     HIPCHK(hipGetLastError());
     return PF_OK;
@@ -411,10 +411,11 @@ pf_status compute_dinv(pf_grid *g, const OpDesc &op, T *dinv)
     return PF_OK;
 }
 
-// True FP64 residual r = b - A x (and ||r||^2 into sc->red[0]); optional
+// True FP64 residual r = b - A x (and ||r||^2 into sc->red[slot]); optional
 // shadow / FP32 copies.  lift: use the Dirichlet values as x (b_lift).
 pf_status residual64(pf_grid *g, const OpDesc &op, const double *dinv, const double *b,
-                     const double *x, double *r, bool lift, double *rt64, float *r32, float *rt32)
+                     const double *x, double *r, bool lift, double *rt64, float *r32, float *rt32,
+                     int slot = 0)
 {
     pfk::ZArgs<double> a = zbase<double>(g, op, dinv);
     a.x = x;
@@ -436,7 +437,9 @@ pf_status residual64(pf_grid *g, const OpDesc &op, const double *dinv, const dou
         a.dval = nullptr;
     }
     PFCHK((zlaunch<pfk::OP_RESID, double>(g, op, a)));
-    return finalize<pfk::FIN_SUM>(g, a.G);
+    // the partials buffer is reused by the next standalone reduction, which
+    // follows in stream order
+    return finalize<pfk::FIN_SUM>(g, a.G, slot);
 }
 
 pf_status read_scalars(pf_grid *g)
@@ -507,10 +510,10 @@ pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
 // Chunk of m iterations (m even) captured once per (precision, system) and
 // replayed.  The graph references only grid-owned buffers.
 template <typename T>
-pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m)
+pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m, bool may_time = true)
 {
-    const bool timed = g_timing.enabled && (g_timing.chunk++ % g_timing.sample) == 0;
-    g->last_timed = timed;
+    const bool timed = may_time && g_timing.enabled && (g_timing.chunk++ % g_timing.sample) == 0;
+    if (may_time) g->last_timed_first = timed;
     if (timed && (int)g->tev.size() < 2 * m) {
         while ((int)g->tev.size() < 2 * m) {
             hipEvent_t e;
@@ -677,36 +680,38 @@ pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter,
     return write_scalars(g);
 }
 
-// Iterate until the device reports a state other than RUN.  The first chunk
-// is sized from the previous run on the same grid and operator (the outer
-// loop repeats similar solves), later chunks are short, so few iterations
-// run past convergence as no-ops; a fixed check_every overrides this.
+// Iterate until the device reports a state other than RUN.  The first batch
+// of iterations is sized from the previous run on the same grid and operator
+// (the outer loop repeats similar warm-started solves): 90% of that count,
+// launched as back-to-back graph chunks of power-of-two lengths with one host
+// read at the end.  Later chunks are short, so few iterations run past
+// convergence as no-ops.  A fixed check_every overrides this.
 template <typename T>
 pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m_fixed, int *status,
                      bool adaptive)
 {
     const int slot = (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0);
     const int start_iter = g->hsc->iter_done;
-    int chunk = 0;
-    for (;; ++chunk) {
-        int m = m_fixed;
-        if (adaptive) {
-            const int expect = g->last_run[slot];
-            if (chunk == 0 && expect >= 8) {
-                m = 4;
-                while (m * 2 <= expect && m < 128) m *= 2;
-            } else if (chunk == 0) {
-                m = m_fixed;
-            } else {
-                m = 8;
-            }
+    for (int batch = 0;; ++batch) {
+        int parts[16];
+        int np = 0;
+        const int expect = g->last_run[slot];
+        if (adaptive && batch == 0 && expect >= 8) {
+            int total = std::max(2, (expect * 9 / 10) & ~1);
+            for (int m = 256; m >= 2 && np < 16; m >>= 1)
+                while (total >= m && np < 16) { parts[np++] = m; total -= m; }
+        } else {
+            parts[np++] = !adaptive ? m_fixed : (batch == 0 ? m_fixed : 8);
         }
         const int before = g->hsc->iter_done;
-        PFCHK(run_chunk<T>(g, op, dinv, w, m));
+        // only the batch's first chunk may be the timed sample: its events are
+        // read after the batch, and its iterations are the first ones run
+        for (int k = 0; k < np; ++k) PFCHK(run_chunk<T>(g, op, dinv, w, parts[k], k == 0));
+        const bool timed = np > 0 && g->last_timed_first;
         PFCHK(read_scalars(g));
-        if (g->last_timed && !op.psi) {
+        if (timed && !op.psi) {
             // iterations whose step A ran in full (later ones exit at once)
-            const int ran = std::min(m, g->hsc->iter_done - before);
+            const int ran = std::min(parts[0], g->hsc->iter_done - before);
             const int pi = sizeof(T) == 8 ? 0 : 1;
             for (int i = 0; i < ran; ++i) {
                 float ms = 0;
@@ -756,6 +761,20 @@ struct LinSolve {
     pf_status result = PF_OK;
 };
 
+// True residual of the current x into red[0] (and the shadow / FP32 copies
+// the next Krylov run starts from).  Asynchronous.
+pf_status ls_round_residual(LinSolve &L)
+{
+    pf_grid *g = L.g;
+    if (L.mixed)
+        PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, nullptr, g->w32.r, g->w32.rt));
+    else
+        PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, g->w64.rt, nullptr, nullptr));
+    return PF_OK;
+}
+
+// dinv, Dirichlet values, ||b_lift||^2 into red[1] and the first true
+// residual into red[0]: one host read for both.
 pf_status ls_init_launch(LinSolve &L)
 {
     pf_grid *g = L.g;
@@ -772,7 +791,8 @@ pf_status ls_init_launch(LinSolve &L)
     hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
                        (const uint8_t *)g->flags, dirbit(L.op), L.op.psi ? nullptr : (const double *)g->dval);
     HIPCHK(hipGetLastError());
-    PFCHK(residual64(g, L.op, L.dinv64, g->b64, nullptr, g->w64.r, true, nullptr, nullptr, nullptr));
+    PFCHK(residual64(g, L.op, L.dinv64, g->b64, nullptr, g->w64.r, true, nullptr, nullptr, nullptr, 1));
+    PFCHK(ls_round_residual(L));
     HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
     return PF_OK;
 }
@@ -781,7 +801,7 @@ pf_status ls_init_launch(LinSolve &L)
 pf_status ls_init_decide(LinSolve &L)
 {
     pf_grid *g = L.g;
-    L.bnorm = std::sqrt(g->hsc->red[0]);
+    L.bnorm = std::sqrt(g->hsc->red[1]);
     if (!std::isfinite(L.bnorm)) {
         L.done = true;
         L.result = PF_ERR_NONFINITE;
@@ -802,12 +822,8 @@ pf_status ls_init_decide(LinSolve &L)
 
 pf_status ls_round_launch(LinSolve &L)
 {
-    pf_grid *g = L.g;
-    if (L.mixed)
-        PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, nullptr, g->w32.r, g->w32.rt));
-    else
-        PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, g->w64.rt, nullptr, nullptr));
-    HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
+    PFCHK(ls_round_residual(L));
+    HIPCHK(hipMemcpyAsync(L.g->hsc, L.g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, L.g->stream));
     return PF_OK;
 }
 
@@ -882,9 +898,13 @@ pf_status solve_internal(pf_grid *g, const OpDesc &op, const pf_lin_opts *o, pf_
     PFCHK(sync(g));
     PFCHK(ls_init_decide(L));
     const int m = chunk_len(g, o);
+    bool first = true;   // the first true residual came with the init read
     while (!L.done) {
-        PFCHK(ls_round_launch(L));
-        PFCHK(sync(g));
+        if (!first) {
+            PFCHK(ls_round_launch(L));
+            PFCHK(sync(g));
+        }
+        first = false;
         bool run = false;
         PFCHK(ls_round_decide(L, &run));
         if (!run) break;
@@ -1044,10 +1064,12 @@ pf_status solve_batch(std::vector<LinSolve> &Ls)
     hipStream_t bs = Ls[0].g->stream;
     int m = 16;
     for (auto &L : Ls) m = std::max(m, chunk_len(L.g, L.o));
-    for (;;) {
-        for (auto &L : Ls)
-            if (!L.done) PFCHK(ls_round_launch(L));
-        for (auto &L : Ls) PFCHK(sync(L.g));
+    for (bool first = true;; first = false) {
+        if (!first) {   // the first true residuals came with the init read
+            for (auto &L : Ls)
+                if (!L.done) PFCHK(ls_round_launch(L));
+            for (auto &L : Ls) PFCHK(sync(L.g));
+        }
         std::vector<LinSolve *> act;
         for (auto &L : Ls) {
             if (L.done) continue;
@@ -1289,11 +1311,10 @@ pf_status pf_residual(pf_grid *g, const double *sigma, const double *b, const do
     op.sigma = sigma;
     PFCHK(compute_dinv<double>(g, op, g->dinv64));
     double *rbuf = r ? r : g->w64.r;
-    PFCHK(residual64(g, op, g->dinv64, b, nullptr, rbuf, true, nullptr, nullptr, nullptr));
+    PFCHK(residual64(g, op, g->dinv64, b, nullptr, rbuf, true, nullptr, nullptr, nullptr, 1));
+    PFCHK(residual64(g, op, g->dinv64, b, x, rbuf, false, nullptr, nullptr, nullptr, 0));
     PFCHK(read_scalars(g));
-    const double bn2 = g->hsc->red[0];
-    PFCHK(residual64(g, op, g->dinv64, b, x, rbuf, false, nullptr, nullptr, nullptr));
-    PFCHK(read_scalars(g));
+    const double bn2 = g->hsc->red[1];
     const double rr = g->hsc->red[0];
     *rel_res = bn2 > 0 ? std::sqrt(rr / bn2) : (rr == 0 ? 0.0 : INFINITY);
     return PF_OK;

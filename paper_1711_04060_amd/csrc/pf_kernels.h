@@ -961,16 +961,17 @@ struct FinArgs {
     Scalars *sc;
     const double *partials;
     int G;
+    int slot;   // result goes to red[slot]
 };
 
 // FIN_SUM / FIN_MAX finish the standalone residual and relaxation reductions
-// into red[0] (the BiCGSTAB steps finish each other's sums themselves).
+// into red[slot] (the BiCGSTAB steps finish each other's sums themselves).
 template <int KIND>
 __device__ __forceinline__ void finalize_block(const FinArgs &f)
 {
     double tot[1];
     final_reduce<1, 256, KIND == FIN_MAX>(tot, f.partials, f.G);
-    if (threadIdx.x == 0) f.sc->red[0] = tot[0];
+    if (threadIdx.x == 0) f.sc->red[f.slot] = tot[0];
 }
 
 template <int KIND>
