@@ -138,18 +138,21 @@ def forms_batch(pf, torch, inputs):
     return res
 
 
-def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400):
+def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0):
     """Configuration 5: 16 bias voltages on the membrane workload, full PF
     nonlinear solves, batched (shared launches, mixed-precision linear
     solves) vs 16 sequential FP64 solves.  Each run is driven in chunks of
     `chunk` outer iterations (warm-started from the last iterate, which is the
-    whole state of the outer loop) so that progress is printed."""
+    whole state of the outer loop) so that progress is printed.  outer_cap > 0
+    stops every bias after that many outer iterations (equal work in both
+    modes: a throughput comparison instead of time to convergence)."""
     vt = inputs.thermal_voltage_mV()
     probs = [inputs.membrane_pore(n, bias_phi=v / vt) for v in inputs.bias_sweep_mV()]
     grids = [pf.grid_from_problem(p) for p in probs]
     res = {}
     for name, prec, batched in (("batched_mixed", pf.PF_MIXED, True), ("sequential_fp64", pf.PF_FP64, False)):
-        prms = [pf.params_for(p, outer_tol=1e-8, max_outer=chunk, lin={"rel_tol": 1e-10, "precision": prec})
+        step = min(chunk, outer_cap) if outer_cap else chunk
+        prms = [pf.params_for(p, outer_tol=1e-8, max_outer=step, lin={"rel_tol": 1e-10, "precision": prec})
                 for p in probs]
         phis = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
         outer = [0] * len(probs)
@@ -170,8 +173,11 @@ def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400):
                     outer[i] += info["outer_iters"]
                     lin += info["total_lin_iters"]
                     prms[i].c.warm_start = 1
-                    if info["status"] == pf.PF_ERR_NOCONV and outer[i] < 20000:
+                    cap = outer_cap if outer_cap else 20000
+                    if info["status"] == pf.PF_ERR_NOCONV and outer[i] < cap:
                         nxt.append(i)
+                    elif info["status"] == pf.PF_ERR_NOCONV and outer_cap:
+                        pass   # stopped at the cap on purpose
                     elif info["status"] != 0:
                         raise RuntimeError(f"bias {i}: status {info['status']}")
                 todo = nxt
@@ -181,7 +187,8 @@ def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400):
         res[name] = dict(seconds=time.perf_counter() - t0, outer_iters=outer, total_lin_iters=lin)
         log(f"[bench] bias sweep {name}: {res[name]['seconds']:.1f} s")
     res["speedup"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
-    res["workload"] = f"membrane_pore {n}^3, 16 biases -150..+150 mV on -z, outer 1e-8, BiCGSTAB 1e-10"
+    res["workload"] = (f"membrane_pore {n}^3, 16 biases -150..+150 mV on -z, outer 1e-8, BiCGSTAB 1e-10"
+                       + (f", every bias stopped after {outer_cap} outer iterations" if outer_cap else ""))
     return res
 
 
@@ -254,6 +261,8 @@ def main():
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--n", type=int, default=97)
     ap.add_argument("--bias-sweep", type=int, default=0, help="also run configuration 5 (16 biases, 129^3)")
+    ap.add_argument("--bias-outer", type=int, default=0,
+                    help="configuration 5: stop every bias after this many outer iterations (0: converge)")
     ap.add_argument("--max-outer", type=int, default=0, help="bounded outer loop (profiler runs only)")
     ap.add_argument("--copy-ref", type=int, default=0, help="run the copy reference kernel (counter scale)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -344,7 +353,8 @@ def main():
         result["forms"]["batch_64"] = forms_batch(pf, torch, inputs)
     if args.bias_sweep:
         log("[bench] forms: 16-bias sweep at 129^3")
-        result.setdefault("forms", {})["bias_sweep_129"] = forms_bias_sweep(pf, torch, inputs)
+        result.setdefault("forms", {})["bias_sweep_129"] = forms_bias_sweep(pf, torch, inputs,
+                                                                           outer_cap=args.bias_outer)
     if args.cpu:
         log("[bench] cpu baseline (oracle sample)")
         result["cpu_baseline"] = cpu_baseline(prob, lin_iters)

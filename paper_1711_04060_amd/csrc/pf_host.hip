@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using pfk::Scalars;
@@ -151,7 +152,8 @@ struct pf_grid {
     double *dval = nullptr;
     double *q = nullptr;               // fixed charge (may stay null)
 
-    ZCfg c64, c32;
+    ZCfg c64, c32;     // step A of BiCGSTAB, residual and products
+    ZCfg cb64, cb32;   // step B of BiCGSTAB (tuned on its own: lighter kernel)
     int Gmax = 1;
 
     // linear solver state
@@ -339,6 +341,13 @@ ZCfg &cfg_ref(pf_grid *g)
     else return g->c32;
 }
 
+template <typename T>
+ZCfg &cfgb_ref(pf_grid *g)
+{
+    if constexpr (sizeof(T) == 8) return g->cb64;
+    else return g->cb32;
+}
+
 // Operator description: which system (potential or PF1 density), constant
 // coefficient or not, diagonal shift.
 struct OpDesc {
@@ -377,10 +386,10 @@ pfk::ZArgs<T> zbase(pf_grid *g, const OpDesc &op, const T *dinv)
     return zbase_cfg<T>(g, op, dinv, cfg_of<T>(g));
 }
 
+// Launch with the shape c (the one a was built for).
 template <int OP, typename T>
-pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a)
+pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a, const ZCfg &c)
 {
-    const ZCfg &c = cfg_of<T>(g);
     hipError_t e = op.psi ? launch_z<OP, T, true>(c, a, g->stream) : launch_z<OP, T, false>(c, a, g->stream);
     if (e != hipSuccess) return fail(PF_ERR_DEVICE, "stencil kernel launch failed: %s", hipGetErrorString(e));
     return PF_OK;
@@ -436,7 +445,7 @@ pf_status residual64(pf_grid *g, const OpDesc &op, const double *dinv, const dou
         a.lift = 1;
         a.dval = nullptr;
     }
-    PFCHK((zlaunch<pfk::OP_RESID, double>(g, op, a)));
+    PFCHK((zlaunch<pfk::OP_RESID, double>(g, op, a, cfg_of<double>(g))));
     // the partials buffer is reused by the next standalone reduction, which
     // follows in stream order
     return finalize<pfk::FIN_SUM>(g, a.G, slot);
@@ -458,7 +467,8 @@ pf_status write_scalars(pf_grid *g)
 // the p/v ping-pong buffers: step A reads p[parity], v[parity] and writes
 // p[parity^1], v[parity^1].
 template <typename T>
-pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c)
+pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c,
+                     int Gb)
 {
     pfk::ZArgs<T> a = zbase_cfg<T>(g, op, dinv, c);
     a.x = w.s;
@@ -472,13 +482,14 @@ pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
     a.out_r = w.r;
     a.partials = g->partA;
     a.pin = g->partB;
-    a.Gin = c.G;
+    a.Gin = Gb;
     a.parity = parity;
     return a;
 }
 
 template <typename T>
-pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c)
+pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c,
+                     int Ga)
 {
     pfk::ZArgs<T> b = zbase_cfg<T>(g, op, dinv, c);
     b.x = w.r;
@@ -488,7 +499,7 @@ pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
     b.out_aux = w.s;
     b.partials = g->partB;
     b.pin = g->partA;
-    b.Gin = c.G;
+    b.Gin = Ga;
     b.parity = parity;
     return b;
 }
@@ -499,11 +510,11 @@ template <typename T>
 pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity,
                     hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
-    const ZCfg &cfg = cfg_of<T>(g);
+    const ZCfg &ca = cfg_ref<T>(g), &cb = cfgb_ref<T>(g);
     if (e0) HIPCHK(hipEventRecord(e0, g->stream));
-    PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, dinv, w, parity, cfg))));
+    PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, dinv, w, parity, ca, cb.G), ca)));
     if (e1) HIPCHK(hipEventRecord(e1, g->stream));
-    PFCHK((zlaunch<pfk::OP_BB, T>(g, op, args_b<T>(g, op, dinv, w, parity, cfg))));
+    PFCHK((zlaunch<pfk::OP_BB, T>(g, op, args_b<T>(g, op, dinv, w, parity, cb, ca.G), cb)));
     return PF_OK;
 }
 
@@ -548,8 +559,9 @@ pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
 
 // ---------------------------------------------------------------- tuner
 
-// Launch shapes chosen per (grid shape, precision) for this process.
-std::map<std::tuple<int, int, int, int>, ZCfg> g_tuned;
+// Launch shapes chosen per (grid shape, precision) for this process: step A
+// (also used by the residual and product kernels) and step B.
+std::map<std::tuple<int, int, int, int>, std::pair<ZCfg, ZCfg>> g_tuned;
 
 bool tuning_enabled()
 {
@@ -558,10 +570,27 @@ bool tuning_enabled()
     return !g_nt_override && !g_ppt_override && !g_kz_override && !g_depth_override;
 }
 
-// Time one BiCGSTAB iteration (steps A and B, which share the shape) for each
-// candidate shape on this grid and keep the fastest.
-// Runs once per grid shape and precision; the grid's workspace holds
-// synthetic vectors meanwhile (every solve reinitialises it).
+// Candidate shapes of the z-march kernels on this grid.
+template <typename T>
+std::vector<ZCfg> tune_candidates(const pf_grid *g)
+{
+    std::vector<ZCfg> out;
+    const int shapes[6][2] = {{256, 1}, {256, 2}, {512, 1}, {512, 2}, {1024, 1}, {1024, 2}};
+    for (auto &sh : shapes)
+        for (int kz : {2, 4, 8, 16, 32})
+            for (int depth : {1, 2}) {
+                ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), sh[0], sh[1], kz, depth);
+                if (c.lds > LDS_MAX || c.G > g->Gmax || kz > g->nz) continue;
+                if ((c.wide && (c.NTZ != 1024 || c.PPT != 1)) || c.depth != depth) continue;
+                out.push_back(c);
+            }
+    return out;
+}
+
+// Time steps A and B of BiCGSTAB separately over the candidate shapes on this
+// grid (A from a fresh start, then B after one run of the best A) and keep
+// the fastest of each.  Runs once per grid shape and precision; the grid's
+// workspace holds synthetic vectors meanwhile (every solve reinitialises it).
 template <typename T>
 pf_status tune(pf_grid *g)
 {
@@ -569,7 +598,8 @@ pf_status tune(pf_grid *g)
     const auto key = std::make_tuple(g->nx, g->ny, g->nz, (int)sizeof(T));
     auto found = g_tuned.find(key);
     if (found != g_tuned.end()) {
-        cfg_ref<T>(g) = found->second;
+        cfg_ref<T>(g) = found->second.first;
+        cfgb_ref<T>(g) = found->second.second;
         return PF_OK;
     }
     Work<T> &w = [&]() -> Work<T> & {
@@ -588,61 +618,83 @@ pf_status tune(pf_grid *g)
     PFCHK(fill<T>(g, dinv, T(0.1), g->N));
     Scalars &h = *g->hsc;
     h = Scalars{};
-    h.rho[0] = h.rho[1] = 1.0; h.alpha[1] = 1.0; h.omega[1] = 1.0; h.stop = pfk::ST_RUN; h.fresh = 1;
+    h.rho[0] = h.rho[1] = 1.0; h.alpha[1] = 1.0; h.omega[1] = 1.0;
+    h.stop = pfk::ST_RUN; h.stop_a = pfk::ST_RUN; h.fresh = 1;
     h.maxit = 1 << 30;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    const ZCfg saved = cfg_ref<T>(g);
-    ZCfg best = saved;
-    float best_ms = 1e30f;
-    const int shapes[6][2] = {{256, 1}, {256, 2}, {512, 1}, {512, 2}, {1024, 1}, {1024, 2}};
+    const std::vector<ZCfg> cand = tune_candidates<T>(g);
     OpDesc op;
     pf_status st = PF_OK;
-    for (auto &sh : shapes) {
-        for (int kz : {2, 4, 8, 16, 32}) {
-          for (int depth : {1, 2}) {
-            ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), sh[0], sh[1], kz, depth);
-            if (c.lds > LDS_MAX || c.G > g->Gmax || kz > g->nz || (c.wide && (c.NTZ != 1024 || c.PPT != 1))) continue;
-            if (c.depth != depth) continue;
-            cfg_ref<T>(g) = c;
-            pfk::ZArgs<T> a = args_a<T>(g, op, dinv, w, 0, c);
-            a.xio = w.r;   // keep the caller's iterate: the timed launches update r in its place
-            const pfk::ZArgs<T> b = args_b<T>(g, op, dinv, w, 0, c);
-            float tot = 0;
-            for (int rep = 0; rep < 4 && st == PF_OK; ++rep) {
-                if ((st = write_scalars(g)) != PF_OK) break;
-                if (hipEventRecord(e0, g->stream) != hipSuccess) { st = fail(PF_ERR_DEVICE, "event record failed"); break; }
-                if (zlaunch<pfk::OP_BA, T>(g, op, a) != PF_OK || zlaunch<pfk::OP_BB, T>(g, op, b) != PF_OK) {
-                    // shape not launchable here: skip it
-                    (void)hipGetLastError();
-                    g_err.clear();
-                    tot = 1e30f;
-                    break;
-                }
-                if (hipEventRecord(e1, g->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    st = fail(PF_ERR_DEVICE, "event timing failed");
-                    break;
-                }
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (rep > 0) tot += ms;
-            }
-            if (st != PF_OK) break;
-            if (tot < best_ms) { best_ms = tot; best = c; }
-          }
-          if (st != PF_OK) break;
+    // mean time per launch of step OP with shape c over 8 back-to-back
+    // launches (after one untimed launch), the best of two such runs; 1e30 if
+    // the shape cannot be launched here
+    auto time_step = [&](auto opc, const pfk::ZArgs<T> &a, const ZCfg &c) -> float {
+        constexpr int OPV = decltype(opc)::value;
+        constexpr int K = 8;
+        float best = 1e30f;
+        if ((st = write_scalars(g)) != PF_OK) return 1e30f;
+        if (zlaunch<OPV, T>(g, op, a, c) != PF_OK) {
+            (void)hipGetLastError();
+            g_err.clear();
+            return 1e30f;
         }
+        for (int run = 0; run < 2; ++run) {
+            if ((st = write_scalars(g)) != PF_OK) return 1e30f;
+            if (hipEventRecord(e0, g->stream) != hipSuccess) {
+                st = fail(PF_ERR_DEVICE, "event record failed");
+                return 1e30f;
+            }
+            for (int k = 0; k < K; ++k)
+                if ((st = zlaunch<OPV, T>(g, op, a, c)) != PF_OK) return 1e30f;
+            if (hipEventRecord(e1, g->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(PF_ERR_DEVICE, "event timing failed");
+                return 1e30f;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, ms / K);
+        }
+        return best;
+    };
+    using OpA = std::integral_constant<int, pfk::OP_BA>;
+    using OpB = std::integral_constant<int, pfk::OP_BB>;
+    ZCfg bestA = cfg_ref<T>(g), bestB = cfgb_ref<T>(g);
+    float msA = 1e30f, msB = 1e30f;
+    for (const ZCfg &c : cand) {
+        pfk::ZArgs<T> a = args_a<T>(g, op, dinv, w, 0, c, c.G);
+        a.xio = w.r;   // keep the caller's iterate: the timed launches update r in its place
+        const float ms = time_step(OpA{}, a, c);
         if (st != PF_OK) break;
+        if (ms < msA) { msA = ms; bestA = c; }
+    }
+    if (st == PF_OK) {
+        // one step A with the chosen shape provides step B's input partials
+        pfk::ZArgs<T> a = args_a<T>(g, op, dinv, w, 0, bestA, bestA.G);
+        a.xio = w.r;
+        st = write_scalars(g);
+        if (st == PF_OK) st = zlaunch<pfk::OP_BA, T>(g, op, a, bestA);
+        for (const ZCfg &c : cand) {
+            if (st != PF_OK) break;
+            const pfk::ZArgs<T> b = args_b<T>(g, op, dinv, w, 0, c, bestA.G);
+            const float ms = time_step(OpB{}, b, c);
+            if (st != PF_OK) break;
+            if (ms < msB) { msB = ms; bestB = c; }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    cfg_ref<T>(g) = (st == PF_OK) ? best : saved;
     if (st != PF_OK) return st;
-    g_tuned[key] = best;
+    cfg_ref<T>(g) = bestA;
+    cfgb_ref<T>(g) = bestB;
+    g_tuned[key] = {bestA, bestB};
     if (getenv("PF_LOG"))
-        fprintf(stderr, "[pf] tuned %dx%dx%d %s: threads %d, strip %d, z-planes %d, depth %d, iteration %.1f us\n", g->nx, g->ny,
-                g->nz, sizeof(T) == 8 ? "fp64" : "fp32", best.NTZ, best.S, best.KZ, best.depth, best_ms / 3 * 1e3);
+        fprintf(stderr,
+                "[pf] tuned %dx%dx%d %s: step A threads %d strip %d z-planes %d depth %d (%.1f us); "
+                "step B threads %d strip %d z-planes %d depth %d (%.1f us)\n",
+                g->nx, g->ny, g->nz, sizeof(T) == 8 ? "fp64" : "fp32", bestA.NTZ, bestA.S, bestA.KZ, bestA.depth,
+                msA * 1e3, bestB.NTZ, bestB.S, bestB.KZ, bestB.depth, msB * 1e3);
     return PF_OK;
 }
 
@@ -962,8 +1014,8 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         if constexpr (sizeof(T) == 8) { w = &g->w64; dinv = L.dinv64; }
         else { w = &g->w32; dinv = L.dinv32; }
         for (int par = 0; par < 2; ++par) {
-            za[par][i] = args_a<T>(g, L.op, dinv, *w, par, c);
-            zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, c);
+            za[par][i] = args_a<T>(g, L.op, dinv, *w, par, c, c.G);
+            zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, c, c.G);
         }
         zstart[i + 1] = zstart[i] + c.G;
         lds = std::max(lds, c.lds);
@@ -1203,8 +1255,8 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     g->bcphi_mask = bp; g->bcpsi_mask = bs;
     for (int f = 0; f < 6; ++f) g->bcval[f] = d->bc_value[f];
     g->ustream = (hipStream_t)d->stream;
-    g->c64 = default_cfg(d->nx, d->ny, d->nz, 8);
-    g->c32 = default_cfg(d->nx, d->ny, d->nz, 4);
+    g->c64 = g->cb64 = default_cfg(d->nx, d->ny, d->nz, 8);
+    g->c32 = g->cb32 = default_cfg(d->nx, d->ny, d->nz, 4);
     if (g->c64.lds > LDS_MAX || g->c32.lds > LDS_MAX) {
         delete g;
         return fail(PF_ERR_ARG, "nx too large for the LDS strip (nx <= ~4800)");
@@ -1332,8 +1384,8 @@ pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, i
     pfk::ZArgs<double> a = zbase<double>(g, op, g->dinv64);
     a.x = x;
     a.out = y;
-    if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a)));
-    else PFCHK((zlaunch<pfk::OP_SPMV, double>(g, op, a)));
+    if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a, cfg_of<double>(g))));
+    else PFCHK((zlaunch<pfk::OP_SPMV, double>(g, op, a, cfg_of<double>(g))));
     return sync(g);
 }
 
@@ -1350,7 +1402,7 @@ pf_status pf_spmv_f32(pf_grid *g, const double *sigma, const float *x, float *y,
     pfk::ZArgs<float> a = zbase<float>(g, op, g->dinv32);
     a.x = x;
     a.out = y;
-    PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a)));
+    PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a, cfg_of<float>(g))));
     return sync(g);
 }
 
