@@ -18,7 +18,9 @@ The JSON line also carries:
                 (its first outer iterations), scaled to a whole solve by the
                 number of BiCGSTAB iterations the solve needs;
   forms         FP64 vs mixed precision on the 193^3 Poisson problem and the
-                64-system batch, each to relative residual 1e-10.
+                64-system batch, each to relative residual 1e-10; the isolated
+                Jacobi-scaled stencil product at 193^3 with operands cycled
+                through three sets (cold in the Infinity Cache).
 """
 import argparse
 import hashlib
@@ -103,6 +105,34 @@ def forms_linear(pf, torch, inputs, timing_sample):
     out["mixed_vs_fp64_rel_l2"] = float(np.linalg.norm(d) / np.linalg.norm(xs["fp64"]))
     out["mixed_speedup"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
     out["workload"] = "sphere_poisson 193^3 (7,189,057 unknowns), rel res 1e-10"
+    return out
+
+
+def forms_spmv_cold(pf, torch, inputs, n=193, sets=3, reps=10):
+    """Isolated Jacobi-scaled stencil product A M^-1 x on the n^3 sphere
+    problem, FP64 and FP32, cycling through `sets` independent grids and
+    (x, y) pairs so that the 256 MB Infinity Cache cannot hold the operands
+    between launches (each FP64 set reads and writes 4 vectors of 57.5 MB at
+    193^3).  Kernel time from HIP events around each launch."""
+    prob = inputs.sphere_poisson(n)
+    grids = [pf.grid_from_problem(prob) for _ in range(sets)]
+    out = {"workload": f"sphere_poisson {n}^3, {sets} operand sets cycled, {reps} launches each"}
+    for name, dt, fn, kind in (("fp64", torch.float64, pf.pf_spmv, pf.TIMING_SPMV_FP64),
+                               ("fp32", torch.float32, pf.pf_spmv_f32, pf.TIMING_SPMV_FP32)):
+        xs = [torch.randn(prob.N, dtype=dt, device="cuda") for _ in range(sets)]
+        ys = [torch.empty(prob.N, dtype=dt, device="cuda") for _ in range(sets)]
+        for i in range(sets):
+            fn(grids[i], None, xs[i], ys[i], 1)   # untimed first launch per set
+        pf.pf_timing_enable(1, 1)
+        for _ in range(reps):
+            for i in range(sets):
+                fn(grids[i], None, xs[i], ys[i], 1)
+        tm = pf.pf_timing_read(kind)
+        pf.pf_timing_enable(0, 1)
+        bpl = tm["bytes"] / max(1, tm["launches"])
+        out[name] = dict(launches=tm["launches"], mean_us=tm["mean_ms"] * 1e3, bytes_per_launch=bpl,
+                         gbs=bpl / (tm["mean_ms"] * 1e-3) / 1e9 if tm["mean_ms"] > 0 else None)
+        out[name]["frac_of_8tbs"] = out[name]["gbs"] / PEAK_HBM_GBS if out[name]["gbs"] else None
     return out
 
 
@@ -351,6 +381,8 @@ def main():
         result["forms"] = {"linear_193": forms_linear(pf, torch, inputs, args.sample)}
         log("[bench] forms: 64-system batch")
         result["forms"]["batch_64"] = forms_batch(pf, torch, inputs)
+        log("[bench] forms: isolated cold stencil product at 193^3")
+        result["forms"]["spmv_cold_193"] = forms_spmv_cold(pf, torch, inputs)
     if args.bias_sweep:
         log("[bench] forms: 16-bias sweep at 129^3")
         result.setdefault("forms", {})["bias_sweep_129"] = forms_bias_sweep(pf, torch, inputs,

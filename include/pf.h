@@ -207,19 +207,24 @@ pf_status pf_nonlinear_solve_batch(int32_t n, pf_grid *const *g, const pf_pf_par
                                    double *const *phi, pf_nl_info *info);
 
 /* Kernel timing for measurement: while enabled, one chunk in every `sample`
- * records HIP events (as graph nodes, on the library's stream) around each
- * launch of the BiCGSTAB step-A stencil kernel (the update of p fused with
- * v = A M^-1 p, the kernel that moves the most bytes per iteration).
+ * records HIP events (on the library's stream, as direct launches) around
+ * each launch of the BiCGSTAB step-A stencil kernel (the previous
+ * iteration's x, r update fused with the p update and v = A M^-1 p: the
+ * kernel that moves the most bytes per iteration), and every Jacobi-scaled
+ * pf_spmv / pf_spmv_f32 call records events around its kernel.
  * enable = 1 clears the accumulators and starts; 0 stops.  Process-wide. */
 pf_status pf_timing_enable(int32_t enable, int32_t sample);
 
-/* Accumulated step-A timings for one precision (PF_FP64 or PF_MIXED = the
- * FP32 inner kernel): launches timed and their mean duration in ms; bytes is
- * the algorithmic HBM traffic of those launches (8 vectors of N elements per
- * launch: r, p, v, dinv, eps, shadow read; p, v written).  The mean excludes
- * the event-bracket latency (dispatch and completion of the launch), which
- * pf_timing_enable measures around an empty one-workgroup kernel. */
-pf_status pf_timing_read(int32_t precision, int64_t *launches, double *mean_ms, double *bytes);
+/* Accumulated timings of one kind: 0 (PF_FP64) and 1 (PF_MIXED, the FP32
+ * inner kernel) = BiCGSTAB step A; 2 and 3 = the Jacobi-scaled products of
+ * pf_spmv and pf_spmv_f32.  launches timed and their mean duration in ms;
+ * bytes is the algorithmic HBM traffic of those launches (step A: 12 vectors
+ * of N elements per launch, s, t, x, p, v, shadow, dinv, eps read and x, r,
+ * p, v written; products: x, eps, dinv read and y written).  The mean
+ * excludes the event-bracket latency (dispatch and completion of the
+ * launch), which pf_timing_enable measures around an empty one-workgroup
+ * kernel.  PF_ERR_ARG for another kind. */
+pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, double *bytes);
 
 /* Thread-local description of the last error (empty string if none). */
 const char *pf_last_error(void);

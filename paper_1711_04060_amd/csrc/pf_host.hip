@@ -57,14 +57,16 @@ constexpr int PW_MAX_G = 1024;   // workgroups of the pointwise kernels
 // launch override (pf_set_launch): threads, points per thread, z-planes
 int g_nt_override = 0, g_ppt_override = 0, g_kz_override = 0, g_depth_override = 0;
 
-// step-A kernel timing (pf_timing_enable / pf_timing_read)
+// kernel timing (pf_timing_enable / pf_timing_read): slots 0, 1 = BiCGSTAB
+// step A in FP64 / FP32; 2, 3 = Jacobi-scaled products of pf_spmv / pf_spmv_f32
 struct Timing {
     bool enabled = false;
     int sample = 8;
     long chunk = 0;
-    long long launches[2] = {0, 0};
-    double ms[2] = {0, 0}, bytes[2] = {0, 0};
+    long long launches[4] = {0, 0, 0, 0};
+    double ms[4] = {0, 0, 0, 0}, bytes[4] = {0, 0, 0, 0};
     double bracket_ms = 0;   // latency of an event bracket around an empty kernel
+    hipEvent_t p0 = nullptr, p1 = nullptr;   // around product launches
 } g_timing;
 
 constexpr size_t LDS_MAX = 152 * 1024;   // dynamic LDS per workgroup (gfx950 has 160 KB; static arrays use the rest)
@@ -1140,6 +1142,18 @@ pf_status solve_batch(std::vector<LinSolve> &Ls)
     return PF_OK;
 }
 
+// Account one timed product launch (events p0, p1 already complete):
+// bytes = x, eps, dinv read and y written.
+pf_status timing_add_product(int slot, double bytes)
+{
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, g_timing.p0, g_timing.p1));
+    g_timing.ms[slot] += ms;
+    g_timing.launches[slot] += 1;
+    g_timing.bytes[slot] += bytes;
+    return PF_OK;
+}
+
 pf_status check_grid(const pf_grid *g)
 {
     if (!g) return fail(PF_ERR_ARG, "null grid");
@@ -1173,10 +1187,15 @@ void pf_lin_opts_default(pf_lin_opts *o)
 pf_status pf_timing_enable(int32_t enable, int32_t sample)
 {
     if (sample <= 0) return fail(PF_ERR_ARG, "sample must be > 0");
+    const hipEvent_t p0 = g_timing.p0, p1 = g_timing.p1;
     g_timing = Timing{};
+    g_timing.p0 = p0;
+    g_timing.p1 = p1;
     g_timing.enabled = enable != 0;
     g_timing.sample = sample;
     if (!g_timing.enabled) return PF_OK;
+    if (!g_timing.p0) HIPCHK(hipEventCreate(&g_timing.p0));
+    if (!g_timing.p1) HIPCHK(hipEventCreate(&g_timing.p1));
     // An event pair around a launch also times the dispatch of the kernel
     // packet and its completion signal.  Measure that bracket around an empty
     // one-workgroup kernel launched the same way; pf_timing_read subtracts it.
@@ -1203,10 +1222,10 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample)
     return PF_OK;
 }
 
-pf_status pf_timing_read(int32_t precision, int64_t *launches, double *mean_ms, double *bytes)
+pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, double *bytes)
 {
-    if (precision != PF_FP64 && precision != PF_MIXED) return fail(PF_ERR_ARG, "unknown precision");
-    const int i = precision == PF_FP64 ? 0 : 1;
+    if (kind < 0 || kind > 3) return fail(PF_ERR_ARG, "kind must be 0..3");
+    const int i = kind;
     if (launches) *launches = g_timing.launches[i];
     if (mean_ms)
         *mean_ms = g_timing.launches[i]
@@ -1384,9 +1403,14 @@ pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, i
     pfk::ZArgs<double> a = zbase<double>(g, op, g->dinv64);
     a.x = x;
     a.out = y;
+    const bool timed = jacobi && g_timing.enabled;
+    if (timed) HIPCHK(hipEventRecord(g_timing.p0, g->stream));
     if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a, cfg_of<double>(g))));
     else PFCHK((zlaunch<pfk::OP_SPMV, double>(g, op, a, cfg_of<double>(g))));
-    return sync(g);
+    if (timed) HIPCHK(hipEventRecord(g_timing.p1, g->stream));
+    PFCHK(sync(g));
+    if (timed) PFCHK(timing_add_product(2, 4.0 * (double)g->N * sizeof(double)));
+    return PF_OK;
 }
 
 pf_status pf_spmv_f32(pf_grid *g, const double *sigma, const float *x, float *y, int32_t jacobi)
@@ -1402,8 +1426,13 @@ pf_status pf_spmv_f32(pf_grid *g, const double *sigma, const float *x, float *y,
     pfk::ZArgs<float> a = zbase<float>(g, op, g->dinv32);
     a.x = x;
     a.out = y;
+    const bool timed = g_timing.enabled;
+    if (timed) HIPCHK(hipEventRecord(g_timing.p0, g->stream));
     PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a, cfg_of<float>(g))));
-    return sync(g);
+    if (timed) HIPCHK(hipEventRecord(g_timing.p1, g->stream));
+    PFCHK(sync(g));
+    if (timed) PFCHK(timing_add_product(3, 4.0 * (double)g->N * sizeof(float)));
+    return PF_OK;
 }
 
 // ------------------------------------------------------------ nonlinear

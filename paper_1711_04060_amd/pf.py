@@ -301,9 +301,13 @@ def pf_timing_enable(enable=1, sample=8):
     _check(load().pf_timing_enable(int(enable), int(sample)), "pf_timing_enable")
 
 
-def pf_timing_read(precision=PF_FP64):
+TIMING_SPMV_FP64, TIMING_SPMV_FP32 = 2, 3   # pf_timing_read kinds of the isolated products
+
+
+def pf_timing_read(kind=PF_FP64):
+    """kind: PF_FP64 / PF_MIXED (BiCGSTAB step A), TIMING_SPMV_FP64 / TIMING_SPMV_FP32."""
     n, ms, by = C.c_int64(), C.c_double(), C.c_double()
-    _check(load().pf_timing_read(int(precision), C.byref(n), C.byref(ms), C.byref(by)), "pf_timing_read")
+    _check(load().pf_timing_read(int(kind), C.byref(n), C.byref(ms), C.byref(by)), "pf_timing_read")
     return dict(launches=n.value, mean_ms=ms.value, bytes=by.value)
 
 

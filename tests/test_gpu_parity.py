@@ -403,3 +403,25 @@ def test_nonlinear_batch_bias_sweep_matches_oracle():
         ref, _, _, _ = oracle.nonlinear_solve(p, p.fixed_charge, sp, 78.45, 1.9, outer_tol=1e-11, lin_tol=1e-13)
         assert info["status"] == 0
         assert _rel(host(phi), ref) <= 1e-9
+
+
+def test_timing_of_products_and_bad_kind():
+    """pf_timing_read kinds 2 and 3 count the Jacobi-scaled products."""
+    pf = _pf()
+    p = inputs.sphere_poisson(33)
+    g = pf.grid_from_problem(p)
+    x = torch.ones(p.N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    pf.pf_timing_enable(1, 1)
+    try:
+        pf.pf_spmv(g, None, x, y, 1)
+        pf.pf_spmv(g, None, x, y, 0)          # the plain product is not timed
+        pf.pf_spmv_f32(g, None, x.float(), y.float(), 1)
+        t64 = pf.pf_timing_read(pf.TIMING_SPMV_FP64)
+        t32 = pf.pf_timing_read(pf.TIMING_SPMV_FP32)
+        assert t64["launches"] == 1 and t64["bytes"] == 4 * p.N * 8 and t64["mean_ms"] >= 0
+        assert t32["launches"] == 1 and t32["bytes"] == 4 * p.N * 4
+        with pytest.raises(pf.PfError):
+            pf.pf_timing_read(4)
+    finally:
+        pf.pf_timing_enable(0, 1)
