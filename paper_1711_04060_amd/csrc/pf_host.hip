@@ -303,10 +303,10 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
     }
 }
 
-template <int OP, typename T, bool CEPS, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, int NTZ, int PPT, bool WIDE, int DEPTH>
 hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
 {
-    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, 512, 1, WIDE, DEPTH>;
+    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, NTZ, PPT, WIDE, DEPTH>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;
         if (c.lds > granted) {
@@ -316,17 +316,39 @@ hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *s
             granted = c.lds;
         }
     }
-    hipLaunchKernelGGL(kern, dim3(c.G), dim3(512), c.lds, s, args, start, n);
+    hipLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), c.lds, s, args, start, n);
     return hipGetLastError();
 }
 
-// c: the batch's combined shape (G = all tiles, lds and wide = the maxima)
+// c: the batch's combined launch (its NTZ, PPT, depth shared by every member;
+// G = all members' tiles, lds and wide = the maxima)
 template <int OP, typename T, bool CEPS>
 hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
 {
-    if (c.wide) return launch_batch_k<OP, T, CEPS, true, 1>(c, args, start, n, s);
-    return c.depth == 2 ? launch_batch_k<OP, T, CEPS, false, 2>(c, args, start, n, s)
-                        : launch_batch_k<OP, T, CEPS, false, 1>(c, args, start, n, s);
+    if (c.wide) {
+        if (c.NTZ == 1024 && c.PPT == 1) return launch_batch_k<OP, T, CEPS, 1024, 1, true, 1>(c, args, start, n, s);
+        return hipErrorInvalidValue;
+    }
+    if (c.depth == 2) {
+        switch (c.NTZ * 10 + c.PPT) {
+        case 2561: return launch_batch_k<OP, T, CEPS, 256, 1, false, 2>(c, args, start, n, s);
+        case 2562: return launch_batch_k<OP, T, CEPS, 256, 2, false, 2>(c, args, start, n, s);
+        case 5121: return launch_batch_k<OP, T, CEPS, 512, 1, false, 2>(c, args, start, n, s);
+        case 5122: return launch_batch_k<OP, T, CEPS, 512, 2, false, 2>(c, args, start, n, s);
+        case 10241: return launch_batch_k<OP, T, CEPS, 1024, 1, false, 2>(c, args, start, n, s);
+        case 10242: return launch_batch_k<OP, T, CEPS, 1024, 2, false, 2>(c, args, start, n, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (c.NTZ * 10 + c.PPT) {
+    case 2561: return launch_batch_k<OP, T, CEPS, 256, 1, false, 1>(c, args, start, n, s);
+    case 2562: return launch_batch_k<OP, T, CEPS, 256, 2, false, 1>(c, args, start, n, s);
+    case 5121: return launch_batch_k<OP, T, CEPS, 512, 1, false, 1>(c, args, start, n, s);
+    case 5122: return launch_batch_k<OP, T, CEPS, 512, 2, false, 1>(c, args, start, n, s);
+    case 10241: return launch_batch_k<OP, T, CEPS, 1024, 1, false, 1>(c, args, start, n, s);
+    case 10242: return launch_batch_k<OP, T, CEPS, 1024, 2, false, 1>(c, args, start, n, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
@@ -983,14 +1005,47 @@ struct BatchBuf {
     int hcap = 0;
 } g_batch;
 
-// Shape shared by every member of a batched launch (one kernel instance):
-// 512 threads, one node per thread, z-chunks sized per grid.
-ZCfg batch_cfg(const pf_grid *g, size_t elem)
+// Launch of one batched BiCGSTAB step: every member shares the kernel
+// instance (threads, nodes per thread, pipeline depth).  Each member grid has
+// been autotuned on its own (first use of its shape); the batch takes the
+// instance most of the work was tuned to (weighted by N) and gives every
+// member the z-chunk length of its own tuned shape.  step: 0 = A, 1 = B.
+template <typename T>
+std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, ZCfg &combined)
 {
-    const int P = g->nx * g->ny;
-    const long strips = (P + 511) / 512;
-    const int kz = (int)std::max<long>(2, std::min<long>(16, strips * g->nz / 256));
-    return make_cfg(g->nx, g->ny, g->nz, elem, 512, 1, kz);
+    std::map<std::tuple<int, int, int>, double> weight;
+    for (const LinSolve *L : act) {
+        const ZCfg &t = step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g);
+        weight[std::make_tuple(t.NTZ, t.PPT, t.depth)] += (double)L->g->N;
+    }
+    auto best = std::max_element(weight.begin(), weight.end(),
+                                 [](const auto &x, const auto &y) { return x.second < y.second; });
+    const int ntz = std::get<0>(best->first), ppt = std::get<1>(best->first), depth = std::get<2>(best->first);
+    std::vector<ZCfg> cs;
+    combined = ZCfg{};
+    combined.NTZ = ntz;
+    combined.PPT = ppt;
+    combined.depth = depth;
+    combined.G = 0;
+    for (const LinSolve *L : act) {
+        const pf_grid *g = L->g;
+        const ZCfg &t = step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g);
+        ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), ntz, ppt, t.KZ, depth);
+        cs.push_back(c);
+        combined.G += c.G;
+        combined.lds = std::max(combined.lds, c.lds);
+        combined.wide = combined.wide || c.wide;
+    }
+    if (combined.wide) {   // only the 1024-thread, one-node-per-thread instance has the WIDE form
+        combined.NTZ = 1024; combined.PPT = 1; combined.depth = 1; combined.G = 0; combined.lds = 0;
+        for (size_t i = 0; i < act.size(); ++i) {
+            const pf_grid *g = act[i]->g;
+            cs[i] = make_cfg(g->nx, g->ny, g->nz, sizeof(T), 1024, 1, cs[i].KZ, 1);
+            combined.G += cs[i].G;
+            combined.lds = std::max(combined.lds, cs[i].lds);
+        }
+    }
+    return cs;
 }
 
 // Run the Krylov iterations of all listed systems (same precision, same
@@ -1002,34 +1057,32 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     const int n = (int)act.size();
     const bool psi = act[0]->op.psi;
     std::vector<pfk::ZArgs<T>> za[2], zb[2];
-    std::vector<int> zstart(n + 1, 0);
+    std::vector<int> astart(n + 1, 0), bstart(n + 1, 0);
     std::vector<const Scalars *> scp(n);
-    size_t lds = 0;
-    bool wide = false;
+    ZCfg ca, cb;   // combined launches of steps A and B
+    const std::vector<ZCfg> csa = batch_shapes<T>(act, 0, ca), csb = batch_shapes<T>(act, 1, cb);
     for (int par = 0; par < 2; ++par) { za[par].resize(n); zb[par].resize(n); }
     for (int i = 0; i < n; ++i) {
         LinSolve &L = *act[i];
         pf_grid *g = L.g;
-        const ZCfg c = batch_cfg(g, sizeof(T));
         Work<T> *w;
         const T *dinv;
         if constexpr (sizeof(T) == 8) { w = &g->w64; dinv = L.dinv64; }
         else { w = &g->w32; dinv = L.dinv32; }
         for (int par = 0; par < 2; ++par) {
-            za[par][i] = args_a<T>(g, L.op, dinv, *w, par, c, c.G);
-            zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, c, c.G);
+            za[par][i] = args_a<T>(g, L.op, dinv, *w, par, csa[i], csb[i].G);
+            zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, csb[i], csa[i].G);
         }
-        zstart[i + 1] = zstart[i] + c.G;
-        lds = std::max(lds, c.lds);
-        wide = wide || c.wide;
+        astart[i + 1] = astart[i] + csa[i].G;
+        bstart[i + 1] = bstart[i] + csb[i].G;
         scp[i] = g->sc;
     }
-    if (lds > LDS_MAX) return fail(PF_ERR_ARG, "batch member too wide for the LDS strip");
+    if (ca.lds > LDS_MAX || cb.lds > LDS_MAX) return fail(PF_ERR_ARG, "batch member too wide for the LDS strip");
     // device tables
     const size_t szZ = sizeof(pfk::ZArgs<T>) * n;
     const size_t szI = sizeof(int) * (n + 1), szP = sizeof(void *) * n, szS = sizeof(Scalars) * n;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t need = 4 * al(szZ) + al(szI) + al(szP) + al(szS);
+    const size_t need = 4 * al(szZ) + 2 * al(szI) + al(szP) + al(szS);
     if (need > g_batch.bytes) {
         if (g_batch.dev) (void)hipFree(g_batch.dev);
         g_batch.dev = nullptr;
@@ -1050,27 +1103,25 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     auto take = [&](size_t sz) { char *p = base + off; off += al(sz); return p; };
     pfk::ZArgs<T> *dA[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
     pfk::ZArgs<T> *dB[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
-    int *dzs = (int *)take(szI);
+    int *das = (int *)take(szI), *dbs = (int *)take(szI);
     const Scalars **dscp = (const Scalars **)take(szP);
     Scalars *dgather = (Scalars *)take(szS);
     for (int par = 0; par < 2; ++par) {
         HIPCHK(hipMemcpyAsync(dA[par], za[par].data(), szZ, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(dB[par], zb[par].data(), szZ, hipMemcpyHostToDevice, stream));
     }
-    HIPCHK(hipMemcpyAsync(dzs, zstart.data(), szI, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(das, astart.data(), szI, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dbs, bstart.data(), szI, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dscp, scp.data(), szP, hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
 
-    const int GZ = zstart[n];
     auto launch_iter = [&](int par) -> pf_status {
-        ZCfg c{};
-        c.NTZ = 512; c.PPT = 1; c.G = GZ; c.lds = lds; c.wide = wide; c.depth = default_depth(sizeof(T), 1);
         hipError_t e;
-        if (psi) e = launch_batch<pfk::OP_BA, T, true>(c, dA[par], dzs, n, stream);
-        else e = launch_batch<pfk::OP_BA, T, false>(c, dA[par], dzs, n, stream);
+        if (psi) e = launch_batch<pfk::OP_BA, T, true>(ca, dA[par], das, n, stream);
+        else e = launch_batch<pfk::OP_BA, T, false>(ca, dA[par], das, n, stream);
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
-        if (psi) e = launch_batch<pfk::OP_BB, T, true>(c, dB[par], dzs, n, stream);
-        else e = launch_batch<pfk::OP_BB, T, false>(c, dB[par], dzs, n, stream);
+        if (psi) e = launch_batch<pfk::OP_BB, T, true>(cb, dB[par], dbs, n, stream);
+        else e = launch_batch<pfk::OP_BB, T, false>(cb, dB[par], dbs, n, stream);
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
         return PF_OK;
     };
