@@ -154,8 +154,10 @@ struct pf_grid {
     double *dval = nullptr;
     double *q = nullptr;               // fixed charge (may stay null)
 
-    ZCfg c64, c32;     // step A of BiCGSTAB, residual and products
+    ZCfg c64, c32;     // step A of BiCGSTAB, residual and plain products
     ZCfg cb64, cb32;   // step B of BiCGSTAB (tuned on its own: lighter kernel)
+    ZCfg cp64, cp32;   // standalone Jacobi-scaled product (tuned on first use)
+    bool tunedp64 = false, tunedp32 = false;
     int Gmax = 1;
 
     // linear solver state
@@ -370,6 +372,13 @@ ZCfg &cfgb_ref(pf_grid *g)
 {
     if constexpr (sizeof(T) == 8) return g->cb64;
     else return g->cb32;
+}
+
+template <typename T>
+ZCfg &cfgp_ref(pf_grid *g)
+{
+    if constexpr (sizeof(T) == 8) return g->cp64;
+    else return g->cp32;
 }
 
 // Operator description: which system (potential or PF1 density), constant
@@ -719,6 +728,83 @@ pf_status tune(pf_grid *g)
                 "step B threads %d strip %d z-planes %d depth %d (%.1f us)\n",
                 g->nx, g->ny, g->nz, sizeof(T) == 8 ? "fp64" : "fp32", bestA.NTZ, bestA.S, bestA.KZ, bestA.depth,
                 msA * 1e3, bestB.NTZ, bestB.S, bestB.KZ, bestB.depth, msB * 1e3);
+    return PF_OK;
+}
+
+// Shapes of the standalone Jacobi-scaled product, per (grid shape, precision).
+std::map<std::tuple<int, int, int, int>, ZCfg> g_tuned_p;
+
+// Time the Jacobi-scaled product A M^-1 x over the candidate shapes on this
+// grid and keep the fastest.  Its four streams (x, 1/D, eps in; y out) favour
+// other shapes than the twelve of step A.  Timed launches cycle through four
+// (x, y) pairs of the grid's workspace so that consecutive launches do not
+// find their vectors in the Infinity Cache.  dinv must hold the operator's
+// inverse diagonal (any finite values would do for timing).
+template <typename T>
+pf_status tune_product(pf_grid *g, const OpDesc &op, const T *dinv)
+{
+    bool &done = sizeof(T) == 8 ? g->tunedp64 : g->tunedp32;
+    if (done || !tuning_enabled()) return PF_OK;
+    const auto key = std::make_tuple(g->nx, g->ny, g->nz, (int)sizeof(T));
+    auto found = g_tuned_p.find(key);
+    if (found != g_tuned_p.end()) {
+        cfgp_ref<T>(g) = found->second;
+        done = true;
+        return PF_OK;
+    }
+    Work<T> &w = [&]() -> Work<T> & {
+        if constexpr (sizeof(T) == 8) return g->w64;
+        else return g->w32;
+    }();
+    T *xs[4] = {w.r, w.s, w.rt, w.t};
+    T *ys[4] = {w.p[0], w.p[1], w.v[0], w.v[1]};
+    for (T *x : xs) PFCHK(fill<T>(g, x, T(1), g->N));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    pf_status st = PF_OK;
+    ZCfg best = cfgp_ref<T>(g);
+    float best_ms = 1e30f;
+    for (const ZCfg &c : tune_candidates<T>(g)) {
+        pfk::ZArgs<T> a = zbase_cfg<T>(g, op, dinv, c);
+        a.x = xs[0];
+        a.out = ys[0];
+        if (zlaunch<pfk::OP_SPMV_JAC, T>(g, op, a, c) != PF_OK) {   // shape not launchable here
+            (void)hipGetLastError();
+            g_err.clear();
+            continue;
+        }
+        constexpr int K = 8;
+        float ms_c = 1e30f;
+        for (int run = 0; run < 2 && st == PF_OK; ++run) {
+            if (hipEventRecord(e0, g->stream) != hipSuccess) { st = fail(PF_ERR_DEVICE, "event record failed"); break; }
+            for (int k = 0; k < K && st == PF_OK; ++k) {
+                a.x = xs[k & 3];
+                a.out = ys[k & 3];
+                st = zlaunch<pfk::OP_SPMV_JAC, T>(g, op, a, c);
+            }
+            if (st != PF_OK) break;
+            if (hipEventRecord(e1, g->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(PF_ERR_DEVICE, "event timing failed");
+                break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms_c = std::min(ms_c, ms / K);
+        }
+        if (st != PF_OK) break;
+        if (ms_c < best_ms) { best_ms = ms_c; best = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PF_OK) return st;
+    cfgp_ref<T>(g) = best;
+    g_tuned_p[key] = best;
+    done = true;
+    if (getenv("PF_LOG"))
+        fprintf(stderr, "[pf] tuned %dx%dx%d %s product: threads %d strip %d z-planes %d depth %d (%.1f us)\n",
+                g->nx, g->ny, g->nz, sizeof(T) == 8 ? "fp64" : "fp32", best.NTZ, best.S, best.KZ, best.depth,
+                best_ms * 1e3);
     return PF_OK;
 }
 
@@ -1325,8 +1411,8 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     g->bcphi_mask = bp; g->bcpsi_mask = bs;
     for (int f = 0; f < 6; ++f) g->bcval[f] = d->bc_value[f];
     g->ustream = (hipStream_t)d->stream;
-    g->c64 = g->cb64 = default_cfg(d->nx, d->ny, d->nz, 8);
-    g->c32 = g->cb32 = default_cfg(d->nx, d->ny, d->nz, 4);
+    g->c64 = g->cb64 = g->cp64 = default_cfg(d->nx, d->ny, d->nz, 8);
+    g->c32 = g->cb32 = g->cp32 = default_cfg(d->nx, d->ny, d->nz, 4);
     if (g->c64.lds > LDS_MAX || g->c32.lds > LDS_MAX) {
         delete g;
         return fail(PF_ERR_ARG, "nx too large for the LDS strip (nx <= ~4800)");
@@ -1451,13 +1537,15 @@ pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, i
     OpDesc op;
     op.sigma = sigma;
     PFCHK(compute_dinv<double>(g, op, g->dinv64));
-    pfk::ZArgs<double> a = zbase<double>(g, op, g->dinv64);
+    if (jacobi) PFCHK(tune_product<double>(g, op, g->dinv64));
+    const ZCfg &c = jacobi ? cfgp_ref<double>(g) : cfg_of<double>(g);
+    pfk::ZArgs<double> a = zbase_cfg<double>(g, op, g->dinv64, c);
     a.x = x;
     a.out = y;
     const bool timed = jacobi && g_timing.enabled;
     if (timed) HIPCHK(hipEventRecord(g_timing.p0, g->stream));
-    if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a, cfg_of<double>(g))));
-    else PFCHK((zlaunch<pfk::OP_SPMV, double>(g, op, a, cfg_of<double>(g))));
+    if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a, c)));
+    else PFCHK((zlaunch<pfk::OP_SPMV, double>(g, op, a, c)));
     if (timed) HIPCHK(hipEventRecord(g_timing.p1, g->stream));
     PFCHK(sync(g));
     if (timed) PFCHK(timing_add_product(2, 4.0 * (double)g->N * sizeof(double)));
@@ -1474,12 +1562,14 @@ pf_status pf_spmv_f32(pf_grid *g, const double *sigma, const float *x, float *y,
     OpDesc op;
     op.sigma = sigma;
     PFCHK(compute_dinv<float>(g, op, g->dinv32));
-    pfk::ZArgs<float> a = zbase<float>(g, op, g->dinv32);
+    PFCHK(tune_product<float>(g, op, g->dinv32));
+    const ZCfg &c = cfgp_ref<float>(g);
+    pfk::ZArgs<float> a = zbase_cfg<float>(g, op, g->dinv32, c);
     a.x = x;
     a.out = y;
     const bool timed = g_timing.enabled;
     if (timed) HIPCHK(hipEventRecord(g_timing.p0, g->stream));
-    PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a, cfg_of<float>(g))));
+    PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a, c)));
     if (timed) HIPCHK(hipEventRecord(g_timing.p1, g->stream));
     PFCHK(sync(g));
     if (timed) PFCHK(timing_add_product(3, 4.0 * (double)g->N * sizeof(float)));
