@@ -15,7 +15,11 @@ Functions follow the paper:
     (Sec. 2, Eq. (1)), by bisection.
   * ``nonlinear_solve``: the sequential PF solver (Sec. 4, Table 2) with the
     PF1/PF2 split of Eqs. (12)-(14) and the inexact-Newton linearisation of
-    Eq. (11).
+    Eq. (11); ``rhs_extra`` adds the interface terms to every PF2 solve.
+  * ``coulomb`` / ``smib_rhs`` / ``interface``: the singular-charge
+    decomposition of Sec. 3 -- phi* of Eq. (5), the Laplace problem of
+    Eqs. (9)-(10), the flux jump of Eq. (8) and the right-hand-side terms of
+    the SMIB rows, Eqs. (17)-(18).
 """
 from __future__ import annotations
 
@@ -65,7 +69,8 @@ class _Species(C.Structure):
 class _NlOpts(C.Structure):
     _fields_ = [("eps_s", C.c_double), ("lc", C.c_double), ("omega", C.c_double),
                 ("outer_tol", C.c_double), ("max_outer", C.c_int), ("lin_tol", C.c_double),
-                ("lin_maxit", C.c_int), ("warm_start", C.c_int), ("bc_psi", C.c_int * 6)]
+                ("lin_maxit", C.c_int), ("warm_start", C.c_int), ("bc_psi", C.c_int * 6),
+                ("rhs_extra", C.c_void_p)]
 
 
 class _NlInfo(C.Structure):
@@ -94,6 +99,10 @@ def _L():
         lib.pfo_steric_root.restype = D
         lib.pfo_nonlinear_solve.argtypes = [C.POINTER(_Grid), P, C.POINTER(_Species),
                                             C.POINTER(_NlOpts), P, P, P, C.POINTER(_NlInfo)]
+        lib.pfo_coulomb.argtypes = [S, P, P, I, P, D, P]
+        lib.pfo_coulomb.restype = None
+        lib.pfo_smib_rhs.argtypes = [C.POINTER(_Grid), D, D, P, P]
+        lib.pfo_interface.argtypes = [C.POINTER(_Grid), I, P, D, D, D, D, I, P, P, P, C.POINTER(_LinInfo)]
         _lib = lib
     return _lib
 
@@ -284,7 +293,7 @@ def fermi(phi, sp, node_type=None, want_conc=True):
 
 def nonlinear_solve(g, fixed_charge, sp, eps_s, lc, omega=0.3, outer_tol=1e-8, max_outer=1000,
                     lin_tol=1e-12, lin_maxit=100000, phi0=None, bc_psi=(DIRICHLET,) * 6,
-                    want_conc=False, check=True):
+                    want_conc=False, check=True, rhs_extra=None):
     """Table 2: initial PF2 solve, then {Fermi, PF1, PF2, relax} to outer_tol."""
     keep = []
     s = _grid(g, keep)
@@ -296,6 +305,9 @@ def nonlinear_solve(g, fixed_charge, sp, eps_s, lc, omega=0.3, outer_tol=1e-8, m
     o.warm_start = 0 if phi0 is None else 1
     for f in range(6):
         o.bc_psi[f] = int(bc_psi[f])
+    extra = None if rhs_extra is None else _f64(rhs_extra).ravel()
+    keep.append(extra)
+    o.rhs_extra = _p(extra)
     q = None if fixed_charge is None else _f64(fixed_charge).ravel()
     phi = np.zeros(N) if phi0 is None else _f64(phi0).ravel().copy()
     conc = np.empty((len(sp.valence), N)) if want_conc else None
@@ -307,3 +319,49 @@ def nonlinear_solve(g, fixed_charge, sp, eps_s, lc, omega=0.3, outer_tol=1e-8, m
     if check and st:
         raise OracleError(st, "nonlinear_solve")
     return phi, d, conc, S
+
+
+# ------------------------------------------- interface treatment (Sec. 3)
+
+def coulomb(points, charges, scale, dirs=None):
+    """phi* of Eq. (5) (``scale`` = lambda / (4 pi eps_m)) or its derivative
+    along face direction dirs[p] (0..5 = -x,+x,-y,+y,-z,+z; 6 = potential)
+    at points [n, 3]; charges [M, 4] = x, y, z, valence."""
+    pts = _f64(points).reshape(-1, 3)
+    ch = _f64(charges).reshape(-1, 4)
+    d = None if dirs is None else np.ascontiguousarray(dirs, dtype=np.int32).ravel()
+    out = np.empty(len(pts))
+    _L().pfo_coulomb(len(pts), _p(pts), _p(d), len(ch), _p(ch), float(scale), _p(out))
+    return out
+
+
+def smib_rhs(g, eps_m, eps_s, jump):
+    """Right-hand-side terms of the SMIB rows (Eqs. (17)-(18)) for flux jumps
+    jump[6, N] on the edges leaving Omega_m (SOLUTE nodes)."""
+    keep = []
+    s = _grid(g, keep)
+    N = g.nx * g.ny * g.nz
+    j = _f64(jump).reshape(6, N)
+    b = np.zeros(N)
+    st = _L().pfo_smib_rhs(C.byref(s), float(eps_m), float(eps_s), _p(j), _p(b))
+    if st:
+        raise OracleError(st, "smib_rhs")
+    return b
+
+
+def interface(g, charges, lam, eps_m, eps_s, tol=1e-12, maxit=100000):
+    """Decomposition of Eq. (5): returns (b_if, phi_reg, phi_lap, info) --
+    SMIB right-hand-side terms, phi* + phi^L on Omega_m, the Laplace solution."""
+    keep = []
+    s = _grid(g, keep)
+    N = g.nx * g.ny * g.nz
+    ch = _f64(charges).reshape(-1, 4)
+    b = np.zeros(N)
+    reg = np.zeros(N)
+    lap = np.zeros(N)
+    info = _LinInfo()
+    st = _L().pfo_interface(C.byref(s), len(ch), _p(ch), float(lam), float(eps_m), float(eps_s),
+                            float(tol), int(maxit), _p(b), _p(reg), _p(lap), C.byref(info))
+    if st:
+        raise OracleError(st, "interface")
+    return b, reg, lap, dict(iters=info.iters, rel_res=info.rel_res)

@@ -13,8 +13,12 @@
  *     shows no preconditioner step).
  *   - Stopping rule: true relative residual ||b - A x||_2 / ||b_lifted||_2
  *     (Table 3 uses an absolute max-norm; the tolerance is a parameter here).
- *   - Interface faces use the harmonic mean of nodal eps (the SMIB rows of
- *     Eqs. (17)-(18) are not reproduced).
+ *   - Interface faces use the harmonic mean of nodal eps.  With eps_m on
+ *     Omega_m, eps_s elsewhere and the interface at edge midpoints this is
+ *     the matrix of the SMIB rows, Eqs. (17)-(18); their right-hand-side
+ *     terms come from pfo_smib_rhs when the singular charges are treated by
+ *     the decomposition of Eq. (5) (pfo_interface), and are absent when the
+ *     charges are spread to nodes instead.
  *   - Neumann faces (Eq. (4)) use a node-centred mirror ghost; a node on a
  *     Dirichlet face is Dirichlet even if it also lies on a Neumann face.
  *   - A node on several Dirichlet faces takes the value of the face that
@@ -423,7 +427,10 @@ int pfo_nonlinear_solve(const pfo_grid *g, const double *fixed_charge,
     if ((st = pfo_dirichlet(g, 1, o->bc_psi, dpsi, vpsi)) != PFO_OK) goto out;
 
     /* fixed charges spread to nodes enter as lambda q / h^3 (Eq. (3) scaled) */
-    for (size_t n = 0; n < N; ++n) src[n] = fixed_charge ? sp->lambda * fixed_charge[n] / h3 : 0.0;
+    for (size_t n = 0; n < N; ++n) {
+        src[n] = fixed_charge ? sp->lambda * fixed_charge[n] / h3 : 0.0;
+        if (o->rhs_extra) src[n] += o->rhs_extra[n];
+    }
 
     pfo_lin_info li;
     int total_lin = 0;
@@ -494,5 +501,200 @@ int pfo_nonlinear_solve(const pfo_grid *g, const double *fixed_charge,
     if (info) { info->outer_iters = it; info->total_lin_iters = total_lin; info->last_delta = delta; }
 out:
     free(A); free(work); free(dphi); free(dpsi);
+    return st;
+}
+
+/* ------------------------- interface treatment, Sec. 3 Eqs. (5)-(10), (17)-(18) */
+
+static const int DI[6] = {-1, 1, 0, 0, 0, 0};
+static const int DJ[6] = {0, 0, -1, 1, 0, 0};
+static const int DK[6] = {0, 0, 0, 0, -1, 1};
+
+void pfo_coulomb(size_t n, const double *pts, const int *dir, int M, const double *charges,
+                 double scale, double *out)
+{
+    for (size_t p = 0; p < n; ++p) {
+        const double *r = pts + 3 * p;
+        int d = dir ? dir[p] : 6;
+        double acc = 0.0;
+        for (int j = 0; j < M; ++j) {
+            const double *c = charges + 4 * (size_t)j;
+            double dx = r[0] - c[0], dy = r[1] - c[1], dz = r[2] - c[2];
+            double dist = sqrt(dx * dx + dy * dy + dz * dz);
+            if (d == 6) {
+                acc += c[3] / dist;
+            } else {
+                /* d/du (1/|r - c|) = -(r - c).u / |r - c|^3 along the unit vector u */
+                double comp = (d < 2) ? dx : (d < 4) ? dy : dz;
+                double sgn = (d & 1) ? 1.0 : -1.0;
+                acc += -c[3] * sgn * comp / (dist * dist * dist);
+            }
+        }
+        out[p] = scale * acc;
+    }
+}
+
+int pfo_smib_rhs(const pfo_grid *g, double eps_m, double eps_s, const double *jump, double *b)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    if (!grid_ok(nx, ny, nz, g->h) || !jump || !b || !g->type || !(eps_m > 0.0) || !(eps_s > 0.0))
+        return PFO_EARG;
+    size_t N = (size_t)nx * ny * nz;
+    unsigned char *isd = (unsigned char *)malloc(N);
+    double *val = (double *)malloc(N * sizeof(double));
+    if (!isd || !val) { free(isd); free(val); return PFO_ENOMEM; }
+    int st = pfo_dirichlet(g, 0, NULL, isd, val);
+    const double cin = -eps_m / ((eps_m + eps_s) * g->h);   /* c0 / h^2 per unit jump */
+    const double cout = -eps_s / ((eps_m + eps_s) * g->h);  /* d0 / h^2 per unit jump */
+    for (int k = 0; k < nz && st == PFO_OK; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t n = IDX(i, j, k);
+                if (isd[n]) continue;
+                int inside = g->type[n] == PFO_SOLUTE;
+                for (int d = 0; d < 6; ++d) {
+                    int a = i + DI[d], bb = j + DJ[d], c = k + DK[d];
+                    if (a < 0 || a >= nx || bb < 0 || bb >= ny || c < 0 || c >= nz) continue;
+                    size_t m = IDX(a, bb, c);
+                    int nb_inside = g->type[m] == PFO_SOLUTE;
+                    if (inside && !nb_inside) b[n] += cin * jump[(size_t)d * N + n];
+                    if (!inside && nb_inside) b[n] += cout * jump[(size_t)(d ^ 1) * N + m];
+                }
+            }
+    free(isd); free(val);
+    return st;
+}
+
+int pfo_interface(const pfo_grid *g, int M, const double *charges, double lambda, double eps_m,
+                  double eps_s, double lap_tol, int lap_maxit, double *b_if, double *phi_reg,
+                  double *phi_lap, pfo_lin_info *lap_info)
+{
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    if (!grid_ok(nx, ny, nz, g->h) || !g->eps || !g->type || !b_if || M < 0 || (M > 0 && !charges) ||
+        !(eps_m > 0.0) || !(eps_s > 0.0) || !isfinite(lambda))
+        return PFO_EARG;
+    const double h = g->h, ih2 = 1.0 / (h * h);
+    size_t N = (size_t)nx * ny * nz;
+    for (size_t n = 0; n < N; ++n) {
+        double want = g->type[n] == PFO_SOLUTE ? eps_m : eps_s;
+        if (g->eps[n] != want) return PFO_EARG;
+    }
+    const double scale = lambda / (4.0 * 3.14159265358979323846 * eps_m);
+    int st = PFO_OK;
+    double *eps1 = (double *)malloc(N * sizeof(double));
+    unsigned char *tl = (unsigned char *)malloc(N);
+    double *fv = (double *)calloc(N, sizeof(double));
+    double *sig = (double *)calloc(N, sizeof(double));
+    double *rhs = (double *)calloc(N, sizeof(double));
+    double *xl = (double *)calloc(N, sizeof(double));
+    double *pmid = (double *)calloc(6 * N, sizeof(double));   /* phi* at edge midpoints */
+    double *gmid = (double *)calloc(6 * N, sizeof(double));   /* outward derivative of phi* there */
+    double *jump = (double *)calloc(6 * N, sizeof(double));
+    if (!eps1 || !tl || !fv || !sig || !rhs || !xl || !pmid || !gmid || !jump) { st = PFO_ENOMEM; goto out; }
+
+    /* phi* and its outward derivative at the midpoint of every edge leaving Omega_m */
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t n = IDX(i, j, k);
+                if (g->type[n] != PFO_SOLUTE) continue;
+                for (int d = 0; d < 6; ++d) {
+                    int a = i + DI[d], bb = j + DJ[d], c = k + DK[d];
+                    if (a < 0 || a >= nx || bb < 0 || bb >= ny || c < 0 || c >= nz) continue;
+                    if (g->type[IDX(a, bb, c)] == PFO_SOLUTE) continue;
+                    double mid[3] = {(i + 0.5 * DI[d]) * h, (j + 0.5 * DJ[d]) * h, (k + 0.5 * DK[d]) * h};
+                    pfo_coulomb(1, mid, NULL, M, charges, scale, &pmid[(size_t)d * N + n]);
+                    pfo_coulomb(1, mid, &d, M, charges, scale, &gmid[(size_t)d * N + n]);
+                }
+            }
+
+    /* Laplace problem, Eqs. (9)-(10), unit coefficient, unknowns on Omega_m.
+     * - Across an edge leaving Omega_m the boundary sits at the midpoint: the
+     *   outside value is the ghost -2 phi*(mid) - phi^L_in (their mean is
+     *   -phi*(mid)); eliminating it adds 1/h^2 to the diagonal and
+     *   -2 phi*(mid)/h^2 to the right-hand side, and the outside node itself
+     *   is decoupled (Dirichlet 0).
+     * - An Omega_m node on a Dirichlet face of the potential takes
+     *   phi^L = -phi* there, so phi-tilde carries the face value.
+     * - On a Neumann face the outward derivative of phi^L is -dphi_star/dn, so
+     *   phi-tilde inherits the zero flux: the mirror ghost gains 2 h g, i.e.
+     *   2 g / h on the right-hand side with g = -dphi_star/dn. */
+    int st_d = PFO_OK;
+    unsigned char *isd = (unsigned char *)malloc(N);
+    double *dval = (double *)malloc(N * sizeof(double));
+    if (!isd || !dval) { free(isd); free(dval); st = PFO_ENOMEM; goto out; }
+    st_d = pfo_dirichlet(g, 0, NULL, isd, dval);
+    for (int k = 0; k < nz && st_d == PFO_OK; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t n = IDX(i, j, k);
+                eps1[n] = 1.0;
+                int inside = g->type[n] == PFO_SOLUTE;
+                tl[n] = (inside && !isd[n]) ? PFO_SOLVENT : PFO_FIXED;
+                double r[3] = {i * h, j * h, k * h};
+                if (inside && isd[n]) {
+                    pfo_coulomb(1, r, NULL, M, charges, scale, &fv[n]);
+                    fv[n] = -fv[n];
+                }
+                if (!inside || isd[n]) continue;
+                for (int d = 0; d < 6; ++d) {
+                    int a = i + DI[d], bb = j + DJ[d], c = k + DK[d];
+                    if (a < 0 || a >= nx || bb < 0 || bb >= ny || c < 0 || c >= nz) {
+                        /* node on the face in direction d, Neumann (not Dirichlet) */
+                        double dn;
+                        pfo_coulomb(1, r, &d, M, charges, scale, &dn);
+                        rhs[n] += 2.0 * (-dn) / h;
+                        continue;
+                    }
+                    if (g->type[IDX(a, bb, c)] == PFO_SOLUTE) continue;
+                    sig[n] += ih2;
+                    rhs[n] += -2.0 * ih2 * pmid[(size_t)d * N + n];
+                }
+            }
+    free(isd);
+    free(dval);
+    if (st_d != PFO_OK) { st = st_d; goto out; }
+    pfo_grid gl = *g;   /* same face kinds; Dirichlet face nodes inside Omega_m are FIXED */
+    gl.eps = eps1;
+    gl.type = tl;
+    gl.fixed_value = fv;
+    for (int f = 0; f < 6; ++f) gl.bc_value[f] = 0.0;
+    st = pfo_linear_solve(&gl, sig, rhs, xl, lap_tol, lap_maxit, lap_info);
+    if (st != PFO_OK) goto out;
+
+    /* flux jumps, Eq. (8): J = eps_m d(phi* + phi^L)/dn at the midpoint, the
+     * phi^L derivative over the half cell from the inside node to the
+     * midpoint, where phi^L = -phi* */
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t n = IDX(i, j, k);
+                if (g->type[n] != PFO_SOLUTE) continue;
+                for (int d = 0; d < 6; ++d) {
+                    int a = i + DI[d], bb = j + DJ[d], c = k + DK[d];
+                    if (a < 0 || a >= nx || bb < 0 || bb >= ny || c < 0 || c >= nz) continue;
+                    if (g->type[IDX(a, bb, c)] == PFO_SOLUTE) continue;
+                    size_t e = (size_t)d * N + n;
+                    jump[e] = eps_m * (gmid[e] + (-pmid[e] - xl[n]) / (0.5 * h));
+                }
+            }
+    memset(b_if, 0, N * sizeof(double));
+    st = pfo_smib_rhs(g, eps_m, eps_s, jump, b_if);
+    if (st != PFO_OK) goto out;
+
+    if (phi_reg) {
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t n = IDX(i, j, k);
+                    if (g->type[n] != PFO_SOLUTE) { phi_reg[n] = 0.0; continue; }
+                    double r[3] = {i * h, j * h, k * h}, ps;
+                    pfo_coulomb(1, r, NULL, M, charges, scale, &ps);
+                    phi_reg[n] = ps + xl[n];
+                }
+    }
+    if (phi_lap) memcpy(phi_lap, xl, N * sizeof(double));
+out:
+    free(eps1); free(tl); free(fv); free(sig); free(rhs); free(xl); free(pmid); free(gmid); free(jump);
     return st;
 }

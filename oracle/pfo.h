@@ -18,7 +18,9 @@
  *   - the Fermi-like concentrations and steric potential (Sec. 2, Eq. (1))
  *     by bisection on the void-fraction equation;
  *   - the sequential nonlinear solver of Sec. 4, Table 2 (initial PF2 solve,
- *     then PF1 / PF2 / relaxation until the max-norm update is small).
+ *     then PF1 / PF2 / relaxation until the max-norm update is small);
+ *   - the singular-charge decomposition of Sec. 3 (Eqs. (5), (8)-(10)) with
+ *     the right-hand-side terms of the SMIB rows (Eqs. (17)-(18)).
  *
  * Units: potentials are phi-hat = e*phi/(kB*T); lengths in the grid's unit;
  * concentrations per cubed length unit; lambda = e^2/(eps0*kB*T) in the
@@ -115,6 +117,8 @@ typedef struct {
     int lin_maxit;
     int warm_start;           /* 1: phi holds the initial phi_0, skip the initial PF2 solve */
     int bc_psi[6];            /* Psi boundary kinds (Dirichlet value 0) */
+    const double *rhs_extra;  /* [N] added to every PF2 right-hand side (the interface
+                                 terms of pfo_interface), or NULL */
 } pfo_nl_opts;
 
 typedef struct {
@@ -128,6 +132,47 @@ typedef struct {
 int pfo_nonlinear_solve(const pfo_grid *g, const double *fixed_charge,
                         const pfo_species *sp, const pfo_nl_opts *o, double *phi,
                         double *conc, double *S, pfo_nl_info *info);
+
+/* ---------------------------- interface treatment, Sec. 3 Eqs. (5)-(10), (17)-(18) */
+
+/* phi* of Eq. (5) in phi-hat units, sum_j scale * z_j / |r - r_j| with
+ * scale = lambda / (4 pi eps_m), or a directional derivative of it, at n
+ * points.  pts [n][3] and charges [M][4] (x, y, z, valence z_j) share one
+ * frame (grid length units).  dir NULL or dir[p] == 6: the potential;
+ * dir[p] in 0..5: the derivative along the unit vector of face direction
+ * dir[p] (-x,+x,-y,+y,-z,+z).  Sums over the charges in index order. */
+void pfo_coulomb(size_t n, const double *pts, const int *dir, int M, const double *charges,
+                 double scale, double *out);
+
+/* Right-hand-side terms of the SMIB rows, Eqs. (17)-(18), added to b.
+ * Omega_m = SOLUTE nodes.  jump[d*N + n] is the flux jump [eps dphi/dn]
+ * (outside minus inside, n pointing out of Omega_m) at the midpoint of the
+ * edge from Omega_m node n to its neighbour in direction d (read only where
+ * that neighbour exists and lies outside Omega_m).  A free row of the
+ * potential system (pfo_dirichlet system 0) inside Omega_m gains
+ * -eps_m J / ((eps_m + eps_s) h) per such edge (c0 / h^2), one outside gains
+ * -eps_s J / ((eps_m + eps_s) h) (d0 / h^2).  The matrix part of the SMIB
+ * rows is the harmonic-mean operator of pfo_assemble when eps is eps_m on
+ * Omega_m and eps_s elsewhere. */
+int pfo_smib_rhs(const pfo_grid *g, double eps_m, double eps_s, const double *jump, double *b);
+
+/* Interface data of the singular-charge decomposition (Eq. (5)):
+ *   phi_star at the Dirichlet nodes of the Laplace problem: nodes outside Omega_m
+ *   next to it, and Omega_m nodes on a domain face;
+ *   phi^L: unit-coefficient Laplace problem (Eq. (9)) on the other Omega_m
+ *   nodes, phi^L = -phi_star at those Dirichlet nodes (Eq. (10), signed so that
+ *   phi_star + phi^L vanishes on the boundary of Omega_m and the total potential
+ *   is continuous);
+ *   J = eps_m (d phi_star / dn + (phi^L_out - phi^L_in) / h) at every edge midpoint
+ *   (Eq. (8)), then pfo_smib_rhs.
+ * eps must equal eps_m on SOLUTE nodes and eps_s on all others.
+ * Outputs [N] (NULL allowed except b_if): b_if = SMIB right-hand-side terms;
+ * phi_reg = phi_star + phi^L on Omega_m nodes, 0 elsewhere (total potential =
+ * phi-tilde + phi_reg); phi_lap = the Laplace solution (its Dirichlet values
+ * at the Dirichlet nodes, 0 on other nodes outside Omega_m). */
+int pfo_interface(const pfo_grid *g, int M, const double *charges, double lambda, double eps_m,
+                  double eps_s, double lap_tol, int lap_maxit, double *b_if, double *phi_reg,
+                  double *phi_lap, pfo_lin_info *lap_info);
 
 #ifdef __cplusplus
 }
