@@ -21,8 +21,12 @@
  *     Dirichlet nodes with their own value.
  *   - Operator: (A x)_i = sum over the six faces f of eps_f (x_i - x_j) / h^2
  *     + sigma_i x_i on free rows, with eps_f = 2 eps_i eps_j / (eps_i + eps_j)
- *     (harmonic mean of nodal values; it replaces the SMIB interface rows of
- *     Eqs. (17)-(18)).  Dirichlet rows are identity rows.
+ *     (harmonic mean of nodal values).  Dirichlet rows are identity rows.
+ *     When eps is eps_m on Omega_m (SOLUTE nodes) and eps_s elsewhere, and
+ *     the interface lies at edge midpoints, these rows are the matrix of the
+ *     SMIB rows of Eqs. (17)-(18); their right-hand-side terms come from
+ *     pf_interface_setup when the charges are treated by the decomposition
+ *     of Eq. (5) instead of being spread to nodes.
  *   - Potentials are phi-hat = e phi / (kB T).  Lengths are in the grid's unit;
  *     lambda = e^2 / (eps0 kB T) and concentrations use the same unit.
  *   - Pointers named "device" must be device memory of the current HIP device
@@ -158,6 +162,9 @@ typedef struct {
     int32_t max_outer;        /* outer iterations, > 0                           */
     int32_t warm_start;       /* 1: phi holds Phi_0 (skip Table 2 step 2)        */
     pf_lin_opts lin;          /* options of every PF1 / PF2 linear solve         */
+    const double *rhs_extra;  /* device [N] added to the right-hand side of every
+                                 PF2 solve (the b_if of pf_interface_setup), or
+                                 NULL                                            */
 } pf_pf_params;
 
 typedef struct {
@@ -225,6 +232,66 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample);
  * launch), which pf_timing_enable measures around an empty one-workgroup
  * kernel.  PF_ERR_ARG for another kind. */
 pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, double *bytes);
+
+/* ---------------- singular-charge decomposition (Sec. 3, Eqs. (5)-(10), (17)-(18)) */
+
+/* phi* of Eq. (5) in phi-hat units, or one of its directional derivatives, at
+ * n points:  out[p] = scale * sum_j z_j / |r_p - r_j|  when dir is NULL or
+ * dir[p] == 6, and  out[p] = scale * d/du sum_j z_j / |r_p - r_j|  along the
+ * unit vector u of face direction dir[p] in 0..5 (-x,+x,-y,+y,-z,+z).
+ * With scale = lambda / (4 pi eps_m) this is the Coulomb potential of the
+ * point charges in a uniform dielectric eps_m.  pts: device [n][3];
+ * dir: device int8 [n] or NULL; charges: device [M][4] = x, y, z, valence
+ * z_j (same frame as pts); out: device [n].  Sums over the charges in index
+ * order; a point on a charge gives a non-finite value.  Runs on `stream`
+ * (hipStream_t, NULL = default stream) and returns when done. */
+pf_status pf_coulomb(const double *pts, const int8_t *dir, int64_t n, const double *charges, int32_t M,
+                     double scale, double *out, void *stream);
+
+typedef struct {
+    int32_t n_charges;     /* M >= 0 point charges inside Omega_m                 */
+    const double *charges; /* device [M][4]: x, y, z measured from node (0,0,0) in
+                              grid length units, valence z_j (units of e)         */
+    double lambda;         /* e^2 / (eps0 kB T) in grid length units              */
+    double eps_m, eps_s;   /* dielectric of Omega_m (SOLUTE) and of every other
+                              node; the grid's eps must match exactly             */
+    pf_lin_opts lin;       /* options of the Laplace solve                        */
+} pf_iface_params;
+
+/* Fill *p: no charges, lambda 0, eps_m 2, eps_s 78.45, lin = defaults with
+ * rel_tol 1e-12. */
+void pf_iface_params_default(pf_iface_params *p);
+
+/* Interface data of the decomposition phi = phi-tilde + phi* + phi^L in
+ * Omega_m, phi = phi-tilde in the solvent (Eq. (5)), on grid g.  Omega_m is
+ * the set of SOLUTE nodes; the interface crosses each edge between a SOLUTE
+ * node and a non-SOLUTE neighbour at its midpoint.
+ *   1. phi* and its outward derivative at every such midpoint, phi* at Omega_m
+ *      nodes on Dirichlet faces (and at all Omega_m nodes if phi_reg is
+ *      wanted), d(phi*)/dn at Omega_m nodes on Neumann faces (pf_coulomb's
+ *      kernel over a compact list of these points);
+ *   2. the Laplace problem of Eqs. (9)-(10) on Omega_m (unit coefficient):
+ *      phi^L = -phi* at the midpoints (so phi* + phi^L vanishes on the
+ *      interface and phi-tilde is continuous), phi^L = -phi* at Omega_m nodes
+ *      on Dirichlet faces, d phi^L/dn = -d(phi*)/dn on Neumann faces; solved
+ *      with this library's BiCGSTAB and the options p->lin;
+ *   3. the flux jump of Eq. (8), J = eps_m d(phi* + phi^L)/dn at each
+ *      midpoint (phi^L's derivative over the half cell to the midpoint), and
+ *      the right-hand-side terms of the SMIB rows, Eqs. (17)-(18): a free
+ *      row of the potential inside Omega_m gains -eps_m J / ((eps_m + eps_s) h)
+ *      per crossing edge, one outside gains -eps_s J / ((eps_m + eps_s) h).
+ * Outputs (device [N]): b_if (required) = those terms, zero elsewhere --
+ * pass it as pf_pf_params.rhs_extra, or add it to the right-hand side of
+ * pf_linear_solve, with no fixed charges spread to nodes; phi_reg (or NULL)
+ * = phi* + phi^L on Omega_m, 0 elsewhere, so that the total potential is
+ * phi-tilde + phi_reg; phi_lap (or NULL) = the Laplace solution (its
+ * Dirichlet values on Dirichlet rows, 0 on other nodes outside Omega_m).
+ * lap_info: host or NULL.  PF_ERR_ARG if eps does not match eps_m / eps_s;
+ * PF_ERR_NONFINITE if a charge sits on an evaluation point; the Laplace
+ * solve's status if it fails.  Allocates and frees its own work space
+ * (about 60 bytes per node). */
+pf_status pf_interface_setup(pf_grid *g, const pf_iface_params *p, double *b_if, double *phi_reg,
+                             double *phi_lap, pf_lin_info *lap_info);
 
 /* Thread-local description of the last error (empty string if none). */
 const char *pf_last_error(void);

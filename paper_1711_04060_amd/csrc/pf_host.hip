@@ -8,6 +8,7 @@
 // nonlinear loop of Tables 2 and 4 runs entirely on the device apart from one
 // status read per outer iteration (the max-norm test of Table 2 step 5).
 #include "pf_kernels.h"
+#include "pf_iface.h"
 #include "../../include/pf.h"
 
 #include <algorithm>
@@ -1747,7 +1748,7 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
         const int B = pw_blocks(g->N);
         const double h3 = g->h * g->h * g->h;
         hipLaunchKernelGGL(pfk::k_source, dim3(B), dim3(NT), 0, g->stream, g->N, (const double *)g->q,
-                           s.sp.lam / h3, g->src);
+                           s.sp.lam / h3, s.p->rhs_extra, g->src);
         HIPCHK(hipGetLastError());
         if (!s.p->warm_start) {
             PFCHK(fill<double>(g, g->phi0, 0.0, g->N));
@@ -1983,6 +1984,184 @@ pf_status pf_nonlinear_solve_batch(int32_t n, pf_grid *const *g, const pf_pf_par
     }
     g_err = first_err;
     return worst;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- singular-charge decomposition
+
+namespace {
+
+// Device buffers of one interface setup, released on every exit path.
+struct IfTemp {
+    std::vector<void *> ptrs;
+    ~IfTemp()
+    {
+        for (void *q : ptrs) (void)hipFree(q);
+    }
+    template <typename T>
+    pf_status alloc(T **p, size_t n)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PF_ERR_ALLOC, "hipMalloc of %zu bytes failed", n * sizeof(T));
+        }
+        ptrs.push_back(q);
+        *p = static_cast<T *>(q);
+        return PF_OK;
+    }
+};
+
+struct GridGuard {
+    pf_grid *g = nullptr;
+    ~GridGuard() { pf_grid_destroy(g); }
+};
+
+pf_status check_iface(const pf_iface_params *p)
+{
+    if (!p) return fail(PF_ERR_ARG, "null interface parameters");
+    if (p->n_charges < 0 || (p->n_charges > 0 && !p->charges))
+        return fail(PF_ERR_ARG, "n_charges must be >= 0 with a charge array");
+    if (!(p->eps_m > 0) || !(p->eps_s > 0) || !std::isfinite(p->eps_m) || !std::isfinite(p->eps_s))
+        return fail(PF_ERR_ARG, "eps_m and eps_s must be finite and > 0");
+    if (!std::isfinite(p->lambda)) return fail(PF_ERR_ARG, "lambda must be finite");
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pf_iface_params_default(pf_iface_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->eps_m = 2.0;
+    p->eps_s = 78.45;
+    pf_lin_opts_default(&p->lin);
+    p->lin.rel_tol = 1e-12;
+}
+
+pf_status pf_coulomb(const double *pts, const int8_t *dir, int64_t n, const double *charges, int32_t M,
+                     double scale, double *out, void *stream)
+{
+    g_err.clear();
+    if (n < 0 || M < 0 || (n > 0 && (!pts || !out)) || (M > 0 && !charges))
+        return fail(PF_ERR_ARG, "pf_coulomb: bad sizes or null arrays");
+    if (n == 0) return PF_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t blocks = ((size_t)n + pfk::IF_NT - 1) / pfk::IF_NT;
+    if (blocks > 0x7fffffffu) return fail(PF_ERR_ARG, "pf_coulomb: too many points");
+    hipLaunchKernelGGL(pfk::k_coulomb_points, dim3((unsigned)blocks), dim3(pfk::IF_NT), 0, s, (size_t)n, pts, dir,
+                       charges, (int)M, scale, out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return PF_OK;
+}
+
+pf_status pf_interface_setup(pf_grid *g, const pf_iface_params *p, double *b_if, double *phi_reg, double *phi_lap,
+                             pf_lin_info *lap_info)
+{
+    PFCHK(check_grid(g));
+    PFCHK(check_iface(p));
+    if (!b_if) return fail(PF_ERR_ARG, "b_if must be a device array of N doubles");
+    PFCHK(begin(g));
+    const size_t N = g->N;
+    const double h = g->h;
+    const double scale = p->lambda / (4.0 * 3.14159265358979323846 * p->eps_m);
+    IfTemp tmp;
+    unsigned *bad = nullptr;
+    PFCHK(tmp.alloc(&bad, 1));
+    // hipMemsetAsync is fine here: this sequence is never captured in a graph
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(unsigned), g->stream));
+    hipLaunchKernelGGL(pfk::k_if_check, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, N, (const uint8_t *)g->flags,
+                       (const double *)g->eps64, p->eps_m, p->eps_s, bad);
+    HIPCHK(hipGetLastError());
+    unsigned hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, g->stream));
+    PFCHK(sync(g));
+    if (hbad) return fail(PF_ERR_ARG, "eps must equal eps_m on SOLUTE nodes and eps_s on all other nodes");
+
+    // evaluation list: masks, workgroup counts, prefix sums, entries
+    pfk::IfGrid ig{g->nx, g->ny, g->nz, h, g->flags, phi_reg ? 1 : 0};
+    const size_t nb = (N + pfk::IF_NT - 1) / pfk::IF_NT;
+    uint16_t *mask = nullptr;
+    unsigned *blk = nullptr, *off = nullptr;
+    PFCHK(tmp.alloc(&mask, N));
+    PFCHK(tmp.alloc(&blk, nb + 1));
+    PFCHK(tmp.alloc(&off, N));
+    hipLaunchKernelGGL(pfk::k_if_mask, dim3((unsigned)nb), dim3(pfk::IF_NT), 0, g->stream, ig, N, mask, blk);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(pfk::k_if_scan, dim3(1), dim3(1024), 0, g->stream, blk, (int)nb);
+    HIPCHK(hipGetLastError());
+    unsigned E = 0;   // at most 7 per node (six directions, one node value), below 2^32 for N < 2^29
+    HIPCHK(hipMemcpyAsync(&E, blk + nb, sizeof E, hipMemcpyDeviceToHost, g->stream));
+    PFCHK(sync(g));
+    unsigned long long *code = nullptr;
+    double *V = nullptr, *D = nullptr;
+    PFCHK(tmp.alloc(&code, E));
+    PFCHK(tmp.alloc(&V, E));
+    PFCHK(tmp.alloc(&D, E));
+    hipLaunchKernelGGL(pfk::k_if_list, dim3((unsigned)nb), dim3(pfk::IF_NT), 0, g->stream, N,
+                       (const uint16_t *)mask, (const unsigned *)blk, off, code);
+    HIPCHK(hipGetLastError());
+    if (E > 0) {
+        hipLaunchKernelGGL(pfk::k_coulomb_entries, dim3((E + pfk::IF_NT - 1) / pfk::IF_NT), dim3(pfk::IF_NT), 0,
+                           g->stream, (size_t)E, (const unsigned long long *)code, g->nx, g->ny, h, p->charges,
+                           (int)p->n_charges, scale, V, D);
+        HIPCHK(hipGetLastError());
+    }
+
+    // Laplace problem (its own grid: unit coefficient, the potential's face kinds)
+    double *eps1 = nullptr, *fv = nullptr, *sig = nullptr, *rhs = nullptr, *xl = nullptr;
+    uint8_t *type = nullptr;
+    PFCHK(tmp.alloc(&eps1, N));
+    PFCHK(tmp.alloc(&type, N));
+    PFCHK(tmp.alloc(&fv, N));
+    PFCHK(tmp.alloc(&sig, N));
+    PFCHK(tmp.alloc(&rhs, N));
+    PFCHK(tmp.alloc(&xl, N));
+    hipLaunchKernelGGL(pfk::k_if_laplace, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, ig, N, (const uint16_t *)mask,
+                       (const unsigned *)off, (const double *)V, (const double *)D, eps1, type, fv, sig, rhs);
+    HIPCHK(hipGetLastError());
+    PFCHK(fill<double>(g, xl, 0.0, N));
+    PFCHK(sync(g));
+    pf_grid_desc ld{};
+    ld.nx = g->nx;
+    ld.ny = g->ny;
+    ld.nz = g->nz;
+    ld.h = h;
+    ld.eps = eps1;
+    ld.node_type = type;
+    ld.fixed_value = fv;
+    for (int f = 0; f < 6; ++f) {
+        ld.bc_phi[f] = ((g->bcphi_mask >> f) & 1) ? PF_BC_NEUMANN : PF_BC_DIRICHLET;
+        ld.bc_value[f] = 0.0;
+        ld.bc_psi[f] = PF_BC_DIRICHLET;
+    }
+    GridGuard gl;
+    PFCHK(pf_grid_create(&ld, &gl.g));
+    pf_lin_info li{};
+    const pf_status lst = pf_linear_solve(gl.g, sig, rhs, xl, &p->lin, &li);
+    if (lap_info) *lap_info = li;
+    if (lst != PF_OK) return lst;
+    g_err.clear();
+
+    // flux jumps and SMIB terms; phi* + phi^L on Omega_m
+    hipLaunchKernelGGL(pfk::k_if_rhs, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, ig, N, (const uint16_t *)mask,
+                       (const unsigned *)off, (const double *)V, (const double *)D, (const double *)xl, p->eps_m,
+                       p->eps_s, b_if, phi_reg);
+    HIPCHK(hipGetLastError());
+    if (phi_lap) HIPCHK(hipMemcpyAsync(phi_lap, xl, N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(unsigned), g->stream));
+    hipLaunchKernelGGL(pfk::k_if_finite, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, N, (const double *)b_if,
+                       (const double *)phi_reg, bad);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, g->stream));
+    PFCHK(sync(g));
+    if (hbad) return fail(PF_ERR_NONFINITE, "interface terms are not finite (a charge on an evaluation point?)");
+    return PF_OK;
 }
 
 }  // extern "C"

@@ -47,7 +47,7 @@
 namespace pfk {
 
 // node flag bits (one byte per node)
-enum : uint8_t { F_DIR_PHI = 1, F_DIR_PSI = 2, F_SOLVENT = 4 };
+enum : uint8_t { F_DIR_PHI = 1, F_DIR_PSI = 2, F_SOLVENT = 4, F_SOLUTE = 8 };
 
 // Device-side BiCGSTAB state (FP64 even when the vectors are FP32).  Values
 // produced inside an iteration are kept per iteration parity q = i & 1: a
@@ -1010,7 +1010,8 @@ __global__ void k_classify(int nx, int ny, int nz, const uint8_t *type, const do
         const uint8_t t = type ? type[n] : 0;
         if (t == 2) { dphi = true; v = fixed_value ? fixed_value[n] : 0.0; }
         if (t != 0) dpsi = true;
-        flags[n] = (dphi ? F_DIR_PHI : 0) | (dpsi ? F_DIR_PSI : 0) | (t == 0 ? F_SOLVENT : 0);
+        flags[n] = (dphi ? F_DIR_PHI : 0) | (dpsi ? F_DIR_PSI : 0) | (t == 0 ? F_SOLVENT : 0) |
+                   (t == 1 ? F_SOLUTE : 0);
         dval[n] = dphi ? v : 0.0;
     }
 }
@@ -1168,12 +1169,16 @@ __global__ void k_fermi(size_t N, const double *phi, const uint8_t *flags, Speci
     }
 }
 
-// Fixed-charge source lambda q / h^3.
-__global__ void k_source(size_t N, const double *q, double scale, double *src)
+// Fixed-charge source lambda q / h^3, plus an extra right-hand side (the
+// interface terms of the singular-charge decomposition) when given.
+__global__ void k_source(size_t N, const double *q, double scale, const double *extra, double *src)
 {
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
-         n += (size_t)gridDim.x * blockDim.x)
-        src[n] = q ? scale * q[n] : 0.0;
+         n += (size_t)gridDim.x * blockDim.x) {
+        double v = q ? scale * q[n] : 0.0;
+        if (extra) v += extra[n];
+        src[n] = v;
+    }
 }
 
 // PF1 with l_c = 0: Psi = -rho_hat / eps_s on free Psi rows, 0 elsewhere.

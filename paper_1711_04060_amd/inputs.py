@@ -214,6 +214,15 @@ def membrane_pore(n: int = 97, seed: int = 2, n_charges: int = 2000, bias_phi: f
                              lc_A=2 * 0.95, eps_s=TABLE1["eps_s"]))
 
 
+def point_charges(prob: Problem) -> np.ndarray:
+    """The problem's point charges as rows (x, y, z, valence), positions
+    measured from node (0, 0, 0) in grid length units (the charges before
+    they are spread to nodes)."""
+    pos = np.asarray(prob.meta["positions"], dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(prob.meta["charges"], dtype=np.float64).ravel()
+    return np.column_stack([pos - np.asarray(prob.origin, dtype=np.float64), q])
+
+
 def thermal_voltage_mV() -> float:
     """kB T / e in mV with Table 1 constants (for converting bias voltages)."""
     return TABLE1["kB"] * TABLE1["T"] / TABLE1["e"] * 1e3

@@ -24,7 +24,8 @@ PF_FP64, PF_MIXED = 0, 1
 EXPORTS = ("pf_grid_create", "pf_grid_destroy", "pf_lin_opts_default", "pf_linear_solve",
            "pf_residual", "pf_spmv", "pf_spmv_f32", "pf_pf_params_default", "pf_nonlinear_solve",
            "pf_fermi", "pf_linear_solve_batch", "pf_nonlinear_solve_batch", "pf_last_error",
-           "pf_set_launch", "pf_timing_enable", "pf_timing_read")
+           "pf_set_launch", "pf_timing_enable", "pf_timing_read", "pf_coulomb",
+           "pf_iface_params_default", "pf_interface_setup")
 
 
 class pf_grid_desc(C.Structure):
@@ -50,7 +51,12 @@ class pf_pf_params(C.Structure):
                 ("eps_s", C.c_double), ("kB", C.c_double), ("T", C.c_double), ("e", C.c_double),
                 ("eps0", C.c_double), ("NA", C.c_double), ("length_unit_A", C.c_double),
                 ("omega", C.c_double), ("outer_tol", C.c_double), ("max_outer", C.c_int32),
-                ("warm_start", C.c_int32), ("lin", pf_lin_opts)]
+                ("warm_start", C.c_int32), ("lin", pf_lin_opts), ("rhs_extra", C.c_void_p)]
+
+
+class pf_iface_params(C.Structure):
+    _fields_ = [("n_charges", C.c_int32), ("charges", C.c_void_p), ("lambda_", C.c_double),
+                ("eps_m", C.c_double), ("eps_s", C.c_double), ("lin", pf_lin_opts)]
 
 
 class pf_nl_info(C.Structure):
@@ -95,8 +101,13 @@ def load():
         lib.pf_set_launch.argtypes = [I32, I32, I32, I32]
         lib.pf_timing_enable.argtypes = [I32, I32]
         lib.pf_timing_read.argtypes = [I32, C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]
+        lib.pf_coulomb.argtypes = [P, P, C.c_int64, P, I32, D, P, P]
+        lib.pf_iface_params_default.argtypes = [C.POINTER(pf_iface_params)]
+        lib.pf_iface_params_default.restype = None
+        lib.pf_interface_setup.argtypes = [P, C.POINTER(pf_iface_params), P, P, P, C.POINTER(pf_lin_info)]
         for name in EXPORTS:
-            if name not in ("pf_grid_destroy", "pf_lin_opts_default", "pf_pf_params_default", "pf_last_error"):
+            if name not in ("pf_grid_destroy", "pf_lin_opts_default", "pf_pf_params_default", "pf_last_error",
+                            "pf_iface_params_default"):
                 getattr(lib, name).restype = C.c_int32
         _lib = lib
     return _lib
@@ -224,6 +235,9 @@ class Params:
         p.radius = self.radius.ctypes.data_as(C.c_void_p)
         p.bath_molar = self.bath.ctypes.data_as(C.c_void_p)
         lin = kw.pop("lin", None)
+        self.rhs_extra = kw.pop("rhs_extra", None)   # device tensor kept alive with the params
+        if self.rhs_extra is not None:
+            p.rhs_extra = _ptr(self.rhs_extra)
         for k, v in kw.items():
             setattr(p, k, v)
         if lin:
@@ -327,3 +341,52 @@ def params_for(prob, lc=None, eps_s=None, **kw) -> Params:
     return Params(sp["valence"], sp["radius_A"], sp["bath_M"],
                   lc=prob.meta.get("lc_A", 0.0) if lc is None else lc,
                   eps_s=prob.meta.get("eps_s", 78.45) if eps_s is None else eps_s, **kw)
+
+
+# ------------------------------------------- singular-charge decomposition
+
+def pf_coulomb(pts, charges, scale, out, dirs=None, stream=None):
+    """phi* of Eq. (5) (scale = lambda / (4 pi eps_m)) or its derivative along
+    face direction dirs[p] (int8, 0..5; 6 = potential) at points pts [n, 3];
+    charges [M, 4] = x, y, z, valence.  All device tensors; `stream` is a
+    torch stream (None = the default stream)."""
+    import torch
+    n = out.numel()
+    M = charges.numel() // 4
+    if pts.numel() != 3 * n or charges.numel() != 4 * M:
+        raise ValueError("pts must be [n, 3] and charges [M, 4]")
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(load().pf_coulomb(_ptr(pts, torch.float64), _ptr(dirs, torch.int8, n), n,
+                             _ptr(charges, torch.float64) if M else None, M, float(scale),
+                             _ptr(out, torch.float64), st), "pf_coulomb")
+
+
+def pf_iface_params_default(**kw) -> pf_iface_params:
+    p = pf_iface_params()
+    load().pf_iface_params_default(C.byref(p))
+    lin = kw.pop("lin", None)
+    for k, v in kw.items():
+        setattr(p, "lambda_" if k == "lam" else k, v)
+    if lin:
+        for k, v in lin.items():
+            setattr(p.lin, k, v)
+    return p
+
+
+def pf_interface_setup(g: Grid, charges, lam, eps_m, eps_s, b_if, phi_reg=None, phi_lap=None,
+                       lin=None, check=True) -> dict:
+    """Interface terms of the decomposition (Sec. 3): fills b_if (and phi_reg
+    = phi* + phi^L on Omega_m, phi_lap = the Laplace solution if given).
+    charges: device [M, 4] in grid length units from node (0, 0, 0)."""
+    import torch
+    M = 0 if charges is None else charges.numel() // 4
+    p = pf_iface_params_default(lam=float(lam), eps_m=float(eps_m), eps_s=float(eps_s), lin=lin)
+    p.n_charges = M
+    p.charges = _ptr(charges, torch.float64) if M else None
+    info = pf_lin_info()
+    code = load().pf_interface_setup(g.handle, C.byref(p), _ptr(b_if, torch.float64, g.N),
+                                     _ptr(phi_reg, torch.float64, g.N), _ptr(phi_lap, torch.float64, g.N),
+                                     C.byref(info))
+    if check:
+        _check(code, "pf_interface_setup")
+    return _info(info)

@@ -1,0 +1,190 @@
+"""GPU parity of the singular-charge decomposition (Sec. 3) against the
+oracle, through the C-ABI.
+
+Bars:
+  * phi* and its derivatives (pf_coulomb): |gpu - oracle| <= 1e-13 times the
+    sum of the magnitudes of the terms (sum |z_j| / r_j, or sum |z_j| / r_j^2),
+    i.e. a few roundings per term whatever the cancellation;
+  * interface terms b_if, phi* + phi^L and phi^L: relative max difference
+    <= 1e-8 of the array's largest magnitude (both sides solve the Laplace
+    problem to relative residual 1e-13; the rest is pointwise);
+  * potential from the decomposition (linear solve with b_if, nonlinear PF
+    loop with b_if as the extra right-hand side): relative L2 <= 1e-9.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_04060_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PI = np.pi
+
+
+def _pf():
+    from paper_1711_04060_amd import pf
+    pf.load()
+    return pf
+
+
+def dev(a, dt=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt or torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("M", [0, 1, 300])
+def test_coulomb_points_match_oracle(M):
+    """Ragged point count, charge tiles of 256 with a ragged tail, every
+    direction code (0..5 derivative, 6 potential) and the dir = NULL form."""
+    pf = _pf()
+    rng = np.random.default_rng(100 + M)
+    n = 1000
+    ch = np.column_stack([rng.uniform(-1, 1, (M, 3)), rng.uniform(-1, 1, M)])
+    pts = rng.uniform(-3, 3, (n, 3))
+    dirs = rng.integers(0, 7, n).astype(np.int8)
+    scale = 0.37
+    ref_d = oracle.coulomb(pts, ch, scale, dirs=dirs.astype(np.int32))
+    ref_p = oracle.coulomb(pts, ch, scale)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    pf.pf_coulomb(dev(pts), dev(ch), scale, out, dirs=dev(dirs, torch.int8))
+    got_d = host(out)
+    pf.pf_coulomb(dev(pts), dev(ch), scale, out)
+    got_p = host(out)
+    r = np.linalg.norm(pts[:, None, :] - ch[None, :, :3], axis=2) if M else np.ones((n, 1))
+    q = np.abs(ch[:, 3]) if M else np.zeros(1)
+    mag_p = scale * (q / r).sum(axis=1)
+    mag_d = scale * (q / r ** 2).sum(axis=1)
+    mag = np.where(dirs == 6, mag_p, mag_d)
+    assert np.all(np.abs(got_d - ref_d) <= 1e-13 * mag + 1e-300)
+    assert np.all(np.abs(got_p - ref_p) <= 1e-13 * mag_p + 1e-300)
+    if M == 0:
+        assert not got_d.any() and not got_p.any()
+
+
+def _born(n, R_cells, eps_m=2.0, eps_s=80.0):
+    c = (n - 1) / 2.0
+    k, j, i = [a.ravel() for a in np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")]
+    r = np.sqrt((i - c) ** 2 + (j - c) ** 2 + (k - c) ** 2)
+    inside = r < R_cells
+    face = (i == 0) | (i == n - 1) | (j == 0) | (j == n - 1) | (k == 0) | (k == n - 1)
+    typ = np.where(inside, oracle.SOLUTE, np.where(face, oracle.FIXED, oracle.SOLVENT)).astype(np.uint8)
+    out_exact = 1.0 / (4 * PI * eps_s * r)
+    g = oracle.Grid(n, n, n, 1.0, np.where(inside, eps_m, eps_s), typ, np.where(face, out_exact, 0.0))
+    return g, np.array([[c, c, c, 1.0]]), 1.0, eps_m, eps_s
+
+
+def _images(n, eps=2.0):
+    """Uniform dielectric, Omega_m meeting a Neumann (x = 0) and a Dirichlet
+    (z = 0) face, FIXED nodes on the other faces."""
+    h = 1.0 / (n - 1)
+    k, j, i = [a.ravel() for a in np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")]
+    half = (n - 1) // 2
+    inside = (i <= half) & (k <= half) & (j >= 1) & (j <= n - 2)
+    fixed = (i == n - 1) | (j == 0) | (j == n - 1) | (k == n - 1)
+    typ = np.where(fixed, oracle.FIXED, np.where(inside, oracle.SOLUTE, oracle.SOLVENT)).astype(np.uint8)
+    rng = np.random.default_rng(5)
+    m = 6
+    pos = np.stack([rng.uniform(0.1, 0.4, m), rng.uniform(0.25, 0.75, m), rng.uniform(0.1, 0.4, m)], 1)
+    real = np.column_stack([pos, np.where(np.arange(m) % 2 == 0, 1.0, -1.0)])
+    fv = np.where(fixed, np.cos(3 * i * h) * np.sin(2 * j * h), 0.0)
+    g = oracle.Grid(n, n, n, h, np.full(n ** 3, eps), typ, fv, bc_phi=(oracle.NEUMANN,) + (oracle.DIRICHLET,) * 5)
+    return g, real, 1.0, eps, eps
+
+
+def _membrane(n, nc):
+    prob = inputs.membrane_pore(n, n_charges=nc)
+    prob = dataclasses.replace(prob, fixed_charge=np.zeros(prob.N))
+    return prob, inputs.point_charges(prob), oracle.lambda_length(1.0), inputs.TABLE1["eps_m"], inputs.TABLE1["eps_s"]
+
+
+def _grid_of(pf, g):
+    return pf.pf_grid_create(g.nx, g.ny, g.nz, g.h, dev(g.eps), dev(g.node_type, torch.uint8), None,
+                             None if g.fixed_value is None else dev(g.fixed_value), g.bc_phi, g.bc_value,
+                             (oracle.DIRICHLET,) * 6)
+
+
+@pytest.mark.parametrize("case", ["born24", "images17", "membrane25"])
+def test_interface_setup_matches_oracle(case):
+    pf = _pf()
+    if case == "born24":
+        g, ch, lam, em, es = _born(24, 6)
+        G = _grid_of(pf, g)
+    elif case == "images17":
+        g, ch, lam, em, es = _images(17)
+        G = _grid_of(pf, g)
+    else:
+        g, ch, lam, em, es = _membrane(25, 300)
+        G = pf.grid_from_problem(g)
+    N = g.nx * g.ny * g.nz
+    rb, rreg, rlap, rinfo = oracle.interface(g, ch, lam, em, es, tol=1e-13)
+    b = torch.empty(N, dtype=torch.float64, device="cuda")
+    reg = torch.empty_like(b)
+    lap = torch.empty_like(b)
+    info = pf.pf_interface_setup(G, dev(ch), lam, em, es, b, reg, lap, lin={"rel_tol": 1e-13})
+    assert info["status"] == 0
+    assert _relmax(host(lap), rlap) <= 1e-8
+    assert _relmax(host(reg), rreg) <= 1e-8
+    assert _relmax(host(b), rb) <= 1e-8
+    assert np.all(host(reg)[g.node_type.ravel() != oracle.SOLUTE] == 0.0)
+    # the potential of the decomposition: phi-tilde from the linear solve, plus phi* + phi^L
+    if case != "membrane25":
+        ref, _ = oracle.linear_solve(g, None, rb, tol=1e-13)
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        pf.pf_linear_solve(G, None, b, x, pf.pf_lin_opts_default(rel_tol=1e-13))
+        assert _rel(host(x) + host(reg), ref + rreg) <= 1e-9
+    # without phi_reg (fewer evaluation points) b_if is unchanged
+    b2 = torch.empty_like(b)
+    pf.pf_interface_setup(G, dev(ch), lam, em, es, b2, lin={"rel_tol": 1e-13})
+    assert _relmax(host(b2), rb) <= 1e-8
+
+
+def test_interface_rejects_mismatched_eps_and_empty_charge_set():
+    pf = _pf()
+    g, ch, lam, em, es = _born(16, 4)
+    G = _grid_of(pf, g)
+    b = torch.empty(g.nx * g.ny * g.nz, dtype=torch.float64, device="cuda")
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_interface_setup(G, dev(ch), lam, 3.0, es, b)
+    assert e.value.code == pf.PF_ERR_ARG
+    reg = torch.full_like(b, 7.0)
+    pf.pf_interface_setup(G, None, lam, em, es, b, reg)
+    assert not host(b).any() and not host(reg).any()
+
+
+def test_nonlinear_with_interface_matches_oracle():
+    """PF loop (Table 2) with the charges treated by the decomposition: the
+    interface terms are the extra PF2 right-hand side and no charge is spread
+    to nodes."""
+    pf = _pf()
+    prob, ch, lam, em, es = _membrane(17, 60)
+    ms = prob.meta["species"]
+    sp = oracle.species_from_molar(ms["valence"], ms["radius_A"], ms["bath_M"])
+    rb, rreg, _, _ = oracle.interface(prob, ch, lam, em, es, tol=1e-13)
+    ref, oinfo, _, _ = oracle.nonlinear_solve(prob, None, sp, 78.45, 1.9, outer_tol=1e-11, lin_tol=1e-13,
+                                              rhs_extra=rb)
+    G = pf.grid_from_problem(prob)
+    b = torch.empty(prob.N, dtype=torch.float64, device="cuda")
+    reg = torch.empty_like(b)
+    pf.pf_interface_setup(G, dev(ch), lam, em, es, b, reg, lin={"rel_tol": 1e-13})
+    prm = pf.params_for(prob, outer_tol=1e-11, lin={"rel_tol": 1e-13}, rhs_extra=b)
+    phi = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
+    info = pf.pf_nonlinear_solve(G, prm, phi)
+    assert info["status"] == 0
+    assert _rel(host(phi), ref) <= 1e-9
+    assert abs(info["outer_iters"] - oinfo["outer_iters"]) <= 3
+    assert _rel(host(phi) + host(reg), ref + rreg) <= 1e-9
