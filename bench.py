@@ -29,12 +29,19 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "time to 1e-10 rel residual & HBM GB/s: FP64 vs mixed-precision vs batched"
 STEP_A_VECTORS = 12.0   # N-vectors step A reads and writes
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector peak
+# Coulomb kernel, per (point, charge) pair: 3 differences, 5 for r^2, 1 for the
+# reciprocal square root, 2 for the potential term and its sum, 5 for the
+# component along the derivative direction, 4 for the derivative term and sum
+COULOMB_FLOP_PER_PAIR = 20.0
 
 
 def log(*a):
@@ -166,6 +173,62 @@ def forms_batch(pf, torch, inputs):
     res["batched_fp64_speedup"] = res["sequential_fp64"]["seconds"] / res["batched_fp64"]["seconds"]
     res["batched_mixed_speedup"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
     return res
+
+
+def forms_interface(pf, torch, inputs, n=97, reps=5):
+    """Singular-charge decomposition (Sec. 3) on the n^3 membrane with its
+    2000 charges: time of pf_interface_setup (Coulomb sums, Laplace solve on
+    Omega_m, SMIB terms); the Coulomb kernel alone over every Omega_m node
+    (potential and one derivative per point, FLOP count per pair below,
+    against the FP64 vector peak); and the PF solve with the interface terms
+    as the extra PF2 right-hand side instead of charges spread to nodes."""
+    import dataclasses
+    prob = dataclasses.replace(inputs.membrane_pore(n), fixed_charge=None)
+    g = pf.grid_from_problem(prob)
+    ch = torch.as_tensor(inputs.point_charges(prob), device="cuda")
+    M = ch.shape[0]
+    lam = inputs.lambda_length_A()
+    em, es = inputs.TABLE1["eps_m"], inputs.TABLE1["eps_s"]
+    b = torch.empty(prob.N, dtype=torch.float64, device="cuda")
+    reg = torch.empty_like(b)
+    pf.pf_interface_setup(g, ch, lam, em, es, b, reg)            # first call: tuning of the Laplace grid
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = pf.pf_interface_setup(g, ch, lam, em, es, b, reg)
+    setup_s = time.perf_counter() - t0
+    # Coulomb kernel over every Omega_m node, timed with events on its stream
+    solute = np.flatnonzero(prob.node_type == inputs.SOLUTE)
+    k, j, i = np.unravel_index(solute, prob.shape)
+    pts = torch.as_tensor(np.column_stack([i, j, k]) * prob.h, device="cuda")
+    dirs = torch.full((len(solute),), 1, dtype=torch.int8, device="cuda")
+    out = torch.empty(len(solute), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    pf.pf_coulomb(pts, ch, 1.0, out, dirs=dirs, stream=st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        pf.pf_coulomb(pts, ch, 1.0, out, dirs=dirs, stream=st)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pairs = float(len(solute)) * M
+    flops = COULOMB_FLOP_PER_PAIR * pairs
+    # PF solve with the decomposition
+    prm = pf.params_for(prob, outer_tol=1e-8, lin={"rel_tol": 1e-10}, rhs_extra=b)
+    phi = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nl = pf.pf_nonlinear_solve(g, prm, phi)
+    solve_s = time.perf_counter() - t0
+    return {"workload": f"membrane_pore {n}^3, {M} charges, Omega_m = {len(solute)} nodes",
+            "setup_seconds": setup_s, "laplace_iters": info["iters"],
+            "coulomb_kernel": {"points": len(solute), "charges": M, "mean_us": ms * 1e3,
+                               "pairs_per_s": pairs / (ms * 1e-3),
+                               "tflops": flops / (ms * 1e-3) / 1e12,
+                               "frac_of_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                               "flop_per_pair": COULOMB_FLOP_PER_PAIR},
+            "pf_solve": {"seconds": solve_s, "outer_iters": nl["outer_iters"],
+                         "lin_iters": nl["total_lin_iters"], "status": nl["status"]}}
 
 
 def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0):
@@ -383,6 +446,8 @@ def main():
         result["forms"]["batch_64"] = forms_batch(pf, torch, inputs)
         log("[bench] forms: isolated cold stencil product at 193^3")
         result["forms"]["spmv_cold_193"] = forms_spmv_cold(pf, torch, inputs)
+        log("[bench] forms: singular-charge decomposition at 97^3")
+        result["forms"]["interface_97"] = forms_interface(pf, torch, inputs)
     if args.bias_sweep:
         log("[bench] forms: 16-bias sweep at 129^3")
         result.setdefault("forms", {})["bias_sweep_129"] = forms_bias_sweep(pf, torch, inputs,

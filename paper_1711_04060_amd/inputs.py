@@ -223,6 +223,12 @@ def point_charges(prob: Problem) -> np.ndarray:
     return np.column_stack([pos - np.asarray(prob.origin, dtype=np.float64), q])
 
 
+def lambda_length_A(unit_A: float = 1.0) -> float:
+    """e^2 / (eps0 kB T) from the Table 1 constants, in units of unit_A Angstrom."""
+    t = TABLE1
+    return t["e"] ** 2 / (t["eps0_F_per_cm"] * 100.0 * t["kB"] * t["T"]) * 1e10 / unit_A
+
+
 def thermal_voltage_mV() -> float:
     """kB T / e in mV with Table 1 constants (for converting bias voltages)."""
     return TABLE1["kB"] * TABLE1["T"] / TABLE1["e"] * 1e3
@@ -242,7 +248,7 @@ def batch_systems(n_sys: int = 64, seed_base: int = 4000, unit_A: float = 10.0):
     sigma = lambda * sum_i z_i^2 c_i on the eps-80 nodes (0 inside), RHS
     lambda q / h^3, zero Dirichlet faces."""
     t = TABLE1
-    lam = t["e"] ** 2 / (t["eps0_F_per_cm"] * 100.0 * t["kB"] * t["T"]) * 1e10 / unit_A
+    lam = lambda_length_A(unit_A)
     per_M = t["NA"] * 1e3 * 1e-30 * unit_A ** 3
     out = []
     for b in range(n_sys):
