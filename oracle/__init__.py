@@ -73,6 +73,12 @@ class _NlOpts(C.Structure):
                 ("rhs_extra", C.c_void_p)]
 
 
+class _Sites(C.Structure):
+    _fields_ = [("n_sites", C.c_int), ("xyz", C.c_void_p), ("radius", C.c_void_p), ("valence", C.c_void_p),
+                ("occupied", C.c_void_p), ("n_atoms", C.c_int), ("atoms", C.c_void_p), ("eps_p", C.c_double),
+                ("eps_b", C.c_double), ("V_sites", C.c_double)]
+
+
 class _NlInfo(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("total_lin_iters", C.c_int),
                 ("last_delta", C.c_double)]
@@ -103,6 +109,11 @@ def _L():
         lib.pfo_coulomb.restype = None
         lib.pfo_smib_rhs.argtypes = [C.POINTER(_Grid), D, D, P, P]
         lib.pfo_interface.argtypes = [C.POINTER(_Grid), I, P, D, D, D, D, I, P, P, P, C.POINTER(_LinInfo)]
+        lib.pfo_bulk_void.argtypes = [C.POINTER(_Species)]
+        lib.pfo_bulk_void.restype = D
+        lib.pfo_site_model.argtypes = [C.POINTER(_Sites), C.POINTER(_Species), P, P, P, P]
+        lib.pfo_site_fill.argtypes = [I, I, I, D, C.POINTER(_Sites), P, P, P]
+        lib.pfo_site_fill.restype = C.c_long
         _lib = lib
     return _lib
 
@@ -365,3 +376,53 @@ def interface(g, charges, lam, eps_m, eps_s, tol=1e-12, maxit=100000):
     if st:
         raise OracleError(st, "interface")
     return b, reg, lap, dict(iters=info.iters, rel_res=info.rel_res)
+
+
+# ------------------------------ filter-region atomic model, Eqs. (19)-(20)
+
+def _sites(sites, keep):
+    xyz = _f64(sites["xyz"]).reshape(-1, 3)
+    rad = _f64(sites["radius"]).ravel()
+    val = _f64(sites["valence"]).ravel()
+    occ = np.ascontiguousarray(sites["occupied"], dtype=np.int32).ravel()
+    atoms = _f64(sites["atoms"]).reshape(-1, 4)
+    keep.extend([xyz, rad, val, occ, atoms])
+    s = _Sites()
+    s.n_sites = len(xyz)
+    s.xyz, s.radius, s.valence, s.occupied = _p(xyz), _p(rad), _p(val), _p(occ)
+    s.n_atoms, s.atoms = len(atoms), _p(atoms)
+    s.eps_p, s.eps_b, s.V_sites = float(sites["eps_p"]), float(sites["eps_b"]), float(sites["V_sites"])
+    return s
+
+
+def bulk_void(sp):
+    keep = []
+    return _L().pfo_bulk_void(C.byref(_species(sp, keep)))
+
+
+def site_model(sites, sp):
+    """Eqs. (19)-(20) at every site: (phi_b, S_b, psi_b, conc_b[n_sites, nsp])."""
+    keep = []
+    s = _sites(sites, keep)
+    spc = _species(sp, keep)
+    n = s.n_sites
+    phi, S, psi = np.empty(n), np.empty(n), np.empty(n)
+    conc = np.empty((n, len(sp.valence)))
+    st = _L().pfo_site_model(C.byref(s), C.byref(spc), _p(phi), _p(S), _p(psi), _p(conc))
+    if st:
+        raise OracleError(st, "site_model")
+    return phi, S, psi, conc
+
+
+def site_fill(nx, ny, nz, h, sites, phi_b, node_type, fixed_value=None):
+    """Filter region: SOLVENT nodes inside a site sphere become FIXED with the
+    nearest site's phi_b.  Returns (node_type, fixed_value, marked)."""
+    keep = []
+    s = _sites(sites, keep)
+    typ = np.ascontiguousarray(node_type, dtype=np.uint8).ravel().copy()
+    fv = np.zeros(nx * ny * nz) if fixed_value is None else _f64(fixed_value).ravel().copy()
+    ph = _f64(phi_b).ravel()
+    marked = _L().pfo_site_fill(int(nx), int(ny), int(nz), float(h), C.byref(s), _p(ph), _p(typ), _p(fv))
+    if marked < 0:
+        raise OracleError(marked, "site_fill")
+    return typ, fv, marked

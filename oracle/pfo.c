@@ -698,3 +698,94 @@ out:
     free(eps1); free(tl); free(fv); free(sig); free(rhs); free(xl); free(pmid); free(gmid); free(jump);
     return st;
 }
+
+/* ------------------------------- filter-region atomic model, Eqs. (19)-(20) */
+
+double pfo_bulk_void(const pfo_species *sp)
+{
+    double lnGB, v0;
+    if (!species_ok(sp, &lnGB, &v0)) return NAN;
+    return sp->steric ? exp(lnGB) : 1.0;
+}
+
+static int sites_ok(const pfo_sites *s)
+{
+    if (s->n_sites < 1 || !s->xyz || !s->radius || !s->valence || !s->occupied) return 0;
+    if (s->n_atoms < 0 || (s->n_atoms > 0 && !s->atoms)) return 0;
+    if (!(s->eps_p > 0.0) || !(s->eps_b > 0.0) || !(s->V_sites > 0.0)) return 0;
+    for (int b = 0; b < s->n_sites; ++b)
+        if (!(s->radius[b] > 0.0) || s->valence[b] == 0.0 || (s->occupied[b] != 0 && s->occupied[b] != 1))
+            return 0;
+    return 1;
+}
+
+int pfo_site_model(const pfo_sites *s, const pfo_species *sp, double *phi_b, double *S_b,
+                   double *psi_b, double *conc_b)
+{
+    const double pi = 3.14159265358979323846;
+    double lnGB, v0;
+    if (!sites_ok(s) || !species_ok(sp, &lnGB, &v0) || !phi_b || !S_b || !psi_b) return PFO_EARG;
+    /* Eq. (20): the same value at every site */
+    double occ = 0.0;
+    for (int m = 0; m < s->n_sites; ++m)
+        if (s->occupied[m]) occ += 4.0 * pi * s->radius[m] * s->radius[m] * s->radius[m] / 3.0;
+    double void_frac = 1.0 - occ / s->V_sites;
+    if (sp->steric && !(void_frac > 0.0)) return PFO_EARG;
+    double S = sp->steric ? log(void_frac) - lnGB : 0.0;
+    for (int b = 0; b < s->n_sites; ++b) {
+        const double *c = s->xyz + 3 * (size_t)b;
+        double a = s->radius[b], acc = 0.0;
+        for (int k = 0; k < 6; ++k) {
+            double A[3] = {c[0], c[1], c[2]};
+            A[k / 2] += (k & 1) ? a : -a;
+            double sa = 0.0, ss = 0.0;
+            for (int j = 0; j < s->n_atoms; ++j) {
+                const double *t = s->atoms + 4 * (size_t)j;
+                double dx = t[0] - A[0], dy = t[1] - A[1], dz = t[2] - A[2];
+                sa += t[3] / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+            for (int m = 0; m < s->n_sites; ++m) {
+                if (m == b || !s->occupied[m]) continue;
+                const double *cm = s->xyz + 3 * (size_t)m;
+                double dx = cm[0] - A[0], dy = cm[1] - A[1], dz = cm[2] - A[2];
+                ss += s->valence[m] / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+            acc += sa / s->eps_p + ss / s->eps_b;
+        }
+        double self = s->occupied[b] ? s->valence[b] / (s->eps_b * a) : 0.0;
+        phi_b[b] = sp->lambda / (4.0 * pi) * (acc / 6.0 + self);
+        S_b[b] = S;
+        psi_b[b] = phi_b[b] - S / s->valence[b];
+        if (conc_b)
+            for (int i = 0; i < sp->nsp; ++i)
+                conc_b[(size_t)b * sp->nsp + i] = sp->cb[i] * exp(-sp->z[i] * phi_b[b] + (sp->v[i] / v0) * S);
+    }
+    return PFO_OK;
+}
+
+long pfo_site_fill(int nx, int ny, int nz, double h, const pfo_sites *s, const double *phi_b,
+                   unsigned char *type, double *fixed_value)
+{
+    if (!grid_ok(nx, ny, nz, h) || !sites_ok(s) || !phi_b || !type || !fixed_value) return PFO_EARG;
+    long marked = 0;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t n = IDX(i, j, k);
+                if (type[n] != PFO_SOLVENT) continue;
+                int best = -1;
+                double bd = 0.0;
+                for (int b = 0; b < s->n_sites; ++b) {
+                    const double *c = s->xyz + 3 * (size_t)b;
+                    double dx = i * h - c[0], dy = j * h - c[1], dz = k * h - c[2];
+                    double d2 = dx * dx + dy * dy + dz * dz;
+                    if (d2 <= s->radius[b] * s->radius[b] && (best < 0 || d2 < bd)) { best = b; bd = d2; }
+                }
+                if (best >= 0) {
+                    type[n] = PFO_FIXED;
+                    fixed_value[n] = phi_b[best];
+                    ++marked;
+                }
+            }
+    return marked;
+}

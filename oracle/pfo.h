@@ -174,6 +174,43 @@ int pfo_interface(const pfo_grid *g, int M, const double *charges, double lambda
                   double eps_s, double lap_tol, int lap_maxit, double *b_if, double *phi_reg,
                   double *phi_lap, pfo_lin_info *lap_info);
 
+/* ------------------------------- filter-region atomic model, Eqs. (19)-(20) */
+
+typedef struct {
+    int n_sites;
+    const double *xyz;        /* [n_sites][3] site centres c_b (grid length units) */
+    const double *radius;     /* [n_sites] a_b */
+    const double *valence;    /* [n_sites] q_b of the ion an occupied site holds (nonzero) */
+    const int *occupied;      /* [n_sites] O_b: 0 or 1 */
+    int n_atoms;
+    const double *atoms;      /* [M][4] x, y, z, partial charge (e) */
+    double eps_p, eps_b;      /* protein and site dielectric */
+    double V_sites;           /* pocket volume of Eq. (20), > 0 */
+} pfo_sites;
+
+/* Bulk void fraction Gamma^B = 1 - sum_i v_i C_i^B of the species (1 when
+ * steric is off, NAN for invalid species). */
+double pfo_bulk_void(const pfo_species *sp);
+
+/* Eq. (19): phi_b (phi-hat units, lambda from sp), the mean over the six
+ * surface points c_b +- a_b e_x, e_y, e_z of the Coulomb sums of the atoms
+ * (eps_p) and of the other occupied sites (eps_b), plus the self term
+ * O_b q_b / (eps_b a_b), all times lambda / (4 pi).  Eq. (20): S_b =
+ * ln((1 - sum_m O_m v_m / V_sites) / Gamma^B) with v_m = 4 pi a_m^3 / 3
+ * (0 when steric is off).  psi_b = phi_b - S_b / q_b (the site's total
+ * potential in phi-hat units).  conc_b [n_sites][nsp] or NULL: Eq. (1) at the
+ * site, C_i^B exp(-z_i phi_b + (v_i / v_0) S_b).  PFO_EARG when the occupied
+ * volume reaches V_sites. */
+int pfo_site_model(const pfo_sites *s, const pfo_species *sp, double *phi_b, double *S_b,
+                   double *psi_b, double *conc_b);
+
+/* Filter region Omega_f: every SOLVENT node within a_b of a site centre
+ * (|r - c_b|^2 <= a_b^2, the nearest centre if several, the lower index on a
+ * tie) becomes FIXED with value phi_b of that site.  Other nodes are left
+ * alone.  Returns the number of nodes marked, or a negative status. */
+long pfo_site_fill(int nx, int ny, int nz, double h, const pfo_sites *s, const double *phi_b,
+                   unsigned char *type, double *fixed_value);
+
 #ifdef __cplusplus
 }
 #endif
