@@ -231,6 +231,50 @@ def forms_interface(pf, torch, inputs, n=97, reps=5):
                          "lin_iters": nl["total_lin_iters"], "status": nl["status"]}}
 
 
+def forms_tps(pf, torch, inputs, n=97, outer_tol=1e-3):
+    """The five states of the exchange cycle on the n^3 membrane: atomic model
+    of the eight sites (Eqs. (19)-(20)), filter-region fill, then the five PF
+    solves one after another and as one batch.  The outer loop stops at the
+    paper's ErrTol of Table 2 (1e-3 on the max-norm update): the occupied
+    sites hold phi-hat values of 50-100 as Dirichlet data, and the relaxed
+    fixed-point iteration approaches 1e-8 only after many thousands of outer
+    iterations there.  BiCGSTAB to relative residual 1e-10."""
+    states = inputs.tps_states(n)
+    prm = pf.params_for(states[0]["problem"], outer_tol=outer_tol, lin={"rel_tol": 1e-10})
+    grids, site_rows = [], []
+    t0 = time.perf_counter()
+    for st in states:
+        prob, s = st["problem"], st["sites"]
+        sites = pf.Sites(s["xyz"], s["radius"], s["valence"], s["occupied"],
+                         torch.as_tensor(st["atoms"], device="cuda"), s["eps_p"], s["eps_b"], s["V_sites"])
+        phi_b, S_b, psi_b, _ = pf.pf_site_model(prm, sites)
+        typ = torch.as_tensor(prob.node_type, device="cuda")
+        fv = torch.as_tensor(prob.fixed_value, device="cuda")
+        marked = pf.pf_site_fill(prob.nx, prob.ny, prob.nz, prob.h, sites, phi_b, typ, fv)
+        grids.append(pf.pf_grid_create(prob.nx, prob.ny, prob.nz, prob.h, torch.as_tensor(prob.eps, device="cuda"),
+                                       typ, torch.as_tensor(prob.fixed_charge, device="cuda"), fv,
+                                       prob.bc_phi, prob.bc_value, prob.bc_psi))
+        site_rows.append(dict(state=st["name"], facing=st["facing"], filter_nodes=marked,
+                              psi_b=dict(zip(inputs.SITE_NAMES, np.round(psi_b, 4).tolist()))))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    res = dict(workload=f"membrane_pore {n}^3, 5 states x 8 sites", outer_tol=outer_tol, setup_seconds=setup_s,
+               sites=site_rows)
+    for name, batched in (("sequential", False), ("batched", True)):
+        phis = [torch.zeros(n ** 3, dtype=torch.float64, device="cuda") for _ in states]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if batched:
+            infos = pf.pf_nonlinear_solve_batch(grids, [prm] * len(grids), phis)
+        else:
+            infos = [pf.pf_nonlinear_solve(g, prm, x) for g, x in zip(grids, phis)]
+        torch.cuda.synchronize()
+        res[name] = dict(seconds=time.perf_counter() - t0, outer_iters=[i["outer_iters"] for i in infos],
+                         status=[i["status"] for i in infos])
+    res["batched_speedup"] = res["sequential"]["seconds"] / res["batched"]["seconds"]
+    return res
+
+
 def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0):
     """Configuration 5: 16 bias voltages on the membrane workload, full PF
     nonlinear solves, batched (shared launches, mixed-precision linear
@@ -354,6 +398,7 @@ def main():
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--n", type=int, default=97)
     ap.add_argument("--bias-sweep", type=int, default=0, help="also run configuration 5 (16 biases, 129^3)")
+    ap.add_argument("--tps", type=int, default=0, help="also run the five exchange-cycle states at 97^3")
     ap.add_argument("--bias-outer", type=int, default=0,
                     help="configuration 5: stop every bias after this many outer iterations (0: converge)")
     ap.add_argument("--max-outer", type=int, default=0, help="bounded outer loop (profiler runs only)")
@@ -448,6 +493,9 @@ def main():
         result["forms"]["spmv_cold_193"] = forms_spmv_cold(pf, torch, inputs)
         log("[bench] forms: singular-charge decomposition at 97^3")
         result["forms"]["interface_97"] = forms_interface(pf, torch, inputs)
+    if args.tps:
+        log("[bench] forms: five exchange-cycle states at 97^3")
+        result.setdefault("forms", {})["tps_97"] = forms_tps(pf, torch, inputs)
     if args.bias_sweep:
         log("[bench] forms: 16-bias sweep at 129^3")
         result.setdefault("forms", {})["bias_sweep_129"] = forms_bias_sweep(pf, torch, inputs,

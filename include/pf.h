@@ -293,6 +293,53 @@ void pf_iface_params_default(pf_iface_params *p);
 pf_status pf_interface_setup(pf_grid *g, const pf_iface_params *p, double *b_if, double *phi_reg,
                              double *phi_lap, pf_lin_info *lap_info);
 
+/* ---------------- filter-region atomic model (Sec. 2, Eqs. (19)-(20)) */
+
+typedef struct {
+    int32_t n_sites;            /* 1..64 access / binding sites                      */
+    const double *site_xyz;     /* host [n_sites][3]: centres c_b, grid length units
+                                   measured from node (0,0,0)                        */
+    const double *site_radius;  /* host [n_sites]: a_b (ion radius of the site)      */
+    const double *site_valence; /* host [n_sites]: q_b of the ion an occupied site
+                                   holds (nonzero)                                   */
+    const int32_t *occupied;    /* host [n_sites]: O_b, 0 or 1                       */
+    int32_t n_atoms;            /* M >= 0 protein atoms                              */
+    const double *atoms;        /* device [M][4]: x, y, z (same frame), charge (e)   */
+    double eps_p, eps_b;        /* protein and site dielectric (Table 1: 20, 10)     */
+    double V_sites;             /* pocket volume of Eq. (20), grid length units^3    */
+} pf_site_params;
+
+/* Atomic model of the filter region.  For every site b (phi-hat units, lambda
+ * from the constants of pp):
+ *   phi_b = lambda/(4 pi) [ (1/6) sum_k ( sum_j z_j / (eps_p |c_j - A_k|)
+ *            + sum_{m != b} O_m q_m / (eps_b |c_m - A_k|) ) + O_b q_b / (eps_b a_b) ]
+ * with A_k the six surface points c_b +- a_b e_x, e_y, e_z (Eq. (19));
+ *   S_b = ln((1 - sum_m O_m v_m / V_sites) / Gamma^B), v_m = 4 pi a_m^3 / 3
+ * (Eq. (20); Gamma^B from the species of pp; S_b = 0 when steric is off);
+ *   psi_b = phi_b - S_b / q_b, the site's total potential in phi-hat units
+ * (the Psi_b of Eqs. (21)-(22) divided by kB T / e);
+ *   conc_b (host [n_sites * n_species] or NULL) = Eq. (1) at the site:
+ *   C_i^B exp(-z_i phi_b + (v_i / v_0) S_b), per cubed grid length unit (as
+ *   the conc output of pf_nonlinear_solve).
+ * phi_b, S_b, psi_b: host [n_sites].  One workgroup per site sums the atoms
+ * in a fixed order.  PF_ERR_ARG when the occupied volume reaches V_sites
+ * with steric on.  Runs on `stream` (NULL = default) and returns when done. */
+pf_status pf_site_model(const pf_pf_params *pp, const pf_site_params *s, double *phi_b, double *S_b,
+                        double *psi_b, double *conc_b, void *stream);
+
+/* Filter region Omega_f as Dirichlet data of the continuum model (Sec. 2:
+ * the atomic model's values bound the continuum problem there): every
+ * SOLVENT node within a_b of a site centre (|r - c_b|^2 <= a_b^2 in plain
+ * FP64; the nearest centre if several, the lower index on a tie) becomes
+ * PF_NODE_FIXED with fixed_value = phi_b of that site.  Other nodes are left
+ * as they are.  node_type: device uint8 [N] in/out; fixed_value: device [N]
+ * in/out; phi_b: host [n_sites]; marked: host or NULL, receives the number of
+ * nodes marked.  Pass the arrays to pf_grid_create afterwards.  Runs on
+ * `stream` (NULL = default) and returns when done. */
+pf_status pf_site_fill(int32_t nx, int32_t ny, int32_t nz, double h, const pf_site_params *s,
+                       const double *phi_b, uint8_t *node_type, double *fixed_value, int64_t *marked,
+                       void *stream);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *pf_last_error(void);
 

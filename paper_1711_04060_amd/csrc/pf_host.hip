@@ -9,6 +9,7 @@
 // status read per outer iteration (the max-norm test of Table 2 step 5).
 #include "pf_kernels.h"
 #include "pf_iface.h"
+#include "pf_sites.h"
 #include "../../include/pf.h"
 
 #include <algorithm>
@@ -2161,6 +2162,108 @@ pf_status pf_interface_setup(pf_grid *g, const pf_iface_params *p, double *b_if,
     HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, g->stream));
     PFCHK(sync(g));
     if (hbad) return fail(PF_ERR_NONFINITE, "interface terms are not finite (a charge on an evaluation point?)");
+    return PF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- filter-region atomic model
+
+namespace {
+
+pf_status check_sites(const pf_site_params *s, std::vector<pfk::SiteRec> &rec)
+{
+    if (!s) return fail(PF_ERR_ARG, "null site parameters");
+    if (s->n_sites < 1 || s->n_sites > pfk::MAX_SITES) return fail(PF_ERR_ARG, "n_sites must be in 1..%d", pfk::MAX_SITES);
+    if (!s->site_xyz || !s->site_radius || !s->site_valence || !s->occupied)
+        return fail(PF_ERR_ARG, "site arrays are required");
+    if (s->n_atoms < 0 || (s->n_atoms > 0 && !s->atoms)) return fail(PF_ERR_ARG, "n_atoms must be >= 0 with an atom array");
+    if (!(s->eps_p > 0) || !(s->eps_b > 0) || !(s->V_sites > 0)) return fail(PF_ERR_ARG, "eps_p, eps_b and V_sites must be > 0");
+    rec.resize(s->n_sites);
+    for (int b = 0; b < s->n_sites; ++b) {
+        const double *c = s->site_xyz + 3 * b;
+        if (!(s->site_radius[b] > 0) || !(s->site_valence[b] != 0) || !std::isfinite(s->site_valence[b]) ||
+            (s->occupied[b] != 0 && s->occupied[b] != 1) || !std::isfinite(c[0] + c[1] + c[2]))
+            return fail(PF_ERR_ARG, "site %d: radius > 0, valence != 0, occupancy 0/1 and a finite centre required", b);
+        rec[b] = pfk::SiteRec{c[0], c[1], c[2], s->site_radius[b], s->site_valence[b], (double)s->occupied[b]};
+    }
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_site_model(const pf_pf_params *pp, const pf_site_params *s, double *phi_b, double *S_b, double *psi_b,
+                        double *conc_b, void *stream)
+{
+    g_err.clear();
+    std::vector<pfk::SiteRec> rec;
+    PFCHK(check_sites(s, rec));
+    if (!pp) return fail(PF_ERR_ARG, "null species parameters");
+    if (!phi_b || !S_b || !psi_b) return fail(PF_ERR_ARG, "phi_b, S_b and psi_b are required");
+    pfk::SpeciesDev sp;
+    PFCHK(species_dev(pp, &sp));
+    double filled = 0;
+    for (const auto &r : rec)
+        if (r.occ != 0) filled += 4.0 * M_PI * r.a * r.a * r.a / 3.0;
+    if (sp.steric && !(filled < s->V_sites))
+        return fail(PF_ERR_ARG, "occupied site volume %.6g must stay below V_sites %.6g", filled, s->V_sites);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n = s->n_sites, w = 3 + sp.nsp;
+    IfTemp tmp;
+    pfk::SiteRec *dsite = nullptr;
+    double *dout = nullptr;
+    PFCHK(tmp.alloc(&dsite, (size_t)n));
+    PFCHK(tmp.alloc(&dout, (size_t)n * w));
+    HIPCHK(hipMemcpyAsync(dsite, rec.data(), n * sizeof(pfk::SiteRec), hipMemcpyHostToDevice, st));
+    pfk::SiteArgs a{dsite, n, s->atoms, s->n_atoms, s->eps_p, s->eps_b, s->V_sites, sp.lam / (4.0 * M_PI), sp, dout};
+    hipLaunchKernelGGL(pfk::k_site_model, dim3(n), dim3(pfk::SITE_NT), 0, st, a);
+    HIPCHK(hipGetLastError());
+    std::vector<double> h((size_t)n * w);
+    HIPCHK(hipMemcpyAsync(h.data(), dout, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int b = 0; b < n; ++b) {
+        phi_b[b] = h[(size_t)b * w];
+        S_b[b] = h[(size_t)b * w + 1];
+        psi_b[b] = h[(size_t)b * w + 2];
+        if (conc_b)
+            for (int i = 0; i < sp.nsp; ++i) conc_b[(size_t)b * sp.nsp + i] = h[(size_t)b * w + 3 + i];
+    }
+    return PF_OK;
+}
+
+pf_status pf_site_fill(int32_t nx, int32_t ny, int32_t nz, double h, const pf_site_params *s, const double *phi_b,
+                       uint8_t *node_type, double *fixed_value, int64_t *marked, void *stream)
+{
+    g_err.clear();
+    std::vector<pfk::SiteRec> rec;
+    PFCHK(check_sites(s, rec));
+    if (nx < 3 || ny < 3 || nz < 3 || !(h > 0) || !std::isfinite(h)) return fail(PF_ERR_ARG, "bad grid shape or spacing");
+    if ((double)nx * ny * nz >= (double)(1u << 29)) return fail(PF_ERR_ARG, "grid too large (N must be < 2^29)");
+    if (!phi_b || !node_type || !fixed_value) return fail(PF_ERR_ARG, "phi_b, node_type and fixed_value are required");
+    for (int b = 0; b < s->n_sites; ++b)
+        if (!std::isfinite(phi_b[b])) return fail(PF_ERR_ARG, "phi_b[%d] is not finite", b);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t N = (size_t)nx * ny * nz;
+    IfTemp tmp;
+    pfk::SiteRec *dsite = nullptr;
+    double *dphi = nullptr;
+    unsigned long long *dcount = nullptr;
+    PFCHK(tmp.alloc(&dsite, (size_t)s->n_sites));
+    PFCHK(tmp.alloc(&dphi, (size_t)s->n_sites));
+    PFCHK(tmp.alloc(&dcount, 1));
+    HIPCHK(hipMemcpyAsync(dsite, rec.data(), s->n_sites * sizeof(pfk::SiteRec), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dphi, phi_b, s->n_sites * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(dcount, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(pfk::k_site_fill, dim3(pw_blocks(N)), dim3(256), 0, st, nx, ny, nz, h,
+                       (const pfk::SiteRec *)dsite, (const double *)dphi, (int)s->n_sites, node_type, fixed_value,
+                       dcount);
+    HIPCHK(hipGetLastError());
+    unsigned long long c = 0;
+    HIPCHK(hipMemcpyAsync(&c, dcount, sizeof c, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (marked) *marked = (int64_t)c;
     return PF_OK;
 }
 

@@ -23,6 +23,7 @@ stand in for it at the same lateral scale, a 40 A box as in Eq. (4)):
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 from dataclasses import dataclass, field
 
@@ -227,6 +228,68 @@ def lambda_length_A(unit_A: float = 1.0) -> float:
     """e^2 / (eps0 kB T) from the Table 1 constants, in units of unit_A Angstrom."""
     t = TABLE1
     return t["e"] ** 2 / (t["eps0_F_per_cm"] * 100.0 * t["kB"] * t["T"]) * 1e10 / unit_A
+
+
+# Synthetic access / binding sites of the filter region (Sec. 2, Fig. 3): a
+# Na+ pathway of five sites and a Ca2+ pathway of three, on two lines parallel
+# to the pore axis, 2 A either side of it.  Positions in A from the box centre.
+SITE_NAMES = ("aS1", "bS2", "bS3", "bS4", "aS5", "aS6", "bS7", "aS8")
+SITE_XYZ_A = ((-2.0, 0.0, 6.0), (-2.0, 0.0, 3.0), (-2.0, 0.0, 0.0), (-2.0, 0.0, -3.0), (-2.0, 0.0, -6.0),
+              (2.0, 0.0, -5.0), (2.0, 0.0, 0.0), (2.0, 0.0, 5.0))
+SITE_ION = ("Na+",) * 5 + ("Ca2+",) * 3
+# The five total-potential states of the exchange cycle (Sec. 2): occupied
+# sites and whether the structure faces inward (z reversed) or outward.
+TPS = (("TPS1", ("bS3", "bS7"), "inward"),
+       ("TPS2", ("aS1", "bS3", "bS7"), "outward"),
+       ("TPS3", ("aS1", "bS2", "bS4", "bS7"), "outward"),
+       ("TPS4", ("bS2", "bS3", "bS4"), "outward"),
+       ("TPS5", ("bS2", "bS3", "bS4"), "inward"))
+
+
+def tps_states(n: int = 97, seed: int = 2, n_charges: int = 2000):
+    """The five states of the exchange cycle on the n^3 membrane.
+
+    The protein atoms are the membrane's shell charges plus twelve chelating
+    oxygens of -0.53 e (together -6.36 e, as Sec. 2 reports for NCX), three
+    around each binding site at 2.4 A from its centre in the plane normal to
+    the pore axis.  They are spread to nodes for the continuum model and kept
+    as point charges for the atomic model of the sites.  Inward-facing states
+    reverse the z coordinate of every atom and site about the box centre.
+    Site centres are moved to their nearest node (so that every site sphere
+    holds at least its centre node), radii are the ion radii (Na+ 0.95 A,
+    Ca2+ 0.99 A), valences 1 and 2, eps_p = 20, eps_b = 10 (Table 1), and the
+    pocket volume of Eq. (20) is twice the volume of the eight site spheres."""
+    base = membrane_pore(n, seed=seed, n_charges=n_charges)
+    h, c = base.h, (n - 1) // 2
+    half = 20.0
+    ion_r = dict(zip(MEMBRANE_SPECIES["name"], MEMBRANE_SPECIES["radius_A"]))
+    radius = np.array([ion_r[x] for x in SITE_ION])
+    valence = np.array([1.0 if x == "Na+" else 2.0 for x in SITE_ION])
+    v_sites = 2.0 * float((4.0 * np.pi * radius ** 3 / 3.0).sum())
+    ox = []
+    for name, xyz in zip(SITE_NAMES, SITE_XYZ_A):
+        if name.startswith("b"):
+            for t in range(3):
+                ang = 2.0 * np.pi * t / 3.0
+                ox.append((xyz[0] + 2.4 * np.cos(ang), xyz[1] + 2.4 * np.sin(ang), xyz[2]))
+    pos = np.vstack([np.asarray(base.meta["positions"], float), np.array(ox)])
+    q = np.concatenate([np.asarray(base.meta["charges"], float), np.full(len(ox), -0.53)])
+    out = []
+    for name, occ_names, facing in TPS:
+        sgn = -1.0 if facing == "inward" else 1.0
+        p = pos * np.array([1.0, 1.0, sgn])
+        ijk = np.rint((p + half) / h).astype(np.int64).T
+        prob = dataclasses.replace(base, name=f"{name}_{n}", fixed_charge=_spread(ijk, q, n),
+                                   fixed_value=np.zeros(base.N),
+                                   meta=dict(base.meta, positions=p, charges=q))
+        sxyz = np.array(SITE_XYZ_A) * np.array([1.0, 1.0, sgn])
+        snode = np.rint((sxyz + half) / h) * h          # nearest node, grid frame
+        occupied = np.array([1 if s in occ_names else 0 for s in SITE_NAMES], np.int32)
+        atoms = np.column_stack([p + half, q])
+        out.append(dict(name=name, facing=facing, problem=prob, atoms=atoms,
+                        sites=dict(xyz=snode, radius=radius, valence=valence, occupied=occupied,
+                                   eps_p=20.0, eps_b=10.0, V_sites=v_sites)))
+    return out
 
 
 def thermal_voltage_mV() -> float:

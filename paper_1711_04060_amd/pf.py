@@ -25,7 +25,7 @@ EXPORTS = ("pf_grid_create", "pf_grid_destroy", "pf_lin_opts_default", "pf_linea
            "pf_residual", "pf_spmv", "pf_spmv_f32", "pf_pf_params_default", "pf_nonlinear_solve",
            "pf_fermi", "pf_linear_solve_batch", "pf_nonlinear_solve_batch", "pf_last_error",
            "pf_set_launch", "pf_timing_enable", "pf_timing_read", "pf_coulomb",
-           "pf_iface_params_default", "pf_interface_setup")
+           "pf_iface_params_default", "pf_interface_setup", "pf_site_model", "pf_site_fill")
 
 
 class pf_grid_desc(C.Structure):
@@ -57,6 +57,12 @@ class pf_pf_params(C.Structure):
 class pf_iface_params(C.Structure):
     _fields_ = [("n_charges", C.c_int32), ("charges", C.c_void_p), ("lambda_", C.c_double),
                 ("eps_m", C.c_double), ("eps_s", C.c_double), ("lin", pf_lin_opts)]
+
+
+class pf_site_params(C.Structure):
+    _fields_ = [("n_sites", C.c_int32), ("site_xyz", C.c_void_p), ("site_radius", C.c_void_p),
+                ("site_valence", C.c_void_p), ("occupied", C.c_void_p), ("n_atoms", C.c_int32),
+                ("atoms", C.c_void_p), ("eps_p", C.c_double), ("eps_b", C.c_double), ("V_sites", C.c_double)]
 
 
 class pf_nl_info(C.Structure):
@@ -105,6 +111,9 @@ def load():
         lib.pf_iface_params_default.argtypes = [C.POINTER(pf_iface_params)]
         lib.pf_iface_params_default.restype = None
         lib.pf_interface_setup.argtypes = [P, C.POINTER(pf_iface_params), P, P, P, C.POINTER(pf_lin_info)]
+        lib.pf_site_model.argtypes = [C.POINTER(pf_pf_params), C.POINTER(pf_site_params), P, P, P, P, P]
+        lib.pf_site_fill.argtypes = [I32, I32, I32, D, C.POINTER(pf_site_params), P, P, P,
+                                     C.POINTER(C.c_int64), P]
         for name in EXPORTS:
             if name not in ("pf_grid_destroy", "pf_lin_opts_default", "pf_pf_params_default", "pf_last_error",
                             "pf_iface_params_default"):
@@ -390,3 +399,59 @@ def pf_interface_setup(g: Grid, charges, lam, eps_m, eps_s, b_if, phi_reg=None, 
     if check:
         _check(code, "pf_interface_setup")
     return _info(info)
+
+
+# ------------------------------------------- filter-region atomic model
+
+class Sites:
+    """pf_site_params plus the arrays it points to.  atoms: device tensor
+    [M, 4]; the site arrays are host arrays."""
+
+    def __init__(self, xyz, radius, valence, occupied, atoms, eps_p=20.0, eps_b=10.0, V_sites=1.0):
+        import torch
+        self.xyz = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+        self.radius = np.ascontiguousarray(radius, np.float64).ravel()
+        self.valence = np.ascontiguousarray(valence, np.float64).ravel()
+        self.occupied = np.ascontiguousarray(occupied, np.int32).ravel()
+        self.atoms = atoms
+        c = pf_site_params()
+        c.n_sites = len(self.xyz)
+        c.site_xyz = self.xyz.ctypes.data_as(C.c_void_p)
+        c.site_radius = self.radius.ctypes.data_as(C.c_void_p)
+        c.site_valence = self.valence.ctypes.data_as(C.c_void_p)
+        c.occupied = self.occupied.ctypes.data_as(C.c_void_p)
+        c.n_atoms = 0 if atoms is None else atoms.numel() // 4
+        c.atoms = _ptr(atoms, torch.float64) if c.n_atoms else None
+        c.eps_p, c.eps_b, c.V_sites = float(eps_p), float(eps_b), float(V_sites)
+        self.c = c
+
+    @property
+    def n(self):
+        return self.c.n_sites
+
+
+def pf_site_model(p: Params, sites: Sites, stream=None):
+    """Eqs. (19)-(20) at every site: numpy (phi_b, S_b, psi_b, conc_b[n_sites, n_species])."""
+    n, nsp = sites.n, p.c.n_species
+    phi, S, psi = np.empty(n), np.empty(n), np.empty(n)
+    conc = np.empty((n, nsp))
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    _check(load().pf_site_model(C.byref(p.c), C.byref(sites.c), P(phi), P(S), P(psi), P(conc), st),
+           "pf_site_model")
+    return phi, S, psi, conc
+
+
+def pf_site_fill(nx, ny, nz, h, sites: Sites, phi_b, node_type, fixed_value, stream=None) -> int:
+    """Mark the filter region: SOLVENT nodes inside a site sphere become FIXED
+    with that site's phi_b (device node_type uint8 and fixed_value float64,
+    both updated in place).  Returns the number of nodes marked."""
+    import torch
+    N = nx * ny * nz
+    ph = np.ascontiguousarray(phi_b, np.float64)
+    marked = C.c_int64()
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(load().pf_site_fill(int(nx), int(ny), int(nz), float(h), C.byref(sites.c), ph.ctypes.data_as(C.c_void_p),
+                               _ptr(node_type, torch.uint8, N), _ptr(fixed_value, torch.float64, N),
+                               C.byref(marked), st), "pf_site_fill")
+    return marked.value

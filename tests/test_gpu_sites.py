@@ -1,0 +1,136 @@
+"""GPU parity of the filter-region atomic model (Eqs. (19)-(20)), the fill
+that makes the site spheres Dirichlet nodes, and the multi-state batched PF
+solve of the exchange cycle's five states, against the oracle.
+
+Bars: phi_b, S_b, psi_b and the site concentrations: relative 1e-12 of the
+magnitude sum (the atom sums are reduced in another order); the fill:
+bit-exact node types and values; PF potentials: relative L2 <= 1e-9 at outer
+tolerance 1e-11, inner 1e-13."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_04060_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MS = inputs.MEMBRANE_SPECIES
+
+
+def _pf():
+    from paper_1711_04060_amd import pf
+    pf.load()
+    return pf
+
+
+def dev(a, dt=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt or torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _sp():
+    return oracle.species_from_molar(MS["valence"], MS["radius_A"], MS["bath_M"])
+
+
+def _random_sites(rng, n_sites, M):
+    xyz = rng.uniform(-3, 3, (n_sites, 3))
+    return dict(xyz=xyz, radius=rng.uniform(0.8, 1.1, n_sites), valence=rng.choice([1.0, 2.0, -1.0], n_sites),
+                occupied=rng.integers(0, 2, n_sites).astype(np.int32),
+                atoms=np.column_stack([rng.uniform(-8, 8, (M, 3)), rng.uniform(-1, 1, M)]),
+                eps_p=20.0, eps_b=10.0, V_sites=200.0)
+
+
+def _pf_sites(pf, s):
+    return pf.Sites(s["xyz"], s["radius"], s["valence"], s["occupied"],
+                    dev(s["atoms"]) if len(s["atoms"]) else None, s["eps_p"], s["eps_b"], s["V_sites"])
+
+
+@pytest.mark.parametrize("M", [0, 7, 600])
+def test_site_model_matches_oracle(M):
+    pf = _pf()
+    rng = np.random.default_rng(30 + M)
+    s = _random_sites(rng, 8, M)
+    sp = _sp()
+    rphi, rS, rpsi, rconc = oracle.site_model(s, sp)
+    prm = pf.Params(MS["valence"], MS["radius_A"], MS["bath_M"])
+    phi, S, psi, conc = pf.pf_site_model(prm, _pf_sites(pf, s))
+    # magnitude of the terms of phi_b: the same sums with every charge positive
+    sa = dict(s, valence=np.abs(s["valence"]), atoms=np.column_stack([s["atoms"][:, :3], np.abs(s["atoms"][:, 3])]))
+    mag = oracle.site_model(sa, sp)[0] + 1e-300
+    assert np.all(np.abs(phi - rphi) <= 1e-12 * mag)
+    np.testing.assert_allclose(S, rS, rtol=1e-14, atol=1e-15)
+    assert np.all(np.abs(psi - rpsi) <= 1e-12 * mag + 1e-14)
+    z = np.abs(np.asarray(MS["valence"]))[None, :]
+    assert np.all(np.abs(conc - rconc) <= (1e-12 * z * mag[:, None] + 1e-13) * rconc)
+
+
+def test_site_fill_matches_oracle_bit_for_bit():
+    pf = _pf()
+    n, h = 23, 0.41
+    rng = np.random.default_rng(8)
+    typ = rng.choice([0, 1, 2], size=n ** 3, p=[0.7, 0.2, 0.1]).astype(np.uint8)
+    fv0 = np.where(typ == 2, rng.normal(size=n ** 3), 0.0)
+    s = _random_sites(rng, 9, 0)
+    s["xyz"] = rng.uniform(0.5, (n - 1) * h - 0.5, (9, 3))
+    s["xyz"][1] = s["xyz"][0] + [0.0, 0.3, 0.0]
+    s["xyz"][2] = (np.rint(s["xyz"][2] / h) + [0.5, 0.0, 0.0]) * h   # a node exactly a_b away: tie cases
+    phi = rng.normal(size=9)
+    rt, rfv, rmarked = oracle.site_fill(n, n, n, h, s, phi, typ, fv0)
+    t = dev(typ, torch.uint8)
+    f = dev(fv0)
+    marked = pf.pf_site_fill(n, n, n, h, _pf_sites(pf, s), phi, t, f)
+    np.testing.assert_array_equal(host(t), rt)
+    np.testing.assert_array_equal(host(f), rfv)
+    assert marked == rmarked and marked > 0
+
+
+def _state_oracle(st, sp):
+    prob = st["problem"]
+    sites = dict(st["sites"], atoms=st["atoms"])
+    phi_b, S_b, psi_b, _ = oracle.site_model(sites, sp)
+    typ, fv, _ = oracle.site_fill(prob.nx, prob.ny, prob.nz, prob.h, sites, phi_b, prob.node_type)
+    p2 = dataclasses.replace(prob, node_type=typ, fixed_value=fv)
+    ref, info, _, _ = oracle.nonlinear_solve(p2, p2.fixed_charge, sp, 78.45, 1.9, outer_tol=1e-11, lin_tol=1e-13)
+    return phi_b, psi_b, ref, info
+
+
+def _state_gpu(pf, st, prm):
+    prob = st["problem"]
+    s = st["sites"]
+    sites = pf.Sites(s["xyz"], s["radius"], s["valence"], s["occupied"], dev(st["atoms"]), s["eps_p"], s["eps_b"],
+                     s["V_sites"])
+    phi_b, S_b, psi_b, _ = pf.pf_site_model(prm, sites)
+    typ = dev(prob.node_type, torch.uint8)
+    fv = dev(prob.fixed_value)
+    pf.pf_site_fill(prob.nx, prob.ny, prob.nz, prob.h, sites, phi_b, typ, fv)
+    g = pf.pf_grid_create(prob.nx, prob.ny, prob.nz, prob.h, dev(prob.eps), typ, dev(prob.fixed_charge), fv,
+                          prob.bc_phi, prob.bc_value, prob.bc_psi)
+    return phi_b, psi_b, g
+
+
+def test_exchange_cycle_states_batched_match_oracle():
+    """Two states of the cycle (TPS1 inward-facing, TPS4 outward-facing) on the
+    17^3 membrane: site model, filter-region fill and the batched PF solve."""
+    pf = _pf()
+    sp = _sp()
+    states = [s for s in inputs.tps_states(17, n_charges=40) if s["name"] in ("TPS1", "TPS4")]
+    prm = pf.params_for(states[0]["problem"], outer_tol=1e-11, lin={"rel_tol": 1e-13})
+    grids, phis, refs = [], [], []
+    for st in states:
+        rphi_b, rpsi_b, ref, info = _state_oracle(st, sp)
+        phi_b, psi_b, g = _state_gpu(pf, st, prm)
+        assert np.all(np.abs(phi_b - rphi_b) <= 1e-11 * (1 + np.abs(rphi_b)))
+        assert np.all(np.abs(psi_b - rpsi_b) <= 1e-11 * (1 + np.abs(rpsi_b)))
+        grids.append(g)
+        phis.append(torch.zeros(st["problem"].N, dtype=torch.float64, device="cuda"))
+        refs.append(ref)
+    infos = pf.pf_nonlinear_solve_batch(grids, [prm] * len(grids), phis)
+    for phi, ref, info in zip(phis, refs, infos):
+        assert info["status"] == 0
+        assert np.linalg.norm(host(phi) - ref) / np.linalg.norm(ref) <= 1e-9
