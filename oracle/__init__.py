@@ -58,7 +58,7 @@ class _Grid(C.Structure):
 
 class _LinInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("rel_res", C.c_double),
-                ("bnorm", C.c_double)]
+                ("bnorm", C.c_double), ("max_res", C.c_double)]
 
 
 class _Species(C.Structure):
@@ -100,6 +100,7 @@ def _L():
         lib.pfo_dia_matvec.restype = None
         lib.pfo_bicgstab.argtypes = [I, I, I, P, P, P, P, P, D, I, C.POINTER(_LinInfo)]
         lib.pfo_linear_solve.argtypes = [C.POINTER(_Grid), P, P, P, D, I, C.POINTER(_LinInfo)]
+        lib.pfo_linear_solve_rule.argtypes = [C.POINTER(_Grid), P, P, P, D, I, I, C.POINTER(_LinInfo)]
         lib.pfo_fermi.argtypes = [S, P, P, C.POINTER(_Species), P, P, P, P]
         lib.pfo_steric_root.argtypes = [D, C.POINTER(_Species)]
         lib.pfo_steric_root.restype = D
@@ -215,8 +216,9 @@ def bicgstab(nx, ny, nz, A, is_dir, value, b, x0=None, tol=1e-12, maxit=100000, 
     return x, d
 
 
-def linear_solve(g, sigma, b, x0=None, tol=1e-12, maxit=100000, check=True):
-    """Assemble + BiCGSTAB for (-div eps grad + sigma) x = b on grid g."""
+def linear_solve(g, sigma, b, x0=None, tol=1e-12, maxit=100000, check=True, rule=0):
+    """Assemble + BiCGSTAB for (-div eps grad + sigma) x = b on grid g.
+    rule 0: stop on the relative L2 residual; 1: on the absolute max norm (Table 3)."""
     keep = []
     s = _grid(g, keep)
     N = g.nx * g.ny * g.nz
@@ -224,8 +226,10 @@ def linear_solve(g, sigma, b, x0=None, tol=1e-12, maxit=100000, check=True):
     b = _f64(b).ravel()
     x = np.zeros(N) if x0 is None else _f64(x0).ravel().copy()
     info = _LinInfo()
-    st = _L().pfo_linear_solve(C.byref(s), _p(sig), _p(b), _p(x), float(tol), int(maxit), C.byref(info))
-    d = dict(status=st, iters=info.iters, restarts=info.restarts, rel_res=info.rel_res, bnorm=info.bnorm)
+    st = _L().pfo_linear_solve_rule(C.byref(s), _p(sig), _p(b), _p(x), float(tol), int(maxit), int(rule),
+                                    C.byref(info))
+    d = dict(status=st, iters=info.iters, restarts=info.restarts, rel_res=info.rel_res, bnorm=info.bnorm,
+             max_res=info.max_res)
     if check and st:
         raise OracleError(st, "linear_solve")
     return x, d

@@ -180,11 +180,35 @@ static void residual(int nx, int ny, int nz, const double *A, const unsigned cha
     for (size_t n = 0; n < N; ++n) r[n] = (is_dir[n] ? value[n] : b[n]) - r[n];
 }
 
+static double maxabs(size_t N, const double *a)
+{
+    double m = 0.0;
+    for (size_t n = 0; n < N; ++n) {
+        double v = fabs(a[n]);
+        if (v > m || isnan(v)) m = v;
+    }
+    return m;
+}
+
+/* The stop test: rule 0, ||r||_2 / ||b_lift||_2 <= tol; rule 1, the absolute
+ * max norm of Table 3, ||r||_inf <= tol. */
+static int small_res(size_t N, const double *r, double bnorm, double tol, int rule)
+{
+    return rule ? maxabs(N, r) <= tol : sqrt(dot(N, r, r)) / bnorm <= tol;
+}
+
 int pfo_bicgstab(int nx, int ny, int nz, const double *A, const unsigned char *is_dir,
                  const double *value, const double *b, double *x, double tol,
                  int maxit, pfo_lin_info *info)
 {
-    if (!(tol > 0.0) || maxit < 0) return PFO_EARG;
+    return pfo_bicgstab_rule(nx, ny, nz, A, is_dir, value, b, x, tol, maxit, 0, info);
+}
+
+int pfo_bicgstab_rule(int nx, int ny, int nz, const double *A, const unsigned char *is_dir,
+                      const double *value, const double *b, double *x, double tol,
+                      int maxit, int rule, pfo_lin_info *info)
+{
+    if (!(tol > 0.0) || maxit < 0 || (rule != 0 && rule != 1)) return PFO_EARG;
     size_t N = (size_t)nx * ny * nz;
     const double *A0 = A;
     double *w = (double *)malloc(10 * N * sizeof(double));
@@ -205,13 +229,13 @@ int pfo_bicgstab(int nx, int ny, int nz, const double *A, const unsigned char *i
     if (bnorm == 0.0) {
         /* homogeneous problem: the solution is x_D */
         memcpy(x, xd, N * sizeof(double));
-        if (info) { info->iters = 0; info->restarts = 0; info->rel_res = 0.0; info->bnorm = 0.0; }
+        if (info) { info->iters = 0; info->restarts = 0; info->rel_res = 0.0; info->bnorm = 0.0; info->max_res = 0.0; }
         free(w);
         return PFO_OK;
     }
     residual(nx, ny, nz, A, is_dir, value, b, x, r);
-    double rnorm = sqrt(dot(N, r, r));
-    if (rnorm / bnorm <= tol) goto done;
+    double rnorm;
+    if (small_res(N, r, bnorm, tol, rule)) goto done;
 
     double rho_old, alpha, omega, rho;
 restart:
@@ -237,11 +261,11 @@ restart:
         if (rtv == 0.0) { ++restarts; goto restart; }
         alpha = rho / rtv;
         for (size_t n = 0; n < N; ++n) s[n] = r[n] - alpha * v[n];
-        if (sqrt(dot(N, s, s)) / bnorm <= tol) {
+        if (small_res(N, s, bnorm, tol, rule)) {
             /* early exit on the half-step residual (Templates form) */
             for (size_t n = 0; n < N; ++n) x[n] += alpha * ph[n];
             residual(nx, ny, nz, A, is_dir, value, b, x, r);
-            if (sqrt(dot(N, r, r)) / bnorm <= tol) goto done;
+            if (small_res(N, r, bnorm, tol, rule)) goto done;
             ++restarts;
             goto restart;
         }
@@ -255,10 +279,10 @@ restart:
         rho_old = rho;
         double rn = sqrt(dot(N, r, r));
         if (!isfinite(rn)) { status = PFO_ENONFINITE; goto done; }
-        if (rn / bnorm <= tol) {
+        if (small_res(N, r, bnorm, tol, rule)) {
             /* confirm with the true residual; continue from it if it fails */
             residual(nx, ny, nz, A, is_dir, value, b, x, r);
-            if (sqrt(dot(N, r, r)) / bnorm <= tol) goto done;
+            if (small_res(N, r, bnorm, tol, rule)) goto done;
             ++restarts;
             goto restart;
         }
@@ -268,17 +292,26 @@ restart:
 done:
     residual(nx, ny, nz, A, is_dir, value, b, x, r);
     rnorm = sqrt(dot(N, r, r));
-    if (info) { info->iters = iters; info->restarts = restarts; info->rel_res = rnorm / bnorm; info->bnorm = bnorm; }
+    if (info) {
+        info->iters = iters; info->restarts = restarts; info->rel_res = rnorm / bnorm; info->bnorm = bnorm;
+        info->max_res = maxabs(N, r);
+    }
     free(w);
     return status;
 done_nores:
-    if (info) { info->iters = 0; info->restarts = 0; info->rel_res = NAN; info->bnorm = bnorm; }
+    if (info) { info->iters = 0; info->restarts = 0; info->rel_res = NAN; info->bnorm = bnorm; info->max_res = NAN; }
     free(w);
     return status;
 }
 
 int pfo_linear_solve(const pfo_grid *g, const double *sigma, const double *b,
                      double *x, double tol, int maxit, pfo_lin_info *info)
+{
+    return pfo_linear_solve_rule(g, sigma, b, x, tol, maxit, 0, info);
+}
+
+int pfo_linear_solve_rule(const pfo_grid *g, const double *sigma, const double *b,
+                          double *x, double tol, int maxit, int rule, pfo_lin_info *info)
 {
     int nx = g->nx, ny = g->ny, nz = g->nz;
     if (!grid_ok(nx, ny, nz, g->h) || !g->eps || !b || !x) return PFO_EARG;
@@ -291,7 +324,7 @@ int pfo_linear_solve(const pfo_grid *g, const double *sigma, const double *b,
     if (!A || !isd || !val) { free(A); free(isd); free(val); return PFO_ENOMEM; }
     int st = pfo_dirichlet(g, 0, NULL, isd, val);
     if (st == PFO_OK) st = pfo_assemble(nx, ny, nz, g->h, g->eps, sigma, g->bc, isd, A);
-    if (st == PFO_OK) st = pfo_bicgstab(nx, ny, nz, A, isd, val, b, x, tol, maxit, info);
+    if (st == PFO_OK) st = pfo_bicgstab_rule(nx, ny, nz, A, isd, val, b, x, tol, maxit, rule, info);
     free(A); free(isd); free(val);
     return st;
 }

@@ -75,6 +75,7 @@ typedef struct {
     int restarts;       /* shadow-residual restarts */
     double rel_res;     /* final true ||b - A x||_2 / ||b_lifted||_2 */
     double bnorm;       /* ||b_lifted||_2 */
+    double max_res;     /* final true ||b - A x||_inf (free rows; Dirichlet rows are 0) */
 } pfo_lin_info;
 
 /* Right-Jacobi BiCGSTAB on A x = b.  x: in = initial guess, out = solution;
@@ -84,9 +85,18 @@ int pfo_bicgstab(int nx, int ny, int nz, const double *A, const unsigned char *i
                  const double *value, const double *b, double *x, double tol,
                  int maxit, pfo_lin_info *info);
 
+/* The same with a choice of stop test: rule 0 as above; rule 1 the absolute
+ * max norm of Table 3, ||r||_inf <= tol, on the recurrence residual and then
+ * confirmed on the true residual. */
+int pfo_bicgstab_rule(int nx, int ny, int nz, const double *A, const unsigned char *is_dir,
+                      const double *value, const double *b, double *x, double tol,
+                      int maxit, int rule, pfo_lin_info *info);
+
 /* Assemble + solve for system 0 of g: (-div eps grad + sigma) x = b. */
 int pfo_linear_solve(const pfo_grid *g, const double *sigma, const double *b,
                      double *x, double tol, int maxit, pfo_lin_info *info);
+int pfo_linear_solve_rule(const pfo_grid *g, const double *sigma, const double *b,
+                          double *x, double tol, int maxit, int rule, pfo_lin_info *info);
 
 typedef struct {
     int nsp;                  /* K+1 species, water last */

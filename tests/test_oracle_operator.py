@@ -260,3 +260,40 @@ def test_dirichlet_precedence():
     assert val[idx(0, 2, 0)] == 3.0 and val[idx(2, 0, 0)] == 3.0
     assert isd[idx(3, 2, 2)] == 0 and isd[idx(3, 3, 3)] == 0
     assert isd.sum() == n ** 3 - (n - 1) ** 3
+
+
+def test_max_norm_stop_rule():
+    """Table 3's absolute max-norm test: the returned x meets ||b - A x||_inf <=
+    tol, recomputed here with a sparse matrix of the same diagonals."""
+    import scipy.sparse as sps
+    g, sigma, b = _stop_rule_problem()
+    N = g.nx * g.ny * g.nz
+    isd, val = oracle.dirichlet(g)
+    A = oracle.assemble(g.nx, g.ny, g.nz, g.h, g.eps, sigma, isd, g.bc_phi)
+    offs = [0, 1, -1, -g.nx, g.nx, -g.nx * g.ny, g.nx * g.ny]
+    # row n of diagonal d holds a[n, n + off_d]
+    M = sps.lil_matrix((N, N))
+    for d, off in enumerate(offs):
+        for n in range(N):
+            m = n + off
+            if 0 <= m < N and A[d, n] != 0.0:
+                M[n, m] += A[d, n]
+    M = M.tocsr()
+    for tol in (1e-3, 1e-7):
+        x, info = oracle.linear_solve(g, sigma, b, tol=tol, rule=1)
+        r = np.where(isd.astype(bool), val - x, b - M @ x)
+        assert np.abs(r).max() <= tol
+        assert info["max_res"] == pytest.approx(np.abs(r).max(), rel=1e-6, abs=1e-15)
+    # the relative rule at a loose tolerance leaves a larger max norm than the strict absolute one
+    x0, i0 = oracle.linear_solve(g, sigma, b, tol=1e-3)
+    x1, i1 = oracle.linear_solve(g, sigma, b, tol=1e-9, rule=1)
+    assert i1["iters"] > i0["iters"]
+
+
+def _stop_rule_problem():
+    rng = np.random.default_rng(12)
+    nx, ny, nz = 9, 8, 7
+    N = nx * ny * nz
+    eps = rng.uniform(1.0, 40.0, N)
+    g = oracle.Grid(nx, ny, nz, 0.3, eps, bc_phi=(D, NM, D, D, NM, D), bc_value=(0.5, 0, -0.25, 0.0, 0, 1.0))
+    return g, rng.uniform(0.0, 2.0, N), rng.normal(size=N)
