@@ -275,6 +275,30 @@ def forms_tps(pf, torch, inputs, n=97, outer_tol=1e-3):
     return res
 
 
+def forms_loop_settings(pf, torch, inputs, n=49):
+    """Outer-loop settings on the n^3 membrane: relaxation weight omega and
+    outer tolerance ErrTol swept with BiCGSTAB to relative residual 1e-10,
+    plus the paper's own settings (Table 2: omega 0.3, ErrTol 1e-3; Table 3:
+    absolute max-norm residual 1e-6 for every linear solve)."""
+    prob = inputs.membrane_pore(n)
+    g = pf.grid_from_problem(prob)
+    runs = []
+    cases = [(w, t, pf.PF_STOP_REL2, 1e-10) for t in (1e-3, 1e-8) for w in (0.1, 0.3, 0.5, 0.7)]
+    cases.append((0.3, 1e-3, pf.PF_STOP_ABS_INF, 1e-6))
+    for omega, tol, rule, ltol in cases:
+        prm = pf.params_for(prob, omega=omega, outer_tol=tol, max_outer=20000,
+                            lin={"rel_tol": ltol, "stop_rule": rule})
+        phi = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = pf.pf_nonlinear_solve(g, prm, phi, check=False)
+        torch.cuda.synchronize()
+        runs.append(dict(omega=omega, outer_tol=tol, linear_stop="abs_inf" if rule else "rel2", linear_tol=ltol,
+                         seconds=time.perf_counter() - t0, outer_iters=info["outer_iters"],
+                         lin_iters=info["total_lin_iters"], status=info["status"]))
+    return dict(workload=f"membrane_pore {n}^3", runs=runs)
+
+
 def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0):
     """Configuration 5: 16 bias voltages on the membrane workload, full PF
     nonlinear solves, batched (shared launches, mixed-precision linear
@@ -399,6 +423,7 @@ def main():
     ap.add_argument("--n", type=int, default=97)
     ap.add_argument("--bias-sweep", type=int, default=0, help="also run configuration 5 (16 biases, 129^3)")
     ap.add_argument("--tps", type=int, default=0, help="also run the five exchange-cycle states at 97^3")
+    ap.add_argument("--loop-settings", type=int, default=0, help="also sweep omega and ErrTol at 49^3")
     ap.add_argument("--bias-outer", type=int, default=0,
                     help="configuration 5: stop every bias after this many outer iterations (0: converge)")
     ap.add_argument("--max-outer", type=int, default=0, help="bounded outer loop (profiler runs only)")
@@ -493,6 +518,9 @@ def main():
         result["forms"]["spmv_cold_193"] = forms_spmv_cold(pf, torch, inputs)
         log("[bench] forms: singular-charge decomposition at 97^3")
         result["forms"]["interface_97"] = forms_interface(pf, torch, inputs)
+    if args.loop_settings:
+        log("[bench] forms: outer-loop settings at 49^3")
+        result.setdefault("forms", {})["loop_settings_49"] = forms_loop_settings(pf, torch, inputs)
     if args.tps:
         log("[bench] forms: five exchange-cycle states at 97^3")
         result.setdefault("forms", {})["tps_97"] = forms_tps(pf, torch, inputs)

@@ -66,6 +66,16 @@ typedef enum { PF_NODE_SOLVENT = 0, PF_NODE_SOLUTE = 1, PF_NODE_FIXED = 2 } pf_n
 
 typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;
 
+/* Stop test of a linear solve.  PF_STOP_REL2: true relative residual
+ * ||b - A x||_2 / ||b_lift||_2 <= rel_tol (the default).  PF_STOP_ABS_INF:
+ * the absolute max norm of Table 3, ||b - A x||_inf <= rel_tol over the free
+ * rows (rel_tol then holds an absolute tolerance, the paper's 1e-6); the
+ * device iteration stops once ||r||_2^2 <= N rel_tol^2 on its recurrence
+ * residual, and the true max norm, checked on the host after each chunk of
+ * iterations, decides (Table 3 tests the recurrence residual after every
+ * iteration). */
+typedef enum { PF_STOP_REL2 = 0, PF_STOP_ABS_INF = 1 } pf_stop_rule;
+
 typedef struct pf_grid pf_grid;   /* opaque; owns device copies of its fields */
 
 typedef struct {
@@ -102,6 +112,7 @@ typedef struct {
     int32_t max_refine;    /* PF_MIXED: maximum refinement steps                     */
     int32_t check_every;   /* iterations per device-side chunk between host checks;
                               0 = library default                                     */
+    int32_t stop_rule;     /* pf_stop_rule                                            */
 } pf_lin_opts;
 
 typedef struct {
@@ -111,10 +122,11 @@ typedef struct {
     double rel_res;        /* final true relative residual                           */
     double seconds;        /* wall time of the call                                  */
     int32_t status;        /* pf_status of the call                                  */
+    double max_res;        /* final true ||b - A x||_inf (PF_STOP_ABS_INF), else -1  */
 } pf_lin_info;
 
 /* Fill *o with defaults: rel_tol 1e-10, max_iter 20000, PF_FP64,
- * inner_tol 1e-5, max_refine 30, check_every 0. */
+ * inner_tol 1e-5, max_refine 30, check_every 0, PF_STOP_REL2. */
 void pf_lin_opts_default(pf_lin_opts *o);
 
 /* Solve (-div eps grad + sigma) x = b on grid g (potential boundary data:

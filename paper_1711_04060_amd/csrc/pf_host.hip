@@ -902,6 +902,7 @@ pf_status check_opts(const pf_lin_opts *o)
     if (o->precision == PF_MIXED && (!(o->inner_tol > 0.0) || o->inner_tol >= 1.0 || o->max_refine <= 0))
         return fail(PF_ERR_ARG, "mixed precision needs 0 < inner_tol < 1 and max_refine > 0");
     if (o->check_every < 0) return fail(PF_ERR_ARG, "check_every must be >= 0");
+    if (o->stop_rule != PF_STOP_REL2 && o->stop_rule != PF_STOP_ABS_INF) return fail(PF_ERR_ARG, "unknown stop_rule");
     return PF_OK;
 }
 
@@ -919,7 +920,7 @@ struct LinSolve {
     bool mixed = false;
     double *dinv64 = nullptr;
     float *dinv32 = nullptr;
-    double bnorm = 0, tol2 = 0, rr = 0;
+    double bnorm = 0, tol2 = 0, rr = 0, rinf = 0;   // rinf: true ||r||_inf (PF_STOP_ABS_INF)
     int iter = 0, restarts = 0, refinements = 0;
     bool started = false, done = false;
     pf_status result = PF_OK;
@@ -934,6 +935,13 @@ pf_status ls_round_residual(LinSolve &L)
         PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, nullptr, g->w32.r, g->w32.rt));
     else
         PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, g->w64.rt, nullptr, nullptr));
+    if (L.o->stop_rule == PF_STOP_ABS_INF) {   // ||r||_inf of the free rows into red[2]
+        const int B = pw_blocks(g->N);
+        hipLaunchKernelGGL(pfk::k_maxabs_free<NT>, dim3(B), dim3(NT), 0, g->stream, g->N, (const double *)g->w64.r,
+                           (const uint8_t *)g->flags, dirbit(L.op), g->partials);
+        HIPCHK(hipGetLastError());
+        PFCHK(finalize<pfk::FIN_MAX>(g, B, 2));
+    }
     return PF_OK;
 }
 
@@ -980,7 +988,11 @@ pf_status ls_init_decide(LinSolve &L)
         L.done = true;
         return PF_OK;
     }
-    L.tol2 = L.o->rel_tol * L.o->rel_tol * L.bnorm * L.bnorm;
+    // the device-side trigger: ||r||_2^2 <= tol2.  For the max-norm rule,
+    // ||r||_inf <= tol implies ||r||_2^2 <= N tol^2, so the trigger fires no
+    // later than the rule can hold; the true max norm then decides.
+    if (L.o->stop_rule == PF_STOP_ABS_INF) L.tol2 = (double)g->N * L.o->rel_tol * L.o->rel_tol;
+    else L.tol2 = L.o->rel_tol * L.o->rel_tol * L.bnorm * L.bnorm;
     return PF_OK;
 }
 
@@ -998,7 +1010,18 @@ pf_status ls_round_decide(LinSolve &L, bool *run)
     *run = false;
     L.rr = g->hsc->red[0];
     if (!std::isfinite(L.rr)) { L.result = PF_ERR_NONFINITE; L.done = true; return PF_OK; }
-    if (L.rr <= L.tol2) { L.done = true; return PF_OK; }
+    if (L.o->stop_rule == PF_STOP_ABS_INF) {
+        L.rinf = g->hsc->red[2];
+        if (L.rinf <= L.o->rel_tol) { L.done = true; return PF_OK; }
+        // the max norm still misses: aim the device trigger at the L2 norm
+        // the max norm should reach if both shrink together (with a margin);
+        // never below tol^2, where ||r||_2 <= tol already implies the rule
+        const double tol = L.o->rel_tol, q = tol / L.rinf;
+        L.tol2 = std::max(tol * tol, std::min(L.tol2, 0.25 * q * q * L.rr));
+    } else if (L.rr <= L.tol2) {
+        L.done = true;
+        return PF_OK;
+    }
     if (!L.mixed) {
         if (L.iter >= L.o->max_iter) { L.result = PF_ERR_NOCONV; L.done = true; return PF_OK; }
         if (L.started) ++L.restarts;
@@ -1043,8 +1066,11 @@ pf_status ls_finish(const LinSolve &L, pf_lin_info *info)
     li.refinements = L.refinements;
     li.restarts = L.restarts;
     li.rel_res = L.bnorm > 0 ? std::sqrt(L.rr) / L.bnorm : 0.0;
+    li.max_res = L.o->stop_rule == PF_STOP_ABS_INF ? L.rinf : -1.0;
     li.status = L.result;
     if (info) *info = li;
+    if (L.result == PF_ERR_NOCONV && L.o->stop_rule == PF_STOP_ABS_INF)
+        return fail(L.result, "no convergence: max residual %.3e after %d iterations", L.rinf, L.iter);
     if (L.result == PF_ERR_NOCONV)
         return fail(L.result, "no convergence: rel_res %.3e after %d iterations", li.rel_res, L.iter);
     if (L.result == PF_ERR_NONFINITE) return fail(L.result, "non-finite value in the iteration");
@@ -1321,6 +1347,7 @@ void pf_lin_opts_default(pf_lin_opts *o)
     o->inner_tol = 1e-5;
     o->max_refine = 30;
     o->check_every = 0;
+    o->stop_rule = PF_STOP_REL2;
 }
 
 pf_status pf_timing_enable(int32_t enable, int32_t sample)

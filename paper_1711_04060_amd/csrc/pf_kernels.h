@@ -1201,6 +1201,23 @@ __global__ void k_rhs_pf2(size_t N, const double *psi, const double *sigma, cons
 
 // Relaxation (Table 2 step 5): Phi := omega Phi_0 + (1 - omega) Phi; the max
 // norm of the change; Phi_0 := Phi.  Result in sc->red[0].
+// Max norm of r over the free rows (flags without dirbit); NaN shows as +inf.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_maxabs_free(size_t N, const double *r, const uint8_t *flags, uint8_t dirbit,
+                                                    double *partials)
+{
+    double acc[1] = {0.0};
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t n = (size_t)blockIdx.x * NT + threadIdx.x; n < N; n += stride) {
+        if (flags[n] & dirbit) continue;
+        double d = fabs(r[n]);
+        if (d != d) d = __builtin_inf();
+        acc[0] = fmax(acc[0], d);
+    }
+    block_reduce<1, NT, true>(acc);
+    store_partials<1>(acc, partials, blockIdx.x);
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_relax(size_t N, double *phi0, double *phi, double omega, double *partials)
 {

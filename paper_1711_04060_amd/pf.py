@@ -20,6 +20,7 @@ PF_ERR_NOCONV, PF_ERR_BREAKDOWN, PF_ERR_NONFINITE = -4, -5, -6
 PF_BC_DIRICHLET, PF_BC_NEUMANN = 0, 1
 PF_NODE_SOLVENT, PF_NODE_SOLUTE, PF_NODE_FIXED = 0, 1, 2
 PF_FP64, PF_MIXED = 0, 1
+PF_STOP_REL2, PF_STOP_ABS_INF = 0, 1
 
 EXPORTS = ("pf_grid_create", "pf_grid_destroy", "pf_lin_opts_default", "pf_linear_solve",
            "pf_residual", "pf_spmv", "pf_spmv_f32", "pf_pf_params_default", "pf_nonlinear_solve",
@@ -37,12 +38,14 @@ class pf_grid_desc(C.Structure):
 
 class pf_lin_opts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
-                ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("check_every", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_refine", C.c_int32), ("check_every", C.c_int32),
+                ("stop_rule", C.c_int32)]
 
 
 class pf_lin_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("restarts", C.c_int32),
-                ("rel_res", C.c_double), ("seconds", C.c_double), ("status", C.c_int32)]
+                ("rel_res", C.c_double), ("seconds", C.c_double), ("status", C.c_int32),
+                ("max_res", C.c_double)]
 
 
 class pf_pf_params(C.Structure):

@@ -425,3 +425,42 @@ def test_timing_of_products_and_bad_kind():
             pf.pf_timing_read(4)
     finally:
         pf.pf_timing_enable(0, 1)
+
+
+# ------------------------------------------------------------- stop rules
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_max_norm_stop_rule(prec):
+    """Table 3's absolute max-norm stop test: the GPU result meets
+    ||b - A x||_inf <= tol with the residual recomputed by the oracle's
+    diagonals, reports that max norm, and the oracle under the same rule
+    agrees on the solution to the accuracy the rule allows."""
+    pf = _pf()
+    rng = np.random.default_rng(12)
+    nx, ny, nz = 41, 37, 29
+    N = nx * ny * nz
+    eps = rng.uniform(1.0, 40.0, N)
+    g = oracle.Grid(nx, ny, nz, 0.3, eps, bc_phi=(D, NM, D, D, NM, D), bc_value=(0.5, 0, -0.25, 0.0, 0, 1.0))
+    sigma = rng.uniform(0.0, 2.0, N)
+    b = rng.normal(size=N)
+    isd, val = oracle.dirichlet(g)
+    A = oracle.assemble(nx, ny, nz, g.h, eps, sigma, isd, g.bc_phi)
+    G = pf.pf_grid_create(nx, ny, nz, g.h, dev(eps), None, None, None, g.bc_phi, g.bc_value)
+    for tol in (1e-4, 1e-8):
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        info = pf.pf_linear_solve(G, dev(sigma), dev(b), x, pf.pf_lin_opts_default(rel_tol=tol, precision=prec,
+                                                                               stop_rule=pf.PF_STOP_ABS_INF))
+        xg = host(x)
+        r = np.where(isd.astype(bool), 0.0, b - oracle.dia_matvec(nx, ny, nz, A, xg))
+        rmax = np.abs(r).max()
+        assert rmax <= tol
+        # the residual itself is only defined to the rounding of its terms
+        terms = (np.abs(b) + oracle.dia_matvec(nx, ny, nz, np.abs(A), np.abs(xg))).max()
+        assert abs(info["max_res"] - rmax) <= 1e-6 * rmax + 64 * EPS64 * terms
+        ref, rinfo = oracle.linear_solve(g, sigma, b, tol=tol, rule=1)
+        # both residuals are within tol; the solutions differ by at most about kappa tol
+        assert np.abs(xg - ref).max() <= 1e3 * tol
+    # the default rule reports no max norm
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    info = pf.pf_linear_solve(G, dev(sigma), dev(b), x, pf.pf_lin_opts_default())
+    assert info["max_res"] == -1.0
