@@ -1120,21 +1120,29 @@ struct BatchBuf {
 } g_batch;
 
 // Launch of one batched BiCGSTAB step: every member shares the kernel
-// instance (threads, nodes per thread, pipeline depth).  Each member grid has
-// been autotuned on its own (first use of its shape); the batch takes the
-// instance most of the work was tuned to (weighted by N) and gives every
-// member the z-chunk length of its own tuned shape.  step: 0 = A, 1 = B.
+// instance (threads, nodes per thread, pipeline depth).  Two policies:
+//   0: the instance most of the work was tuned to on its own (weighted by N),
+//      each member with the z-chunk length of its own tuned shape;
+//   1: 512 threads, one node per thread, z-chunks of clamp(strips nz / 256,
+//      2, 16) planes (a batch has more tiles than one system, so longer
+//      chunks lose less to the planes above and below each chunk).
+// step: 0 = A, 1 = B.
 template <typename T>
-std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, ZCfg &combined)
+std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int policy, ZCfg &combined)
 {
-    std::map<std::tuple<int, int, int>, double> weight;
-    for (const LinSolve *L : act) {
-        const ZCfg &t = step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g);
-        weight[std::make_tuple(t.NTZ, t.PPT, t.depth)] += (double)L->g->N;
+    int ntz = 512, ppt = 1, depth = default_depth(sizeof(T), 1);
+    if (policy == 0) {
+        std::map<std::tuple<int, int, int>, double> weight;
+        for (const LinSolve *L : act) {
+            const ZCfg &t = step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g);
+            weight[std::make_tuple(t.NTZ, t.PPT, t.depth)] += (double)L->g->N;
+        }
+        auto best = std::max_element(weight.begin(), weight.end(),
+                                     [](const auto &x, const auto &y) { return x.second < y.second; });
+        ntz = std::get<0>(best->first);
+        ppt = std::get<1>(best->first);
+        depth = std::get<2>(best->first);
     }
-    auto best = std::max_element(weight.begin(), weight.end(),
-                                 [](const auto &x, const auto &y) { return x.second < y.second; });
-    const int ntz = std::get<0>(best->first), ppt = std::get<1>(best->first), depth = std::get<2>(best->first);
     std::vector<ZCfg> cs;
     combined = ZCfg{};
     combined.NTZ = ntz;
@@ -1143,8 +1151,14 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, ZCf
     combined.G = 0;
     for (const LinSolve *L : act) {
         const pf_grid *g = L->g;
-        const ZCfg &t = step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g);
-        ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), ntz, ppt, t.KZ, depth);
+        int kz;
+        if (policy == 0) {
+            kz = (step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g)).KZ;
+        } else {
+            const long strips = ((long)g->nx * g->ny + 511) / 512;
+            kz = (int)std::max<long>(2, std::min<long>(16, strips * g->nz / 256));
+        }
+        ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), ntz, ppt, kz, depth);
         cs.push_back(c);
         combined.G += c.G;
         combined.lds = std::max(combined.lds, c.lds);
@@ -1162,6 +1176,19 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, ZCf
     return cs;
 }
 
+// Policy chosen per batch composition (precision, operator kind, member
+// shapes) by timing the first two chunks of its first run, one per policy.
+std::map<std::vector<long>, int> g_batch_policy;
+
+// One instantiated graph chunk of a batched Krylov run under one policy.
+struct BatchPlan {
+    hipGraphExec_t exec = nullptr;
+    ~BatchPlan()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
 // Run the Krylov iterations of all listed systems (same precision, same
 // operator kind) together: one launch per kernel per iteration covers every
 // system, captured as a graph chunk and replayed until no system is RUN.
@@ -1170,33 +1197,25 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
 {
     const int n = (int)act.size();
     const bool psi = act[0]->op.psi;
-    std::vector<pfk::ZArgs<T>> za[2], zb[2];
-    std::vector<int> astart(n + 1, 0), bstart(n + 1, 0);
-    std::vector<const Scalars *> scp(n);
-    ZCfg ca, cb;   // combined launches of steps A and B
-    const std::vector<ZCfg> csa = batch_shapes<T>(act, 0, ca), csb = batch_shapes<T>(act, 1, cb);
-    for (int par = 0; par < 2; ++par) { za[par].resize(n); zb[par].resize(n); }
-    for (int i = 0; i < n; ++i) {
-        LinSolve &L = *act[i];
-        pf_grid *g = L.g;
-        Work<T> *w;
-        const T *dinv;
-        if constexpr (sizeof(T) == 8) { w = &g->w64; dinv = L.dinv64; }
-        else { w = &g->w32; dinv = L.dinv32; }
-        for (int par = 0; par < 2; ++par) {
-            za[par][i] = args_a<T>(g, L.op, dinv, *w, par, csa[i], csb[i].G);
-            zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, csb[i], csa[i].G);
-        }
-        astart[i + 1] = astart[i] + csa[i].G;
-        bstart[i + 1] = bstart[i] + csb[i].G;
-        scp[i] = g->sc;
+    std::vector<long> key = {(long)sizeof(T), psi ? 1L : 0L};
+    {
+        std::vector<long> shapes;
+        for (const LinSolve *L : act) shapes.push_back(((long)L->g->nx * 4096 + L->g->ny) * 4096 + L->g->nz);
+        std::sort(shapes.begin(), shapes.end());
+        key.insert(key.end(), shapes.begin(), shapes.end());
     }
-    if (ca.lds > LDS_MAX || cb.lds > LDS_MAX) return fail(PF_ERR_ARG, "batch member too wide for the LDS strip");
-    // device tables
+    const auto known = g_batch_policy.find(key);
+    // only batches of several members are compared (small ones keep policy 0)
+    const int npol = (known != g_batch_policy.end() || !tuning_enabled() || n < 4) ? 1 : 2;
+    const int pol0 = known != g_batch_policy.end() ? known->second : 0;
+
+    // device tables: per policy the step A / B arguments (two parities) and
+    // tile start tables; shared scalar pointers and gather buffer
     const size_t szZ = sizeof(pfk::ZArgs<T>) * n;
     const size_t szI = sizeof(int) * (n + 1), szP = sizeof(void *) * n, szS = sizeof(Scalars) * n;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t need = 4 * al(szZ) + 2 * al(szI) + al(szP) + al(szS);
+    const size_t per_pol = 4 * al(szZ) + 2 * al(szI);
+    const size_t need = npol * per_pol + al(szP) + al(szS);
     if (need > g_batch.bytes) {
         if (g_batch.dev) (void)hipFree(g_batch.dev);
         g_batch.dev = nullptr;
@@ -1215,59 +1234,105 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     char *base = (char *)g_batch.dev;
     size_t off = 0;
     auto take = [&](size_t sz) { char *p = base + off; off += al(sz); return p; };
-    pfk::ZArgs<T> *dA[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
-    pfk::ZArgs<T> *dB[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
-    int *das = (int *)take(szI), *dbs = (int *)take(szI);
+    std::vector<const Scalars *> scp(n);
+    for (int i = 0; i < n; ++i) scp[i] = act[i]->g->sc;
     const Scalars **dscp = (const Scalars **)take(szP);
     Scalars *dgather = (Scalars *)take(szS);
-    for (int par = 0; par < 2; ++par) {
-        HIPCHK(hipMemcpyAsync(dA[par], za[par].data(), szZ, hipMemcpyHostToDevice, stream));
-        HIPCHK(hipMemcpyAsync(dB[par], zb[par].data(), szZ, hipMemcpyHostToDevice, stream));
-    }
-    HIPCHK(hipMemcpyAsync(das, astart.data(), szI, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(dbs, bstart.data(), szI, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dscp, scp.data(), szP, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipStreamSynchronize(stream));
 
-    auto launch_iter = [&](int par) -> pf_status {
-        hipError_t e;
-        if (psi) e = launch_batch<pfk::OP_BA, T, true>(ca, dA[par], das, n, stream);
-        else e = launch_batch<pfk::OP_BA, T, false>(ca, dA[par], das, n, stream);
-        if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
-        if (psi) e = launch_batch<pfk::OP_BB, T, true>(cb, dB[par], dbs, n, stream);
-        else e = launch_batch<pfk::OP_BB, T, false>(cb, dB[par], dbs, n, stream);
-        if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
-        return PF_OK;
-    };
-    hipGraph_t graph;
-    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
-    pf_status st = PF_OK;
-    for (int i = 0; i < m && st == PF_OK; ++i) st = launch_iter(i & 1);
-    hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
-    hipError_t e = hipStreamEndCapture(stream, &graph);
-    if (st != PF_OK) return st;
-    if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
-    hipGraphExec_t exec;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
+    BatchPlan plans[2];
+    for (int k = 0; k < npol; ++k) {
+        const int pol = npol == 1 ? pol0 : k;
+        std::vector<pfk::ZArgs<T>> za[2], zb[2];
+        std::vector<int> astart(n + 1, 0), bstart(n + 1, 0);
+        ZCfg ca, cb;   // combined launches of steps A and B
+        const std::vector<ZCfg> csa = batch_shapes<T>(act, 0, pol, ca), csb = batch_shapes<T>(act, 1, pol, cb);
+        for (int par = 0; par < 2; ++par) { za[par].resize(n); zb[par].resize(n); }
+        for (int i = 0; i < n; ++i) {
+            LinSolve &L = *act[i];
+            pf_grid *g = L.g;
+            Work<T> *w;
+            const T *dinv;
+            if constexpr (sizeof(T) == 8) { w = &g->w64; dinv = L.dinv64; }
+            else { w = &g->w32; dinv = L.dinv32; }
+            for (int par = 0; par < 2; ++par) {
+                za[par][i] = args_a<T>(g, L.op, dinv, *w, par, csa[i], csb[i].G);
+                zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, csb[i], csa[i].G);
+            }
+            astart[i + 1] = astart[i] + csa[i].G;
+            bstart[i + 1] = bstart[i] + csb[i].G;
+        }
+        if (ca.lds > LDS_MAX || cb.lds > LDS_MAX) return fail(PF_ERR_ARG, "batch member too wide for the LDS strip");
+        pfk::ZArgs<T> *dA[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
+        pfk::ZArgs<T> *dB[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
+        int *das = (int *)take(szI), *dbs = (int *)take(szI);
+        for (int par = 0; par < 2; ++par) {
+            HIPCHK(hipMemcpyAsync(dA[par], za[par].data(), szZ, hipMemcpyHostToDevice, stream));
+            HIPCHK(hipMemcpyAsync(dB[par], zb[par].data(), szZ, hipMemcpyHostToDevice, stream));
+        }
+        HIPCHK(hipMemcpyAsync(das, astart.data(), szI, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(dbs, bstart.data(), szI, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));   // the host vectors above go out of scope
+
+        auto launch_iter = [&](int par) -> pf_status {
+            hipError_t e;
+            if (psi) e = launch_batch<pfk::OP_BA, T, true>(ca, dA[par], das, n, stream);
+            else e = launch_batch<pfk::OP_BA, T, false>(ca, dA[par], das, n, stream);
+            if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
+            if (psi) e = launch_batch<pfk::OP_BB, T, true>(cb, dB[par], dbs, n, stream);
+            else e = launch_batch<pfk::OP_BB, T, false>(cb, dB[par], dbs, n, stream);
+            if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
+            return PF_OK;
+        };
+        hipGraph_t graph;
+        HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+        pf_status st = PF_OK;
+        for (int i = 0; i < m && st == PF_OK; ++i) st = launch_iter(i & 1);
+        hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
+        hipError_t e = hipStreamEndCapture(stream, &graph);
+        if (st != PF_OK) return st;
+        if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&plans[k].exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            plans[k].exec = nullptr;
+            return fail(PF_ERR_DEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
+        }
+    }
+
     status.assign(n, pfk::ST_RUN);
-    for (;;) {
-        e = hipGraphLaunch(exec, stream);
+    double secs[2] = {0, 0};
+    int use = 0;   // plan index of the next chunk
+    for (int chunk = 0;; ++chunk) {
+        const auto t0 = std::chrono::steady_clock::now();
+        hipError_t e = hipGraphLaunch(plans[use].exec, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(g_batch.hsc, dgather, szS, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) {
-            (void)hipGraphExecDestroy(exec);
-            return fail(PF_ERR_DEVICE, "batched chunk failed: %s", hipGetErrorString(e));
-        }
-        bool any = false;
+        if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched chunk failed: %s", hipGetErrorString(e));
+        bool any = false, all = true;
         for (int i = 0; i < n; ++i) {
             status[i] = g_batch.hsc[i].stop;
             any |= status[i] == pfk::ST_RUN;
+            all &= status[i] == pfk::ST_RUN;
+        }
+        if (npol == 2 && chunk < 2) {
+            secs[use] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (!all) {   // a member stopped: the two chunks are no longer alike; keep policy 0
+                use = 0;
+                g_batch_policy[key] = 0;
+                chunk = 2;
+            } else if (chunk == 0) {
+                use = 1;
+            } else {
+                use = secs[1] < secs[0] ? 1 : 0;
+                g_batch_policy[key] = use;
+                if (getenv("PF_LOG"))
+                    fprintf(stderr, "[pf] batch of %d: chunk of %d iterations %.2f ms (members' shapes), %.2f ms "
+                                    "(512-thread strips); keeping policy %d\n", n, m, secs[0] * 1e3, secs[1] * 1e3, use);
+            }
         }
         if (!any) break;
     }
-    (void)hipGraphExecDestroy(exec);
     for (int i = 0; i < n; ++i) *act[i]->g->hsc = g_batch.hsc[i];
     return PF_OK;
 }
