@@ -134,29 +134,48 @@ __global__ __launch_bounds__(IF_NT) void k_if_list(size_t N, const uint16_t *mas
         if (m & (1u << kind)) code[e++] = ((unsigned long long)n << 4) | (unsigned)kind;
 }
 
-// Accumulate sum_j z_j / |r - r_j| and sum_j z_j d/du (1 / |r - r_j|) over
-// one LDS tile of charges (x, y, z, z_j), in charge order.
-__device__ __forceinline__ void coulomb_tile(const double4 *ch, int cnt, double px, double py, double pz,
-                                             double ux, double uy, double uz, double &phi, double &der)
+// 1/sqrt(x) for x > 0: the hardware estimate refined by one third-order
+// step of the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2
+// (Householder's method of order 3 for y^-2 = x), which takes the estimate's
+// relative error e to about e^3.  x = 0 gives a non-finite value.
+__device__ __forceinline__ double rsqrt_refined(double x)
 {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// Accumulate sum_j z_j / |r - r_j| and sum_j z_j d/da (1 / |r - r_j|) along
+// the thread's axis a over one LDS tile of charges (x, y, z, z_j), in charge
+// order.  The point's coordinates come in rotated so that the axis is the
+// first one (pa), and each charge's coordinates are read in the same
+// rotation (per-lane LDS offsets: lanes of one wave read words of the same
+// record, so the reads broadcast without bank conflicts).
+__device__ __forceinline__ void coulomb_tile(const double4 *ch, int cnt, double pa, double pb, double pc, int oa,
+                                             int ob, int oc, double &phi, double &der)
+{
+    const char *base = reinterpret_cast<const char *>(ch);
     for (int j = 0; j < cnt; ++j) {
-        const double4 c = ch[j];
-        const double dx = px - c.x, dy = py - c.y, dz = pz - c.z;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const double inv = rsqrt(r2);
-        const double qi = c.w * inv;
+        const char *rec = base + 32 * j;
+        const double ca = *reinterpret_cast<const double *>(rec + oa);
+        const double cb = *reinterpret_cast<const double *>(rec + ob);
+        const double cc = *reinterpret_cast<const double *>(rec + oc);
+        const double q = *reinterpret_cast<const double *>(rec + 24);
+        const double da = pa - ca, db = pb - cb, dc = pc - cc;
+        const double r2 = da * da + db * db + dc * dc;
+        const double inv = rsqrt_refined(r2);
+        const double qi = q * inv;
         phi += qi;
-        const double comp = dx * ux + dy * uy + dz * uz;
-        der -= qi * inv * inv * comp;
+        der -= qi * (inv * inv) * da;
     }
 }
 
-// Unit vector of face direction d (0..5); d outside 0..5 gives +x (unused).
-__device__ __forceinline__ void face_unit(int d, double &ux, double &uy, double &uz)
+// Byte offsets of the rotated coordinates for axis a (x, y, z = 0, 1, 2).
+__device__ __forceinline__ void axis_offsets(int a, int &oa, int &ob, int &oc)
 {
-    ux = d == 0 ? -1.0 : (d == 1 || d > 5 || d < 0) ? 1.0 : 0.0;
-    uy = d == 2 ? -1.0 : d == 3 ? 1.0 : 0.0;
-    uz = d == 4 ? -1.0 : d == 5 ? 1.0 : 0.0;
+    oa = 8 * a;
+    ob = 8 * (a == 0 ? 1 : a == 1 ? 2 : 0);
+    oc = 8 * (a == 0 ? 2 : a == 1 ? 0 : 1);
 }
 
 // Stage charges [t0, t0 + IF_CT) into LDS (every thread of the workgroup takes part).
@@ -180,7 +199,8 @@ __global__ __launch_bounds__(IF_NT) void k_coulomb_entries(size_t E, const unsig
 {
     __shared__ double4 tile[IF_CT];
     const size_t e = (size_t)blockIdx.x * IF_NT + threadIdx.x;
-    double px = 0, py = 0, pz = 0, ux = 1, uy = 0, uz = 0;
+    double p[3] = {0, 0, 0}, sgn = 1.0;
+    int axis = 0;
     if (e < E) {
         const unsigned long long cd = code[e];
         const size_t n = (size_t)(cd >> 4);
@@ -196,19 +216,25 @@ __global__ __launch_bounds__(IF_NT) void k_coulomb_entries(size_t E, const unsig
         } else if (kind >= IF_FACE0) {
             d = kind - IF_FACE0;
         }
-        px = fi * h;
-        py = fj * h;
-        pz = fk * h;
-        face_unit(d, ux, uy, uz);
+        p[0] = fi * h;
+        p[1] = fj * h;
+        p[2] = fk * h;
+        if (d >= 0) {
+            axis = d >> 1;
+            sgn = (d & 1) ? 1.0 : -1.0;
+        }
     }
+    int oa, ob, oc;
+    axis_offsets(axis, oa, ob, oc);
+    const double pa = p[axis], pb = p[(axis + 1) % 3], pc = p[(axis + 2) % 3];
     double phi = 0.0, der = 0.0;
     for (int t0 = 0; t0 < M; t0 += IF_CT) {
         const int cnt = stage_charges(tile, charges, M, t0);
-        coulomb_tile(tile, cnt, px, py, pz, ux, uy, uz, phi, der);
+        coulomb_tile(tile, cnt, pa, pb, pc, oa, ob, oc, phi, der);
     }
     if (e < E) {
         V[e] = scale * phi;
-        D[e] = scale * der;
+        D[e] = scale * sgn * der;
     }
 }
 
@@ -219,21 +245,25 @@ __global__ __launch_bounds__(IF_NT) void k_coulomb_points(size_t n, const double
 {
     __shared__ double4 tile[IF_CT];
     const size_t p = (size_t)blockIdx.x * IF_NT + threadIdx.x;
-    double px = 0, py = 0, pz = 0, ux = 1, uy = 0, uz = 0;
+    double c[3] = {0, 0, 0};
     int d = 6;
     if (p < n) {
-        px = pts[3 * p];
-        py = pts[3 * p + 1];
-        pz = pts[3 * p + 2];
+        c[0] = pts[3 * p];
+        c[1] = pts[3 * p + 1];
+        c[2] = pts[3 * p + 2];
         d = dir ? (int)dir[p] : 6;
-        face_unit(d, ux, uy, uz);
     }
+    const bool deriv = d >= 0 && d < 6;
+    const int axis = deriv ? d >> 1 : 0;
+    int oa, ob, oc;
+    axis_offsets(axis, oa, ob, oc);
+    const double pa = c[axis], pb = c[(axis + 1) % 3], pc = c[(axis + 2) % 3];
     double phi = 0.0, der = 0.0;
     for (int t0 = 0; t0 < M; t0 += IF_CT) {
         const int cnt = stage_charges(tile, charges, M, t0);
-        coulomb_tile(tile, cnt, px, py, pz, ux, uy, uz, phi, der);
+        coulomb_tile(tile, cnt, pa, pb, pc, oa, ob, oc, phi, der);
     }
-    if (p < n) out[p] = scale * (d >= 0 && d < 6 ? der : phi);
+    if (p < n) out[p] = scale * (deriv ? ((d & 1) ? der : -der) : phi);
 }
 
 // Laplace problem of Eqs. (9)-(10), unit coefficient, unknowns on the

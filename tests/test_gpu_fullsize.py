@@ -9,8 +9,14 @@ benchmark uses (autotuned), where the oracle cannot afford a whole solve:
     bisection (same bar as the small-grid test);
   * 97^3 membrane PF solve: the returned potential satisfies the discrete PF
     system (PF2 with the rho' terms cancelled, Psi from PF1) evaluated by the
-    oracle's assembly, Fermi and BiCGSTAB.
+    oracle's assembly, Fermi and BiCGSTAB;
+  * 97^3 membrane through the singular-charge decomposition with its 2000
+    charges: the interface terms and phi* + phi^L against the whole oracle
+    computation, and the Coulomb kernel over every Omega_m node (the launch
+    the benchmark times) at 512 sampled nodes against the oracle's sums.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -120,3 +126,32 @@ def test_pf_solve_97_satisfies_discrete_system(membrane97):
     # residual; its contraction near the fixed point is slow (~0.996 per outer
     # iteration), so the potential can still be ~2.5e-6 from the fixed point
     assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(rhs[isd == 0])
+
+
+def test_decomposition_97_against_oracle():
+    pf = _pf()
+    prob = dataclasses.replace(inputs.membrane_pore(97), fixed_charge=None)
+    ch = inputs.point_charges(prob)
+    lam, em, es = inputs.lambda_length_A(), inputs.TABLE1["eps_m"], inputs.TABLE1["eps_s"]
+    oprob = dataclasses.replace(prob, fixed_charge=np.zeros(prob.N))
+    rb, rreg, rlap, _ = oracle.interface(oprob, ch, lam, em, es, tol=1e-13)
+    g = pf.grid_from_problem(prob)
+    b = torch.empty(prob.N, dtype=torch.float64, device="cuda")
+    reg = torch.empty_like(b)
+    lap = torch.empty_like(b)
+    info = pf.pf_interface_setup(g, dev(ch), lam, em, es, b, reg, lap, lin={"rel_tol": 1e-13})
+    assert info["status"] == 0
+    for got, want in ((lap, rlap), (reg, rreg), (b, rb)):
+        got = got.cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
+    # the Coulomb kernel as the benchmark launches it: every Omega_m node, one derivative each
+    solute = np.flatnonzero(prob.node_type == inputs.SOLUTE)
+    k, j, i = np.unravel_index(solute, prob.shape)
+    pts = np.column_stack([i, j, k]) * prob.h
+    out = torch.empty(len(solute), dtype=torch.float64, device="cuda")
+    pf.pf_coulomb(dev(pts), dev(ch), 1.0, out, dirs=torch.ones(len(solute), dtype=torch.int8, device="cuda"))
+    pick = np.random.default_rng(3).choice(len(solute), 512, replace=False)
+    ref = oracle.coulomb(pts[pick], ch, 1.0, dirs=np.ones(512, np.int32))
+    r = np.linalg.norm(pts[pick][:, None, :] - ch[None, :, :3], axis=2)
+    mag = (np.abs(ch[:, 3])[None, :] / r ** 2).sum(axis=1)
+    assert np.all(np.abs(out.cpu().numpy()[pick] - ref) <= 1e-13 * mag)
