@@ -272,6 +272,32 @@ def test_zero_rhs_and_noconv_and_bad_args():
     assert e.value.code == pf.PF_ERR_ARG
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_nan_in_sigma_or_b_is_reported(prec):
+    """A NaN injected into sigma (on a free row) or into b ends the solve
+    with PF_ERR_NONFINITE, in both precisions, instead of iterating."""
+    pf = _pf()
+    p = inputs.sphere_poisson(17)
+    g = pf.grid_from_problem(p)
+    x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    free = 3 + 17 * (4 + 17 * 5)           # interior solvent node (a free row)
+    assert p.node_type[free] == inputs.SOLVENT
+    sigma = np.zeros(p.N)
+    sigma[free] = np.nan
+    opts = pf.pf_lin_opts_default(precision=prec)
+    info = pf.pf_linear_solve(g, dev(sigma), dev(p.b), x, opts, check=False)
+    assert info["status"] == pf.PF_ERR_NONFINITE
+    b = p.b.copy()
+    b[free] = np.nan
+    x.zero_()
+    info = pf.pf_linear_solve(g, None, dev(b), x, opts, check=False)
+    assert info["status"] == pf.PF_ERR_NONFINITE
+    # the grid still solves a good system afterwards
+    x.zero_()
+    info = pf.pf_linear_solve(g, None, dev(p.b), x, opts)
+    assert info["status"] == 0
+
+
 def test_singular_neumann_terminates():
     pf = _pf()
     n = 9
