@@ -248,9 +248,10 @@ pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, doubl
 /* ---------------- singular-charge decomposition (Sec. 3, Eqs. (5)-(10), (17)-(18)) */
 
 /* phi* of Eq. (5) in phi-hat units, or one of its directional derivatives, at
- * n points:  out[p] = scale * sum_j z_j / |r_p - r_j|  when dir is NULL or
- * dir[p] == 6, and  out[p] = scale * d/du sum_j z_j / |r_p - r_j|  along the
- * unit vector u of face direction dir[p] in 0..5 (-x,+x,-y,+y,-z,+z).
+ * n points:  out[p] = scale * d/du sum_j z_j / |r_p - r_j|  along the unit
+ * vector u of face direction dir[p] in 0..5 (-x,+x,-y,+y,-z,+z), and
+ * out[p] = scale * sum_j z_j / |r_p - r_j|  when dir is NULL or dir[p] holds
+ * any other value (6 by convention).
  * With scale = lambda / (4 pi eps_m) this is the Coulomb potential of the
  * point charges in a uniform dielectric eps_m.  pts: device [n][3];
  * dir: device int8 [n] or NULL; charges: device [M][4] = x, y, z, valence
