@@ -78,6 +78,25 @@ def run_nonlinear(pf, torch, prob, prm):
 g_cache = {}
 
 
+def forms_pf_mixed(pf, torch, prob, phi64):
+    """The benchmark's own 97^3 PF solve with every linear solve in mixed
+    precision (FP32 BiCGSTAB inside FP64 refinement to the same 1e-10 true
+    relative residual), against the FP64 solve's potential phi64."""
+    prm = pf.params_for(prob, outer_tol=1e-8, lin={"rel_tol": 1e-10, "precision": pf.PF_MIXED})
+    phi = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
+    g = g_cache[prob.name]
+    pf.pf_nonlinear_solve(g, prm, phi)             # first use of the FP32 workspace: tuning
+    phi.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = pf.pf_nonlinear_solve(g, prm, phi)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    rel = float(torch.linalg.vector_norm(phi - phi64) / torch.linalg.vector_norm(phi64))
+    return dict(seconds=sec, outer_iters=info["outer_iters"], lin_iters=info["total_lin_iters"],
+                rel_l2_vs_fp64=rel)
+
+
 def forms_linear(pf, torch, inputs, timing_sample):
     """FP64 vs mixed precision on the 193^3 sphere Poisson problem."""
     import numpy as np
@@ -260,18 +279,24 @@ def forms_tps(pf, torch, inputs, n=97, outer_tol=1e-3):
     setup_s = time.perf_counter() - t0
     res = dict(workload=f"membrane_pore {n}^3, 5 states x 8 sites", outer_tol=outer_tol, setup_seconds=setup_s,
                sites=site_rows)
-    for name, batched in (("sequential", False), ("batched", True)):
+    prm_mixed = pf.params_for(states[0]["problem"], outer_tol=outer_tol,
+                              lin={"rel_tol": 1e-10, "precision": pf.PF_MIXED})
+    for name, batched, p in (("sequential", False, prm), ("batched", True, prm), ("batched_mixed", True, prm_mixed)):
         phis = [torch.zeros(n ** 3, dtype=torch.float64, device="cuda") for _ in states]
+        if name == "batched_mixed":   # first use of the FP32 workspaces (tuning) outside the timing
+            pf.pf_nonlinear_solve(grids[0], p, phis[0])
+            phis[0].zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if batched:
-            infos = pf.pf_nonlinear_solve_batch(grids, [prm] * len(grids), phis)
+            infos = pf.pf_nonlinear_solve_batch(grids, [p] * len(grids), phis)
         else:
-            infos = [pf.pf_nonlinear_solve(g, prm, x) for g, x in zip(grids, phis)]
+            infos = [pf.pf_nonlinear_solve(g, p, x) for g, x in zip(grids, phis)]
         torch.cuda.synchronize()
         res[name] = dict(seconds=time.perf_counter() - t0, outer_iters=[i["outer_iters"] for i in infos],
                          status=[i["status"] for i in infos])
     res["batched_speedup"] = res["sequential"]["seconds"] / res["batched"]["seconds"]
+    res["batched_mixed_speedup"] = res["sequential"]["seconds"] / res["batched_mixed"]["seconds"]
     return res
 
 
@@ -510,8 +535,10 @@ def main():
         },
     }
     if args.forms:
+        log("[bench] forms: 97^3 PF solve with mixed-precision linear solves")
+        result["forms"] = {"pf_solve_97_mixed": forms_pf_mixed(pf, torch, prob, phi)}
         log("[bench] forms: 193^3 FP64 vs mixed")
-        result["forms"] = {"linear_193": forms_linear(pf, torch, inputs, args.sample)}
+        result["forms"]["linear_193"] = forms_linear(pf, torch, inputs, args.sample)
         log("[bench] forms: 64-system batch")
         result["forms"]["batch_64"] = forms_batch(pf, torch, inputs)
         log("[bench] forms: isolated cold stencil product at 193^3")
