@@ -188,3 +188,31 @@ def test_nonlinear_with_interface_matches_oracle():
     assert _rel(host(phi), ref) <= 1e-9
     assert abs(info["outer_iters"] - oinfo["outer_iters"]) <= 3
     assert _rel(host(phi) + host(reg), ref + rreg) <= 1e-9
+
+
+def test_interface_setup_non_cubic_grid():
+    """Index arithmetic on a non-cubic grid (21 x 17 x 13, anisotropic box),
+    Omega_m an off-centre block meeting a Neumann and a Dirichlet face."""
+    pf = _pf()
+    nx, ny, nz, h = 21, 17, 13, 0.25
+    k, j, i = [a.ravel() for a in np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")]
+    inside = (i <= 9) & (j >= 3) & (j <= 12) & (k <= 6)
+    typ = np.where(inside, oracle.SOLUTE, oracle.SOLVENT).astype(np.uint8)
+    eps = np.where(inside, 2.0, 78.45)
+    g = oracle.Grid(nx, ny, nz, h, eps, typ, None, bc_phi=(oracle.NEUMANN, oracle.DIRICHLET, oracle.NEUMANN,
+                                                           oracle.NEUMANN, oracle.DIRICHLET, oracle.DIRICHLET),
+                    bc_value=(0.0, 0.3, 0.0, 0.0, -0.2, 0.0))
+    rng = np.random.default_rng(21)
+    m = 40
+    pos = np.column_stack([rng.uniform(0.2, 2.1, m), rng.uniform(0.9, 2.9, m), rng.uniform(0.1, 1.4, m)])
+    ch = np.column_stack([pos, rng.uniform(-1, 1, m)])
+    rb, rreg, rlap, _ = oracle.interface(g, ch, 7.0, 2.0, 78.45, tol=1e-13)
+    G = _grid_of(pf, g)
+    N = nx * ny * nz
+    b = torch.empty(N, dtype=torch.float64, device="cuda")
+    reg = torch.empty_like(b)
+    lap = torch.empty_like(b)
+    pf.pf_interface_setup(G, dev(ch), 7.0, 2.0, 78.45, b, reg, lap, lin={"rel_tol": 1e-13})
+    assert _relmax(host(lap), rlap) <= 1e-8
+    assert _relmax(host(reg), rreg) <= 1e-8
+    assert _relmax(host(b), rb) <= 1e-8

@@ -134,3 +134,21 @@ def test_exchange_cycle_states_batched_match_oracle():
     for phi, ref, info in zip(phis, refs, infos):
         assert info["status"] == 0
         assert np.linalg.norm(host(phi) - ref) / np.linalg.norm(ref) <= 1e-9
+
+
+def test_site_fill_non_cubic_grid():
+    pf = _pf()
+    nx, ny, nz, h = 19, 11, 7, 0.37
+    rng = np.random.default_rng(19)
+    typ = rng.choice([0, 1], size=nx * ny * nz, p=[0.85, 0.15]).astype(np.uint8)
+    s = _random_sites(rng, 5, 0)
+    s["xyz"] = np.column_stack([rng.uniform(0, (nx - 1) * h, 5), rng.uniform(0, (ny - 1) * h, 5),
+                                rng.uniform(0, (nz - 1) * h, 5)])
+    phi = rng.normal(size=5)
+    rt, rfv, rmarked = oracle.site_fill(nx, ny, nz, h, s, phi, typ)
+    t = dev(typ, torch.uint8)
+    f = torch.zeros(nx * ny * nz, dtype=torch.float64, device="cuda")
+    marked = pf.pf_site_fill(nx, ny, nz, h, _pf_sites(pf, s), phi, t, f)
+    np.testing.assert_array_equal(host(t), rt)
+    np.testing.assert_array_equal(host(f), rfv)
+    assert marked == rmarked
