@@ -419,7 +419,7 @@ def pmc_summary(fetch_csv, write_csv, workload, copy_bytes):
     return out
 
 
-def cpu_baseline(prob, lin_iters_full, budget_outer=2):
+def cpu_baseline(prob, lin_iters_full, budget_outer=2, with_interface=False):
     """Oracle on the first outer iterations of the same solve, scaled by the
     BiCGSTAB iteration count of the whole solve."""
     import oracle
@@ -431,10 +431,21 @@ def cpu_baseline(prob, lin_iters_full, budget_outer=2):
                                             check=False)
     t = time.perf_counter() - t0
     per_iter = t / max(1, info["total_lin_iters"])
-    return dict(value=per_iter * lin_iters_full, unit="s", cores=1, kind="oracle",
-                sample=(f"oracle (serial FP64, 1 thread) on the initial PF2 solve plus {info['outer_iters']} "
-                        f"outer iterations of the same 97^3 solve: {t:.1f} s for {info['total_lin_iters']} "
-                        f"BiCGSTAB iterations, scaled to the {lin_iters_full} iterations of the full solve"))
+    out = dict(value=per_iter * lin_iters_full, unit="s", cores=1, kind="oracle",
+               sample=(f"oracle (serial FP64, 1 thread) on the initial PF2 solve plus {info['outer_iters']} "
+                       f"outer iterations of the same 97^3 solve: {t:.1f} s for {info['total_lin_iters']} "
+                       f"BiCGSTAB iterations, scaled to the {lin_iters_full} iterations of the full solve"))
+    if with_interface:
+        # the decomposition's interface setup on the same membrane (compare forms.interface_97.setup_seconds)
+        import dataclasses
+        import numpy as np
+        from paper_1711_04060_amd import inputs
+        p2 = dataclasses.replace(prob, fixed_charge=np.zeros(prob.N))
+        t0 = time.perf_counter()
+        oracle.interface(p2, inputs.point_charges(prob), inputs.lambda_length_A(), inputs.TABLE1["eps_m"],
+                         inputs.TABLE1["eps_s"], tol=1e-12)
+        out["interface_setup_seconds"] = time.perf_counter() - t0
+    return out
 
 
 def main():
@@ -557,7 +568,7 @@ def main():
                                                                            outer_cap=args.bias_outer)
     if args.cpu:
         log("[bench] cpu baseline (oracle sample)")
-        result["cpu_baseline"] = cpu_baseline(prob, lin_iters)
+        result["cpu_baseline"] = cpu_baseline(prob, lin_iters, with_interface=bool(args.forms))
     print(json.dumps(result), flush=True)
 
 
