@@ -216,3 +216,30 @@ def test_interface_setup_non_cubic_grid():
     assert _relmax(host(lap), rlap) <= 1e-8
     assert _relmax(host(reg), rreg) <= 1e-8
     assert _relmax(host(b), rb) <= 1e-8
+
+
+def test_batched_nonlinear_with_interface_terms():
+    """Two membranes (different charge sets) through the decomposition, solved
+    as one batch: each member's extra right-hand side stays its own."""
+    pf = _pf()
+    sp = oracle.species_from_molar(*(inputs.MEMBRANE_SPECIES[k] for k in ("valence", "radius_A", "bath_M")))
+    grids, phis, prms, refs, keep = [], [], [], [], []
+    for seed in (2, 7):
+        prob = dataclasses.replace(inputs.membrane_pore(17, seed=seed, n_charges=40), fixed_charge=np.zeros(17 ** 3))
+        ch = inputs.point_charges(prob)
+        lam, em, es = oracle.lambda_length(1.0), inputs.TABLE1["eps_m"], inputs.TABLE1["eps_s"]
+        rb, _, _, _ = oracle.interface(prob, ch, lam, em, es, tol=1e-13)
+        ref, _, _, _ = oracle.nonlinear_solve(prob, None, sp, 78.45, 1.9, outer_tol=1e-11, lin_tol=1e-13,
+                                              rhs_extra=rb)
+        G = pf.grid_from_problem(prob)
+        b = torch.empty(prob.N, dtype=torch.float64, device="cuda")
+        pf.pf_interface_setup(G, dev(ch), lam, em, es, b, lin={"rel_tol": 1e-13})
+        prms.append(pf.params_for(prob, outer_tol=1e-11, lin={"rel_tol": 1e-13}, rhs_extra=b))
+        grids.append(G)
+        phis.append(torch.zeros(prob.N, dtype=torch.float64, device="cuda"))
+        refs.append(ref)
+        keep.append(b)
+    infos = pf.pf_nonlinear_solve_batch(grids, prms, phis)
+    for phi, ref, info in zip(phis, refs, infos):
+        assert info["status"] == 0
+        assert _rel(host(phi), ref) <= 1e-9

@@ -490,3 +490,22 @@ def test_max_norm_stop_rule(prec):
     x = torch.zeros(N, dtype=torch.float64, device="cuda")
     info = pf.pf_linear_solve(G, dev(sigma), dev(b), x, pf.pf_lin_opts_default())
     assert info["max_res"] == -1.0
+
+
+def test_batch_with_max_norm_stop_rule():
+    """The absolute max-norm stop rule inside a batched solve: every member
+    meets ||b - A x||_inf <= tol (residual recomputed from the oracle's
+    diagonals)."""
+    pf = _pf()
+    probs = [p for p in inputs.batch_systems(n_sys=16, seed_base=4100) if p.nx <= 57][:4]
+    grids = [pf.grid_from_problem(p) for p in probs]
+    tol = 1e-6
+    xs = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
+    infos = pf.pf_linear_solve_batch(grids, [dev(p.sigma) for p in probs], [dev(p.b) for p in probs], xs,
+                                     pf.pf_lin_opts_default(rel_tol=tol, stop_rule=pf.PF_STOP_ABS_INF))
+    for p, x, info in zip(probs, xs, infos):
+        isd, val = oracle.dirichlet(p)
+        A = oracle.assemble(p.nx, p.ny, p.nz, p.h, p.eps, p.sigma, isd, p.bc_phi)
+        r = np.where(isd.astype(bool), 0.0, p.b - oracle.dia_matvec(p.nx, p.ny, p.nz, A, host(x)))
+        assert info["status"] == 0
+        assert np.abs(r).max() <= tol
