@@ -297,3 +297,26 @@ def _stop_rule_problem():
     eps = rng.uniform(1.0, 40.0, N)
     g = oracle.Grid(nx, ny, nz, 0.3, eps, bc_phi=(D, NM, D, D, NM, D), bc_value=(0.5, 0, -0.25, 0.0, 0, 1.0))
     return g, rng.uniform(0.0, 2.0, N), rng.normal(size=N)
+
+
+def test_pf1_operator_sine_modes():
+    """PF1's operator eps_s (1 - lc^2 Lap_h) (Eq. (12), constant coefficient
+    eps_s lc^2 on every face, eps_s on the diagonal): the Dirichlet sine modes
+    are eigenvectors with eigenvalue eps_s (1 + lc^2 lambda_m)."""
+    nx, ny, nz, h, eps_s, lc = 9, 8, 7, 0.4, 78.45, 1.9
+    N = nx * ny * nz
+    g = _grid(nx, ny, nz, h, eps_s * lc * lc, [D] * 6)
+    isd, _ = oracle.dirichlet(g)
+    A = oracle.assemble(nx, ny, nz, h, np.full(N, eps_s * lc * lc), np.full(N, eps_s), isd)
+    i, j, k = _ijk(nx, ny, nz)
+    for modes in ((1, 1, 1), (2, 3, 4)):
+        u = np.ones(N)
+        lam = 0.0
+        for idx, n, m in zip((i, j, k), (nx, ny, nz), modes):
+            u *= np.sin(m * math.pi * idx / (n - 1))
+            lam += math.sin(m * math.pi / (2 * (n - 1))) ** 2
+        lam *= 4.0 / h ** 2
+        Au = oracle.dia_matvec(nx, ny, nz, A, u)
+        free = isd == 0
+        want = eps_s * (1.0 + lc * lc * lam)
+        np.testing.assert_allclose(Au[free], want * u[free], rtol=0, atol=1e-12 * want)
