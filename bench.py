@@ -390,44 +390,16 @@ def copy_reference(torch, mib=512):
     return n * 8
 
 
-def pmc_summary(fetch_csv, write_csv, workload, copy_bytes):
-    """Per-launch HBM traffic of step A from two rocprofv3 --pmc runs (CSV),
-    each counter scaled by its reading on the copy kernel of known size."""
-    import csv
-
-    def per_kernel(path, counter):
-        vals = {}
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] != counter:
-                continue
-            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
-        return vals
-
-    out = {"workload": workload, "source_hash": kernel_source_hash(), "copy_bytes": copy_bytes}
-    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        v = per_kernel(path, counter)
-        copy = [x for k, xs in v.items() if "copy" in k.lower() for x in xs]
-        copy_read = max(copy) if copy else None
-        step_a = [x for k, xs in v.items() if "k_zmarch<3, double, false" in k for x in xs]
-        big = sorted(step_a)[len(step_a) // 2:] if step_a else []   # launches that ran (not early exits)
-        mean = sum(big) / len(big) if big else None
-        scale = (copy_bytes / copy_read) if copy_read else None
-        out[counter] = dict(step_a_raw_bytes=mean, copy_raw_bytes=copy_read, scale=scale,
-                            step_a_bytes=(mean * scale) if (mean and scale) else None, launches=len(step_a))
-    f, w = out["FETCH_SIZE"]["step_a_bytes"], out["WRITE_SIZE"]["step_a_bytes"]
-    out["hbm_bytes_per_launch"] = (f + w) if (f is not None and w is not None) else None
-    return out
-
-
-PMC_FAMILIES_193 = {"step_a_fp64": "k_zmarch<3, double, false", "step_b_fp64": "k_zmarch<4, double, false",
+PMC_FAMILIES = {"step_a_fp64": "k_zmarch<3, double, false", "step_b_fp64": "k_zmarch<4, double, false",
                     "step_a_fp32": "k_zmarch<3, float, false", "step_b_fp32": "k_zmarch<4, float, false"}
 VECTORS = {"step_a": 12, "step_b": 7}
 
 
 def pmc_summary_families(fetch_csv, write_csv, workload, copy_bytes, n_nodes):
-    """Per-launch counter traffic of the BiCGSTAB step kernels of the 193^3
-    linear solves: for each family the most frequent instance (the tuned
-    shape; the autotuner's candidates run a few launches each), averaged over
+    """Per-launch counter traffic of the BiCGSTAB step kernels (variable-
+    coefficient form; FP64, and FP32 where the run has it) from two
+    rocprofv3 --pmc runs (CSV): for each family the most frequent instance
+    (the pinned shape), averaged over
     its dispatches that read at least half the algorithmic bytes (launches
     queued after convergence exit early and are left out), each counter
     scaled by its reading on the copy kernel of known size."""
@@ -442,7 +414,7 @@ def pmc_summary_families(fetch_csv, write_csv, workload, copy_bytes, n_nodes):
             if r["Counter_Name"] == counter:
                 vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
         raw[counter] = vals
-    for fam, pat in PMC_FAMILIES_193.items():
+    for fam, pat in PMC_FAMILIES.items():
         names = Counter()
         for k, xs in raw["FETCH_SIZE"].items():
             if pat in k:
@@ -472,6 +444,8 @@ def pmc_summary_families(fetch_csv, write_csv, workload, copy_bytes, n_nodes):
             row["counter_bytes"] = row["FETCH_SIZE"] + row["WRITE_SIZE"]
             row["counter_over_algorithmic"] = row["counter_bytes"] / alg
         out["kernels"][fam] = row
+    a = out["kernels"].get("step_a_fp64", {})
+    out["hbm_bytes_per_launch"] = a.get("counter_bytes")   # the roofline's `traffic`
     return out
 
 
@@ -548,6 +522,9 @@ def main():
     ap.add_argument("--copy-ref", type=int, default=0, help="run the copy reference kernel (counter scale)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc CSVs into the traffic file and exit")
+    ap.add_argument("--pin-shape", type=str, default="",
+                    help="threads,strip,zplanes,depth: launch shape of every stencil kernel instead of the "
+                         "autotuner's (for counter runs, whose serialised launches distort the tuner)")
     ap.add_argument("--linear193-only", type=int, default=0,
                     help="run only the 193^3 FP64 and mixed linear solves (for traces and counters) and exit")
     args = ap.parse_args()
@@ -556,8 +533,8 @@ def main():
             print(json.dumps(pmc_summary_families(args.pmc_summary[0], args.pmc_summary[1], "sphere_poisson_193",
                                                   512 * (1 << 20), 193 ** 3), indent=1))
         else:
-            print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], f"membrane_pore_{args.n}",
-                                         512 * (1 << 20)), indent=1))
+            print(json.dumps(pmc_summary_families(args.pmc_summary[0], args.pmc_summary[1], f"membrane_pore_{args.n}",
+                                                  512 * (1 << 20), args.n ** 3), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path "
@@ -571,6 +548,9 @@ def main():
 
     if args.copy_ref:
         copy_reference(torch)
+    if args.pin_shape:
+        nt, strip, kz, depth = (int(v) for v in args.pin_shape.split(","))
+        pf.pf_set_launch(strip, kz, nt, depth)
     if args.linear193_only:
         print(json.dumps({"linear_193": linear193_only(pf, torch, inputs)}), flush=True)
         return

@@ -818,15 +818,13 @@ int chunk_len(const pf_grid *g, const pf_lin_opts *o)
 }
 
 // Reset the Krylov state from a residual already in w.r / w.rt with
-// ||r||^2 = rr.  Keeps the cumulative iteration count.  Asynchronous.  The
-// first step A reads r from s (r = s - omega t with t = 0) and p = v = 0.
+// ||r||^2 = rr.  Keeps the cumulative iteration count.  Asynchronous: one
+// kernel zeroes p, v, t (and x when zero_x), copies r to s and writes the
+// scalar block, whose host copy is set to the same values.  The first step A
+// reads r from s (r = s - omega t with t = 0) and p = v = 0.
 template <typename T>
-pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter, int maxit)
+pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter, int maxit, bool zero_x = false)
 {
-    PFCHK(fill<T>(g, w.p[0], T(0), g->N));
-    PFCHK(fill<T>(g, w.v[0], T(0), g->N));
-    PFCHK(fill<T>(g, w.t, T(0), g->N));
-    HIPCHK(hipMemcpyAsync(w.s, w.r, g->N * sizeof(T), hipMemcpyDeviceToDevice, g->stream));
     Scalars &h = *g->hsc;
     h = Scalars{};
     h.rho[0] = rr;            // shadow = r, so rho_0 = ||r||^2
@@ -841,7 +839,10 @@ pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter,
     h.stop = pfk::ST_RUN;
     h.stop_a = pfk::ST_RUN;
     h.fresh = 1;
-    return write_scalars(g);
+    hipLaunchKernelGGL((pfk::k_krylov_start<T>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.p[0],
+                       w.v[0], w.t, w.s, (const T *)w.r, zero_x ? w.x : (T *)nullptr, h, g->sc);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
 }
 
 // Iterate until the device reports a state other than RUN.  The first batch
@@ -1035,9 +1036,8 @@ pf_status ls_round_decide(LinSolve &L, bool *run)
             return PF_OK;
         }
         ++L.refinements;
-        PFCHK(fill<float>(g, g->w32.x, 0.0f, g->N));
         const double itol2 = L.o->inner_tol * L.o->inner_tol;
-        PFCHK(krylov_start<float>(g, g->w32, L.rr, std::max(itol2 * L.rr, L.tol2), L.iter, L.o->max_iter));
+        PFCHK(krylov_start<float>(g, g->w32, L.rr, std::max(itol2 * L.rr, L.tol2), L.iter, L.o->max_iter, true));
     }
     *run = true;
     return PF_OK;
@@ -1786,13 +1786,15 @@ struct NlSys {
 // right-hand side bs[i] and initial guess / result xs[i] (grid buffers).
 // Batched phases run every member's Krylov iterations in shared launches.
 pf_status nl_linear_phase(std::vector<NlSys *> &sys, const std::vector<OpDesc> &ops,
-                          const std::vector<const double *> &bs, const std::vector<double *> &xs, bool batched)
+                          const std::vector<const double *> &bs, const std::vector<const double *> &x0s,
+                          const std::vector<double *> &xs, bool batched)
 {
     const size_t n = sys.size();
-    for (size_t i = 0; i < n; ++i) {
+    for (size_t i = 0; i < n; ++i) {   // right-hand side and initial guess into the grid's solve buffers
         pf_grid *g = sys[i]->g;
-        HIPCHK(hipMemcpyAsync(g->b64, bs[i], g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
-        HIPCHK(hipMemcpyAsync(g->w64.x, xs[i], g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+        hipLaunchKernelGGL(pfk::k_copy2, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->b64, bs[i], g->w64.x,
+                           x0s[i]);
+        HIPCHK(hipGetLastError());
     }
     bool same_prec = true;
     for (size_t i = 1; i < n; ++i) same_prec &= sys[i]->p->lin.precision == sys[0]->p->lin.precision;
@@ -1856,16 +1858,17 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
     {   // step 2
         std::vector<NlSys *> cold;
         std::vector<OpDesc> ops;
-        std::vector<const double *> bs;
+        std::vector<const double *> bs, x0s;
         std::vector<double *> xs;
         for (auto &s : S) {
             if (s.p->warm_start) continue;
             cold.push_back(&s);
             ops.push_back(OpDesc{});
             bs.push_back(s.g->src);
+            x0s.push_back(s.g->phi0);
             xs.push_back(s.g->phi0);
         }
-        if (!cold.empty()) PFCHK(nl_linear_phase(cold, ops, bs, xs, batched));
+        if (!cold.empty()) PFCHK(nl_linear_phase(cold, ops, bs, x0s, xs, batched));
     }
     for (;;) {
         std::vector<NlSys *> act;
@@ -1885,7 +1888,7 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
         {
             std::vector<NlSys *> pf1;
             std::vector<OpDesc> ops;
-            std::vector<const double *> bs;
+            std::vector<const double *> bs, x0s;
             std::vector<double *> xs;
             for (NlSys *s : act) {
                 pf_grid *g = s->g;
@@ -1897,6 +1900,7 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
                     pf1.push_back(s);
                     ops.push_back(op);
                     bs.push_back(g->rhs1);
+                    x0s.push_back(g->psi);
                     xs.push_back(g->psi);
                 } else {
                     hipLaunchKernelGGL(pfk::k_psi_local, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
@@ -1904,13 +1908,13 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
                     HIPCHK(hipGetLastError());
                 }
             }
-            if (!pf1.empty()) PFCHK(nl_linear_phase(pf1, ops, bs, xs, batched));
+            if (!pf1.empty()) PFCHK(nl_linear_phase(pf1, ops, bs, x0s, xs, batched));
         }
         // PF2
         {
             std::vector<NlSys *> pf2;
             std::vector<OpDesc> ops;
-            std::vector<const double *> bs;
+            std::vector<const double *> bs, x0s;
             std::vector<double *> xs;
             for (NlSys *s : act) {
                 if (s->done) continue;
@@ -1919,15 +1923,15 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
                                    (const double *)g->psi, (const double *)g->sig, (const double *)g->phi0,
                                    (const double *)g->src, s->p->eps_s, g->rhs2);
                 HIPCHK(hipGetLastError());
-                HIPCHK(hipMemcpyAsync(g->phi, g->phi0, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
                 OpDesc op;
                 op.sigma = g->sig;
                 pf2.push_back(s);
                 ops.push_back(op);
                 bs.push_back(g->rhs2);
+                x0s.push_back(g->phi0);   // warm start from Phi_0; the solution goes to phi
                 xs.push_back(g->phi);
             }
-            if (!pf2.empty()) PFCHK(nl_linear_phase(pf2, ops, bs, xs, batched));
+            if (!pf2.empty()) PFCHK(nl_linear_phase(pf2, ops, bs, x0s, xs, batched));
         }
         // relaxation and max-norm test (Table 2 step 5)
         for (NlSys *s : act) {

@@ -1048,6 +1048,38 @@ __global__ void k_fill(size_t N, T *dst, T v)
         dst[n] = v;
 }
 
+// Two copies of N doubles in one launch: d0 = s0, d1 = s1.
+__global__ void k_copy2(size_t N, double *d0, const double *s0, double *d1, const double *s1)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        d0[n] = s0[n];
+        d1[n] = s1[n];
+    }
+}
+
+// Start (or restart) of a BiCGSTAB run in one launch: p = v = t = 0, s = r,
+// x = 0 when xz is given (the correction of a refinement step), and the
+// scalar block set to `init` (threads of the first workgroup copy it word by
+// word).  The next step kernels read all of it after this launch.
+template <typename T>
+__global__ void k_krylov_start(size_t N, T *p, T *v, T *t, T *s, const T *r, T *xz, Scalars init, Scalars *sc)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
+        p[n] = T(0);
+        v[n] = T(0);
+        t[n] = T(0);
+        s[n] = r[n];
+        if (xz) xz[n] = T(0);
+    }
+    static_assert(sizeof(Scalars) % 4 == 0, "scalar block is copied in 32-bit words");
+    constexpr unsigned W = sizeof(Scalars) / 4;
+    static_assert(W <= 256, "one word per thread of the first workgroup");
+    if (blockIdx.x == 0 && threadIdx.x < W)
+        reinterpret_cast<unsigned *>(sc)[threadIdx.x] = reinterpret_cast<const unsigned *>(&init)[threadIdx.x];
+}
+
 // Inverse diagonal of the operator: 1 / (sum_f c_f + sigma) on free rows,
 // -1 on Dirichlet rows.  Computed in FP64 and rounded to T.
 template <typename T, bool CEPS>
