@@ -123,6 +123,9 @@ typedef struct {
     double seconds;        /* wall time of the call                                  */
     int32_t status;        /* pf_status of the call                                  */
     double max_res;        /* final true ||b - A x||_inf (PF_STOP_ABS_INF), else -1  */
+    int32_t fp64_fallback; /* PF_MIXED: 1 if a refinement step failed to lower the true
+                              residual and the solve finished in FP64 (the step is
+                              undone first), else 0                                   */
 } pf_lin_info;
 
 /* Fill *o with defaults: rel_tol 1e-10, max_iter 20000, PF_FP64,

@@ -913,7 +913,11 @@ pf_status check_opts(const pf_lin_opts *o)
 //   ls_init        dinv, Dirichlet values, ||b_lift|| (read back);
 //   ls_round_*     true FP64 residual (read back), then either finish or
 //                  start a Krylov run (FP64 restart, or FP32 correction);
-//   ls_after       account for the run (FP32: x += d).
+//   ls_after       account for the run (FP32: x += d, the previous x kept in
+//                  the idle FP64 vector s).
+// A refinement step whose correction does not lower the true residual (an
+// FP32 Krylov run that lost its accuracy on a badly conditioned system) is
+// undone, and the solve continues with FP64 Krylov runs (ls_fallback).
 struct LinSolve {
     pf_grid *g = nullptr;
     OpDesc op;
@@ -922,8 +926,9 @@ struct LinSolve {
     double *dinv64 = nullptr;
     float *dinv32 = nullptr;
     double bnorm = 0, tol2 = 0, rr = 0, rinf = 0;   // rinf: true ||r||_inf (PF_STOP_ABS_INF)
+    double rr_start = 0;                             // ||r||^2 when the last refinement step began
     int iter = 0, restarts = 0, refinements = 0;
-    bool started = false, done = false;
+    bool started = false, done = false, fallback = false;
     pf_status result = PF_OK;
 };
 
@@ -1004,12 +1009,29 @@ pf_status ls_round_launch(LinSolve &L)
     return PF_OK;
 }
 
+// Undo the last FP32 correction (x from before it is in w64.s) and continue
+// the solve in FP64: the true residual and the FP64 shadow are computed again
+// and read back.
+pf_status ls_fallback(LinSolve &L)
+{
+    pf_grid *g = L.g;
+    HIPCHK(hipMemcpyAsync(g->w64.x, g->w64.s, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+    L.mixed = false;
+    L.fallback = true;
+    PFCHK(ls_round_residual(L));
+    HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
+    PFCHK(sync(g));
+    L.rr = g->hsc->red[0];
+    return PF_OK;
+}
+
 // After the stream has synchronised: finish, or start a Krylov run (*run).
 pf_status ls_round_decide(LinSolve &L, bool *run)
 {
     pf_grid *g = L.g;
     *run = false;
     L.rr = g->hsc->red[0];
+    if (L.mixed && L.refinements > 0 && !(L.rr < L.rr_start)) PFCHK(ls_fallback(L));
     if (!std::isfinite(L.rr)) { L.result = PF_ERR_NONFINITE; L.done = true; return PF_OK; }
     if (L.o->stop_rule == PF_STOP_ABS_INF) {
         L.rinf = g->hsc->red[2];
@@ -1036,6 +1058,7 @@ pf_status ls_round_decide(LinSolve &L, bool *run)
             return PF_OK;
         }
         ++L.refinements;
+        L.rr_start = L.rr;
         const double itol2 = L.o->inner_tol * L.o->inner_tol;
         PFCHK(krylov_start<float>(g, g->w32, L.rr, std::max(itol2 * L.rr, L.tol2), L.iter, L.o->max_iter, true));
     }
@@ -1048,13 +1071,20 @@ pf_status ls_after(LinSolve &L, int st)
 {
     pf_grid *g = L.g;
     L.iter = g->hsc->iter_done;
-    if (st == pfk::ST_NONFINITE) { L.result = PF_ERR_NONFINITE; L.done = true; return PF_OK; }
     if (L.mixed) {
+        // keep x from before the correction; a non-finite FP32 run adds
+        // nothing, so the next true residual equals the last one and the
+        // solve falls back to FP64 (ls_round_decide)
         if (st == pfk::ST_RESTART) ++L.restarts;
-        hipLaunchKernelGGL(pfk::k_correct, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
-                           (const float *)g->w32.x, (const uint8_t *)g->flags, dirbit(L.op));
-        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(g->w64.s, g->w64.x, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+        if (st != pfk::ST_NONFINITE) {
+            hipLaunchKernelGGL(pfk::k_correct, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
+                               (const float *)g->w32.x, (const uint8_t *)g->flags, dirbit(L.op));
+            HIPCHK(hipGetLastError());
+        }
+        return PF_OK;
     }
+    if (st == pfk::ST_NONFINITE) { L.result = PF_ERR_NONFINITE; L.done = true; return PF_OK; }
     // FP64: CONV, MAXIT and RESTART all return to the true residual
     return PF_OK;
 }
@@ -1068,6 +1098,7 @@ pf_status ls_finish(const LinSolve &L, pf_lin_info *info)
     li.rel_res = L.bnorm > 0 ? std::sqrt(L.rr) / L.bnorm : 0.0;
     li.max_res = L.o->stop_rule == PF_STOP_ABS_INF ? L.rinf : -1.0;
     li.status = L.result;
+    li.fp64_fallback = L.fallback ? 1 : 0;
     if (info) *info = li;
     if (L.result == PF_ERR_NOCONV && L.o->stop_rule == PF_STOP_ABS_INF)
         return fail(L.result, "no convergence: max residual %.3e after %d iterations", L.rinf, L.iter);
@@ -1363,10 +1394,18 @@ pf_status solve_batch(std::vector<LinSolve> &Ls)
         }
         if (act.empty()) break;
         for (LinSolve *L : act) PFCHK(sync(L->g));   // Krylov starts written
+        // members that fell back to FP64 run apart from those still refining in FP32
+        std::vector<LinSolve *> a32, a64;
+        for (LinSolve *L : act) (L->mixed ? a32 : a64).push_back(L);
         std::vector<int> st;
-        if (act[0]->mixed) PFCHK(batch_krylov_run<float>(act, bs, m, st));
-        else PFCHK(batch_krylov_run<double>(act, bs, m, st));
-        for (size_t i = 0; i < act.size(); ++i) PFCHK(ls_after(*act[i], st[i]));
+        if (!a32.empty()) {
+            PFCHK(batch_krylov_run<float>(a32, bs, m, st));
+            for (size_t i = 0; i < a32.size(); ++i) PFCHK(ls_after(*a32[i], st[i]));
+        }
+        if (!a64.empty()) {
+            PFCHK(batch_krylov_run<double>(a64, bs, m, st));
+            for (size_t i = 0; i < a64.size(); ++i) PFCHK(ls_after(*a64[i], st[i]));
+        }
     }
     for (auto &L : Ls) PFCHK(sync(L.g));
     return PF_OK;

@@ -45,7 +45,7 @@ class pf_lin_opts(C.Structure):
 class pf_lin_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("restarts", C.c_int32),
                 ("rel_res", C.c_double), ("seconds", C.c_double), ("status", C.c_int32),
-                ("max_res", C.c_double)]
+                ("max_res", C.c_double), ("fp64_fallback", C.c_int32)]
 
 
 class pf_pf_params(C.Structure):

@@ -308,6 +308,41 @@ def test_singular_neumann_terminates():
     assert info["status"] in (pf.PF_ERR_NOCONV, pf.PF_ERR_BREAKDOWN, pf.PF_ERR_NONFINITE)
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_mixed_falls_back_to_fp64_when_fp32_fails(batched):
+    """Coefficients whose FP32 face terms overflow (eps ~ 1e38 with 1/h^2 =
+    100; FP64 represents them without trouble) leave the FP32 Krylov run
+    without a usable correction: the refinement step is undone, the solve
+    finishes in FP64 and reports it, and the result meets the FP64 bar
+    against the oracle.  In a batch, only that member falls back; a member
+    with ordinary coefficients keeps refining in FP32."""
+    pf = _pf()
+    rng = np.random.default_rng(21)
+    n = 17
+    p = _rand_problem(n, n, n, seed=21, h=0.1)
+    p = inputs.Problem(name="big_eps", nx=n, ny=n, nz=n, h=0.1, origin=(0, 0, 0), eps=p.eps * 1e36,
+                       node_type=p.node_type, fixed_charge=np.zeros(p.N), bc_phi=(D,) * 6,
+                       bc_value=(0.0,) * 6, fixed_value=p.fixed_value)
+    b = rng.normal(size=p.N)
+    ref, _ = oracle.linear_solve(p, None, b, tol=1e-13)
+    opts = pf.pf_lin_opts_default(precision=pf.PF_MIXED, rel_tol=1e-12)
+    g = pf.grid_from_problem(p)
+    x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    if not batched:
+        info = pf.pf_linear_solve(g, None, dev(b), x, opts)
+    else:
+        q = inputs.sphere_poisson(n)
+        gq = pf.grid_from_problem(q)
+        xq = torch.zeros(q.N, dtype=torch.float64, device="cuda")
+        infos = pf.pf_linear_solve_batch([g, gq], [None, None], [dev(b), dev(q.b)], [x, xq], opts)
+        info, iq = infos
+        assert iq["status"] == 0 and iq["fp64_fallback"] == 0 and iq["refinements"] >= 1
+        assert pf.pf_residual(gq, None, dev(q.b), xq) <= 1e-12
+    assert info["status"] == 0 and info["fp64_fallback"] == 1 and info["refinements"] >= 1
+    assert pf.pf_residual(g, None, dev(b), x) <= 1e-12
+    assert _rel(host(x), ref) <= 1e-9
+
+
 # ------------------------------------------------------------------- Fermi
 
 def _membrane_params(pf, **kw):
