@@ -447,6 +447,17 @@ def test_linear_batch_rejects_shared_grid():
     with pytest.raises(pf.PfError) as e:
         pf.pf_linear_solve_batch([g, g], None, [b, b], xs)
     assert e.value.code == pf.PF_ERR_ARG
+    # empty batches are valid calls that do nothing
+    assert pf.pf_linear_solve_batch([], None, [], []) == []
+    assert pf.pf_nonlinear_solve_batch([], [], []) == []
+    # a batch of one solves like the single call (the batched kernel's
+    # launch shape may differ, so to the FP64 bar rather than bit for bit)
+    x1 = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    (info,) = pf.pf_linear_solve_batch([g], None, [b], [x1])
+    x0 = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    pf.pf_linear_solve(g, None, b, x0)
+    assert info["status"] == 0 and info["rel_res"] <= 1e-10
+    assert _rel(host(x1), host(x0)) <= 1e-7
 
 
 def test_nonlinear_batch_bias_sweep_matches_oracle():
