@@ -378,6 +378,35 @@ def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0):
     return res
 
 
+def copy_ceiling(torch):
+    """Achievable device bandwidth of this part for plain streaming kernels
+    (torch's own elementwise kernels, FP64): a copy (1 read, 1 write) and a
+    three-operand product (3 reads, 1 write) per buffer size, timed with
+    events over 20 launches after 3 warm-up launches; the smaller sizes stay
+    in the Infinity Cache between launches."""
+    out = []
+    for mib in (32, 96, 512, 2048):
+        n = mib * (1 << 20) // 8
+        a = torch.rand(n, dtype=torch.float64, device="cuda")
+        b, c, d = torch.rand_like(a), torch.rand_like(a), torch.empty_like(a)
+        row = {"mib_per_buffer": mib}
+        for name, fn, nbuf in (("copy", lambda: d.copy_(a), 2), ("addcmul", lambda: torch.addcmul(a, b, c, out=d), 4)):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3 / 20
+            row[name + "_tbs"] = nbuf * n * 8 / sec / 1e12
+        out.append(row)
+        del a, b, c, d
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_reference(torch, mib=512):
     """A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE give the
     counters' scale (bytes per reported KiB) for the traffic figure."""
@@ -522,6 +551,8 @@ def main():
     ap.add_argument("--copy-ref", type=int, default=0, help="run the copy reference kernel (counter scale)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc CSVs into the traffic file and exit")
+    ap.add_argument("--copy-ceiling", type=int, default=0,
+                    help="measure plain streaming bandwidth (copy, 3-operand product) at several sizes and exit")
     ap.add_argument("--pin-shape", type=str, default="",
                     help="threads,strip,zplanes,depth: launch shape of every stencil kernel instead of the "
                          "autotuner's (for counter runs, whose serialised launches distort the tuner)")
@@ -546,6 +577,9 @@ def main():
     pf.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.copy_ceiling:
+        print(json.dumps({"copy_ceiling": copy_ceiling(torch)}), flush=True)
+        return
     if args.copy_ref:
         copy_reference(torch)
     if args.pin_shape:
