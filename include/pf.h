@@ -107,7 +107,9 @@ typedef struct {
     int32_t max_iter;      /* BiCGSTAB iterations (all refinements together), > 0    */
     int32_t precision;     /* pf_precision: PF_FP64, or PF_MIXED = FP32 inner BiCGSTAB
                               (FP32 eps, iterates and stencil; FP64 reductions and
-                              scalars) inside FP64 iterative refinement               */
+                              scalars) inside FP64 iterative refinement; a refinement
+                              step that does not lower the true residual is undone
+                              and the solve continues in FP64 (fp64_fallback)         */
     double inner_tol;      /* PF_MIXED: relative residual target of each inner solve */
     int32_t max_refine;    /* PF_MIXED: maximum refinement steps                     */
     int32_t check_every;   /* iterations per device-side chunk between host checks;
