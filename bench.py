@@ -378,6 +378,65 @@ def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0):
     return res
 
 
+def trace_summary(paths, top=12):
+    """Busy and idle time of the GPU from rocprofv3 kernel (and memory-copy)
+    trace CSVs: the union of activity intervals, the idle gaps between
+    consecutive activities by size and by the pair of activities around them,
+    and the busy time per kernel."""
+    import csv
+    import re
+    from collections import Counter
+
+    def short(name):
+        name = name.replace("void ", "")
+        m = re.match(r"(pfk::\w+)(<[^>]*>)?", name)
+        return (m.group(1) + (m.group(2) or "")) if m else name[:40]
+
+    ev = []
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            nm = r.get("Kernel_Name") or ("copy " + r.get("Direction", "?"))
+            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(nm)))
+    ev.sort()
+    if not ev:
+        return {}
+    busy, end, prev = 0, ev[0][0], "start"
+    gaps, gapn, kern, kn, hist = Counter(), Counter(), Counter(), Counter(), Counter()
+    durs = {}
+    for s0, e0, nm in ev:
+        kern[nm] += e0 - s0
+        kn[nm] += 1
+        durs.setdefault(nm, []).append(e0 - s0)
+        if s0 > end:
+            g = s0 - end
+            gaps[f"{prev} -> {nm}"] += g
+            gapn[f"{prev} -> {nm}"] += 1
+            b = 1
+            while b * 2 <= g / 1000:
+                b *= 2
+            hist[b] += g
+        busy += max(0, e0 - max(s0, end))
+        if e0 > end:
+            end, prev = e0, nm
+    span = ev[-1][1] - ev[0][0]
+    return {"events": len(ev), "span_s": span * 1e-9, "busy_s": busy * 1e-9, "idle_s": (span - busy) * 1e-9,
+            "idle_by_gap_us_at_least": {str(b): v * 1e-9 for b, v in sorted(hist.items())},
+            "top_gaps": [{"pair": k, "seconds": v * 1e-9, "count": gapn[k], "mean_us": v / gapn[k] * 1e-3}
+                         for k, v in gaps.most_common(top)],
+            "busy_by_kernel": [dict({"kernel": k, "seconds": v * 1e-9, "count": kn[k], "mean_us": v / kn[k] * 1e-3},
+                                    **_full_launches(durs[k])) for k, v in kern.most_common(top)]}
+
+
+def _full_launches(d):
+    """Mean duration of the launches that did their work: those of at least a
+    quarter of the median (BiCGSTAB launches queued after convergence exit
+    at once and take a few percent of a full one)."""
+    d = sorted(d)
+    cut = 0.25 * d[len(d) // 2]
+    full = [x for x in d if x >= cut]
+    return {"count_full": len(full), "mean_us_full": sum(full) / len(full) * 1e-3}
+
+
 def copy_ceiling(torch):
     """Achievable device bandwidth of this part for plain streaming kernels
     (torch's own elementwise kernels, FP64): a copy (1 read, 1 write) and a
@@ -551,6 +610,8 @@ def main():
     ap.add_argument("--copy-ref", type=int, default=0, help="run the copy reference kernel (counter scale)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc CSVs into the traffic file and exit")
+    ap.add_argument("--trace-summary", nargs="+", metavar="CSV",
+                    help="summarise rocprofv3 kernel / memory-copy trace CSVs (busy, idle gaps) and exit")
     ap.add_argument("--copy-ceiling", type=int, default=0,
                     help="measure plain streaming bandwidth (copy, 3-operand product) at several sizes and exit")
     ap.add_argument("--pin-shape", type=str, default="",
@@ -559,6 +620,9 @@ def main():
     ap.add_argument("--linear193-only", type=int, default=0,
                     help="run only the 193^3 FP64 and mixed linear solves (for traces and counters) and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary), indent=1))
+        return
     if args.pmc_summary:
         if args.linear193_only:
             print(json.dumps(pmc_summary_families(args.pmc_summary[0], args.pmc_summary[1], "sphere_poisson_193",

@@ -244,10 +244,11 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample);
  * pf_spmv and pf_spmv_f32.  launches timed and their mean duration in ms;
  * bytes is the algorithmic HBM traffic of those launches (step A: 12 vectors
  * of N elements per launch, s, t, x, p, v, shadow, dinv, eps read and x, r,
- * p, v written; products: x, eps, dinv read and y written).  The mean
- * excludes the event-bracket latency (dispatch and completion of the
- * launch), which pf_timing_enable measures around an empty one-workgroup
- * kernel.  PF_ERR_ARG for another kind. */
+ * p, v written; products: x, eps, dinv read and y written).  The mean is
+ * that of the event brackets, which also hold the dispatch and completion
+ * of the launch: it bounds the kernel's duration from above (no correction
+ * is subtracted; an estimate of that latency does not survive a profiler,
+ * which adds its own per-dispatch cost).  PF_ERR_ARG for another kind. */
 pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, double *bytes);
 
 /* ---------------- singular-charge decomposition (Sec. 3, Eqs. (5)-(10), (17)-(18)) */

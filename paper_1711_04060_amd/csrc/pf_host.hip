@@ -8,6 +8,7 @@
 // nonlinear loop of Tables 2 and 4 runs entirely on the device apart from one
 // status read per outer iteration (the max-norm test of Table 2 step 5).
 #include "pf_kernels.h"
+#include <hip/hip_ext.h>
 #include "pf_iface.h"
 #include "pf_sites.h"
 #include "../../include/pf.h"
@@ -67,7 +68,6 @@ struct Timing {
     long chunk = 0;
     long long launches[4] = {0, 0, 0, 0};
     double ms[4] = {0, 0, 0, 0}, bytes[4] = {0, 0, 0, 0};
-    double bracket_ms = 0;   // latency of an event bracket around an empty kernel
     hipEvent_t p0 = nullptr, p1 = nullptr;   // around product launches
 } g_timing;
 
@@ -258,8 +258,12 @@ pf_status ensure_work(pf_grid *g)
 
 // --------------------------------------------------------------- launches
 
+// e0, e1 (optional): events that the dispatch itself stamps at the kernel's
+// start and end (hipExtLaunchKernel), so their interval is the kernel's own
+// duration, without the marker packets of separate event records.
 template <int OP, typename T, bool CEPS, int NTZ, int PPT, bool WIDE = false, int DEPTH = 1>
-hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
+hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEvent_t e0 = nullptr,
+                     hipEvent_t e1 = nullptr)
 {
     auto kern = pfk::k_zmarch<OP, T, CEPS, NTZ, PPT, WIDE, DEPTH>;
     if (c.lds > 64 * 1024) {
@@ -271,15 +275,17 @@ hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
             granted = c.lds;
         }
     }
-    hipLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), c.lds, s, a);
+    if (e0 || e1) hipExtLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), (std::uint32_t)c.lds, s, e0, e1, 0u, a);
+    else hipLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), c.lds, s, a);
     return hipGetLastError();
 }
 
 template <int OP, typename T, bool CEPS>
-hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
+hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEvent_t e0 = nullptr,
+                    hipEvent_t e1 = nullptr)
 {
     if (c.wide) {
-        if (c.NTZ == 1024 && c.PPT == 1) return launch_zk<OP, T, CEPS, 1024, 1, true>(c, a, s);
+        if (c.NTZ == 1024 && c.PPT == 1) return launch_zk<OP, T, CEPS, 1024, 1, true>(c, a, s, e0, e1);
         return hipErrorInvalidValue;
     }
     // the BiCGSTAB steps and the Jacobi-scaled product come in both pipeline
@@ -287,22 +293,22 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s)
     constexpr bool PIPE = (OP == pfk::OP_BA || OP == pfk::OP_BB || OP == pfk::OP_SPMV_JAC);
     if (PIPE && c.depth == 2) {
         switch (c.NTZ * 10 + c.PPT) {
-        case 2561: return launch_zk<OP, T, CEPS, 256, 1, false, 2>(c, a, s);
-        case 2562: return launch_zk<OP, T, CEPS, 256, 2, false, 2>(c, a, s);
-        case 5121: return launch_zk<OP, T, CEPS, 512, 1, false, 2>(c, a, s);
-        case 5122: return launch_zk<OP, T, CEPS, 512, 2, false, 2>(c, a, s);
-        case 10241: return launch_zk<OP, T, CEPS, 1024, 1, false, 2>(c, a, s);
-        case 10242: return launch_zk<OP, T, CEPS, 1024, 2, false, 2>(c, a, s);
+        case 2561: return launch_zk<OP, T, CEPS, 256, 1, false, 2>(c, a, s, e0, e1);
+        case 2562: return launch_zk<OP, T, CEPS, 256, 2, false, 2>(c, a, s, e0, e1);
+        case 5121: return launch_zk<OP, T, CEPS, 512, 1, false, 2>(c, a, s, e0, e1);
+        case 5122: return launch_zk<OP, T, CEPS, 512, 2, false, 2>(c, a, s, e0, e1);
+        case 10241: return launch_zk<OP, T, CEPS, 1024, 1, false, 2>(c, a, s, e0, e1);
+        case 10242: return launch_zk<OP, T, CEPS, 1024, 2, false, 2>(c, a, s, e0, e1);
         default: return hipErrorInvalidValue;
         }
     }
     switch (c.NTZ * 10 + c.PPT) {
-    case 2561: return launch_zk<OP, T, CEPS, 256, 1>(c, a, s);
-    case 2562: return launch_zk<OP, T, CEPS, 256, 2>(c, a, s);
-    case 5121: return launch_zk<OP, T, CEPS, 512, 1>(c, a, s);
-    case 5122: return launch_zk<OP, T, CEPS, 512, 2>(c, a, s);
-    case 10241: return launch_zk<OP, T, CEPS, 1024, 1>(c, a, s);
-    case 10242: return launch_zk<OP, T, CEPS, 1024, 2>(c, a, s);
+    case 2561: return launch_zk<OP, T, CEPS, 256, 1>(c, a, s, e0, e1);
+    case 2562: return launch_zk<OP, T, CEPS, 256, 2>(c, a, s, e0, e1);
+    case 5121: return launch_zk<OP, T, CEPS, 512, 1>(c, a, s, e0, e1);
+    case 5122: return launch_zk<OP, T, CEPS, 512, 2>(c, a, s, e0, e1);
+    case 10241: return launch_zk<OP, T, CEPS, 1024, 1>(c, a, s, e0, e1);
+    case 10242: return launch_zk<OP, T, CEPS, 1024, 2>(c, a, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -423,9 +429,11 @@ pfk::ZArgs<T> zbase(pf_grid *g, const OpDesc &op, const T *dinv)
 
 // Launch with the shape c (the one a was built for).
 template <int OP, typename T>
-pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a, const ZCfg &c)
+pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a, const ZCfg &c, hipEvent_t e0 = nullptr,
+                  hipEvent_t e1 = nullptr)
 {
-    hipError_t e = op.psi ? launch_z<OP, T, true>(c, a, g->stream) : launch_z<OP, T, false>(c, a, g->stream);
+    hipError_t e = op.psi ? launch_z<OP, T, true>(c, a, g->stream, e0, e1)
+                          : launch_z<OP, T, false>(c, a, g->stream, e0, e1);
     if (e != hipSuccess) return fail(PF_ERR_DEVICE, "stencil kernel launch failed: %s", hipGetErrorString(e));
     return PF_OK;
 }
@@ -546,9 +554,7 @@ pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
                     hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     const ZCfg &ca = cfg_ref<T>(g), &cb = cfgb_ref<T>(g);
-    if (e0) HIPCHK(hipEventRecord(e0, g->stream));
-    PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, dinv, w, parity, ca, cb.G), ca)));
-    if (e1) HIPCHK(hipEventRecord(e1, g->stream));
+    PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, dinv, w, parity, ca, cb.G), ca, e0, e1)));
     PFCHK((zlaunch<pfk::OP_BB, T>(g, op, args_b<T>(g, op, dinv, w, parity, cb, ca.G), cb)));
     return PF_OK;
 }
@@ -1466,29 +1472,6 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample)
     if (!g_timing.enabled) return PF_OK;
     if (!g_timing.p0) HIPCHK(hipEventCreate(&g_timing.p0));
     if (!g_timing.p1) HIPCHK(hipEventCreate(&g_timing.p1));
-    // An event pair around a launch also times the dispatch of the kernel
-    // packet and its completion signal.  Measure that bracket around an empty
-    // one-workgroup kernel launched the same way; pf_timing_read subtracts it.
-    hipStream_t st;
-    hipEvent_t e0, e1;
-    HIPCHK(hipStreamCreate(&st));
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    std::vector<float> v;
-    for (int i = 0; i < 25; ++i) {
-        if (hipEventRecord(e0, st) != hipSuccess) break;
-        hipLaunchKernelGGL(pfk::k_fill<double>, dim3(1), dim3(NT), 0, st, (size_t)0, (double *)nullptr, 0.0);
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) break;
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && i >= 5) v.push_back(ms);
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipStreamDestroy(st);
-    if (!v.empty()) {
-        std::sort(v.begin(), v.end());
-        g_timing.bracket_ms = v[v.size() / 2];
-    }
     return PF_OK;
 }
 
@@ -1498,9 +1481,7 @@ pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, doubl
     const int i = kind;
     if (launches) *launches = g_timing.launches[i];
     if (mean_ms)
-        *mean_ms = g_timing.launches[i]
-                       ? std::max(0.0, g_timing.ms[i] / g_timing.launches[i] - g_timing.bracket_ms)
-                       : 0.0;
+        *mean_ms = g_timing.launches[i] ? g_timing.ms[i] / g_timing.launches[i] : 0.0;
     if (bytes) *bytes = g_timing.bytes[i];
     return PF_OK;
 }
@@ -1676,10 +1657,9 @@ pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, i
     a.x = x;
     a.out = y;
     const bool timed = jacobi && g_timing.enabled;
-    if (timed) HIPCHK(hipEventRecord(g_timing.p0, g->stream));
-    if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a, c)));
+    hipEvent_t t0 = timed ? g_timing.p0 : nullptr, t1 = timed ? g_timing.p1 : nullptr;
+    if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a, c, t0, t1)));
     else PFCHK((zlaunch<pfk::OP_SPMV, double>(g, op, a, c)));
-    if (timed) HIPCHK(hipEventRecord(g_timing.p1, g->stream));
     PFCHK(sync(g));
     if (timed) PFCHK(timing_add_product(2, 4.0 * (double)g->N * sizeof(double)));
     return PF_OK;
@@ -1701,9 +1681,8 @@ pf_status pf_spmv_f32(pf_grid *g, const double *sigma, const float *x, float *y,
     a.x = x;
     a.out = y;
     const bool timed = g_timing.enabled;
-    if (timed) HIPCHK(hipEventRecord(g_timing.p0, g->stream));
-    PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a, c)));
-    if (timed) HIPCHK(hipEventRecord(g_timing.p1, g->stream));
+    PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a, c, timed ? g_timing.p0 : nullptr,
+                                             timed ? g_timing.p1 : nullptr)));
     PFCHK(sync(g));
     if (timed) PFCHK(timing_add_product(3, 4.0 * (double)g->N * sizeof(float)));
     return PF_OK;

@@ -85,3 +85,28 @@ def test_traffic_only_from_current_source_and_workload(tmp_path, monkeypatch):
     assert bench.traffic_from_profiles("membrane_pore_49") is None          # other workload
     (csrc / "pf_kernels.h").write_text("// kernel source, changed\n")
     assert bench.traffic_from_profiles("membrane_pore_97") is None          # kernel changed
+
+
+def test_trace_summary_busy_idle_and_gaps(tmp_path):
+    path = tmp_path / "k.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        # A [0, 10 us), B [12, 20), overlapping C [15, 30), A [40, 50)
+        for name, s0, e0 in (("void pfk::k_a<1>(x)", 0, 10_000), ("void pfk::k_b(x)", 12_000, 20_000),
+                             ("void pfk::k_c(x)", 15_000, 30_000), ("void pfk::k_a<1>(x)", 40_000, 50_000)):
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": s0, "End_Timestamp": e0})
+    out = bench.trace_summary([str(path)])
+    assert out["events"] == 4
+    assert out["span_s"] == pytest.approx(50e-6)
+    assert out["busy_s"] == pytest.approx(38e-6)     # [0, 10) + [12, 30) + [40, 50)
+    assert out["idle_s"] == pytest.approx(12e-6)
+    pairs = {g["pair"]: g for g in out["top_gaps"]}
+    assert pairs["pfk::k_a<1> -> pfk::k_b"]["mean_us"] == pytest.approx(2.0)
+    assert pairs["pfk::k_c -> pfk::k_a<1>"]["mean_us"] == pytest.approx(10.0)
+    busy = {k["kernel"]: k for k in out["busy_by_kernel"]}
+    assert busy["pfk::k_a<1>"]["count"] == 2 and busy["pfk::k_a<1>"]["seconds"] == pytest.approx(20e-6)
+    assert busy["pfk::k_a<1>"]["mean_us_full"] == pytest.approx(10.0)
+    # early exits (a few percent of a full launch) are left out of the full-launch mean
+    assert bench._full_launches([1000, 20_000, 21_000, 900, 19_000]) == {"count_full": 3,
+                                                                        "mean_us_full": pytest.approx(20.0)}
