@@ -41,13 +41,34 @@ SOLVENT, SOLUTE, FIXED = 0, 1, 2
 OK, EARG, ENOMEM, ENOCONV, EBREAKDOWN, ENONFINITE = 0, -1, -2, -4, -5, -6
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain FP64, no contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
-               "-shared", "-Wall", "-Wno-unused-function", "-Wno-maybe-uninitialized", "-o", _LIB, _SRC, "-lm"]
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_use_omp = False
+
+_CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared", "-Wall",
+           "-Wno-unused-function", "-Wno-maybe-uninitialized"]
+
+
+def build(force: bool = True, openmp: bool = False) -> str:
+    """Compile the oracle with gcc (plain FP64, no contraction, no fast-math).
+
+    openmp=True builds liboracle_omp.so from the same source with -fopenmp:
+    only loops with independent iterations run in parallel and every sum
+    stays sequential, so it returns the same bits as the serial library
+    (checked by a CPU test).  It serves the golden-file script only."""
+    lib = _LIB_OMP if openmp else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        extra = ["-fopenmp"] if openmp else ["-Wno-unknown-pragmas"]
+        cmd = ["gcc", *_CFLAGS, *extra, "-o", lib, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-    return _LIB
+    return lib
+
+
+def use_openmp() -> None:
+    """Load the OpenMP build (before the first oracle call of the process)."""
+    global _use_omp
+    if _lib is not None and not _use_omp:
+        raise RuntimeError("the serial oracle library is already loaded")
+    _use_omp = True
 
 
 class _Grid(C.Structure):
@@ -90,9 +111,10 @@ _lib = None
 def _L():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        lib = C.CDLL(_LIB)
+        path = _LIB_OMP if _use_omp else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build(force=False, openmp=_use_omp)
+        lib = C.CDLL(path)
         P, I, D, S = C.c_void_p, C.c_int, C.c_double, C.c_size_t
         lib.pfo_dirichlet.argtypes = [C.POINTER(_Grid), I, P, P, P]
         lib.pfo_assemble.argtypes = [I, I, I, D, P, P, P, P, P]

@@ -4,7 +4,11 @@
  * TEST INFRASTRUCTURE ONLY: called by tests, the smoke check and the
  * benchmark's CPU-baseline leg; never by the product library.  Plain loops,
  * sequential sums in index order, no blocking, no fusion.  Built with
- * -O2 -ffp-contract=off and without fast-math.
+ * -O2 -ffp-contract=off and without fast-math.  The OpenMP pragmas mark
+ * loops whose iterations are independent (the mat-vec rows, pointwise vector
+ * updates, the pointwise Fermi update); every sum stays a sequential loop,
+ * so a build with -fopenmp (used to write the large golden files) gives the
+ * same bits as the serial build, which ignores them.
  *
  * Readings of the paper that the code depends on (each is also listed in
  * the design notes):
@@ -146,6 +150,7 @@ void pfo_dia_matvec(int nx, int ny, int nz, const double *A, const double *x, do
     const double *A0 = A, *A1 = A + N, *A2 = A + 2 * N, *A3 = A + 3 * N;
     const double *A4 = A + 4 * N, *A5 = A + 5 * N, *A6 = A + 6 * N;
     size_t sx = 1, sy = (size_t)nx, sz = (size_t)nx * ny;
+#pragma omp parallel for
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -177,6 +182,7 @@ static void residual(int nx, int ny, int nz, const double *A, const unsigned cha
 {
     size_t N = (size_t)nx * ny * nz;
     pfo_dia_matvec(nx, ny, nz, A, x, r);
+#pragma omp parallel for
     for (size_t n = 0; n < N; ++n) r[n] = (is_dir[n] ? value[n] : b[n]) - r[n];
 }
 
@@ -254,27 +260,34 @@ restart:
         fresh = 0;
         ++iters;
         double beta = (rho / rho_old) * (alpha / omega);
+        #pragma omp parallel for
         for (size_t n = 0; n < N; ++n) p[n] = r[n] + beta * (p[n] - omega * v[n]);
+        #pragma omp parallel for
         for (size_t n = 0; n < N; ++n) ph[n] = minv[n] * p[n];
         pfo_dia_matvec(nx, ny, nz, A, ph, v);
         double rtv = dot(N, rt, v);
         if (rtv == 0.0) { ++restarts; goto restart; }
         alpha = rho / rtv;
+        #pragma omp parallel for
         for (size_t n = 0; n < N; ++n) s[n] = r[n] - alpha * v[n];
         if (small_res(N, s, bnorm, tol, rule)) {
             /* early exit on the half-step residual (Templates form) */
+            #pragma omp parallel for
             for (size_t n = 0; n < N; ++n) x[n] += alpha * ph[n];
             residual(nx, ny, nz, A, is_dir, value, b, x, r);
             if (small_res(N, r, bnorm, tol, rule)) goto done;
             ++restarts;
             goto restart;
         }
+        #pragma omp parallel for
         for (size_t n = 0; n < N; ++n) sh[n] = minv[n] * s[n];
         pfo_dia_matvec(nx, ny, nz, A, sh, t);
         double tt = dot(N, t, t);
         if (tt == 0.0) { ++restarts; goto restart; }
         omega = dot(N, t, s) / tt;
+        #pragma omp parallel for
         for (size_t n = 0; n < N; ++n) x[n] += alpha * ph[n] + omega * sh[n];
+        #pragma omp parallel for
         for (size_t n = 0; n < N; ++n) r[n] = s[n] - omega * t[n];
         rho_old = rho;
         double rn = sqrt(dot(N, r, r));
@@ -409,6 +422,7 @@ int pfo_fermi(size_t N, const double *phi, const unsigned char *type,
     double lnGB, v0;
     if (!species_ok(sp, &lnGB, &v0)) return PFO_EARG;
     int bad = 0;
+#pragma omp parallel for reduction(| : bad)
     for (size_t n = 0; n < N; ++n) {
         int solvent = !type || type[n] == PFO_SOLVENT;
         double rh = 0.0, sg = 0.0, Sn = 0.0;

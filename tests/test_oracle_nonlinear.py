@@ -198,3 +198,70 @@ def test_max_outer_reports_noconv():
     p, sp = _small_membrane()
     phi, info, _, _ = oracle.nonlinear_solve(p, p.fixed_charge, sp, 78.45, 1.9, max_outer=3, check=False)
     assert info["status"] == oracle.ENOCONV and info["outer_iters"] == 3
+
+
+def test_pf1_branch_gouy_chapman():
+    """The same PB limit run through the PF1 solve (l_c = 1e-3 A > 0 instead
+    of the local l_c = 0 branch): Eq. (12) then gives Psi = -rho/eps_s up to
+    O(l_c^2/h^2) ~ 1e-6, so the loop must again reproduce Gouy-Chapman to
+    O(h^2).  A sign error in the PF1 right-hand side (-rho) or in the PF2
+    coupling (-eps_s Psi) turns the screening around and fails this."""
+    L, phi_s, eps_s = 200.0, 2.0, 78.45
+    sp = oracle.species_from_molar((1.0, -1.0), (1.0, 1.0), (0.1, 0.1), steric=False)
+    kappa = math.sqrt(sp.lam * 2 * sp.conc[0] / eps_s)
+    errs = []
+    for h in (1.0, 0.5):
+        nz = int(round(L / h)) + 1
+        g = _column_grid(nz, h, np.full(nz, eps_s), np.zeros(nz), (phi_s, 0.0))
+        phi, info, _, _ = oracle.nonlinear_solve(g, None, sp, eps_s, 1e-3, outer_tol=1e-13, lin_tol=1e-14,
+                                                bc_psi=g.bc_phi)
+        z = np.arange(nz) * h
+        exact = 4 * np.arctanh(math.tanh(phi_s / 4) * np.exp(-kappa * z))
+        errs.append(np.abs(phi.reshape(nz, 9)[:, 0] - exact).max())
+        assert errs[-1] <= 0.1 * (kappa * h) ** 2
+    assert 1.9 <= math.log2(errs[0] / errs[1]) <= 2.1, errs
+
+
+def _fourth_order_exact(z, L, V, lc, kappa):
+    """l_c^2 phi'''' - phi'' + kappa^2 phi = 0 on [0, L], phi(0) = V,
+    phi(L) = 0, phi''(0) = phi''(L) = 0: decaying exponentials of the two
+    roots m^2 = (1 +- sqrt(1 - 4 l_c^2 kappa^2)) / (2 l_c^2), from each end."""
+    d = math.sqrt(1.0 - 4.0 * lc * lc * kappa * kappa)
+    m = np.sqrt(np.array([(1.0 - d) / (2 * lc * lc), (1.0 + d) / (2 * lc * lc)]))
+    # unknowns a1, a2 (modes e^{-m z}), b1, b2 (modes e^{-m (L - z)})
+    def rows(zz, deriv2):
+        f = m ** 2 if deriv2 else np.ones(2)
+        return np.concatenate([f * np.exp(-m * zz), f * np.exp(-m * (L - zz))])
+    M = np.array([rows(0.0, False), rows(L, False), rows(0.0, True), rows(L, True)])
+    c = np.linalg.solve(M, np.array([V, 0.0, 0.0, 0.0]))
+    return (c[:2, None] * np.exp(-m[:, None] * z[None, :])).sum(0) + \
+        (c[2:, None] * np.exp(-m[:, None] * (L - z[None, :]))).sum(0)
+
+
+def test_linearised_fourth_order_with_correlation():
+    """Correlation on (l_c = 1.9 A): with a small boundary potential the
+    Fermi update is linear, rho = -sigma phi with sigma = eps_s kappa^2, and
+    the fixed point of the loop is the linearised PF equation (Eqs. (2),
+    (12)-(14)) l_c^2 phi'''' - phi'' + kappa^2 phi = 0 with phi'' = Psi = 0
+    on the Dirichlet faces.  Its closed form comes from the roots of
+    l_c^2 m^4 - m^2 + kappa^2 = 0; the oracle must match it to O(h^2)."""
+    L, V, eps_s, lc = 200.0, 1e-3, 78.45, 1.9
+    sp = oracle.species_from_molar((1.0, -1.0), (1.0, 1.0), (0.1, 0.1), steric=False)
+    kappa = math.sqrt(sp.lam * 2 * sp.conc[0] / eps_s)
+    assert 4 * lc * lc * kappa * kappa < 1     # two real decay rates
+    errs = []
+    for h in (1.0, 0.5):
+        nz = int(round(L / h)) + 1
+        g = _column_grid(nz, h, np.full(nz, eps_s), np.zeros(nz), (V, 0.0))
+        phi, info, _, _ = oracle.nonlinear_solve(g, None, sp, eps_s, lc, outer_tol=1e-16, lin_tol=1e-14,
+                                                bc_psi=g.bc_phi, max_outer=5000)
+        z = np.arange(nz) * h
+        exact = _fourth_order_exact(z, L, V, lc, kappa)
+        errs.append(np.abs(phi.reshape(nz, 9)[:, 0] - exact).max() / V)
+    # the short decay length l_c sets the discretisation error
+    assert errs[1] <= 0.05 * (h / lc) ** 2
+    assert 1.8 <= math.log2(errs[0] / errs[1]) <= 2.2, errs
+    # and the solution differs from the l_c = 0 (Debye-Hueckel) profile by
+    # far more than that error
+    dh = V * np.exp(-kappa * np.arange(int(round(L / 0.5)) + 1) * 0.5)
+    assert np.abs(phi.reshape(-1, 9)[:, 0] / V - dh / V).max() > 20 * errs[1]
