@@ -966,6 +966,12 @@ pf_status ls_init_launch(LinSolve &L)
     PFCHK(ensure_work<double>(g));
     L.mixed = L.o->precision == PF_MIXED;
     if (L.mixed) PFCHK(ensure_work<float>(g));
+    if (L.op.sigma) {   // sigma >= 0 on free rows, read back with ||b_lift||
+        PFCHK(fill<int>(g, &g->sc->neg_shift, 0, 1));
+        hipLaunchKernelGGL(pfk::k_check_shift, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, L.op.sigma,
+                           (const uint8_t *)g->flags, dirbit(L.op), &g->sc->neg_shift);
+        HIPCHK(hipGetLastError());
+    }
     L.dinv64 = L.op.psi ? g->dinv64_psi : g->dinv64;
     PFCHK(compute_dinv<double>(g, L.op, L.dinv64));
     if (L.mixed) {
@@ -985,6 +991,11 @@ pf_status ls_init_launch(LinSolve &L)
 pf_status ls_init_decide(LinSolve &L)
 {
     pf_grid *g = L.g;
+    if (L.op.sigma && g->hsc->neg_shift) {
+        L.done = true;
+        L.result = PF_ERR_ARG;
+        return PF_OK;
+    }
     L.bnorm = std::sqrt(g->hsc->red[1]);
     if (!std::isfinite(L.bnorm)) {
         L.done = true;
@@ -1112,6 +1123,7 @@ pf_status ls_finish(const LinSolve &L, pf_lin_info *info)
         return fail(L.result, "no convergence: rel_res %.3e after %d iterations", li.rel_res, L.iter);
     if (L.result == PF_ERR_NONFINITE) return fail(L.result, "non-finite value in the iteration");
     if (L.result == PF_ERR_BREAKDOWN) return fail(L.result, "repeated BiCGSTAB breakdown");
+    if (L.result == PF_ERR_ARG) return fail(L.result, "sigma must be >= 0 on every free row");
     return PF_OK;
 }
 

@@ -68,6 +68,7 @@ struct Scalars {
     int stop;          // ST_RUN while iterating, else the terminal state
     int stop_a;        // state decided by the last step A, published by the step B after it
     int fresh;         // 1 from a (re)start until step B of the first iteration
+    int neg_shift;     // set when a free row of the operator has sigma < 0
 };
 enum { ST_RUN = 0, ST_CONV = 1, ST_RESTART = 3, ST_NONFINITE = 4, ST_MAXIT = 5 };
 
@@ -140,11 +141,7 @@ __device__ __forceinline__ float rcp_pos(float d) { return __builtin_amdgcn_rcpf
 template <typename T>
 __device__ __forceinline__ T face(T a, T b, T ih2)
 {
-#ifdef PF_FACE_IEEE
-    return (T(2) * a * b) / (a + b) * ih2;
-#else
     return (T(2) * a * b * ih2) * rcp_pos(a + b);
-#endif
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -886,7 +883,8 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                 if constexpr (!CEPS) ne[hm[u] - lo] = he[u];
             }
         }
-        if (WIDE && nhalo > HMAX * NT) {
+        // (plane k+1 exists only when the tile stages it: k + 1 < k1 <= nz)
+        if (WIDE && stage_next && nhalo > HMAX * NT) {
             for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
                 const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
                 Raw<T> w;
@@ -1106,6 +1104,17 @@ __global__ void k_dinv(int nx, int ny, int nz, double ih2, double ceps, const do
         D += sigma ? sigma[n] : sig_const;
         dinv[n] = (T)(1.0 / D);
     }
+}
+
+// Flag a negative diagonal shift on a free row (sigma must be >= 0; a NaN is
+// left to the solver's non-finite checks).  *neg must be zero on entry.
+__global__ void k_check_shift(size_t N, const double *sigma, const uint8_t *flags, uint8_t dirbit, int *neg)
+{
+    int b = 0;
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x)
+        if (!(flags[n] & dirbit) && sigma[n] < 0.0) b = 1;
+    if (b) atomicOr(neg, 1);
 }
 
 // x_i := Dirichlet value on Dirichlet rows (potential system) or 0 (PF1).

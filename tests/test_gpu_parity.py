@@ -298,6 +298,34 @@ def test_nan_in_sigma_or_b_is_reported(prec):
     assert info["status"] == 0
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_negative_sigma_is_rejected(prec):
+    """sigma < 0 on a free row breaks the operator's precondition (a
+    nonnegative diagonal shift, so that D > 0 and the Jacobi scaling is
+    defined): the solve returns PF_ERR_ARG before iterating, single and
+    batched.  A negative value on a Dirichlet row is not read and passes."""
+    pf = _pf()
+    p = inputs.sphere_poisson(17)
+    g = pf.grid_from_problem(p)
+    x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    free = 3 + 17 * (4 + 17 * 5)
+    opts = pf.pf_lin_opts_default(precision=prec)
+    sigma = np.full(p.N, 0.5)
+    sigma[free] = -1e-3
+    info = pf.pf_linear_solve(g, dev(sigma), dev(p.b), x, opts, check=False)
+    assert info["status"] == pf.PF_ERR_ARG
+    g2 = pf.grid_from_problem(p)
+    x2 = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    infos = pf.pf_linear_solve_batch([g, g2], [dev(sigma), None], [dev(p.b), dev(p.b)], [x, x2], opts,
+                                     check=False)
+    assert infos[0]["status"] == pf.PF_ERR_ARG and infos[1]["status"] == 0
+    sigma[free] = 0.5
+    sigma[0] = -5.0                        # corner: a Dirichlet row
+    x.zero_()
+    info = pf.pf_linear_solve(g, dev(sigma), dev(p.b), x, opts)
+    assert info["status"] == 0
+
+
 def test_singular_neumann_terminates():
     pf = _pf()
     n = 9
