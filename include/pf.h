@@ -150,10 +150,12 @@ pf_status pf_linear_solve(pf_grid *g, const double *sigma, const double *b, doub
 pf_status pf_residual(pf_grid *g, const double *sigma, const double *b, const double *x,
                       double *rel_res, double *r);
 
-/* Stencil operator application y = A x (jacobi = 0) or y = A M^-1 x
+/* Stencil operator application y = A x (jacobi = 0) or y = M^-1 A x
  * (jacobi = 1, M = diag(A), identity on Dirichlet rows) with the operator of
- * pf_linear_solve.  x, y: device [N], distinct.  The FP64 form is the
- * matrix-vector product of Table 3 steps 11 and 14, matrix-free. */
+ * pf_linear_solve.  x, y: device [N], distinct.  The FP64 forms are the
+ * matrix-vector product of Table 3 steps 11 and 14, matrix-free; the scaled
+ * one is the product as the solver applies it (its Krylov vectors are kept
+ * scaled by M^-1, so v^ = M^-1 A p^ for p^ = M^-1 p). */
 pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, int32_t jacobi);
 
 /* Same in FP32 (the inner operator of PF_MIXED): FP32 eps and vectors.
@@ -231,24 +233,27 @@ pf_status pf_nonlinear_solve_batch(int32_t n, pf_grid *const *g, const pf_pf_par
                                    double *const *phi, pf_nl_info *info);
 
 /* Kernel timing for measurement: while enabled, one chunk in every `sample`
- * records HIP events (on the library's stream, as direct launches) around
- * each launch of the BiCGSTAB step-A stencil kernel (the previous
- * iteration's x, r update fused with the p update and v = A M^-1 p: the
- * kernel that moves the most bytes per iteration), and every Jacobi-scaled
- * pf_spmv / pf_spmv_f32 call records events around its kernel.
+ * (single solves and batches counted together) records HIP events (on the
+ * library's stream, as direct launches) around each launch of the BiCGSTAB
+ * step-A stencil kernel (the previous iteration's x, r update fused with the
+ * p update and v = A p^: the kernel that moves the most bytes per
+ * iteration), and every Jacobi-scaled pf_spmv / pf_spmv_f32 call records
+ * events around its kernel.
  * enable = 1 clears the accumulators and starts; 0 stops.  Process-wide. */
 pf_status pf_timing_enable(int32_t enable, int32_t sample);
 
 /* Accumulated timings of one kind: 0 (PF_FP64) and 1 (PF_MIXED, the FP32
- * inner kernel) = BiCGSTAB step A; 2 and 3 = the Jacobi-scaled products of
- * pf_spmv and pf_spmv_f32.  launches timed and their mean duration in ms;
- * bytes is the algorithmic HBM traffic of those launches (step A: 12 vectors
- * of N elements per launch, s, t, x, p, v, shadow, dinv, eps read and x, r,
- * p, v written; products: x, eps, dinv read and y written).  The mean is
- * that of the event brackets, which also hold the dispatch and completion
- * of the launch: it bounds the kernel's duration from above (no correction
- * is subtracted; an estimate of that latency does not survive a profiler,
- * which adds its own per-dispatch cost).  PF_ERR_ARG for another kind. */
+ * inner kernel) = BiCGSTAB step A of single solves; 2 and 3 = the
+ * Jacobi-scaled products of pf_spmv and pf_spmv_f32; 4 and 5 = the batched
+ * step A (one launch over every member) in FP64 and FP32.  launches timed and
+ * their mean duration in ms; bytes is the algorithmic HBM traffic of those
+ * launches.  Step A moves 11 vectors of N elements per launch (s^, p^, v^,
+ * t^, eps, x and the shadow read; x, r^, p^, v^ written), 12 with a shift
+ * array sigma, and for PF1 10 vectors plus one flag byte per node; a batched
+ * launch counts the members still iterating.  Products: x, eps (and sigma)
+ * read, y written.  The mean is that of the event brackets, which also hold
+ * the dispatch and completion of the launch: it bounds the kernel's duration
+ * from above.  PF_ERR_ARG for another kind. */
 pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, double *bytes);
 
 /* ---------------- singular-charge decomposition (Sec. 3, Eqs. (5)-(10), (17)-(18)) */

@@ -19,8 +19,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -61,13 +63,15 @@ constexpr int PW_MAX_G = 1024;   // workgroups of the pointwise kernels
 int g_nt_override = 0, g_ppt_override = 0, g_kz_override = 0, g_depth_override = 0;
 
 // kernel timing (pf_timing_enable / pf_timing_read): slots 0, 1 = BiCGSTAB
-// step A in FP64 / FP32; 2, 3 = Jacobi-scaled products of pf_spmv / pf_spmv_f32
+// step A in FP64 / FP32; 2, 3 = Jacobi-scaled products of pf_spmv /
+// pf_spmv_f32; 4, 5 = batched step A in FP64 / FP32
+constexpr int TIMING_SLOTS = 6;
 struct Timing {
     bool enabled = false;
     int sample = 8;
     long chunk = 0;
-    long long launches[4] = {0, 0, 0, 0};
-    double ms[4] = {0, 0, 0, 0}, bytes[4] = {0, 0, 0, 0};
+    long long launches[TIMING_SLOTS] = {};
+    double ms[TIMING_SLOTS] = {}, bytes[TIMING_SLOTS] = {};
     hipEvent_t p0 = nullptr, p1 = nullptr;   // around product launches
 } g_timing;
 
@@ -131,6 +135,17 @@ ZCfg default_cfg(int nx, int ny, int nz, size_t elem)
 
 int pw_blocks(size_t N) { return (int)std::min<size_t>(PW_MAX_G, (N + NT - 1) / NT); }
 
+// Captured iteration chunks of a grid: chunk length, element size, kernel
+// form and the shift array the SIG form reads (grid-owned).
+struct GraphKey {
+    int m, elem, form;
+    const void *sig;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(m, elem, form, sig) < std::tie(o.m, o.elem, o.form, o.sig);
+    }
+};
+
 template <typename T>
 struct Work {
     T *x = nullptr, *r = nullptr, *rt = nullptr, *p[2] = {nullptr, nullptr},
@@ -150,7 +165,7 @@ struct pf_grid {
     double bcval[6] = {0, 0, 0, 0, 0, 0};
     std::vector<void *> allocs;
 
-    double *eps64 = nullptr;
+    double *eps64 = nullptr;           // coefficient field; sign bit set on Dirichlet rows (F_DIR_PHI)
     float *eps32 = nullptr;
     uint8_t *flags = nullptr;
     double *dval = nullptr;
@@ -163,8 +178,7 @@ struct pf_grid {
     int Gmax = 1;
 
     // linear solver state
-    double *dinv64 = nullptr, *dinv64_psi = nullptr;
-    float *dinv32 = nullptr, *dinv32_psi = nullptr;
+    float *sig32 = nullptr;            // FP32 copy of the shift of the current PF_MIXED solve
     double *b64 = nullptr;
     Work<double> w64;
     Work<float> w32;
@@ -173,7 +187,8 @@ struct pf_grid {
     double *partials = nullptr;                                // standalone reductions
     double *partA = nullptr, *partB = nullptr;   // BiCGSTAB steps A, B
     double *sink = nullptr;            // target of the stencil kernels' masked stores
-    std::map<long, hipGraphExec_t> graphs;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    double *sig64 = nullptr;           // copy of a caller's shift array for the solve (allocated on use)
     std::vector<hipEvent_t> tev;       // timing events (2 per iteration of a chunk)
     bool last_timed_first = false;   // the first chunk of the last batch ran timed
     int last_run[4] = {0, 0, 0, 0};    // iterations of the last Krylov run per (precision, system)
@@ -231,8 +246,6 @@ pf_status ensure_work(pf_grid *g)
     if constexpr (sizeof(T) == 8) {
         if (g->have64) return PF_OK;
         Work<double> &w = g->w64;
-        PFCHK(dalloc(g, &g->dinv64, g->N));
-        PFCHK(dalloc(g, &g->dinv64_psi, g->N));
         PFCHK(dalloc(g, &g->b64, g->N));
         for (double **p : {&w.x, &w.r, &w.rt, &w.p[0], &w.p[1], &w.v[0], &w.v[1], &w.s, &w.t})
             PFCHK(dalloc(g, p, g->N));
@@ -243,8 +256,7 @@ pf_status ensure_work(pf_grid *g)
         PFCHK(ensure_work<double>(g));
         Work<float> &w = g->w32;
         PFCHK(dalloc(g, &g->eps32, g->N));
-        PFCHK(dalloc(g, &g->dinv32, g->N));
-        PFCHK(dalloc(g, &g->dinv32_psi, g->N));
+        PFCHK(dalloc(g, &g->sig32, g->N));
         for (float **p : {&w.x, &w.r, &w.rt, &w.p[0], &w.p[1], &w.v[0], &w.v[1], &w.s, &w.t})
             PFCHK(dalloc(g, p, g->N));
         hipLaunchKernelGGL((pfk::k_convert<float>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream,
@@ -261,11 +273,11 @@ pf_status ensure_work(pf_grid *g)
 // e0, e1 (optional): events that the dispatch itself stamps at the kernel's
 // start and end (hipExtLaunchKernel), so their interval is the kernel's own
 // duration, without the marker packets of separate event records.
-template <int OP, typename T, bool CEPS, int NTZ, int PPT, bool WIDE = false, int DEPTH = 1>
+template <int OP, typename T, bool CEPS, bool SIG, int NTZ, int PPT, bool WIDE = false, int DEPTH = 1>
 hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEvent_t e0 = nullptr,
                      hipEvent_t e1 = nullptr)
 {
-    auto kern = pfk::k_zmarch<OP, T, CEPS, NTZ, PPT, WIDE, DEPTH>;
+    auto kern = pfk::k_zmarch<OP, T, CEPS, SIG, NTZ, PPT, WIDE, DEPTH>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;   // per instantiation
         if (c.lds > granted) {
@@ -280,12 +292,12 @@ hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEv
     return hipGetLastError();
 }
 
-template <int OP, typename T, bool CEPS>
+template <int OP, typename T, bool CEPS, bool SIG>
 hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEvent_t e0 = nullptr,
                     hipEvent_t e1 = nullptr)
 {
     if (c.wide) {
-        if (c.NTZ == 1024 && c.PPT == 1) return launch_zk<OP, T, CEPS, 1024, 1, true>(c, a, s, e0, e1);
+        if (c.NTZ == 1024 && c.PPT == 1) return launch_zk<OP, T, CEPS, SIG, 1024, 1, true>(c, a, s, e0, e1);
         return hipErrorInvalidValue;
     }
     // the BiCGSTAB steps and the Jacobi-scaled product come in both pipeline
@@ -293,30 +305,31 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEve
     constexpr bool PIPE = (OP == pfk::OP_BA || OP == pfk::OP_BB || OP == pfk::OP_SPMV_JAC);
     if (PIPE && c.depth == 2) {
         switch (c.NTZ * 10 + c.PPT) {
-        case 2561: return launch_zk<OP, T, CEPS, 256, 1, false, 2>(c, a, s, e0, e1);
-        case 2562: return launch_zk<OP, T, CEPS, 256, 2, false, 2>(c, a, s, e0, e1);
-        case 5121: return launch_zk<OP, T, CEPS, 512, 1, false, 2>(c, a, s, e0, e1);
-        case 5122: return launch_zk<OP, T, CEPS, 512, 2, false, 2>(c, a, s, e0, e1);
-        case 10241: return launch_zk<OP, T, CEPS, 1024, 1, false, 2>(c, a, s, e0, e1);
-        case 10242: return launch_zk<OP, T, CEPS, 1024, 2, false, 2>(c, a, s, e0, e1);
+        case 2561: return launch_zk<OP, T, CEPS, SIG, 256, 1, false, 2>(c, a, s, e0, e1);
+        case 2562: return launch_zk<OP, T, CEPS, SIG, 256, 2, false, 2>(c, a, s, e0, e1);
+        case 5121: return launch_zk<OP, T, CEPS, SIG, 512, 1, false, 2>(c, a, s, e0, e1);
+        case 5122: return launch_zk<OP, T, CEPS, SIG, 512, 2, false, 2>(c, a, s, e0, e1);
+        case 10241: return launch_zk<OP, T, CEPS, SIG, 1024, 1, false, 2>(c, a, s, e0, e1);
+        case 10242: return launch_zk<OP, T, CEPS, SIG, 1024, 2, false, 2>(c, a, s, e0, e1);
         default: return hipErrorInvalidValue;
         }
     }
     switch (c.NTZ * 10 + c.PPT) {
-    case 2561: return launch_zk<OP, T, CEPS, 256, 1>(c, a, s, e0, e1);
-    case 2562: return launch_zk<OP, T, CEPS, 256, 2>(c, a, s, e0, e1);
-    case 5121: return launch_zk<OP, T, CEPS, 512, 1>(c, a, s, e0, e1);
-    case 5122: return launch_zk<OP, T, CEPS, 512, 2>(c, a, s, e0, e1);
-    case 10241: return launch_zk<OP, T, CEPS, 1024, 1>(c, a, s, e0, e1);
-    case 10242: return launch_zk<OP, T, CEPS, 1024, 2>(c, a, s, e0, e1);
+    case 2561: return launch_zk<OP, T, CEPS, SIG, 256, 1>(c, a, s, e0, e1);
+    case 2562: return launch_zk<OP, T, CEPS, SIG, 256, 2>(c, a, s, e0, e1);
+    case 5121: return launch_zk<OP, T, CEPS, SIG, 512, 1>(c, a, s, e0, e1);
+    case 5122: return launch_zk<OP, T, CEPS, SIG, 512, 2>(c, a, s, e0, e1);
+    case 10241: return launch_zk<OP, T, CEPS, SIG, 1024, 1>(c, a, s, e0, e1);
+    case 10242: return launch_zk<OP, T, CEPS, SIG, 1024, 2>(c, a, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int OP, typename T, bool CEPS, int NTZ, int PPT, bool WIDE, int DEPTH>
-hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
+template <int OP, typename T, bool CEPS, bool SIG, int NTZ, int PPT, bool WIDE, int DEPTH>
+hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s,
+                          hipEvent_t e0, hipEvent_t e1)
 {
-    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, NTZ, PPT, WIDE, DEPTH>;
+    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, SIG, NTZ, PPT, WIDE, DEPTH>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;
         if (c.lds > granted) {
@@ -326,39 +339,57 @@ hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *s
             granted = c.lds;
         }
     }
-    hipLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), c.lds, s, args, start, n);
+    if (e0 || e1) hipExtLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), (std::uint32_t)c.lds, s, e0, e1, 0u, args, start, n);
+    else hipLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), c.lds, s, args, start, n);
     return hipGetLastError();
 }
 
 // c: the batch's combined launch (its NTZ, PPT, depth shared by every member;
 // G = all members' tiles, lds and wide = the maxima)
-template <int OP, typename T, bool CEPS>
-hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s)
+template <int OP, typename T, bool CEPS, bool SIG>
+hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     if (c.wide) {
-        if (c.NTZ == 1024 && c.PPT == 1) return launch_batch_k<OP, T, CEPS, 1024, 1, true, 1>(c, args, start, n, s);
+        if (c.NTZ == 1024 && c.PPT == 1)
+            return launch_batch_k<OP, T, CEPS, SIG, 1024, 1, true, 1>(c, args, start, n, s, e0, e1);
         return hipErrorInvalidValue;
     }
     if (c.depth == 2) {
         switch (c.NTZ * 10 + c.PPT) {
-        case 2561: return launch_batch_k<OP, T, CEPS, 256, 1, false, 2>(c, args, start, n, s);
-        case 2562: return launch_batch_k<OP, T, CEPS, 256, 2, false, 2>(c, args, start, n, s);
-        case 5121: return launch_batch_k<OP, T, CEPS, 512, 1, false, 2>(c, args, start, n, s);
-        case 5122: return launch_batch_k<OP, T, CEPS, 512, 2, false, 2>(c, args, start, n, s);
-        case 10241: return launch_batch_k<OP, T, CEPS, 1024, 1, false, 2>(c, args, start, n, s);
-        case 10242: return launch_batch_k<OP, T, CEPS, 1024, 2, false, 2>(c, args, start, n, s);
+        case 2561: return launch_batch_k<OP, T, CEPS, SIG, 256, 1, false, 2>(c, args, start, n, s, e0, e1);
+        case 2562: return launch_batch_k<OP, T, CEPS, SIG, 256, 2, false, 2>(c, args, start, n, s, e0, e1);
+        case 5121: return launch_batch_k<OP, T, CEPS, SIG, 512, 1, false, 2>(c, args, start, n, s, e0, e1);
+        case 5122: return launch_batch_k<OP, T, CEPS, SIG, 512, 2, false, 2>(c, args, start, n, s, e0, e1);
+        case 10241: return launch_batch_k<OP, T, CEPS, SIG, 1024, 1, false, 2>(c, args, start, n, s, e0, e1);
+        case 10242: return launch_batch_k<OP, T, CEPS, SIG, 1024, 2, false, 2>(c, args, start, n, s, e0, e1);
         default: return hipErrorInvalidValue;
         }
     }
     switch (c.NTZ * 10 + c.PPT) {
-    case 2561: return launch_batch_k<OP, T, CEPS, 256, 1, false, 1>(c, args, start, n, s);
-    case 2562: return launch_batch_k<OP, T, CEPS, 256, 2, false, 1>(c, args, start, n, s);
-    case 5121: return launch_batch_k<OP, T, CEPS, 512, 1, false, 1>(c, args, start, n, s);
-    case 5122: return launch_batch_k<OP, T, CEPS, 512, 2, false, 1>(c, args, start, n, s);
-    case 10241: return launch_batch_k<OP, T, CEPS, 1024, 1, false, 1>(c, args, start, n, s);
-    case 10242: return launch_batch_k<OP, T, CEPS, 1024, 2, false, 1>(c, args, start, n, s);
+    case 2561: return launch_batch_k<OP, T, CEPS, SIG, 256, 1, false, 1>(c, args, start, n, s, e0, e1);
+    case 2562: return launch_batch_k<OP, T, CEPS, SIG, 256, 2, false, 1>(c, args, start, n, s, e0, e1);
+    case 5121: return launch_batch_k<OP, T, CEPS, SIG, 512, 1, false, 1>(c, args, start, n, s, e0, e1);
+    case 5122: return launch_batch_k<OP, T, CEPS, SIG, 512, 2, false, 1>(c, args, start, n, s, e0, e1);
+    case 10241: return launch_batch_k<OP, T, CEPS, SIG, 1024, 1, false, 1>(c, args, start, n, s, e0, e1);
+    case 10242: return launch_batch_k<OP, T, CEPS, SIG, 1024, 2, false, 1>(c, args, start, n, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
+}
+
+// The three kernel forms of an operator: PF1 (constant coefficient), the
+// potential system with a shift array (sigma read at every own node), and
+// without one.  Only the BiCGSTAB steps have the shift-array form; the other
+// kernels read sigma at their outputs.
+enum { FORM_PLAIN = 0, FORM_SIG = 1, FORM_CEPS = 2 };
+
+template <int OP, typename T>
+hipError_t launch_batch_form(int form, const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n,
+                             hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+{
+    if (form == FORM_CEPS) return launch_batch<OP, T, true, false>(c, args, start, n, s, e0, e1);
+    if (form == FORM_SIG) return launch_batch<OP, T, false, true>(c, args, start, n, s, e0, e1);
+    return launch_batch<OP, T, false, false>(c, args, start, n, s, e0, e1);
 }
 
 template <typename T>
@@ -400,8 +431,22 @@ struct OpDesc {
 
 uint8_t dirbit(const OpDesc &op) { return op.psi ? pfk::F_DIR_PSI : pfk::F_DIR_PHI; }
 
+// Kernel form of the BiCGSTAB steps for this operator.
+int step_form(const OpDesc &op) { return op.psi ? FORM_CEPS : (op.sigma ? FORM_SIG : FORM_PLAIN); }
+
+// Vectors of N elements step A moves per launch: s^, p^, v^, t^, eps read at
+// every staged node, x and the shadow at own nodes, x, r^, p^, v^ written;
+// sigma as one more read in the SIG form; the PF1 form reads one flag byte
+// per node instead of eps.
+double step_a_bytes(const OpDesc &op, size_t N, size_t elem)
+{
+    const int form = step_form(op);
+    const double vec = form == FORM_CEPS ? 10.0 : (form == FORM_SIG ? 12.0 : 11.0);
+    return vec * (double)N * (double)elem + (form == FORM_CEPS ? (double)N : 0.0);
+}
+
 template <typename T>
-pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const T *dinv, const ZCfg &c)
+pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const ZCfg &c)
 {
     pfk::ZArgs<T> a{};
     a.nx = g->nx; a.ny = g->ny; a.nz = g->nz; a.P = g->nx * g->ny;
@@ -409,9 +454,17 @@ pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const T *dinv, const ZCfg 
     const double ih2 = 1.0 / (g->h * g->h);
     a.ih2 = (T)ih2;
     a.ceps = (T)(op.ceps * ih2);
-    if constexpr (sizeof(T) == 8) a.eps = g->eps64;
-    else a.eps = g->eps32;
-    a.dinv = dinv;
+    a.cdiag = (T)(6.0 * op.ceps * ih2 + op.sig_const);
+    a.cidiag = (T)(1.0 / (6.0 * op.ceps * ih2 + op.sig_const));
+    a.flags = g->flags;
+    a.dirbit = dirbit(op);
+    if constexpr (sizeof(T) == 8) {
+        a.eps = g->eps64;
+        a.sig = op.sigma;
+    } else {
+        a.eps = g->eps32;
+        a.sig = op.sigma ? g->sig32 : nullptr;   // converted by the mixed solve's set-up
+    }
     a.sigma = op.sigma;
     a.sig_const = op.sig_const;
     a.dval = g->dval;
@@ -422,18 +475,23 @@ pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const T *dinv, const ZCfg 
 }
 
 template <typename T>
-pfk::ZArgs<T> zbase(pf_grid *g, const OpDesc &op, const T *dinv)
+pfk::ZArgs<T> zbase(pf_grid *g, const OpDesc &op)
 {
-    return zbase_cfg<T>(g, op, dinv, cfg_of<T>(g));
+    return zbase_cfg<T>(g, op, cfg_of<T>(g));
 }
 
-// Launch with the shape c (the one a was built for).
+// Launch with the shape c (the one a was built for).  The BiCGSTAB steps
+// pick their kernel form from the operator; the other kernels have the plain
+// and the PF1 form.
 template <int OP, typename T>
 pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a, const ZCfg &c, hipEvent_t e0 = nullptr,
                   hipEvent_t e1 = nullptr)
 {
-    hipError_t e = op.psi ? launch_z<OP, T, true>(c, a, g->stream, e0, e1)
-                          : launch_z<OP, T, false>(c, a, g->stream, e0, e1);
+    constexpr bool STEP = (OP == pfk::OP_BA || OP == pfk::OP_BB);
+    hipError_t e;
+    if (op.psi) e = launch_z<OP, T, true, false>(c, a, g->stream, e0, e1);
+    else if (STEP && op.sigma) e = launch_z<OP, T, false, STEP>(c, a, g->stream, e0, e1);
+    else e = launch_z<OP, T, false, false>(c, a, g->stream, e0, e1);
     if (e != hipSuccess) return fail(PF_ERR_DEVICE, "stencil kernel launch failed: %s", hipGetErrorString(e));
     return PF_OK;
 }
@@ -447,37 +505,32 @@ pf_status finalize(pf_grid *g, int G, int slot = 0)
     return PF_OK;
 }
 
-template <typename T>
-pf_status compute_dinv(pf_grid *g, const OpDesc &op, T *dinv)
+// Set-up of an operator for FP32 kernels: the FP32 copy of its shift array.
+pf_status prepare_f32(pf_grid *g, const OpDesc &op)
 {
-    const double ih2 = 1.0 / (g->h * g->h);
-    if (op.psi)
-        hipLaunchKernelGGL((pfk::k_dinv<T, true>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->nx,
-                           g->ny, g->nz, ih2, op.ceps * ih2, (const double *)g->eps64, op.sigma,
-                           op.sig_const, (const uint8_t *)g->flags, dirbit(op), dinv);
-    else
-        hipLaunchKernelGGL((pfk::k_dinv<T, false>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->nx,
-                           g->ny, g->nz, ih2, op.ceps * ih2, (const double *)g->eps64, op.sigma,
-                           op.sig_const, (const uint8_t *)g->flags, dirbit(op), dinv);
+    if (!op.sigma) return PF_OK;
+    hipLaunchKernelGGL((pfk::k_convert<float>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, op.sigma,
+                       g->sig32);
     HIPCHK(hipGetLastError());
     return PF_OK;
 }
 
 // True FP64 residual r = b - A x (and ||r||^2 into sc->red[slot]); optional
-// shadow / FP32 copies.  lift: use the Dirichlet values as x (b_lift).
-pf_status residual64(pf_grid *g, const OpDesc &op, const double *dinv, const double *b,
-                     const double *x, double *r, bool lift, double *rt64, float *r32, float *rt32,
-                     int slot = 0)
+// shadow copies (r) and Krylov start vectors (s^ = D^-1 r), FP64 or FP32.
+// lift: use the Dirichlet values as x (b_lift).
+pf_status residual64(pf_grid *g, const OpDesc &op, const double *b, const double *x, double *r, bool lift,
+                     double *rt64, float *rt32, double *rs64, float *rs32, int slot = 0)
 {
-    pfk::ZArgs<double> a = zbase<double>(g, op, dinv);
+    pfk::ZArgs<double> a = zbase<double>(g, op);
     a.x = x;
     a.out = r;
     a.b = b;
     a.lift = lift ? 1 : 0;
     a.dval = op.psi ? nullptr : g->dval;
     a.rt64 = rt64;
-    a.r32 = r32;
     a.rt32 = rt32;
+    a.rs64 = rs64;
+    a.rs32 = rs32;
     if (lift && op.psi) {
         // PF1: Dirichlet value 0 everywhere, so b_lift = b on free rows
         a.lift = 0;
@@ -510,10 +563,9 @@ pf_status write_scalars(pf_grid *g)
 // the p/v ping-pong buffers: step A reads p[parity], v[parity] and writes
 // p[parity^1], v[parity^1].
 template <typename T>
-pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c,
-                     int Gb)
+pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, Work<T> &w, int parity, const ZCfg &c, int Gb)
 {
-    pfk::ZArgs<T> a = zbase_cfg<T>(g, op, dinv, c);
+    pfk::ZArgs<T> a = zbase_cfg<T>(g, op, c);
     a.x = w.s;
     a.y0 = w.p[parity];
     a.y1 = w.v[parity];
@@ -531,10 +583,9 @@ pfk::ZArgs<T> args_a(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
 }
 
 template <typename T>
-pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity, const ZCfg &c,
-                     int Ga)
+pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, Work<T> &w, int parity, const ZCfg &c, int Ga)
 {
-    pfk::ZArgs<T> b = zbase_cfg<T>(g, op, dinv, c);
+    pfk::ZArgs<T> b = zbase_cfg<T>(g, op, c);
     b.x = w.r;
     b.y0 = w.v[parity ^ 1];
     b.rt = w.rt;
@@ -550,19 +601,20 @@ pfk::ZArgs<T> args_b(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
 // One BiCGSTAB iteration: stencil step A (x, r of the previous iteration;
 // p, v), stencil step B (s, t).
 template <typename T>
-pf_status iteration(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int parity,
-                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+pf_status iteration(pf_grid *g, const OpDesc &op, Work<T> &w, int parity, hipEvent_t e0 = nullptr,
+                    hipEvent_t e1 = nullptr)
 {
     const ZCfg &ca = cfg_ref<T>(g), &cb = cfgb_ref<T>(g);
-    PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, dinv, w, parity, ca, cb.G), ca, e0, e1)));
-    PFCHK((zlaunch<pfk::OP_BB, T>(g, op, args_b<T>(g, op, dinv, w, parity, cb, ca.G), cb)));
+    PFCHK((zlaunch<pfk::OP_BA, T>(g, op, args_a<T>(g, op, w, parity, ca, cb.G), ca, e0, e1)));
+    PFCHK((zlaunch<pfk::OP_BB, T>(g, op, args_b<T>(g, op, w, parity, cb, ca.G), cb)));
     return PF_OK;
 }
 
-// Chunk of m iterations (m even) captured once per (precision, system) and
-// replayed.  The graph references only grid-owned buffers.
+// Chunk of m iterations (m even) captured once per (precision, operator
+// form, system) and replayed.  The graph references only grid-owned buffers
+// and the operator's shift array, which is part of the key.
 template <typename T>
-pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m, bool may_time = true)
+pf_status run_chunk(pf_grid *g, const OpDesc &op, Work<T> &w, int m, bool may_time = true)
 {
     const bool timed = may_time && g_timing.enabled && (g_timing.chunk++ % g_timing.sample) == 0;
     if (may_time) g->last_timed_first = timed;
@@ -575,16 +627,16 @@ pf_status run_chunk(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int
     }
     if (timed) {
         // sampled chunk: direct launches with HIP events around step A
-        for (int i = 0; i < m; ++i) PFCHK(iteration<T>(g, op, dinv, w, i & 1, g->tev[2 * i], g->tev[2 * i + 1]));
+        for (int i = 0; i < m; ++i) PFCHK(iteration<T>(g, op, w, i & 1, g->tev[2 * i], g->tev[2 * i + 1]));
         return PF_OK;
     }
-    const long key = (long)m * 16 + (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0);
+    const GraphKey key{m, (int)sizeof(T), step_form(op), op.sigma};
     auto it = g->graphs.find(key);
     if (it == g->graphs.end()) {
         hipGraph_t graph;
         HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
         pf_status st = PF_OK;
-        for (int i = 0; i < m && st == PF_OK; ++i) st = iteration<T>(g, op, dinv, w, i & 1);
+        for (int i = 0; i < m && st == PF_OK; ++i) st = iteration<T>(g, op, w, i & 1);
         hipError_t e = hipStreamEndCapture(g->stream, &graph);
         if (st != PF_OK) return st;
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -647,16 +699,12 @@ pf_status tune(pf_grid *g)
         if constexpr (sizeof(T) == 8) return g->w64;
         else return g->w32;
     }();
-    T *dinv = nullptr;
-    if constexpr (sizeof(T) == 8) dinv = g->dinv64;
-    else dinv = g->dinv32;
     PFCHK(fill<T>(g, w.r, T(1), g->N));
     PFCHK(fill<T>(g, w.s, T(1), g->N));
     PFCHK(fill<T>(g, w.t, T(0), g->N));
     PFCHK(fill<T>(g, w.rt, T(1), g->N));
     PFCHK(fill<T>(g, w.p[0], T(0), g->N));
     PFCHK(fill<T>(g, w.v[0], T(0), g->N));
-    PFCHK(fill<T>(g, dinv, T(0.1), g->N));
     Scalars &h = *g->hsc;
     h = Scalars{};
     h.rho[0] = h.rho[1] = 1.0; h.alpha[1] = 1.0; h.omega[1] = 1.0;
@@ -704,7 +752,7 @@ pf_status tune(pf_grid *g)
     ZCfg bestA = cfg_ref<T>(g), bestB = cfgb_ref<T>(g);
     float msA = 1e30f, msB = 1e30f;
     for (const ZCfg &c : cand) {
-        pfk::ZArgs<T> a = args_a<T>(g, op, dinv, w, 0, c, c.G);
+        pfk::ZArgs<T> a = args_a<T>(g, op, w, 0, c, c.G);
         a.xio = w.r;   // keep the caller's iterate: the timed launches update r in its place
         const float ms = time_step(OpA{}, a, c);
         if (st != PF_OK) break;
@@ -712,13 +760,13 @@ pf_status tune(pf_grid *g)
     }
     if (st == PF_OK) {
         // one step A with the chosen shape provides step B's input partials
-        pfk::ZArgs<T> a = args_a<T>(g, op, dinv, w, 0, bestA, bestA.G);
+        pfk::ZArgs<T> a = args_a<T>(g, op, w, 0, bestA, bestA.G);
         a.xio = w.r;
         st = write_scalars(g);
         if (st == PF_OK) st = zlaunch<pfk::OP_BA, T>(g, op, a, bestA);
         for (const ZCfg &c : cand) {
             if (st != PF_OK) break;
-            const pfk::ZArgs<T> b = args_b<T>(g, op, dinv, w, 0, c, bestA.G);
+            const pfk::ZArgs<T> b = args_b<T>(g, op, w, 0, c, bestA.G);
             const float ms = time_step(OpB{}, b, c);
             if (st != PF_OK) break;
             if (ms < msB) { msB = ms; bestB = c; }
@@ -742,14 +790,13 @@ pf_status tune(pf_grid *g)
 // Shapes of the standalone Jacobi-scaled product, per (grid shape, precision).
 std::map<std::tuple<int, int, int, int>, ZCfg> g_tuned_p;
 
-// Time the Jacobi-scaled product A M^-1 x over the candidate shapes on this
-// grid and keep the fastest.  Its four streams (x, 1/D, eps in; y out) favour
-// other shapes than the twelve of step A.  Timed launches cycle through four
+// Time the Jacobi-scaled product D^-1 A x over the candidate shapes on this
+// grid and keep the fastest.  Its three streams (x, eps in; y out) favour
+// other shapes than the eleven of step A.  Timed launches cycle through four
 // (x, y) pairs of the grid's workspace so that consecutive launches do not
-// find their vectors in the Infinity Cache.  dinv must hold the operator's
-// inverse diagonal (any finite values would do for timing).
+// find their vectors in the Infinity Cache.
 template <typename T>
-pf_status tune_product(pf_grid *g, const OpDesc &op, const T *dinv)
+pf_status tune_product(pf_grid *g, const OpDesc &op)
 {
     bool &done = sizeof(T) == 8 ? g->tunedp64 : g->tunedp32;
     if (done || !tuning_enabled()) return PF_OK;
@@ -774,7 +821,7 @@ pf_status tune_product(pf_grid *g, const OpDesc &op, const T *dinv)
     ZCfg best = cfgp_ref<T>(g);
     float best_ms = 1e30f;
     for (const ZCfg &c : tune_candidates<T>(g)) {
-        pfk::ZArgs<T> a = zbase_cfg<T>(g, op, dinv, c);
+        pfk::ZArgs<T> a = zbase_cfg<T>(g, op, c);
         a.x = xs[0];
         a.out = ys[0];
         if (zlaunch<pfk::OP_SPMV_JAC, T>(g, op, a, c) != PF_OK) {   // shape not launchable here
@@ -823,11 +870,12 @@ int chunk_len(const pf_grid *g, const pf_lin_opts *o)
     return m;
 }
 
-// Reset the Krylov state from a residual already in w.r / w.rt with
-// ||r||^2 = rr.  Keeps the cumulative iteration count.  Asynchronous: one
-// kernel zeroes p, v, t (and x when zero_x), copies r to s and writes the
-// scalar block, whose host copy is set to the same values.  The first step A
-// reads r from s (r = s - omega t with t = 0) and p = v = 0.
+// Reset the Krylov state from a residual already in w.s (s^ = D^-1 r) and
+// w.rt (the shadow r) with ||r||^2 = rr.  Keeps the cumulative iteration
+// count.  Asynchronous: one kernel zeroes p^, v^, t^ (and x when zero_x) and
+// writes the scalar block, whose host copy is set to the same values.  The
+// first step A reads r^ from s^ (r^ = s^ - omega t^ with t^ = 0) and
+// p^ = v^ = 0.
 template <typename T>
 pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter, int maxit, bool zero_x = false)
 {
@@ -846,7 +894,7 @@ pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter,
     h.stop_a = pfk::ST_RUN;
     h.fresh = 1;
     hipLaunchKernelGGL((pfk::k_krylov_start<T>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.p[0],
-                       w.v[0], w.t, w.s, (const T *)w.r, zero_x ? w.x : (T *)nullptr, h, g->sc);
+                       w.v[0], w.t, zero_x ? w.x : (T *)nullptr, h, g->sc);
     HIPCHK(hipGetLastError());
     return PF_OK;
 }
@@ -858,8 +906,7 @@ pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter,
 // read at the end.  Later chunks are short, so few iterations run past
 // convergence as no-ops.  A fixed check_every overrides this.
 template <typename T>
-pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, int m_fixed, int *status,
-                     bool adaptive)
+pf_status krylov_run(pf_grid *g, const OpDesc &op, Work<T> &w, int m_fixed, int *status, bool adaptive)
 {
     const int slot = (sizeof(T) == 8 ? 0 : 2) + (op.psi ? 1 : 0);
     const int start_iter = g->hsc->iter_done;
@@ -877,7 +924,7 @@ pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
         const int before = g->hsc->iter_done;
         // only the batch's first chunk may be the timed sample: its events are
         // read after the batch, and its iterations are the first ones run
-        for (int k = 0; k < np; ++k) PFCHK(run_chunk<T>(g, op, dinv, w, parts[k], k == 0));
+        for (int k = 0; k < np; ++k) PFCHK(run_chunk<T>(g, op, w, parts[k], k == 0));
         const bool timed = np > 0 && g->last_timed_first;
         PFCHK(read_scalars(g));
         if (timed && !op.psi) {
@@ -889,7 +936,7 @@ pf_status krylov_run(pf_grid *g, const OpDesc &op, const T *dinv, Work<T> &w, in
                 HIPCHK(hipEventElapsedTime(&ms, g->tev[2 * i], g->tev[2 * i + 1]));
                 g_timing.ms[pi] += ms;
                 g_timing.launches[pi] += 1;
-                g_timing.bytes[pi] += 12.0 * (double)g->N * sizeof(T);
+                g_timing.bytes[pi] += step_a_bytes(op, g->N, sizeof(T));
             }
         }
         if (g->hsc->stop != pfk::ST_RUN) {
@@ -929,8 +976,6 @@ struct LinSolve {
     OpDesc op;
     const pf_lin_opts *o = nullptr;
     bool mixed = false;
-    double *dinv64 = nullptr;
-    float *dinv32 = nullptr;
     double bnorm = 0, tol2 = 0, rr = 0, rinf = 0;   // rinf: true ||r||_inf (PF_STOP_ABS_INF)
     double rr_start = 0;                             // ||r||^2 when the last refinement step began
     int iter = 0, restarts = 0, refinements = 0;
@@ -944,9 +989,9 @@ pf_status ls_round_residual(LinSolve &L)
 {
     pf_grid *g = L.g;
     if (L.mixed)
-        PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, nullptr, g->w32.r, g->w32.rt));
+        PFCHK(residual64(g, L.op, g->b64, g->w64.x, g->w64.r, false, nullptr, g->w32.rt, nullptr, g->w32.s));
     else
-        PFCHK(residual64(g, L.op, L.dinv64, g->b64, g->w64.x, g->w64.r, false, g->w64.rt, nullptr, nullptr));
+        PFCHK(residual64(g, L.op, g->b64, g->w64.x, g->w64.r, false, g->w64.rt, nullptr, g->w64.s, nullptr));
     if (L.o->stop_rule == PF_STOP_ABS_INF) {   // ||r||_inf of the free rows into red[2]
         const int B = pw_blocks(g->N);
         hipLaunchKernelGGL(pfk::k_maxabs_free<NT>, dim3(B), dim3(NT), 0, g->stream, g->N, (const double *)g->w64.r,
@@ -972,16 +1017,18 @@ pf_status ls_init_launch(LinSolve &L)
                            (const uint8_t *)g->flags, dirbit(L.op), &g->sc->neg_shift);
         HIPCHK(hipGetLastError());
     }
-    L.dinv64 = L.op.psi ? g->dinv64_psi : g->dinv64;
-    PFCHK(compute_dinv<double>(g, L.op, L.dinv64));
-    if (L.mixed) {
-        L.dinv32 = L.op.psi ? g->dinv32_psi : g->dinv32;
-        PFCHK(compute_dinv<float>(g, L.op, L.dinv32));
+    if (L.op.sigma && L.op.sigma != g->sig) {
+        // the iteration's kernels (and their captured graphs) read a
+        // grid-owned copy of a caller's shift array
+        if (!g->sig64) PFCHK(dalloc(g, &g->sig64, g->N));
+        HIPCHK(hipMemcpyAsync(g->sig64, L.op.sigma, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
+        L.op.sigma = g->sig64;
     }
+    if (L.mixed) PFCHK(prepare_f32(g, L.op));
     hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
                        (const uint8_t *)g->flags, dirbit(L.op), L.op.psi ? nullptr : (const double *)g->dval);
     HIPCHK(hipGetLastError());
-    PFCHK(residual64(g, L.op, L.dinv64, g->b64, nullptr, g->w64.r, true, nullptr, nullptr, nullptr, 1));
+    PFCHK(residual64(g, L.op, g->b64, nullptr, g->w64.r, true, nullptr, nullptr, nullptr, nullptr, 1));
     PFCHK(ls_round_residual(L));
     HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
     return PF_OK;
@@ -1149,8 +1196,8 @@ pf_status solve_internal(pf_grid *g, const OpDesc &op, const pf_lin_opts *o, pf_
         if (!run) break;
         int st = 0;
         const bool adaptive = o->check_every == 0;
-        if (L.mixed) PFCHK(krylov_run<float>(g, op, L.dinv32, g->w32, m, &st, adaptive));
-        else PFCHK(krylov_run<double>(g, op, L.dinv64, g->w64, m, &st, adaptive));
+        if (L.mixed) PFCHK(krylov_run<float>(g, L.op, g->w32, m, &st, adaptive));
+        else PFCHK(krylov_run<double>(g, L.op, g->w64, m, &st, adaptive));
         PFCHK(ls_after(L, st));
     }
     return ls_finish(L, info);
@@ -1166,6 +1213,7 @@ struct BatchBuf {
     size_t bytes = 0;
     Scalars *hsc = nullptr;
     int hcap = 0;
+    std::vector<hipEvent_t> ev;   // kernel timing of sampled chunks
 } g_batch;
 
 // Launch of one batched BiCGSTAB step: every member shares the kernel
@@ -1229,9 +1277,13 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
 // shapes) by timing the first two chunks of its first run, one per policy.
 std::map<std::vector<long>, int> g_batch_policy;
 
-// One instantiated graph chunk of a batched Krylov run under one policy.
+// One instantiated graph chunk of a batched Krylov run under one policy, and
+// the launches it holds (for the sampled chunks of kernel timing, which run
+// as direct launches with events around step A).
 struct BatchPlan {
     hipGraphExec_t exec = nullptr;
+    std::function<pf_status(int, hipEvent_t, hipEvent_t)> launch_iter;
+    std::function<void()> gather;
     ~BatchPlan()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -1246,7 +1298,13 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
 {
     const int n = (int)act.size();
     const bool psi = act[0]->op.psi;
-    std::vector<long> key = {(long)sizeof(T), psi ? 1L : 0L};
+    // one kernel form for every member: the SIG form if any member has a
+    // shift array (members without one read zeros)
+    int form = psi ? FORM_CEPS : FORM_PLAIN;
+    if (!psi)
+        for (const LinSolve *L : act)
+            if (L->op.sigma) form = FORM_SIG;
+    std::vector<long> key = {(long)sizeof(T), (long)form};
     {
         std::vector<long> shapes;
         for (const LinSolve *L : act) shapes.push_back(((long)L->g->nx * 4096 + L->g->ny) * 4096 + L->g->nz);
@@ -1301,12 +1359,22 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
             LinSolve &L = *act[i];
             pf_grid *g = L.g;
             Work<T> *w;
-            const T *dinv;
-            if constexpr (sizeof(T) == 8) { w = &g->w64; dinv = L.dinv64; }
-            else { w = &g->w32; dinv = L.dinv32; }
+            if constexpr (sizeof(T) == 8) w = &g->w64;
+            else w = &g->w32;
+            const T *zero_sig = nullptr;
+            if (form == FORM_SIG && !L.op.sigma) {
+                if constexpr (sizeof(T) == 8) {
+                    if (!g->sig64) PFCHK(dalloc(g, &g->sig64, g->N));
+                    zero_sig = g->sig64;
+                } else {
+                    zero_sig = g->sig32;
+                }
+                PFCHK(fill<T>(g, const_cast<T *>(zero_sig), T(0), g->N));
+            }
             for (int par = 0; par < 2; ++par) {
-                za[par][i] = args_a<T>(g, L.op, dinv, *w, par, csa[i], csb[i].G);
-                zb[par][i] = args_b<T>(g, L.op, dinv, *w, par, csb[i], csa[i].G);
+                za[par][i] = args_a<T>(g, L.op, *w, par, csa[i], csb[i].G);
+                zb[par][i] = args_b<T>(g, L.op, *w, par, csb[i], csa[i].G);
+                if (zero_sig) za[par][i].sig = zb[par][i].sig = zero_sig;
             }
             astart[i + 1] = astart[i] + csa[i].G;
             bstart[i + 1] = bstart[i] + csb[i].G;
@@ -1323,21 +1391,21 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         HIPCHK(hipMemcpyAsync(dbs, bstart.data(), szI, hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));   // the host vectors above go out of scope
 
-        auto launch_iter = [&](int par) -> pf_status {
-            hipError_t e;
-            if (psi) e = launch_batch<pfk::OP_BA, T, true>(ca, dA[par], das, n, stream);
-            else e = launch_batch<pfk::OP_BA, T, false>(ca, dA[par], das, n, stream);
+        plans[k].launch_iter = [=](int par, hipEvent_t e0, hipEvent_t e1) -> pf_status {
+            hipError_t e = launch_batch_form<pfk::OP_BA, T>(form, ca, dA[par], das, n, stream, e0, e1);
             if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
-            if (psi) e = launch_batch<pfk::OP_BB, T, true>(cb, dB[par], dbs, n, stream);
-            else e = launch_batch<pfk::OP_BB, T, false>(cb, dB[par], dbs, n, stream);
+            e = launch_batch_form<pfk::OP_BB, T>(form, cb, dB[par], dbs, n, stream);
             if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
             return PF_OK;
+        };
+        plans[k].gather = [=]() {
+            hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
         };
         hipGraph_t graph;
         HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
         pf_status st = PF_OK;
-        for (int i = 0; i < m && st == PF_OK; ++i) st = launch_iter(i & 1);
-        hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
+        for (int i = 0; i < m && st == PF_OK; ++i) st = plans[k].launch_iter(i & 1, nullptr, nullptr);
+        plans[k].gather();
         hipError_t e = hipStreamEndCapture(stream, &graph);
         if (st != PF_OK) return st;
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
@@ -1352,12 +1420,50 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     status.assign(n, pfk::ST_RUN);
     double secs[2] = {0, 0};
     int use = 0;   // plan index of the next chunk
+    // kernel timing: iterations done per member before the chunk, step-A bytes per member
+    std::vector<int> before(n);
+    std::vector<double> abytes(n);
+    for (int i = 0; i < n; ++i) {
+        before[i] = act[i]->g->hsc->iter_done;
+        abytes[i] = step_a_bytes(act[i]->op, act[i]->g->N, sizeof(T));
+    }
+    const int tslot = sizeof(T) == 8 ? 4 : 5;
     for (int chunk = 0;; ++chunk) {
         const auto t0 = std::chrono::steady_clock::now();
-        hipError_t e = hipGraphLaunch(plans[use].exec, stream);
+        const bool timed = g_timing.enabled && (g_timing.chunk++ % g_timing.sample) == 0;
+        hipError_t e = hipSuccess;
+        if (timed) {
+            while ((int)g_batch.ev.size() < 2 * m) {
+                hipEvent_t ev;
+                HIPCHK(hipEventCreate(&ev));
+                g_batch.ev.push_back(ev);
+            }
+            for (int i = 0; i < m; ++i)
+                PFCHK(plans[use].launch_iter(i & 1, g_batch.ev[2 * i], g_batch.ev[2 * i + 1]));
+            plans[use].gather();
+            e = hipGetLastError();
+        } else {
+            e = hipGraphLaunch(plans[use].exec, stream);
+        }
         if (e == hipSuccess) e = hipMemcpyAsync(g_batch.hsc, dgather, szS, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched chunk failed: %s", hipGetErrorString(e));
+        if (timed) {
+            // launch j of the chunk did a member's whole step A while the
+            // member still iterated: j <= the iterations it completed here
+            for (int j = 0; j < m; ++j) {
+                double bytes = 0;
+                for (int i = 0; i < n; ++i)
+                    if (status[i] == pfk::ST_RUN && j <= g_batch.hsc[i].iter_done - before[i]) bytes += abytes[i];
+                if (bytes == 0) break;
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, g_batch.ev[2 * j], g_batch.ev[2 * j + 1]));
+                g_timing.ms[tslot] += ms;
+                g_timing.launches[tslot] += 1;
+                g_timing.bytes[tslot] += bytes;
+            }
+        }
+        for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
         bool any = false, all = true;
         for (int i = 0; i < n; ++i) {
             status[i] = g_batch.hsc[i].stop;
@@ -1430,7 +1536,7 @@ pf_status solve_batch(std::vector<LinSolve> &Ls)
 }
 
 // Account one timed product launch (events p0, p1 already complete):
-// bytes = x, eps, dinv read and y written.
+// bytes = x, eps (and sigma) read and y written.
 pf_status timing_add_product(int slot, double bytes)
 {
     float ms = 0;
@@ -1489,7 +1595,7 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample)
 
 pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, double *bytes)
 {
-    if (kind < 0 || kind > 3) return fail(PF_ERR_ARG, "kind must be 0..3");
+    if (kind < 0 || kind >= TIMING_SLOTS) return fail(PF_ERR_ARG, "kind must be 0..%d", TIMING_SLOTS - 1);
     const int i = kind;
     if (launches) *launches = g_timing.launches[i];
     if (mean_ms)
@@ -1589,6 +1695,9 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     hipLaunchKernelGGL(pfk::k_classify, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, d->nx, d->ny, d->nz,
                        d->node_type, d->fixed_value, bp, fv, bs, g->flags, g->dval);
     if (hipGetLastError() != hipSuccess) return cleanup(fail(PF_ERR_DEVICE, "classify launch failed"));
+    hipLaunchKernelGGL(pfk::k_mark_dirichlet, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, N,
+                       (const uint8_t *)g->flags, g->eps64);
+    if (hipGetLastError() != hipSuccess) return cleanup(fail(PF_ERR_DEVICE, "Dirichlet mark launch failed"));
     if ((st = sync(g)) != PF_OK) return cleanup(st);
     *out = g;
     return PF_OK;
@@ -1643,10 +1752,9 @@ pf_status pf_residual(pf_grid *g, const double *sigma, const double *b, const do
     PFCHK(ensure_work<double>(g));
     OpDesc op;
     op.sigma = sigma;
-    PFCHK(compute_dinv<double>(g, op, g->dinv64));
     double *rbuf = r ? r : g->w64.r;
-    PFCHK(residual64(g, op, g->dinv64, b, nullptr, rbuf, true, nullptr, nullptr, nullptr, 1));
-    PFCHK(residual64(g, op, g->dinv64, b, x, rbuf, false, nullptr, nullptr, nullptr, 0));
+    PFCHK(residual64(g, op, b, nullptr, rbuf, true, nullptr, nullptr, nullptr, nullptr, 1));
+    PFCHK(residual64(g, op, b, x, rbuf, false, nullptr, nullptr, nullptr, nullptr, 0));
     PFCHK(read_scalars(g));
     const double bn2 = g->hsc->red[1];
     const double rr = g->hsc->red[0];
@@ -1662,10 +1770,9 @@ pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, i
     PFCHK(ensure_work<double>(g));
     OpDesc op;
     op.sigma = sigma;
-    PFCHK(compute_dinv<double>(g, op, g->dinv64));
-    if (jacobi) PFCHK(tune_product<double>(g, op, g->dinv64));
+    if (jacobi) PFCHK(tune_product<double>(g, op));
     const ZCfg &c = jacobi ? cfgp_ref<double>(g) : cfg_of<double>(g);
-    pfk::ZArgs<double> a = zbase_cfg<double>(g, op, g->dinv64, c);
+    pfk::ZArgs<double> a = zbase_cfg<double>(g, op, c);
     a.x = x;
     a.out = y;
     const bool timed = jacobi && g_timing.enabled;
@@ -1673,7 +1780,7 @@ pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, i
     if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a, c, t0, t1)));
     else PFCHK((zlaunch<pfk::OP_SPMV, double>(g, op, a, c)));
     PFCHK(sync(g));
-    if (timed) PFCHK(timing_add_product(2, 4.0 * (double)g->N * sizeof(double)));
+    if (timed) PFCHK(timing_add_product(2, (sigma ? 4.0 : 3.0) * (double)g->N * sizeof(double)));
     return PF_OK;
 }
 
@@ -1686,17 +1793,16 @@ pf_status pf_spmv_f32(pf_grid *g, const double *sigma, const float *x, float *y,
     PFCHK(ensure_work<float>(g));
     OpDesc op;
     op.sigma = sigma;
-    PFCHK(compute_dinv<float>(g, op, g->dinv32));
-    PFCHK(tune_product<float>(g, op, g->dinv32));
+    PFCHK(tune_product<float>(g, op));
     const ZCfg &c = cfgp_ref<float>(g);
-    pfk::ZArgs<float> a = zbase_cfg<float>(g, op, g->dinv32, c);
+    pfk::ZArgs<float> a = zbase_cfg<float>(g, op, c);
     a.x = x;
     a.out = y;
     const bool timed = g_timing.enabled;
     PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a, c, timed ? g_timing.p0 : nullptr,
                                              timed ? g_timing.p1 : nullptr)));
     PFCHK(sync(g));
-    if (timed) PFCHK(timing_add_product(3, 4.0 * (double)g->N * sizeof(float)));
+    if (timed) PFCHK(timing_add_product(3, 3.0 * (double)g->N * sizeof(float) + (sigma ? 8.0 * (double)g->N : 0.0)));
     return PF_OK;
 }
 

@@ -344,13 +344,14 @@ __global__ void k_if_rhs(IfGrid g, size_t N, const uint16_t *mask, const unsigne
 
 // Every node of Omega_m must carry eps_m and every other node eps_s (the
 // harmonic-mean faces are then the SMIB matrix).  bad |= 1 on a mismatch.
+// eps is the grid's coefficient field, whose sign marks Dirichlet rows.
 __global__ void k_if_check(size_t N, const uint8_t *flags, const double *eps, double eps_m, double eps_s,
                            unsigned *bad)
 {
     unsigned b = 0;
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
          n += (size_t)gridDim.x * blockDim.x)
-        if (eps[n] != ((flags[n] & F_SOLUTE) ? eps_m : eps_s)) b = 1u;
+        if (fabs(eps[n]) != ((flags[n] & F_SOLUTE) ? eps_m : eps_s)) b = 1u;
     if (b) atomicOr(bad, b);
 }
 

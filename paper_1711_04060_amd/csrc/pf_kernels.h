@@ -5,13 +5,22 @@
 // evaluated matrix-free from the nodal coefficient field e (or a constant for
 // the PF1 operator), never stored as the seven diagonals of Sec. 4.
 //
-// Jacobi preconditioning (Sec. 4, Table 3, right-preconditioned) enters
-// through dinv: dinv_i = 1 / A_ii on free rows and -1 on Dirichlet rows (the
-// identity row's inverse diagonal is 1; the sign marks the row).  Since
-// A_ii * dinv_i = 1, (A M^-1 x)_i = x_i - sum_f c_f |dinv_j| x_j on free rows:
-// sigma appears only inside dinv, so the shifted PF2 operator costs no more
-// bytes per point than the Poisson one.
-//
+// Jacobi preconditioning (Sec. 4, Table 3, right-preconditioned with
+// M = diag(A) = D) is carried by the storage of the Krylov vectors: every
+// vector the stencil reads at a neighbour is kept scaled by D^-1 (p^ = D^-1 p,
+// v^, r^, s^, t^ likewise).  Table 3's updates are linear, so they keep their
+// form in the scaled vectors (p^ = r^ + beta (p^ - omega v^), s^ = r^ - alpha
+// v^, x += alpha p^ + omega s^, r^ = s^ - omega t^), and the products the
+// iteration needs become
+//   v^ = D^-1 A p^ = p^ - D^-1 sum_f c_f p^_j,
+// which use D only at the node itself.  D_i = sum_f c_f + sigma_i is formed
+// there from the coefficient field the stencil stages anyway, so no inverse
+// diagonal is stored or read.  The inner products use the unscaled values,
+// D times the stored one (v = D v^, r = D r^), and are the ones of Table 3.
+// Dirichlet rows (identity rows; every Krylov vector is 0 there) are marked
+// by the sign bit of the stored coefficient (e < 0), or by a flag byte for the
+// constant-coefficient PF1 operator, which reads no coefficient field.
+
 // Stencil kernels march along z.  A workgroup owns a strip of S consecutive
 // nodes of the flattened xy plane (m = i + nx*j) and a chunk of z planes.
 // For each plane it stages the strip plus one row of halo on each side
@@ -23,10 +32,10 @@
 //
 // BiCGSTAB (Table 3, right Jacobi preconditioning) runs as two fused stencil
 // kernels per iteration i:
-//   step A: finishes iteration i-1 (x += alpha M^-1 p + omega M^-1 s,
-//           r = s - omega t), forms p = r + beta (p - omega v) and
-//           v = A M^-1 p, and sums shadow . v and r . r;
-//   step B: s = r - alpha v, t = A M^-1 s, and sums t.s, t.t, s.s,
+//   step A: finishes iteration i-1 (x += alpha p^ + omega s^,
+//           r^ = s^ - omega t^), forms p^ = r^ + beta (p^ - omega v^) and
+//           v^ = D^-1 A p^, and sums shadow . v and r . r;
+//   step B: s^ = r^ - alpha v^, t^ = D^-1 A s^, and sums t.s, t.t, s.s,
 //           shadow . s and shadow . t.
 // beta needs rho_i = shadow . r_i before step A forms p; with r_i = s - omega t
 // it is shadow . s - omega shadow . t, known from step B's sums.
@@ -81,28 +90,32 @@ struct ZArgs {
     int S, KZ, nstrips, G;      // strip length, z planes per workgroup, strips, workgroups
     int lmax;                   // LDS elements per array (>= S + 2*nx)
     T ih2;                      // 1/h^2
-    T ceps;                     // constant face coefficient (already / h^2), CEPS form
-    const T *eps;               // nodal coefficient field (non-CEPS)
-    const T *dinv;              // inverse diagonal, -1 on Dirichlet rows
-    const T *x;                 // SPMV*/RESID operand; BA: s; BB: r
-    const T *y0;                // BA: p (previous); BB: v
-    const T *y1;                // BA: v (previous)
-    const T *y2;                // BA: t
-    const T *rt;                // BA, BB: shadow residual
+    T ceps;                     // CEPS form: constant face coefficient (already / h^2)
+    T cdiag, cidiag;            // CEPS form: constant diagonal 6 ceps + sigma and its inverse
+    const T *eps;               // coefficient field, sign bit set on Dirichlet rows (non-CEPS)
+    const uint8_t *flags;       // CEPS form: node flags, Dirichlet rows have bit dirbit
+    uint8_t dirbit;
+    const T *sig;               // SIG form (BA, BB): diagonal shift sigma
+    const T *x;                 // SPMV*/RESID operand; BA: s^; BB: r^
+    const T *y0;                // BA: p^ (previous); BB: v^
+    const T *y1;                // BA: v^ (previous)
+    const T *y2;                // BA: t^
+    const T *rt;                // BA, BB: shadow residual (unscaled)
     T *xio;                     // BA: iterate x (read and updated in place)
-    T *out;                     // SPMV*: y; RESID: r; BA: v (new); BB: t
-    T *out_aux;                 // BA: p (new); BB: s
-    T *out_r;                   // BA: r (new)
+    T *out;                     // SPMV*: y; RESID: r; BA: v^ (new); BB: t^
+    T *out_aux;                 // BA: p^ (new); BB: s^
+    T *out_r;                   // BA: r^ (new)
     T *sink;                    // SINK_ELEMS doubles: target of masked stores (BA, BB)
-    // residual extras (FP64 only)
-    const double *b;            // right-hand side
-    const double *sigma;        // diagonal shift or null
+    // product and residual extras (FP64 data)
+    const double *b;            // RESID: right-hand side
+    const double *sigma;        // SPMV*, RESID: diagonal shift or null
     double sig_const;           // used when sigma is null
-    const double *dval;         // Dirichlet values (lift form)
+    const double *dval;         // RESID lift form: Dirichlet values (0 on free rows) or null
     int lift;                   // RESID: use x = Dirichlet values on Dirichlet rows, 0 elsewhere
-    float *r32;                 // RESID: optional FP32 copy of r
-    double *rt64;               // RESID: optional shadow copy (FP64)
-    float *rt32;                // RESID: optional shadow copy (FP32)
+    double *rt64;               // RESID: optional shadow copy r (FP64)
+    float *rt32;                // RESID: optional shadow copy r (FP32)
+    double *rs64;               // RESID: optional Krylov start D^-1 r (FP64)
+    float *rs32;                // RESID: optional Krylov start D^-1 r (FP32)
     // reduction and scalars
     Scalars *sc;
     double *partials;           // [G][PSTRIDE] partials written by this kernel
@@ -367,19 +380,18 @@ __device__ __forceinline__ void fin_b_store(Scalars *sc, const FinB &f, int q)
 
 // --------------------------------------------------- z-marching stencil
 
-template <typename T>
-__device__ __forceinline__ T absT(T x) { return x < T(0) ? -x : x; }
+// |x| (a source modifier of the instruction that consumes it)
+__device__ __forceinline__ double absT(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float absT(float x) { return __builtin_fabsf(x); }
 
-// Per-node quantities of the staged plane for each operation:
-//   val: the value the stencil reads at neighbours;
-//   aux: the node's own unscaled value (BA: new p, BB: s, SPMV_JAC: x);
-//   d:   dinv at the node (row mask and Jacobi scale).
 // Loading (raw) and staging are split so that the loads of a plane can be
 // issued two march steps before their values are needed.  OWN loads add what
-// only the node's own outputs read (the shadow residual; BA: x).
+// only the node's own outputs read (the shadow residual; BA: x; the shift
+// sigma in the SIG form; the flag byte in the CEPS form).
 template <typename T>
 struct Raw {
-    T d, e, x0, x1, x2, x3, x4, t;
+    T e, x0, x1, x2, x3, x4, t, sg;
+    uint8_t f;
 };
 
 // Load of element g (g < 2^29 nodes, so the byte offset fits 32 bits): the
@@ -391,53 +403,48 @@ __device__ __forceinline__ U ldx(const U *base, unsigned g)
     return *reinterpret_cast<const U *>(reinterpret_cast<const char *>(base) + g * (unsigned)sizeof(U));
 }
 
-template <int OP, typename T, bool CEPS, bool OWN>
+template <int OP, typename T, bool CEPS, bool SIG, bool OWN>
 __device__ __forceinline__ void load_raw(const ZArgs<T> &a, unsigned g, Raw<T> &w)
 {
-    w.d = ldx(a.dinv, g);
     if constexpr (!CEPS) w.e = ldx(a.eps, g);
+    if constexpr (CEPS && OWN) w.f = a.flags[g];
+    if constexpr (SIG && OWN) w.sg = ldx(a.sig, g);
     if constexpr (OP == OP_SPMV || OP == OP_SPMV_JAC) {
         w.x0 = ldx(a.x, g);
     } else if constexpr (OP == OP_RESID) {
         if (a.lift) w.x0 = a.dval ? (T)ldx(a.dval, g) : T(0);
         else w.x0 = ldx(a.x, g);
     } else if constexpr (OP == OP_BA) {
-        w.x0 = ldx(a.x, g);    // s
-        w.x1 = ldx(a.y0, g);   // p (previous)
-        w.x2 = ldx(a.y1, g);   // v (previous)
-        w.x3 = ldx(a.y2, g);   // t
+        w.x0 = ldx(a.x, g);    // s^
+        w.x1 = ldx(a.y0, g);   // p^ (previous)
+        w.x2 = ldx(a.y1, g);   // v^ (previous)
+        w.x3 = ldx(a.y2, g);   // t^
         if constexpr (OWN) {
             w.x4 = ldx((const T *)a.xio, g);
             w.t = ldx(a.rt, g);
         }
     } else {
-        w.x0 = ldx(a.x, g);    // r
-        w.x1 = ldx(a.y0, g);   // v
+        w.x0 = ldx(a.x, g);    // r^
+        w.x1 = ldx(a.y0, g);   // v^
         if constexpr (OWN) w.t = ldx(a.rt, g);
     }
 }
 
+// The value the stencil reads at a staged node (also the node's own stored
+// output where the step has one).
 template <int OP, typename T>
-__device__ __forceinline__ void stage_raw(const Raw<T> &w, T &val, T &aux, double alpha, double omega,
-                                          double beta)
+__device__ __forceinline__ T stage_raw(const Raw<T> &w, double alpha, double omega, double beta)
 {
-    const T d = w.d;
-    if constexpr (OP == OP_SPMV || OP == OP_RESID) {
-        val = w.x0;
-        aux = val;
-    } else if constexpr (OP == OP_SPMV_JAC) {
-        aux = w.x0;
-        val = absT(d) * aux;
-    } else if constexpr (OP == OP_BA) {
-        // r = s - omega t (Table 3 step 17 of the previous iteration), then
-        // p = r + beta (p - omega v)   (step 9)
+    if constexpr (OP == OP_BA) {
+        // r^ = s^ - omega t^ (Table 3 step 17 of the previous iteration), then
+        // p^ = r^ + beta (p^ - omega v^)   (step 9)
         const T r = w.x0 - (T)omega * w.x3;
-        aux = r + (T)beta * (w.x1 - (T)omega * w.x2);
-        val = absT(d) * aux;
-    } else {  // OP_BB
-        // s = r - alpha v   (Table 3 step 13)
-        aux = w.x0 - (T)alpha * w.x1;
-        val = absT(d) * aux;
+        return r + (T)beta * (w.x1 - (T)omega * w.x2);
+    } else if constexpr (OP == OP_BB) {
+        // s^ = r^ - alpha v^   (Table 3 step 13)
+        return w.x0 - (T)alpha * w.x1;
+    } else {
+        return w.x0;
     }
 }
 
@@ -474,24 +481,14 @@ __device__ __forceinline__ void sink_store(T *slot)
     *reinterpret_cast<T *>(reinterpret_cast<char *>(slot) + d) = T(0);
 }
 
-// Step A's own-node update of the previous iteration (Table 3 steps 16, 17):
-// x += alpha M^-1 p + omega M^-1 s, r = s - omega t.
+// Step A's own-node update of the previous iteration (Table 3 steps 16, 17)
+// in the scaled vectors: x += alpha p^ + omega s^, r^ = s^ - omega t^.
 template <typename T>
 __device__ __forceinline__ void stage_xr(const Raw<T> &w, T &xn, T &rn, double alpha, double omega)
 {
-    const T d = absT(w.d);
     rn = w.x0 - (T)omega * w.x3;
-    xn = w.x4 + (T)alpha * (d * w.x1) + (T)omega * (d * w.x0);
+    xn = w.x4 + (T)alpha * w.x1 + (T)omega * w.x0;
 }
-
-// The residual form stages Dirichlet rows of the lifted operand as zero.
-template <int OP, typename T>
-__device__ __forceinline__ T resid_val(const ZArgs<T> &a, const Raw<T> &w, T val)
-{
-    if constexpr (OP == OP_RESID) return (a.lift && !(w.d < T(0))) ? T(0) : val;
-    else return val;
-}
-
 
 // A staged value materialised in a register of its own at this point of the
 // step.  Without it the compiler keeps a staged value in the register its
@@ -508,6 +505,12 @@ __device__ __forceinline__ T own_reg(T x)
     else asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
     return y;
 }
+__device__ __forceinline__ uint8_t own_reg(uint8_t x)
+{
+    unsigned y;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"((unsigned)x));
+    return (uint8_t)y;
+}
 
 // One workgroup's tile: logical tile index lb (strip, z-chunk) and partial
 // slot `slot` of the system described by a.
@@ -519,9 +522,11 @@ __device__ __forceinline__ T own_reg(T x)
 // issued unconditionally with its plane clamped into the tile's range and
 // its node clamped into the strip, so the number of loads per step is fixed
 // and the wait before staging a plane covers only that plane's loads.
-template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, bool SIG, int NT, int PPT, bool WIDE, int DEPTH>
 __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, const int slot)
 {
+    static_assert(!SIG || OP == OP_BA || OP == OP_BB, "the SIG form is a BiCGSTAB step form");
+    static_assert(!(SIG && CEPS), "the CEPS form has a constant shift");
     // halo nodes per thread kept in registers (both halo rows fit when
     // 2 nx <= HMAX*NT); the WIDE form stages the rest in a slower
     // synchronous loop, for planes wider than that
@@ -592,11 +597,11 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     Raw<T> rA[PPT], hA[HMAX], rB[PPT], hB[HMAX];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        load_raw<OP, T, CEPS, true>(a, gown(q, k0), rc[q]);
-        load_raw<OP, T, CEPS, false>(a, gown(q, max(k0 - 1, 0)), rp[q]);
+        load_raw<OP, T, CEPS, SIG, true>(a, gown(q, k0), rc[q]);
+        load_raw<OP, T, CEPS, SIG, false>(a, gown(q, max(k0 - 1, 0)), rp[q]);
     }
 #pragma unroll
-    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k0), hc[u]);
+    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, false>(a, ghal(u, k0), hc[u]);
     // The sets go out in the order of the march steps (own, halo, then as
     // many stores as a step makes, here to the sink), so that at the loop's
     // first wait the loads of each set are as far from the newest event as in
@@ -606,17 +611,17 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     constexpr int NST = PPT * ((OP == OP_BA) ? 4 : (OP == OP_BB) ? 2 : (OP == OP_SPMV_JAC) ? 1 : 0);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, true>(a, gown(q, k0 + 1), rA[q]);
+    for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, true>(a, gown(q, k0 + 1), rA[q]);
 #pragma unroll
-    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k0 + 1), hA[u]);
+    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, false>(a, ghal(u, k0 + 1), hA[u]);
 #pragma unroll
     for (int j = 0; j < NST; ++j) sink_store(a.sink + threadIdx.x);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (DEPTH == 2) {
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, true>(a, gown(q, k0 + 2), rB[q]);
+        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, true>(a, gown(q, k0 + 2), rB[q]);
 #pragma unroll
-        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k0 + 2), hB[u]);
+        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, false>(a, ghal(u, k0 + 2), hB[u]);
 #pragma unroll
         for (int j = 0; j < NST; ++j) sink_store(a.sink + threadIdx.x);
         __builtin_amdgcn_sched_barrier(0);
@@ -627,9 +632,9 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     // this iteration in BB
     double alpha = 0, omega = 0, beta = 0;
     if constexpr (OP == OP_BA) {
-        // finish step B of the previous iteration (a fresh start has r in s,
-        // t = 0, p = v = 0: with alpha = omega = beta = 0 the update keeps x
-        // and sets p = r)
+        // finish step B of the previous iteration (a fresh start has r^ in s^,
+        // t^ = 0, p^ = v^ = 0: with alpha = omega = beta = 0 the update keeps x
+        // and sets p^ = r^)
         if (!fresh) {
             double tot[5];
             sum_loaded_partials<5>(tot, pl, a.pin, a.Gin);
@@ -675,10 +680,11 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     T *leps1 = lval1 + a.lmax;
 
     T vp[PPT], vc[PPT], vn[PPT];   // staged value, planes k-1, k, k+1
-    T ep[PPT], ec[PPT], en[PPT];   // coefficient field
-    T ac[PPT], an[PPT];            // aux, planes k, k+1
-    T dc[PPT], dn[PPT];            // dinv, planes k, k+1
+    T ep[PPT], ec[PPT], en[PPT];   // coefficient field (signed), planes k-1, k, k+1
     T tc[PPT], tn[PPT];            // shadow residual (BA, BB), planes k, k+1
+    T rc_[PPT], rn_[PPT];          // BA: r^ of planes k, k+1
+    T sc_[PPT], sn_[PPT];          // SIG: sigma of planes k, k+1
+    uint8_t fc[PPT], fn[PPT];      // CEPS: flag bytes of planes k, k+1
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
@@ -686,26 +692,27 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     // ---- stage plane k0 (registers + LDS buffer 0) and plane k0-1 (registers)
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        stage_raw<OP, T>(rc[q], vc[q], ac[q], alpha, omega, beta);
-        vc[q] = resid_val<OP, T>(a, rc[q], vc[q]);
-        dc[q] = rc[q].d;
+        vc[q] = stage_raw<OP, T>(rc[q], alpha, omega, beta);
         ec[q] = CEPS ? T(0) : rc[q].e;
         tc[q] = SCAL ? rc[q].t : T(0);
-        T ax;
-        stage_raw<OP, T>(rp[q], vp[q], ax, alpha, omega, beta);
-        vp[q] = resid_val<OP, T>(a, rp[q], vp[q]);
+        sc_[q] = SIG ? rc[q].sg : T(0);
+        fc[q] = CEPS ? rc[q].f : (uint8_t)0;
+        vp[q] = stage_raw<OP, T>(rp[q], alpha, omega, beta);
         ep[q] = CEPS ? T(0) : rp[q].e;
-        vn[q] = en[q] = an[q] = dn[q] = tn[q] = T(0);
-        if (ok[q]) {
-            const unsigned g0 = gown(q, k0);
-            if constexpr (SCAL) a.out_aux[g0] = ac[q];
-            if constexpr (OP == OP_BA) {
-                T xn, rn;
-                stage_xr<T>(rc[q], xn, rn, alpha, omega);
+        vn[q] = en[q] = tn[q] = rn_[q] = sn_[q] = T(0);
+        fn[q] = 0;
+        rc_[q] = T(0);
+        if constexpr (OP == OP_BA) {
+            T xn;
+            stage_xr<T>(rc[q], xn, rc_[q], alpha, omega);
+            if (ok[q]) {
+                const unsigned g0 = gown(q, k0);
                 a.xio[g0] = xn;
-                a.out_r[g0] = rn;
-                acc[1] += (double)rn * (double)rn;
+                a.out_r[g0] = rc_[q];
             }
+        }
+        if (ok[q]) {
+            if constexpr (SCAL) a.out_aux[gown(q, k0)] = vc[q];
             lval0[ox[q]] = vc[q];
             if constexpr (!CEPS) leps0[ox[q]] = ec[q];
         }
@@ -713,9 +720,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
     for (int u = 0; u < HMAX; ++u) {
         if (hok[u]) {
-            T v, ax;
-            stage_raw<OP, T>(hc[u], v, ax, alpha, omega, beta);
-            lval0[hm[u] - lo] = resid_val<OP, T>(a, hc[u], v);
+            lval0[hm[u] - lo] = stage_raw<OP, T>(hc[u], alpha, omega, beta);
             if constexpr (!CEPS) leps0[hm[u] - lo] = hc[u].e;
         }
     }
@@ -723,10 +728,8 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
             const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
             Raw<T> w;
-            load_raw<OP, T, CEPS, false>(a, (unsigned)m + Pu * (unsigned)k0, w);
-            T v, ax;
-            stage_raw<OP, T>(w, v, ax, alpha, omega, beta);
-            lval0[m - lo] = resid_val<OP, T>(a, w, v);
+            load_raw<OP, T, CEPS, false, false>(a, (unsigned)m + Pu * (unsigned)k0, w);
+            lval0[m - lo] = stage_raw<OP, T>(w, alpha, omega, beta);
             if constexpr (!CEPS) leps0[m - lo] = w.e;
         }
     }
@@ -743,26 +746,23 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         const bool has_up = (k + 1) < nz;
         const bool stage_next = (k + 1) < k1;
         // (1) stage plane k+1 from the raw loads issued DEPTH steps ago
-        T xn[PPT], rn[PPT];   // BA: updated x, r of plane k+1
+        T xn[PPT];   // BA: updated x of plane k+1
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-            stage_raw<OP, T>(ro[q], vn[q], an[q], alpha, omega, beta);
-            vn[q] = own_reg(resid_val<OP, T>(a, ro[q], vn[q]));
-            an[q] = own_reg(an[q]);
-            dn[q] = own_reg(ro[q].d);
+            vn[q] = own_reg(stage_raw<OP, T>(ro[q], alpha, omega, beta));
             if constexpr (!CEPS) en[q] = own_reg(ro[q].e);
+            if constexpr (CEPS) fn[q] = own_reg(ro[q].f);
+            if constexpr (SIG) sn_[q] = own_reg(ro[q].sg);
             if constexpr (SCAL) tn[q] = own_reg(ro[q].t);
             if constexpr (OP == OP_BA) {
-                stage_xr<T>(ro[q], xn[q], rn[q], alpha, omega);
+                stage_xr<T>(ro[q], xn[q], rn_[q], alpha, omega);
                 xn[q] = own_reg(xn[q]);
-                rn[q] = own_reg(rn[q]);
+                rn_[q] = own_reg(rn_[q]);
             }
         }
 #pragma unroll
         for (int u = 0; u < HMAX; ++u) {
-            T ax;
-            stage_raw<OP, T>(rh[u], hv[u], ax, alpha, omega, beta);
-            hv[u] = own_reg(resid_val<OP, T>(a, rh[u], hv[u]));
+            hv[u] = own_reg(stage_raw<OP, T>(rh[u], alpha, omega, beta));
             if constexpr (!CEPS) he[u] = own_reg(rh[u].e);
         }
         // (2) refill the set with plane k+1+DEPTH (clamped: re-reads of a plane
@@ -771,9 +771,9 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         //     above, so the loads can reuse its registers.
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, true>(a, gown(q, k + 1 + DEPTH), ro[q]);
+        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, true>(a, gown(q, k + 1 + DEPTH), ro[q]);
 #pragma unroll
-        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, false>(a, ghal(u, k + 1 + DEPTH), rh[u]);
+        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, false>(a, ghal(u, k + 1 + DEPTH), rh[u]);
         if constexpr (SCAL) {
             // own outputs of plane k+1 when the tile owns it (else the sink)
 #pragma unroll
@@ -781,24 +781,21 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                 const bool keep = stage_next && ok[q];
                 const unsigned g1 = gown(q, k + 1);
                 T *sk = a.sink + threadIdx.x + q * NT;
-                *pick(keep, a.out_aux + g1, sk) = an[q];
+                *pick(keep, a.out_aux + g1, sk) = vn[q];
                 if constexpr (OP == OP_BA) {
                     *pick(keep, a.xio + g1, sk) = xn[q];
-                    *pick(keep, a.out_r + g1, sk) = rn[q];
-                    const double r2 = (double)rn[q] * (double)rn[q];
-                    acc[1] += keep ? r2 : 0.0;
+                    *pick(keep, a.out_r + g1, sk) = rn_[q];
                 }
             }
         }
         // mirror ghosts across the z faces, written into the register planes
         // (uniform branches, static indices)
-        if (!has_up) {
+        T vu[PPT], eu[PPT];
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) { vn[q] = vp[q]; en[q] = ep[q]; }
-        }
+        for (int q = 0; q < PPT; ++q) { vu[q] = has_up ? vn[q] : vp[q]; eu[q] = has_up ? en[q] : ep[q]; }
         if (k == 0) {
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) { vp[q] = vn[q]; ep[q] = en[q]; }
+            for (int q = 0; q < PPT; ++q) { vp[q] = vu[q]; ep[q] = eu[q]; }
         }
         // (3) output for plane k (live: uniform)
         const T *lv = cur ? lval1 : lval0;
@@ -806,57 +803,70 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             const size_t g = (size_t)om[q] + Ps * k;
-            const T vu = vn[q];
-            const T vd = vp[q];
-            T sum, csum = T(0);
+            T sum, D;
+            bool dir;
             if constexpr (CEPS) {
                 const T c = a.ceps;
-                sum = c * (lv[oxm[q]] + lv[oxp[q]] + lv[oym[q]] + lv[oyp[q]] + vu + vd);
-                csum = T(6) * c;
+                sum = c * (lv[oxm[q]] + lv[oxp[q]] + lv[oym[q]] + lv[oyp[q]] + vu[q] + vp[q]);
+                D = a.cdiag;
+                dir = (fc[q] & a.dirbit) != 0;
             } else {
-                const T e = ec[q];
-                const T c0 = face(e, le[oxm[q]], ih2), c1 = face(e, le[oxp[q]], ih2);
-                const T c2 = face(e, le[oym[q]], ih2), c3 = face(e, le[oyp[q]], ih2);
-                const T c4 = face(e, ep[q], ih2), c5 = face(e, en[q], ih2);
-                sum = c0 * lv[oxm[q]] + c1 * lv[oxp[q]] + c2 * lv[oym[q]] + c3 * lv[oyp[q]] +
-                      c4 * vd + c5 * vu;
-                csum = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
+                const T e = absT(ec[q]);
+                const T c0 = face(e, absT(le[oxm[q]]), ih2), c1 = face(e, absT(le[oxp[q]]), ih2);
+                const T c2 = face(e, absT(le[oym[q]]), ih2), c3 = face(e, absT(le[oyp[q]]), ih2);
+                const T c4 = face(e, absT(ep[q]), ih2), c5 = face(e, absT(eu[q]), ih2);
+                sum = c0 * lv[oxm[q]] + c1 * lv[oxp[q]] + c2 * lv[oym[q]] + c3 * lv[oyp[q]] + c4 * vp[q] +
+                      c5 * vu[q];
+                D = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
+                if constexpr (SIG) D += sc_[q];
+                dir = ec[q] < T(0);
             }
-            const bool freerow = dc[q] > T(0);
             if constexpr (OP == OP_SPMV) {
                 if (live && ok[q]) {
-                    const double sg = a.sigma ? a.sigma[g] : a.sig_const;
-                    const T D = csum + (T)sg;
-                    a.out[g] = freerow ? D * vc[q] - sum : vc[q];
+                    const T Dt = CEPS ? D : D + (T)(a.sigma ? a.sigma[g] : a.sig_const);
+                    a.out[g] = dir ? vc[q] : Dt * vc[q] - sum;
                 }
             } else if constexpr (OP == OP_SPMV_JAC) {
-                *pick(live && ok[q], a.out + g, a.sink + threadIdx.x + q * NT) = freerow ? ac[q] - sum : ac[q];
+                // y = D^-1 A x (the scaled product of the iteration)
+                T y = vc[q];
+                if (!CEPS && a.sigma && live) D += (T)a.sigma[g];
+                if (!dir) y = vc[q] - sum * (CEPS ? a.cidiag : rcp_pos(D));
+                *pick(live && ok[q], a.out + g, a.sink + threadIdx.x + q * NT) = y;
             } else if constexpr (OP == OP_RESID) {
                 if (live && ok[q]) {
-                    const double sg = a.sigma ? a.sigma[g] : a.sig_const;
-                    const double D = (double)csum + sg;
-                    const double Ax = D * (double)vc[q] - (double)sum;
-                    const double r = freerow ? a.b[g] - Ax : 0.0;
+                    const double Dd = CEPS ? (double)D : (double)D + (a.sigma ? a.sigma[g] : a.sig_const);
+                    const double Ax = Dd * (double)vc[q] - (double)sum;
+                    const double r = dir ? 0.0 : a.b[g] - Ax;
                     a.out[g] = (T)r;
-                    if (a.r32) a.r32[g] = (float)r;
                     if (a.rt64) a.rt64[g] = r;
                     if (a.rt32) a.rt32[g] = (float)r;
+                    if (a.rs64 || a.rs32) {
+                        const double rs = r * rcp_pos(Dd);
+                        if (a.rs64) a.rs64[g] = rs;
+                        if (a.rs32) a.rs32[g] = (float)rs;
+                    }
                     acc[0] += r * r;
                 }
             } else if constexpr (OP == OP_BA) {
-                // v = A M^-1 p  (Table 3 step 11), then shadow . v (step 12)
-                const T v = freerow ? ac[q] - sum : T(0);
+                // v = A p^ (Table 3 step 11, with the scaled p), stored as
+                // v^ = D^-1 v; shadow . v (step 12) and ||r||^2 of the
+                // previous iteration's r = D r^
+                const T iD = CEPS ? a.cidiag : rcp_pos(D);
+                const T v = dir ? T(0) : D * vc[q] - sum;
                 const bool keep = live && ok[q];
-                *pick(keep, a.out + g, a.sink + threadIdx.x + q * NT) = v;
-                const double rv = (double)tc[q] * (double)v;
-                acc[0] += keep ? rv : 0.0;
+                *pick(keep, a.out + g, a.sink + threadIdx.x + q * NT) = v * iD;
+                const double r = dir ? 0.0 : (double)D * (double)rc_[q];
+                acc[0] += keep ? (double)tc[q] * (double)v : 0.0;
+                acc[1] += keep ? r * r : 0.0;
             } else {
-                // t = A M^-1 s  (step 14); t.s, t.t (step 15), s.s (half-step
-                // test), shadow . s and shadow . t (rho of the next iteration)
-                const T t = freerow ? ac[q] - sum : T(0);
-                const double s = (double)ac[q];
+                // t = A s^ (step 14), stored as t^ = D^-1 t; t.s, t.t
+                // (step 15), s.s (half-step test), shadow . s and shadow . t
+                // (rho of the next iteration), with s = D s^
+                const T iD = CEPS ? a.cidiag : rcp_pos(D);
+                const T t = dir ? T(0) : D * vc[q] - sum;
+                const double s = dir ? 0.0 : (double)D * (double)vc[q];
                 const bool keep = live && ok[q];
-                *pick(keep, a.out + g, a.sink + threadIdx.x + q * NT) = t;
+                *pick(keep, a.out + g, a.sink + threadIdx.x + q * NT) = t * iD;
                 const double m = keep ? 1.0 : 0.0;
                 acc[0] += m * ((double)t * s);
                 acc[1] += m * ((double)t * (double)t);
@@ -888,10 +898,8 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
                 const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
                 Raw<T> w;
-                load_raw<OP, T, CEPS, false>(a, (unsigned)m + Pu * (unsigned)(k + 1), w);
-                T v, ax;
-                stage_raw<OP, T>(w, v, ax, alpha, omega, beta);
-                nv[m - lo] = resid_val<OP, T>(a, w, v);
+                load_raw<OP, T, CEPS, false, false>(a, (unsigned)m + Pu * (unsigned)(k + 1), w);
+                nv[m - lo] = stage_raw<OP, T>(w, alpha, omega, beta);
                 if constexpr (!CEPS) ne[m - lo] = w.e;
             }
         }
@@ -904,7 +912,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         for (int q = 0; q < PPT; ++q) {
             vp[q] = vc[q]; vc[q] = vn[q];
             ep[q] = ec[q]; ec[q] = en[q];
-            ac[q] = an[q]; dc[q] = dn[q]; tc[q] = tn[q];
+            tc[q] = tn[q]; rc_[q] = rn_[q]; sc_[q] = sn_[q]; fc[q] = fn[q];
         }
     };
     if constexpr (DEPTH == 2) {
@@ -922,10 +930,10 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     }
 }
 
-template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, bool SIG, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
 {
-    zmarch_tile<OP, T, CEPS, NT, PPT, WIDE, DEPTH>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
+    zmarch_tile<OP, T, CEPS, SIG, NT, PPT, WIDE, DEPTH>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
 }
 
 // System owning global block b: start[s] <= b < start[s+1].
@@ -941,14 +949,14 @@ __device__ __forceinline__ int batch_system(const int *start, int nsys, int b)
 
 // Batched form: one launch covers the tiles of nsys systems (grids of any
 // size); each system keeps its own scalars, partials and status.
-template <int OP, typename T, bool CEPS, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, bool SIG, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch_batch(const ZArgs<T> *__restrict__ args,
                                                      const int *__restrict__ start, int nsys)
 {
     const int s = batch_system(start, nsys, blockIdx.x);
     const int lb = blockIdx.x - start[s];
     const ZArgs<T> a = args[s];   // private copy: stores cannot alias it
-    zmarch_tile<OP, T, CEPS, NT, PPT, WIDE, DEPTH>(a, lb, lb);
+    zmarch_tile<OP, T, CEPS, SIG, NT, PPT, WIDE, DEPTH>(a, lb, lb);
 }
 
 // ------------------------------------------------------------ finalize
@@ -1056,19 +1064,19 @@ __global__ void k_copy2(size_t N, double *d0, const double *s0, double *d1, cons
     }
 }
 
-// Start (or restart) of a BiCGSTAB run in one launch: p = v = t = 0, s = r,
-// x = 0 when xz is given (the correction of a refinement step), and the
-// scalar block set to `init` (threads of the first workgroup copy it word by
-// word).  The next step kernels read all of it after this launch.
+// Start (or restart) of a BiCGSTAB run in one launch: p^ = v^ = t^ = 0, x = 0
+// when xz is given (the correction of a refinement step), and the scalar
+// block set to `init` (threads of the first workgroup copy it word by word).
+// The residual kernel has already written s^ = D^-1 r and the shadow r.  The
+// next step kernels read all of it after this launch.
 template <typename T>
-__global__ void k_krylov_start(size_t N, T *p, T *v, T *t, T *s, const T *r, T *xz, Scalars init, Scalars *sc)
+__global__ void k_krylov_start(size_t N, T *p, T *v, T *t, T *xz, Scalars init, Scalars *sc)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
         p[n] = T(0);
         v[n] = T(0);
         t[n] = T(0);
-        s[n] = r[n];
         if (xz) xz[n] = T(0);
     }
     static_assert(sizeof(Scalars) % 4 == 0, "scalar block is copied in 32-bit words");
@@ -1078,32 +1086,14 @@ __global__ void k_krylov_start(size_t N, T *p, T *v, T *t, T *s, const T *r, T *
         reinterpret_cast<unsigned *>(sc)[threadIdx.x] = reinterpret_cast<const unsigned *>(&init)[threadIdx.x];
 }
 
-// Inverse diagonal of the operator: 1 / (sum_f c_f + sigma) on free rows,
-// -1 on Dirichlet rows.  Computed in FP64 and rounded to T.
-template <typename T, bool CEPS>
-__global__ void k_dinv(int nx, int ny, int nz, double ih2, double ceps, const double *eps,
-                       const double *sigma, double sig_const, const uint8_t *flags, uint8_t dirbit,
-                       T *dinv)
+// Mark the Dirichlet rows of the potential system in the coefficient field:
+// e := -e where the flags carry F_DIR_PHI (the stencil kernels take |e| for
+// the face coefficients and read the row kind from the sign).
+__global__ void k_mark_dirichlet(size_t N, const uint8_t *flags, double *eps)
 {
-    const size_t N = (size_t)nx * ny * nz, P = (size_t)nx * ny;
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
-         n += (size_t)gridDim.x * blockDim.x) {
-        if (flags[n] & dirbit) { dinv[n] = T(-1); continue; }
-        const int i = (int)(n % nx), j = (int)((n / nx) % ny), k = (int)(n / P);
-        double D;
-        if (CEPS) {
-            D = 6.0 * ceps;
-        } else {
-            const double e = eps[n];
-            const size_t nb[6] = {i > 0 ? n - 1 : n + 1, i < nx - 1 ? n + 1 : n - 1,
-                                  j > 0 ? n - nx : n + nx, j < ny - 1 ? n + nx : n - nx,
-                                  k > 0 ? n - P : n + P, k < nz - 1 ? n + P : n - P};
-            D = 0.0;
-            for (int f = 0; f < 6; ++f) D += (2.0 * e * eps[nb[f]]) / (e + eps[nb[f]]) * ih2;
-        }
-        D += sigma ? sigma[n] : sig_const;
-        dinv[n] = (T)(1.0 / D);
-    }
+         n += (size_t)gridDim.x * blockDim.x)
+        if (flags[n] & F_DIR_PHI) eps[n] = -eps[n];
 }
 
 // Flag a negative diagonal shift on a free row (sigma must be >= 0; a NaN is

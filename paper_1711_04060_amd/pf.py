@@ -328,10 +328,12 @@ def pf_timing_enable(enable=1, sample=8):
 
 
 TIMING_SPMV_FP64, TIMING_SPMV_FP32 = 2, 3   # pf_timing_read kinds of the isolated products
+TIMING_BATCH_FP64, TIMING_BATCH_FP32 = 4, 5  # batched BiCGSTAB step A
 
 
 def pf_timing_read(kind=PF_FP64):
-    """kind: PF_FP64 / PF_MIXED (BiCGSTAB step A), TIMING_SPMV_FP64 / TIMING_SPMV_FP32."""
+    """kind: PF_FP64 / PF_MIXED (BiCGSTAB step A), TIMING_SPMV_FP64 / TIMING_SPMV_FP32,
+    TIMING_BATCH_FP64 / TIMING_BATCH_FP32."""
     n, ms, by = C.c_int64(), C.c_double(), C.c_double()
     _check(load().pf_timing_read(int(kind), C.byref(n), C.byref(ms), C.byref(by)), "pf_timing_read")
     return dict(launches=n.value, mean_ms=ms.value, bytes=by.value)

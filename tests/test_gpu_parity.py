@@ -93,11 +93,10 @@ def test_spmv_fp64_matches_dia(shape, with_sigma):
     ref = oracle.dia_matvec(nx, ny, nz, A, x)
     bound = 16 * EPS64 * _abs_terms(p, A, x)
     assert np.all(np.abs(host(y) - ref) <= bound)
-    # Jacobi-preconditioned operator A M^-1 x, M = diag(A)
+    # Jacobi-scaled operator M^-1 A x, M = diag(A)
     pf.pf_spmv(g, None if sigma is None else dev(sigma), dev(x), y, 1)
-    xm = x / A[0]
-    ref = oracle.dia_matvec(nx, ny, nz, A, xm)
-    bound = 16 * EPS64 * _abs_terms(p, A, xm)
+    ref = oracle.dia_matvec(nx, ny, nz, A, x) / A[0]
+    bound = 16 * EPS64 * _abs_terms(p, A, x) / np.abs(A[0])
     assert np.all(np.abs(host(y) - ref) <= bound)
 
 
@@ -113,9 +112,9 @@ def test_spmv_fp32_matches_dia(shape):
     g = pf.grid_from_problem(p)
     y = torch.empty(p.N, dtype=torch.float32, device="cuda")
     pf.pf_spmv_f32(g, dev(sigma), dev(x, torch.float32), y, 1)
-    xm = x.astype(np.float64) / A[0]
-    ref = oracle.dia_matvec(nx, ny, nz, A, xm)
-    bound = 24 * EPS32 * _abs_terms(p, A, xm)
+    x64 = x.astype(np.float64)
+    ref = oracle.dia_matvec(nx, ny, nz, A, x64) / A[0]
+    bound = 24 * EPS32 * _abs_terms(p, A, x64) / np.abs(A[0])
     assert np.all(np.abs(host(y).astype(np.float64) - ref) <= bound)
 
 
@@ -191,8 +190,8 @@ def test_launch_shapes_and_pipeline_depths(launch):
     x = rng.normal(size=p.N)
     y = torch.empty(p.N, dtype=torch.float64, device="cuda")
     pf.pf_spmv(g, dev(sigma), dev(x), y, 1)
-    xm = x / A[0]
-    assert np.all(np.abs(host(y) - oracle.dia_matvec(p.nx, p.ny, p.nz, A, xm)) <= 16 * EPS64 * _abs_terms(p, A, xm))
+    ref_y = oracle.dia_matvec(p.nx, p.ny, p.nz, A, x) / A[0]
+    assert np.all(np.abs(host(y) - ref_y) <= 16 * EPS64 * _abs_terms(p, A, x) / np.abs(A[0]))
     xs = torch.zeros(p.N, dtype=torch.float64, device="cuda")
     info = pf.pf_linear_solve(g, dev(sigma), dev(b), xs, pf.pf_lin_opts_default(rel_tol=1e-12))
     assert info["status"] == 0 and _rel(host(xs), ref) <= 1e-9
@@ -213,8 +212,8 @@ def test_wide_planes():
     x = rng.normal(size=p.N)
     y = torch.empty(p.N, dtype=torch.float64, device="cuda")
     pf.pf_spmv(g, None, dev(x), y, 1)
-    xm = x / A[0]
-    assert np.all(np.abs(host(y) - oracle.dia_matvec(p.nx, p.ny, p.nz, A, xm)) <= 16 * EPS64 * _abs_terms(p, A, xm))
+    ref_y = oracle.dia_matvec(p.nx, p.ny, p.nz, A, x) / A[0]
+    assert np.all(np.abs(host(y) - ref_y) <= 16 * EPS64 * _abs_terms(p, A, x) / np.abs(A[0]))
     xs = torch.zeros(p.N, dtype=torch.float64, device="cuda")
     info = pf.pf_linear_solve(g, None, dev(b), xs, pf.pf_lin_opts_default(rel_tol=1e-12))
     assert info["status"] == 0 and _rel(host(xs), ref) <= 1e-9
@@ -519,10 +518,10 @@ def test_timing_of_products_and_bad_kind():
         pf.pf_spmv_f32(g, None, x.float(), y.float(), 1)
         t64 = pf.pf_timing_read(pf.TIMING_SPMV_FP64)
         t32 = pf.pf_timing_read(pf.TIMING_SPMV_FP32)
-        assert t64["launches"] == 1 and t64["bytes"] == 4 * p.N * 8 and t64["mean_ms"] >= 0
-        assert t32["launches"] == 1 and t32["bytes"] == 4 * p.N * 4
+        assert t64["launches"] == 1 and t64["bytes"] == 3 * p.N * 8 and t64["mean_ms"] >= 0
+        assert t32["launches"] == 1 and t32["bytes"] == 3 * p.N * 4
         with pytest.raises(pf.PfError):
-            pf.pf_timing_read(4)
+            pf.pf_timing_read(6)
     finally:
         pf.pf_timing_enable(0, 1)
 
