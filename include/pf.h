@@ -150,6 +150,26 @@ pf_status pf_linear_solve(pf_grid *g, const double *sigma, const double *b, doub
 pf_status pf_residual(pf_grid *g, const double *sigma, const double *b, const double *x,
                       double *rel_res, double *r);
 
+/* Size of the device scratch of pf_residual_noalloc (one copy per device). */
+#define PF_NOALLOC_SCRATCH_BYTES (2u << 20)
+
+/* pf_residual for callers that cannot allocate device memory (code between
+ * graph-capture calls, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result, with the reduction partials and sums in a
+ * fixed device scratch array of PF_NOALLOC_SCRATCH_BYTES per device (held
+ * until the process ends) instead of grid or workspace buffers, and no call
+ * of hipMalloc, hipFree or any other allocating routine.  r is required
+ * (device [N], receives b - A x, 0 on Dirichlet rows); rel_res as in
+ * pf_residual.  The grid's workspace is not used, so the call works on a
+ * grid that has never solved.  Limit: the residual kernel's workgroup
+ * partials (8 doubles each) must fit the scratch after a 256-byte header,
+ * i.e. at most 32764 workgroups; longer z-chunks are used when the grid's
+ * usual launch shape has more, and PF_ERR_ARG is returned when even that
+ * does not fit.  Every call on one device shares that device's scratch:
+ * calls that overlap on one device (other threads, other streams) race. */
+pf_status pf_residual_noalloc(pf_grid *g, const double *sigma, const double *b, const double *x,
+                              double *rel_res, double *r);
+
 /* Stencil operator application y = A x (jacobi = 0) or y = M^-1 A x
  * (jacobi = 1, M = diag(A), identity on Dirichlet rows) with the operator of
  * pf_linear_solve.  x, y: device [N], distinct.  The FP64 forms are the

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <type_traits>
@@ -155,6 +156,7 @@ struct Work {
 }  // namespace
 
 struct pf_grid {
+    int device = 0;                    // device current at creation (owner of every buffer and the stream)
     int nx = 0, ny = 0, nz = 0;
     size_t N = 0;
     double h = 0;
@@ -517,11 +519,16 @@ pf_status prepare_f32(pf_grid *g, const OpDesc &op)
 
 // True FP64 residual r = b - A x (and ||r||^2 into sc->red[slot]); optional
 // shadow copies (r) and Krylov start vectors (s^ = D^-1 r), FP64 or FP32.
-// lift: use the Dirichlet values as x (b_lift).
+// lift: use the Dirichlet values as x (b_lift).  The launch shape c, the
+// partials buffer and the scalar block are the grid's unless given.
 pf_status residual64(pf_grid *g, const OpDesc &op, const double *b, const double *x, double *r, bool lift,
-                     double *rt64, float *rt32, double *rs64, float *rs32, int slot = 0)
+                     double *rt64, float *rt32, double *rs64, float *rs32, int slot = 0,
+                     const ZCfg *cshape = nullptr, double *partials = nullptr, Scalars *sc = nullptr)
 {
-    pfk::ZArgs<double> a = zbase<double>(g, op);
+    const ZCfg &c = cshape ? *cshape : cfg_of<double>(g);
+    pfk::ZArgs<double> a = zbase_cfg<double>(g, op, c);
+    if (partials) a.partials = partials;
+    if (sc) a.sc = sc;
     a.x = x;
     a.out = r;
     a.b = b;
@@ -541,10 +548,13 @@ pf_status residual64(pf_grid *g, const OpDesc &op, const double *b, const double
         a.lift = 1;
         a.dval = nullptr;
     }
-    PFCHK((zlaunch<pfk::OP_RESID, double>(g, op, a, cfg_of<double>(g))));
+    PFCHK((zlaunch<pfk::OP_RESID, double>(g, op, a, c)));
     // the partials buffer is reused by the next standalone reduction, which
     // follows in stream order
-    return finalize<pfk::FIN_SUM>(g, a.G, slot);
+    pfk::FinArgs f{a.sc, a.partials, a.G, slot};
+    hipLaunchKernelGGL((pfk::k_finalize<pfk::FIN_SUM>), dim3(1), dim3(256), 0, g->stream, f);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
 }
 
 pf_status read_scalars(pf_grid *g)
@@ -1639,6 +1649,7 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
         bs |= (d->bc_psi[f] == PF_BC_NEUMANN) << f;
     }
     pf_grid *g = new pf_grid();
+    if (hipGetDevice(&g->device) != hipSuccess) { delete g; return fail(PF_ERR_DEVICE, "hipGetDevice failed"); }
     g->nx = d->nx; g->ny = d->ny; g->nz = d->nz; g->N = N; g->h = d->h;
     g->bcphi_mask = bp; g->bcpsi_mask = bs;
     for (int f = 0; f < 6; ++f) g->bcval[f] = d->bc_value[f];
@@ -1758,6 +1769,77 @@ pf_status pf_residual(pf_grid *g, const double *sigma, const double *b, const do
     PFCHK(read_scalars(g));
     const double bn2 = g->hsc->red[1];
     const double rr = g->hsc->red[0];
+    *rel_res = bn2 > 0 ? std::sqrt(rr / bn2) : (rr == 0 ? 0.0 : INFINITY);
+    return PF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- residual without allocation
+
+// Device scratch of pf_residual_noalloc: a scalar block (its red[] slots
+// receive the two sums) followed by the workgroup partials.  One copy per
+// device, held until the process ends.  In host code the name stands for a
+// host-side symbol, never a device address: host code uses the per-device
+// pointer from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[PF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current.
+pf_status scratch_for(int dev, void **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PF_ERR_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(PF_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_residual_noalloc(pf_grid *g, const double *sigma, const double *b, const double *x,
+                              double *rel_res, double *r)
+{
+    PFCHK(check_grid(g));
+    if (!b || !x || !rel_res || !r) return fail(PF_ERR_ARG, "b, x, rel_res and r are required");
+    void *base = nullptr;
+    PFCHK(scratch_for(g->device, &base));
+    const size_t head = (sizeof(Scalars) + 255) & ~(size_t)255;
+    const size_t cap = (PF_NOALLOC_SCRATCH_BYTES - head) / (pfk::PSTRIDE * sizeof(double));
+    // pf_residual's launch shape; longer z-chunks only if its partials do not fit
+    ZCfg c = cfg_of<double>(g);
+    while ((size_t)c.G > cap && c.KZ < g->nz) c = make_cfg(g->nx, g->ny, g->nz, 8, c.NTZ, c.PPT, 2 * c.KZ, 1);
+    if ((size_t)c.G > cap)
+        return fail(PF_ERR_ARG, "grid needs %d workgroup partials; the scratch holds %zu", c.G, cap);
+    Scalars *sc = static_cast<Scalars *>(base);
+    double *part = reinterpret_cast<double *>(static_cast<char *>(base) + head);
+    PFCHK(begin(g));
+    OpDesc op;
+    op.sigma = sigma;
+    PFCHK(residual64(g, op, b, nullptr, r, true, nullptr, nullptr, nullptr, nullptr, 1, &c, part, sc));
+    PFCHK(residual64(g, op, b, x, r, false, nullptr, nullptr, nullptr, nullptr, 0, &c, part, sc));
+    double red[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(red, sc->red, sizeof red, hipMemcpyDeviceToHost, g->stream));
+    PFCHK(sync(g));
+    const double rr = red[0], bn2 = red[1];
     *rel_res = bn2 > 0 ? std::sqrt(rr / bn2) : (rr == 0 ? 0.0 : INFINITY);
     return PF_OK;
 }

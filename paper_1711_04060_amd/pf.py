@@ -23,7 +23,7 @@ PF_FP64, PF_MIXED = 0, 1
 PF_STOP_REL2, PF_STOP_ABS_INF = 0, 1
 
 EXPORTS = ("pf_grid_create", "pf_grid_destroy", "pf_lin_opts_default", "pf_linear_solve",
-           "pf_residual", "pf_spmv", "pf_spmv_f32", "pf_pf_params_default", "pf_nonlinear_solve",
+           "pf_residual", "pf_residual_noalloc", "pf_spmv", "pf_spmv_f32", "pf_pf_params_default", "pf_nonlinear_solve",
            "pf_fermi", "pf_linear_solve_batch", "pf_nonlinear_solve_batch", "pf_last_error",
            "pf_set_launch", "pf_timing_enable", "pf_timing_read", "pf_coulomb",
            "pf_iface_params_default", "pf_interface_setup", "pf_site_model", "pf_site_fill")
@@ -97,6 +97,7 @@ def load():
         lib.pf_lin_opts_default.restype = None
         lib.pf_linear_solve.argtypes = [P, P, P, P, C.POINTER(pf_lin_opts), C.POINTER(pf_lin_info)]
         lib.pf_residual.argtypes = [P, P, P, P, C.POINTER(D), P]
+        lib.pf_residual_noalloc.argtypes = [P, P, P, P, C.POINTER(D), P]
         lib.pf_spmv.argtypes = [P, P, P, P, I32]
         lib.pf_spmv_f32.argtypes = [P, P, P, P, I32]
         lib.pf_pf_params_default.argtypes = [C.POINTER(pf_pf_params)]
@@ -218,6 +219,16 @@ def pf_residual(g: Grid, sigma, b, x, r=None) -> float:
     _check(load().pf_residual(g.handle, _ptr(sigma, torch.float64, g.N), _ptr(b, torch.float64, g.N),
                               _ptr(x, torch.float64, g.N), C.byref(rel), _ptr(r, torch.float64, g.N)),
            "pf_residual")
+    return rel.value
+
+
+def pf_residual_noalloc(g: Grid, sigma, b, x, r) -> float:
+    """pf_residual without any allocation (scratch in a static device array); r is required."""
+    import torch
+    rel = C.c_double()
+    _check(load().pf_residual_noalloc(g.handle, _ptr(sigma, torch.float64, g.N), _ptr(b, torch.float64, g.N),
+                                      _ptr(x, torch.float64, g.N), C.byref(rel), _ptr(r, torch.float64, g.N)),
+           "pf_residual_noalloc")
     return rel.value
 
 
