@@ -1,26 +1,35 @@
 #!/usr/bin/env python
 """Benchmark of the Poisson-Fermi hot path on one MI355X.
 
-A step is one full nonlinear Poisson-Fermi solve (Sec. 4, Tables 2 and 4) of
-the 97^3 membrane workload from phi = 0: initial PF2 solve, then Fermi update,
-PF1 solve, PF2 solve and relaxation until the max-norm update is below 1e-8,
-every linear solve Jacobi-BiCGSTAB to relative residual 1e-10.  All inputs are
-resident in device memory before the timed region starts.
+A step is one batched solve of the 64 linearised Poisson-Boltzmann systems
+(sizes 33^3 to 129^3, 49,173,256 unknowns, each the PF2 operator at
+phi_0 = 0 with its own charge set and bath), every member Jacobi-BiCGSTAB
+(Sec. 4, Table 3) in FP64 from x = 0 to true relative residual 1e-10, all
+members' iterations in shared launches (one launch per BiCGSTAB step kernel
+per iteration covering every member still iterating).  This is the largest
+single-GPU workload of the benchmark set.  All inputs are resident in device
+memory before the timed region starts.
 
 The JSON line also carries:
-  roofline      the BiCGSTAB step-A stencil kernel (the previous iteration's
-                x, r update, the p update and v = A M^-1 p in one pass),
-                timed with HIP events on the library's stream during the
-                timed steps; algorithmic bytes = 12 vectors of N doubles per
-                launch (reads s, t, x, p, v, shadow, dinv, eps; writes x, r,
-                p, v);
-  cpu_baseline  the serial FP64 oracle on a bounded sample of the same solve
-                (its first outer iterations), scaled to a whole solve by the
-                number of BiCGSTAB iterations the solve needs;
-  forms         FP64 vs mixed precision on the 193^3 Poisson problem and the
-                64-system batch, each to relative residual 1e-10; the isolated
-                Jacobi-scaled stencil product at 193^3 with operands cycled
-                through three sets (cold in the Infinity Cache).
+  roofline      the batched BiCGSTAB step-A stencil kernel (the previous
+                iteration's x, r update, the p update and v = A p^ in one
+                pass over every iterating member), timed with HIP events on
+                the library's stream in one chunk of iterations out of
+                --sample during the timed steps; algorithmic bytes per launch
+                = 12 vectors of N doubles of every member still iterating
+                (reads s^, p^, v^, t^, eps, sigma, x, shadow; writes x, r^,
+                p^, v^);
+  cpu_baseline  the serial FP64 oracle, pinned to one core, on a bounded
+                sample of the members, extrapolated to the whole batch by
+                node-iterations;
+  forms         batched mixed precision and sequential FP64 on the same
+                batch; FP64 vs mixed on the 193^3 Poisson problem with the
+                per-iteration fraction of the HBM roofline; the isolated
+                Jacobi-scaled product at 193^3 with cold operands; the
+                device's streaming ceiling from the library's own probe; the
+                97^3 full PF solve (cache-resident); the singular-charge
+                decomposition; the 16-bias PF sweep at 129^3 with a stated
+                outer-iteration cap.
 """
 import argparse
 import hashlib
@@ -36,7 +45,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "time to 1e-10 rel residual & HBM GB/s: FP64 vs mixed-precision vs batched"
-STEP_A_VECTORS = 12.0   # N-vectors step A reads and writes
+# Bytes of one BiCGSTAB iteration in units of N elements: the method's own
+# count for the fused schedule (operator from eps alone; reads r, p, v, eps,
+# shadow / r, v, eps / x, p, s, t, shadow, eps; writes p, v / s, t / x, r),
+# and this build's two kernels (step A 11, step B 6 for Poisson).
+ITER_VECTORS_METHOD = 20.0
+ITER_VECTORS_BUILD = 17.0
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector peak
 # Coulomb kernel, per (point, charge) pair: 3 differences, 5 for r^2, 1 for the
 # reciprocal square root, 2 for the potential term and its sum, 5 for the
@@ -54,47 +68,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload):
-    """HBM bytes per step-A launch from committed rocprofv3 PMC summaries, if
-    they were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "pmc_bicg_step_a.json")
-    if not os.path.exists(path):
+PMC_BATCH_FILE = os.path.join(ROOT, "profiles", "pmc_batch64_step_a.json")
+
+
+def traffic_from_profiles(bytes_per_launch):
+    """HBM bytes per launch of the batched FP64 step A: the committed
+    rocprofv3 counter ratio (counter bytes / algorithmic bytes over the
+    counted launches) times this run's algorithmic bytes per launch, if the
+    counters were taken on the current kernel source; else None."""
+    if not os.path.exists(PMC_BATCH_FILE):
         return None
     try:
-        d = json.load(open(path))
+        d = json.load(open(PMC_BATCH_FILE))
     except Exception:
         return None
-    if d.get("source_hash") != kernel_source_hash() or d.get("workload") != workload:
+    if d.get("source_hash") != kernel_source_hash() or not d.get("counter_over_algorithmic"):
         return None
-    return d.get("hbm_bytes_per_launch")
-
-
-def run_nonlinear(pf, torch, prob, prm):
-    phi = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
-    info = pf.pf_nonlinear_solve(g_cache[prob.name], prm, phi, check=prm.c.max_outer >= 5000)
-    return info, phi
-
-
-g_cache = {}
-
-
-def forms_pf_mixed(pf, torch, prob, phi64):
-    """The benchmark's own 97^3 PF solve with every linear solve in mixed
-    precision (FP32 BiCGSTAB inside FP64 refinement to the same 1e-10 true
-    relative residual), against the FP64 solve's potential phi64."""
-    prm = pf.params_for(prob, outer_tol=1e-8, lin={"rel_tol": 1e-10, "precision": pf.PF_MIXED})
-    phi = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
-    g = g_cache[prob.name]
-    pf.pf_nonlinear_solve(g, prm, phi)             # first use of the FP32 workspace: tuning
-    phi.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = pf.pf_nonlinear_solve(g, prm, phi)
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    rel = float(torch.linalg.vector_norm(phi - phi64) / torch.linalg.vector_norm(phi64))
-    return dict(seconds=sec, outer_iters=info["outer_iters"], lin_iters=info["total_lin_iters"],
-                rel_l2_vs_fp64=rel)
+    return d["counter_over_algorithmic"] * bytes_per_launch
 
 
 def forms_linear(pf, torch, inputs, timing_sample):
@@ -122,11 +112,15 @@ def forms_linear(pf, torch, inputs, timing_sample):
         t = sorted(times)[1]
         rel = pf.pf_residual(g, None, b, x)
         xs[name] = x.cpu().numpy()
-        bpl = STEP_A_VECTORS * prob.N * (8 if prec == pf.PF_FP64 else 4)
+        elem = 8 if prec == pf.PF_FP64 else 4
+        t_iter = t / info["iters"]      # whole solve (residuals, refinement, host checks included)
         out[name] = dict(seconds=t, iters=info["iters"], refinements=info["refinements"],
-                         rel_res=rel, iters_per_s=info["iters"] / t,
+                         rel_res=rel, iters_per_s=info["iters"] / t, us_per_iter=t_iter * 1e6,
+                         iter_frac_method_bytes=ITER_VECTORS_METHOD * prob.N * elem / t_iter / 1e9 / PEAK_HBM_GBS,
+                         iter_frac_build_bytes=ITER_VECTORS_BUILD * prob.N * elem / t_iter / 1e9 / PEAK_HBM_GBS,
                          step_a_mean_us=tm["mean_ms"] * 1e3,
-                         step_a_gbs=(bpl / (tm["mean_ms"] * 1e-3) / 1e9) if tm["launches"] else None)
+                         step_a_gbs=(tm["bytes"] / tm["launches"] / (tm["mean_ms"] * 1e-3) / 1e9)
+                         if tm["launches"] else None)
     d = xs["mixed"] - xs["fp64"]
     out["mixed_vs_fp64_rel_l2"] = float(np.linalg.norm(d) / np.linalg.norm(xs["fp64"]))
     out["mixed_speedup"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
@@ -135,11 +129,12 @@ def forms_linear(pf, torch, inputs, timing_sample):
 
 
 def forms_spmv_cold(pf, torch, inputs, n=193, sets=3, reps=10):
-    """Isolated Jacobi-scaled stencil product A M^-1 x on the n^3 sphere
+    """Isolated Jacobi-scaled stencil product M^-1 A x on the n^3 sphere
     problem, FP64 and FP32, cycling through `sets` independent grids and
     (x, y) pairs so that the 256 MB Infinity Cache cannot hold the operands
-    between launches (each FP64 set reads and writes 4 vectors of 57.5 MB at
-    193^3).  Kernel time from HIP events around each launch."""
+    between launches (each FP64 set reads and writes 3 vectors of 57.5 MB at
+    193^3: x, eps in, y out).  Kernel time from HIP events around each
+    launch."""
     prob = inputs.sphere_poisson(n)
     grids = [pf.grid_from_problem(prob) for _ in range(sets)]
     out = {"workload": f"sphere_poisson {n}^3, {sets} operand sets cycled, {reps} launches each"}
@@ -162,36 +157,114 @@ def forms_spmv_cold(pf, torch, inputs, n=193, sets=3, reps=10):
     return out
 
 
-def forms_batch(pf, torch, inputs):
-    """64 linearised-PB systems (33^3..129^3), each to rel. res. 1e-10:
-    sequential FP64 solves vs one batched launch sequence (FP64 and mixed)."""
-    probs = inputs.batch_systems()
-    grids = [pf.grid_from_problem(p) for p in probs]
-    bs = [torch.as_tensor(p.b, device="cuda") for p in probs]
-    sg = [torch.as_tensor(p.sigma, device="cuda") for p in probs]
-    xs = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
-    res = {}
-    for name, prec, batched in (("sequential_fp64", pf.PF_FP64, False), ("batched_fp64", pf.PF_FP64, True),
-                                ("batched_mixed", pf.PF_MIXED, True)):
+class Batch:
+    """The 64-system batch resident on the device: grids, right-hand sides,
+    shifts and solution vectors."""
+
+    def __init__(self, pf, torch, inputs):
+        self.probs = inputs.batch_systems()
+        self.grids = [pf.grid_from_problem(p) for p in self.probs]
+        self.bs = [torch.as_tensor(p.b, device="cuda") for p in self.probs]
+        self.sg = [torch.as_tensor(p.sigma, device="cuda") for p in self.probs]
+        self.xs = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in self.probs]
+        self.unknowns = sum(p.N for p in self.probs)
+
+    def solve(self, pf, torch, prec, batched):
+        for x in self.xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         opts = pf.pf_lin_opts_default(precision=prec)
+        if batched:
+            infos = pf.pf_linear_solve_batch(self.grids, self.sg, self.bs, self.xs, opts)
+        else:
+            infos = [pf.pf_linear_solve(g, s, b, x, opts) for g, s, b, x in zip(self.grids, self.sg, self.bs, self.xs)]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, infos
+
+    def max_rel_res(self, pf):
+        return max(pf.pf_residual(g, s, b, x) for g, s, b, x in zip(self.grids, self.sg, self.bs, self.xs))
+
+
+def forms_batch(pf, torch, batch, value_s, reps=3):
+    """Batched mixed precision (FP32 inner BiCGSTAB, FP64 refinement) and 64
+    sequential FP64 solves on the headline batch, each to 1e-10; the median
+    of `reps` runs after one untimed run.  The batched FP32 step A is timed
+    as the headline's FP64 one."""
+    res = {}
+    for name, prec, batched in (("batched_mixed", pf.PF_MIXED, True), ("sequential_fp64", pf.PF_FP64, False)):
+        batch.solve(pf, torch, prec, batched)          # first use: FP32 workspaces and tuning
         times = []
-        for rep in range(2):                       # first pass: tuning, workspaces
-            for x in xs:
-                x.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            if batched:
-                infos = pf.pf_linear_solve_batch(grids, sg, bs, xs, opts)
-            else:
-                infos = [pf.pf_linear_solve(gr, s, b, x, opts) for gr, s, b, x in zip(grids, sg, bs, xs)]
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        res[name] = dict(seconds=times[-1], total_iters=sum(i["iters"] for i in infos),
-                         max_rel_res=max(pf.pf_residual(gr, s, b, x) for gr, s, b, x in zip(grids, sg, bs, xs)))
-    res["unknowns"] = sum(p.N for p in probs)
-    res["batched_fp64_speedup"] = res["sequential_fp64"]["seconds"] / res["batched_fp64"]["seconds"]
-    res["batched_mixed_speedup"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
+        if name == "batched_mixed":
+            pf.pf_timing_enable(1, 4)
+        for _ in range(reps):
+            t, infos = batch.solve(pf, torch, prec, batched)
+            times.append(t)
+        row = dict(seconds=sorted(times)[len(times) // 2], total_iters=sum(i["iters"] for i in infos),
+                   max_rel_res=batch.max_rel_res(pf), fp64_fallbacks=sum(i["fp64_fallback"] for i in infos))
+        if name == "batched_mixed":
+            tm = pf.pf_timing_read(pf.TIMING_BATCH_FP32)
+            pf.pf_timing_enable(0, 1)
+            row["step_a_fp32"] = dict(launches=tm["launches"], mean_us=tm["mean_ms"] * 1e3,
+                                      gbs=tm["bytes"] / tm["launches"] / (tm["mean_ms"] * 1e-3) / 1e9
+                                      if tm["launches"] else None)
+        res[name] = row
+    res["batched_fp64_seconds"] = value_s
+    res["batched_fp64_speedup_vs_sequential"] = res["sequential_fp64"]["seconds"] / value_s
+    res["batched_mixed_speedup_vs_sequential"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
+    res["batched_mixed_speedup_vs_batched_fp64"] = value_s / res["batched_mixed"]["seconds"]
     return res
+
+
+def forms_ceiling(pf, torch, n=193 ** 3 + 1, reps=30):
+    """The device's streaming ceiling from the library's probe kernel (FP64,
+    three operand sets of n doubles cycled so that the Infinity Cache cannot
+    hold them; 64- and 128-bit lane accesses)."""
+    out = []
+    for kind in (0, 1, 2):
+        r, w = pf.STREAM_MIX[kind]
+        sets = [[torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(r + w)] for _ in range(3)]
+        for width in (8, 16):
+            us = pf.pf_stream_probe(kind, width, sets, reps=reps)
+            out.append(dict(reads=r, writes=w, bytes_per_access=width, mean_us=us,
+                            tbs=(r + w) * n * 8 / us * 1e-6))
+        del sets
+        torch.cuda.empty_cache()
+    return {"arrays_of_doubles": n, "runs": out, "best_tbs": max(x["tbs"] for x in out)}
+
+
+def forms_pf97(pf, torch, inputs):
+    """Configuration 2: the full PF nonlinear solve on the 97^3 membrane
+    (outer 1e-8, BiCGSTAB 1e-10), FP64 and with mixed-precision linear
+    solves.  Its ~100 MB working set stays in the 256 MB Infinity Cache, so
+    the step-A rate is an effective (cache-resident) GB/s, not an HBM
+    fraction."""
+    prob = inputs.membrane_pore(97)
+    g = pf.grid_from_problem(prob)
+    out = {"workload": "membrane_pore 97^3 (912,673 nodes): full PF solve, outer 1e-8, BiCGSTAB 1e-10"}
+    phis = {}
+    for name, prec in (("fp64", pf.PF_FP64), ("mixed", pf.PF_MIXED)):
+        prm = pf.params_for(prob, outer_tol=1e-8, lin={"rel_tol": 1e-10, "precision": prec})
+        phi = torch.zeros(prob.N, dtype=torch.float64, device="cuda")
+        pf.pf_nonlinear_solve(g, prm, phi)              # tuning, workspaces
+        phi.zero_()
+        pf.pf_timing_enable(1, 16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = pf.pf_nonlinear_solve(g, prm, phi)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        tm = pf.pf_timing_read(prec)
+        pf.pf_timing_enable(0, 1)
+        phis[name] = phi
+        out[name] = dict(seconds=sec, outer_iters=info["outer_iters"], lin_iters=info["total_lin_iters"],
+                         step_a_mean_us=tm["mean_ms"] * 1e3,
+                         step_a_effective_gbs_cache_resident=tm["bytes"] / tm["launches"] / (tm["mean_ms"] * 1e-3)
+                         / 1e9 if tm["launches"] else None)
+    out["mixed_vs_fp64_rel_l2"] = float(torch.linalg.vector_norm(phis["mixed"] - phis["fp64"])
+                                        / torch.linalg.vector_norm(phis["fp64"]))
+    out["mixed_speedup"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
 
 
 def forms_interface(pf, torch, inputs, n=97, reps=5):
@@ -478,62 +551,44 @@ def copy_reference(torch, mib=512):
     return n * 8
 
 
-PMC_FAMILIES = {"step_a_fp64": "k_zmarch<3, double, false", "step_b_fp64": "k_zmarch<4, double, false",
-                    "step_a_fp32": "k_zmarch<3, float, false", "step_b_fp32": "k_zmarch<4, float, false"}
-VECTORS = {"step_a": 12, "step_b": 7}
+PMC_BATCH_KERNEL = "k_zmarch_batch<3, double, false, true"   # batched step A, FP64, shift-array form
 
 
-def pmc_summary_families(fetch_csv, write_csv, workload, copy_bytes, n_nodes):
-    """Per-launch counter traffic of the BiCGSTAB step kernels (variable-
-    coefficient form; FP64, and FP32 where the run has it) from two
-    rocprofv3 --pmc runs (CSV): for each family the most frequent instance
-    (the pinned shape), averaged over
-    its dispatches that read at least half the algorithmic bytes (launches
-    queued after convergence exit early and are left out), each counter
-    scaled by its reading on the copy kernel of known size."""
+def _counter_rows(path, counter):
     import csv
-    from collections import Counter
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+    return vals
 
-    out = {"workload": workload, "source_hash": kernel_source_hash(), "copy_bytes": copy_bytes, "kernels": {}}
-    raw = {}
+
+def pmc_summary_batch(fetch_csv, write_csv, copy_bytes, alg_log):
+    """Counter traffic of the batched FP64 step A from two rocprofv3 --pmc
+    runs (CSV) of `bench.py --pmc-run 1`: FETCH_SIZE and WRITE_SIZE summed
+    over every dispatch of that kernel (the run times every chunk, so each
+    dispatch is also in the algorithmic count the run printed to alg_log),
+    each counter scaled by its reading on the copy kernel of known size."""
+    alg = None
+    for line in open(alg_log):
+        if line.startswith("{") and "pmc_run" in line:
+            alg = json.loads(line)["pmc_run"]
+    out = {"kernel": PMC_BATCH_KERNEL, "source_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
+           "algorithmic": alg}
+    tot = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        vals = {}
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] == counter:
-                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
-        raw[counter] = vals
-    for fam, pat in PMC_FAMILIES.items():
-        names = Counter()
-        for k, xs in raw["FETCH_SIZE"].items():
-            if pat in k:
-                names[k] += len(xs)
-        if not names:
-            continue
-        name = names.most_common(1)[0][0]
-        elem = 8 if "double" in pat else 4
-        alg = VECTORS[fam[:6]] * n_nodes * elem
-        row = {"kernel": name.split("(")[0].replace("void ", ""), "algorithmic_bytes": alg}
-        scales = {}
-        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
-            copy = [x for k, xs in raw[counter].items() if "copy" in k.lower() for x in xs]
-            scales[counter] = copy_bytes / max(copy) if copy else None
-        fetch = raw["FETCH_SIZE"].get(name, [])
-        write = raw["WRITE_SIZE"].get(name, [])
-        keep = [i for i, x in enumerate(fetch) if scales["FETCH_SIZE"] and x * scales["FETCH_SIZE"] >= 0.5 * alg]
-        row["dispatches"] = len(fetch)
-        row["dispatches_counted"] = len(keep)
-        row["runs_aligned"] = len(fetch) == len(write)   # same launches in both runs (pinned shapes)
-        for counter, xs in (("FETCH_SIZE", fetch), ("WRITE_SIZE", write)):
-            sel = [xs[i] for i in keep if i < len(xs)]
-            sc = scales[counter]
-            row[counter] = sum(sel) / len(sel) * sc if (sel and sc) else None
-            row[counter + "_scale"] = sc
-        if row["FETCH_SIZE"] is not None and row["WRITE_SIZE"] is not None:
-            row["counter_bytes"] = row["FETCH_SIZE"] + row["WRITE_SIZE"]
-            row["counter_over_algorithmic"] = row["counter_bytes"] / alg
-        out["kernels"][fam] = row
-    a = out["kernels"].get("step_a_fp64", {})
-    out["hbm_bytes_per_launch"] = a.get("counter_bytes")   # the roofline's `traffic`
+        rows = _counter_rows(path, counter)
+        copy = [x for k, xs in rows.items() if "copy" in k.lower() for x in xs]
+        scale = copy_bytes / max(copy) if copy else None
+        mine = [x for k, xs in rows.items() if PMC_BATCH_KERNEL in k for x in xs]
+        out[counter + "_dispatches"] = len(mine)
+        out[counter + "_scale"] = scale
+        tot[counter] = sum(mine) * scale if (mine and scale) else None
+    if alg and all(tot.values()) and alg["launches_timed"]:
+        out["dispatches_match"] = out["FETCH_SIZE_dispatches"] == out["WRITE_SIZE_dispatches"] == alg["launches_timed"]
+        out["counter_bytes_per_launch"] = (tot["FETCH_SIZE"] + tot["WRITE_SIZE"]) / out["FETCH_SIZE_dispatches"]
+        out["algorithmic_bytes_per_launch"] = alg["bytes_timed"] / alg["launches_timed"]
+        out["counter_over_algorithmic"] = out["counter_bytes_per_launch"] / out["algorithmic_bytes_per_launch"]
     return out
 
 
@@ -563,53 +618,78 @@ def linear193_only(pf, torch, inputs):
     return res
 
 
-def cpu_baseline(prob, lin_iters_full, budget_outer=2, with_interface=False):
-    """Oracle on the first outer iterations of the same solve, scaled by the
-    BiCGSTAB iteration count of the whole solve."""
+CPU_SAMPLE_SIZES = (33, 65, 97, 129)   # one member of each of these sizes
+
+
+def _cpu_sample_job(indices):
+    """Child process body: the oracle's solves of the listed batch members,
+    pinned to core 0; prints one JSON line per member."""
+    os.sched_setaffinity(0, {0})
     import oracle
-    ms = prob.meta["species"]
-    sp = oracle.species_from_molar(ms["valence"], ms["radius_A"], ms["bath_M"])
-    t0 = time.perf_counter()
-    phi, info, _, _ = oracle.nonlinear_solve(prob, prob.fixed_charge, sp, 78.45, prob.meta["lc_A"],
-                                            outer_tol=1e-8, lin_tol=1e-10, max_outer=budget_outer,
-                                            check=False)
-    t = time.perf_counter() - t0
-    per_iter = t / max(1, info["total_lin_iters"])
-    out = dict(value=per_iter * lin_iters_full, unit="s", cores=1, kind="oracle",
-               sample=(f"oracle (serial FP64, 1 thread) on the initial PF2 solve plus {info['outer_iters']} "
-                       f"outer iterations of the same 97^3 solve: {t:.1f} s for {info['total_lin_iters']} "
-                       f"BiCGSTAB iterations, scaled to the {lin_iters_full} iterations of the full solve"))
-    if with_interface:
-        # the decomposition's interface setup on the same membrane (compare forms.interface_97.setup_seconds)
-        import dataclasses
-        import numpy as np
-        from paper_1711_04060_amd import inputs
-        p2 = dataclasses.replace(prob, fixed_charge=np.zeros(prob.N))
+    from paper_1711_04060_amd import inputs
+    probs = inputs.batch_systems()
+    for i in indices:
+        p = probs[i]
         t0 = time.perf_counter()
-        oracle.interface(p2, inputs.point_charges(prob), inputs.lambda_length_A(), inputs.TABLE1["eps_m"],
-                         inputs.TABLE1["eps_s"], tol=1e-12)
-        out["interface_setup_seconds"] = time.perf_counter() - t0
-    return out
+        _, info = oracle.linear_solve(p, p.sigma, p.b, tol=1e-10)
+        print(json.dumps(dict(member=i, n=p.nx, N=p.N, iters=info["iters"], seconds=time.perf_counter() - t0)),
+              flush=True)
+
+
+def cpu_baseline(batch, infos_fp64):
+    """The serial FP64 oracle (Table 3 BiCGSTAB on the seven-diagonal matrix)
+    on one member of each size in CPU_SAMPLE_SIZES, in a child process pinned
+    to one core, extrapolated to the whole batch by node-iterations (the GPU
+    FP64 run's iteration count of every member times its size)."""
+    import subprocess
+    sizes = {}
+    for i, p in enumerate(batch.probs):
+        sizes.setdefault(p.nx, i)
+    pick = [sizes[n] for n in CPU_SAMPLE_SIZES if n in sizes]
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-sample-job", ",".join(map(str, pick))]
+    out = subprocess.run(cmd, capture_output=True, text=True, check=True).stdout
+    rows = [json.loads(line) for line in out.splitlines() if line.startswith("{")]
+    t = sum(r["seconds"] for r in rows)
+    node_iters = sum(r["iters"] * r["N"] for r in rows)
+    total_node_iters = sum(info["iters"] * p.N for info, p in zip(infos_fp64, batch.probs))
+    model, nproc = "unknown", os.cpu_count()
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+    except (OSError, ValueError):
+        pass
+    return dict(value=t / node_iters * total_node_iters, unit="s", cores=1, kind="oracle",
+                sample=(f"serial FP64 oracle (BiCGSTAB of Table 3 on the seven-diagonal matrix), pinned to core 0, "
+                        f"on members of sizes {[r['n'] for r in rows]}: {t:.1f} s for "
+                        f"{node_iters / 1e6:.1f} M node-iterations, extrapolated to the batch's "
+                        f"{total_node_iters / 1e9:.2f} G node-iterations"),
+                extrapolated=True, cpu_model=model, nproc=nproc, pinned="core 0 (sched_setaffinity)",
+                members=rows)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--sample", type=int, default=16, help="time step A in one batch of chunks out of this many")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sample", type=int, default=4, help="time step A in one chunk of iterations out of this many")
     ap.add_argument("--forms", type=int, default=1)
     ap.add_argument("--cpu", type=int, default=1)
-    ap.add_argument("--n", type=int, default=97)
-    ap.add_argument("--bias-sweep", type=int, default=0, help="also run configuration 5 (16 biases, 129^3)")
+    ap.add_argument("--bias-outer", type=int, default=100,
+                    help="configuration 5: stop every bias after this many outer iterations (0: converge)")
+    ap.add_argument("--bias-sweep", type=int, default=1, help="run configuration 5 (16 biases, 129^3)")
+    ap.add_argument("--bias-n", type=int, default=129)
     ap.add_argument("--tps", type=int, default=0, help="also run the five exchange-cycle states at 97^3")
     ap.add_argument("--loop-settings", type=int, default=0, help="also sweep omega and ErrTol at 49^3")
-    ap.add_argument("--bias-outer", type=int, default=0,
-                    help="configuration 5: stop every bias after this many outer iterations (0: converge)")
-    ap.add_argument("--max-outer", type=int, default=0, help="bounded outer loop (profiler runs only)")
     ap.add_argument("--copy-ref", type=int, default=0, help="run the copy reference kernel (counter scale)")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="summarise two rocprofv3 --pmc CSVs into the traffic file and exit")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "RUN_LOG"),
+                    help="summarise two rocprofv3 --pmc CSVs of a --pmc-run (and its printed algorithmic "
+                         "bytes) into the traffic file and exit")
+    ap.add_argument("--pmc-run", type=int, default=0,
+                    help="counter run: the headline steps only, every chunk timed (--sample 1), launch shapes "
+                         "pinned, and the algorithmic bytes of the timed launches printed")
     ap.add_argument("--trace-summary", nargs="+", metavar="CSV",
                     help="summarise rocprofv3 kernel / memory-copy trace CSVs (busy, idle gaps) and exit")
     ap.add_argument("--copy-ceiling", type=int, default=0,
@@ -619,17 +699,17 @@ def main():
                          "autotuner's (for counter runs, whose serialised launches distort the tuner)")
     ap.add_argument("--linear193-only", type=int, default=0,
                     help="run only the 193^3 FP64 and mixed linear solves (for traces and counters) and exit")
+    ap.add_argument("--cpu-sample-job", type=str, default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_sample_job:
+        _cpu_sample_job([int(v) for v in args.cpu_sample_job.split(",")])
+        return
     if args.trace_summary:
         print(json.dumps(trace_summary(args.trace_summary), indent=1))
         return
     if args.pmc_summary:
-        if args.linear193_only:
-            print(json.dumps(pmc_summary_families(args.pmc_summary[0], args.pmc_summary[1], "sphere_poisson_193",
-                                                  512 * (1 << 20), 193 ** 3), indent=1))
-        else:
-            print(json.dumps(pmc_summary_families(args.pmc_summary[0], args.pmc_summary[1], f"membrane_pore_{args.n}",
-                                                  512 * (1 << 20), args.n ** 3), indent=1))
+        print(json.dumps(pmc_summary_batch(args.pmc_summary[0], args.pmc_summary[1], 512 * (1 << 20),
+                                           args.pmc_summary[2]), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path "
@@ -652,34 +732,36 @@ def main():
     if args.linear193_only:
         print(json.dumps({"linear_193": linear193_only(pf, torch, inputs)}), flush=True)
         return
-    prob = inputs.membrane_pore(args.n)
-    g_cache[prob.name] = pf.grid_from_problem(prob)
-    extra = {"max_outer": args.max_outer} if args.max_outer else {}
-    prm = pf.params_for(prob, outer_tol=1e-8, lin={"rel_tol": 1e-10}, **extra)
-    log(f"[bench] workload {prob.name}: N={prob.N}, warmup {args.warmup}, steps {args.steps}")
+    if args.pmc_run:
+        args.sample, args.forms, args.cpu, args.bias_sweep = 1, 0, 0, 0
+
+    batch = Batch(pf, torch, inputs)
+    log(f"[bench] workload batch_64: {len(batch.probs)} systems, {batch.unknowns} unknowns, "
+        f"warmup {args.warmup}, steps {args.steps}")
     for w in range(args.warmup):
-        info, _ = run_nonlinear(pf, torch, prob, prm)
-        log(f"[bench] warmup {w}: outer {info['outer_iters']} lin {info['total_lin_iters']} "
-            f"{info['seconds']:.2f} s")
+        t, infos = batch.solve(pf, torch, pf.PF_FP64, True)
+        log(f"[bench] warmup {w}: {t:.3f} s, {sum(i['iters'] for i in infos)} iterations")
     pf.pf_timing_enable(1, args.sample)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
-    for s in range(args.steps):
-        info, phi = run_nonlinear(pf, torch, prob, prm)
-        infos.append(info)
-        log(f"[bench] step {s}: outer {info['outer_iters']} lin {info['total_lin_iters']} "
-            f"delta {info['last_delta']:.2e} {info['seconds']:.2f} s")
+    for s_ in range(args.steps):
+        t, infos = batch.solve(pf, torch, pf.PF_FP64, True)
+        log(f"[bench] step {s_}: {t:.3f} s, {sum(i['iters'] for i in infos)} iterations, "
+            f"max rel res {max(i['rel_res'] for i in infos):.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    tm = pf.pf_timing_read(pf.PF_FP64)
+    tm = pf.pf_timing_read(pf.TIMING_BATCH_FP64)
     pf.pf_timing_enable(0, 1)
     sec_per_step = elapsed / args.steps
-    bytes_per_launch = STEP_A_VECTORS * prob.N * 8
-    achieved = bytes_per_launch / (tm["mean_ms"] * 1e-3) / 1e9 if tm["launches"] else 0.0
-    traffic = traffic_from_profiles(prob.name)
-    lin_iters = infos[-1]["total_lin_iters"]
-
+    total_iters = sum(i["iters"] for i in infos)
+    node_iters = sum(i["iters"] * p.N for i, p in zip(infos, batch.probs))
+    bpl = tm["bytes"] / tm["launches"] if tm["launches"] else 0.0
+    achieved = bpl / (tm["mean_ms"] * 1e-3) / 1e9 if tm["launches"] else 0.0
+    if args.pmc_run:
+        print(json.dumps({"pmc_run": {"launches_timed": tm["launches"], "bytes_timed": tm["bytes"],
+                                      "mean_us": tm["mean_ms"] * 1e3}}), flush=True)
+        return
+    max_res = batch.max_rel_res(pf)
     result = {
         "metric": METRIC,
         "value": sec_per_step,
@@ -694,50 +776,57 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"membrane_pore {args.n}^3 ({prob.N} nodes, 40 A box, slab+pore+2000-charge shell, "
-                         "Na/Ca/Cl/water, steric on, lc 1.9 A): full PF nonlinear solve, outer 1e-8, "
-                         "BiCGSTAB 1e-10"),
-            "outer_iters": infos[-1]["outer_iters"],
-            "bicgstab_iters": lin_iters,
-            "bicgstab_iters_per_s": lin_iters / sec_per_step,
+            "workload": (f"batch_64: 64 linearised-PB systems 33^3..129^3 ({batch.unknowns:,} unknowns), each "
+                         "Jacobi-BiCGSTAB FP64 from x = 0 to true rel. residual 1e-10, batched (one launch per "
+                         "step kernel per iteration over all iterating members)"),
+            "members": len(batch.probs),
+            "unknowns": batch.unknowns,
+            "bicgstab_iters_total": total_iters,
+            "bicgstab_iters_max_member": max(i["iters"] for i in infos),
+            "node_iters_per_s": node_iters / sec_per_step,
+            "max_true_rel_res": max_res,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "BiCGSTAB step A (previous x, r update + p update + v = A M^-1 p + 2 dots), FP64",
+            "kernel": ("batched BiCGSTAB step A, FP64, shift-array form (previous x, r^ update + p^ update + "
+                       "v^ = D^-1 A p^ + 2 dots over every iterating member)"),
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": traffic,
+            "traffic": traffic_from_profiles(bpl),
             "launches_timed": tm["launches"],
             "mean_us": tm["mean_ms"] * 1e3,
-            "bytes_per_launch": bytes_per_launch,
+            "bytes_per_launch": bpl,
+            "bytes_rule": "12 vectors x N x 8 B per member still iterating at that launch",
         },
     }
     if args.forms:
-        log("[bench] forms: 97^3 PF solve with mixed-precision linear solves")
-        result["forms"] = {"pf_solve_97_mixed": forms_pf_mixed(pf, torch, prob, phi)}
+        log("[bench] forms: batch_64 mixed and sequential")
+        result["forms"] = {"batch_64": forms_batch(pf, torch, batch, sec_per_step)}
+        log("[bench] forms: streaming ceiling")
+        result["forms"]["ceiling"] = forms_ceiling(pf, torch)
         log("[bench] forms: 193^3 FP64 vs mixed")
         result["forms"]["linear_193"] = forms_linear(pf, torch, inputs, args.sample)
-        log("[bench] forms: 64-system batch")
-        result["forms"]["batch_64"] = forms_batch(pf, torch, inputs)
         log("[bench] forms: isolated cold stencil product at 193^3")
         result["forms"]["spmv_cold_193"] = forms_spmv_cold(pf, torch, inputs)
+        log("[bench] forms: 97^3 PF solve")
+        result["forms"]["pf_97"] = forms_pf97(pf, torch, inputs)
         log("[bench] forms: singular-charge decomposition at 97^3")
         result["forms"]["interface_97"] = forms_interface(pf, torch, inputs)
+    if args.bias_sweep:
+        log(f"[bench] forms: 16-bias sweep at {args.bias_n}^3")
+        result.setdefault("forms", {})["bias_sweep"] = forms_bias_sweep(pf, torch, inputs, n=args.bias_n,
+                                                                        outer_cap=args.bias_outer)
     if args.loop_settings:
         log("[bench] forms: outer-loop settings at 49^3")
         result.setdefault("forms", {})["loop_settings_49"] = forms_loop_settings(pf, torch, inputs)
     if args.tps:
         log("[bench] forms: five exchange-cycle states at 97^3")
         result.setdefault("forms", {})["tps_97"] = forms_tps(pf, torch, inputs)
-    if args.bias_sweep:
-        log("[bench] forms: 16-bias sweep at 129^3")
-        result.setdefault("forms", {})["bias_sweep_129"] = forms_bias_sweep(pf, torch, inputs,
-                                                                           outer_cap=args.bias_outer)
     if args.cpu:
         log("[bench] cpu baseline (oracle sample)")
-        result["cpu_baseline"] = cpu_baseline(prob, lin_iters, with_interface=bool(args.forms))
+        result["cpu_baseline"] = cpu_baseline(batch, infos)
     print(json.dumps(result), flush=True)
 
 

@@ -276,6 +276,18 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample);
  * from above.  PF_ERR_ARG for another kind. */
 pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, double *bytes);
 
+/* Streaming-bandwidth probe (a measurement aid, no part of the method): the
+ * ceiling the stencil kernels are compared with.  kind 0 streams 1 input and
+ * 1 output array per set, kind 1 3 inputs and 1 output, kind 2 7 inputs and
+ * 4 outputs (every output = the sum of the inputs); width = 8 or 16 bytes per
+ * lane access.  bufs: host array of sets * (inputs + outputs) device pointers
+ * of n doubles each, set by set, inputs first.  After one untimed launch per
+ * set, reps launches cycle through the sets (sets >= 3 of large arrays keep
+ * them out of the 256 MB Infinity Cache); mean_us (host) receives the mean
+ * launch time from HIP events on `stream` (hipStream_t, NULL = default). */
+pf_status pf_stream_probe(int32_t kind, int32_t width, int64_t n, double *const *bufs, int32_t sets, int32_t reps,
+                          void *stream, double *mean_us);
+
 /* ---------------- singular-charge decomposition (Sec. 3, Eqs. (5)-(10), (17)-(18)) */
 
 /* phi* of Eq. (5) in phi-hat units, or one of its directional derivatives, at

@@ -11,6 +11,7 @@
 #include <hip/hip_ext.h>
 #include "pf_iface.h"
 #include "pf_sites.h"
+#include "pf_stream.h"
 #include "../../include/pf.h"
 
 #include <algorithm>
@@ -1841,6 +1842,54 @@ pf_status pf_residual_noalloc(pf_grid *g, const double *sigma, const double *b, 
     PFCHK(sync(g));
     const double rr = red[0], bn2 = red[1];
     *rel_res = bn2 > 0 ? std::sqrt(rr / bn2) : (rr == 0 ? 0.0 : INFINITY);
+    return PF_OK;
+}
+
+pf_status pf_stream_probe(int32_t kind, int32_t width, int64_t n, double *const *bufs, int32_t sets, int32_t reps,
+                          void *stream, double *mean_us)
+{
+    g_err.clear();
+    static const int RW[3][2] = {{1, 1}, {3, 1}, {7, 4}};
+    if (kind < 0 || kind > 2) return fail(PF_ERR_ARG, "kind must be 0, 1 or 2");
+    if (width != 8 && width != 16) return fail(PF_ERR_ARG, "width must be 8 or 16 bytes");
+    if (n <= 0 || sets <= 0 || reps <= 0 || !bufs || !mean_us) return fail(PF_ERR_ARG, "bad probe arguments");
+    const int R = RW[kind][0], W = RW[kind][1], V = width / 8;
+    if (n % V) return fail(PF_ERR_ARG, "n must be a multiple of %d", V);
+    std::vector<pfk::StreamArgs> args(sets);
+    for (int s = 0; s < sets; ++s) {
+        for (int r = 0; r < R; ++r) args[s].in[r] = bufs[(size_t)s * (R + W) + r];
+        for (int w = 0; w < W; ++w) args[s].out[w] = bufs[(size_t)s * (R + W) + R + w];
+        args[s].n = (size_t)n;
+        for (int j = 0; j < R + W; ++j)
+            if (!bufs[(size_t)s * (R + W) + j]) return fail(PF_ERR_ARG, "null buffer");
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    const int G = (int)std::min<int64_t>(16384, std::max<int64_t>(1, (n / V + 255) / 256));
+    auto launch = [&](const pfk::StreamArgs &a) {
+        switch (kind * 2 + (V - 1)) {
+        case 0: hipLaunchKernelGGL((pfk::k_stream<1, 1, 1>), dim3(G), dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((pfk::k_stream<1, 1, 2>), dim3(G), dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((pfk::k_stream<3, 1, 1>), dim3(G), dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((pfk::k_stream<3, 1, 2>), dim3(G), dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((pfk::k_stream<7, 4, 1>), dim3(G), dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((pfk::k_stream<7, 4, 2>), dim3(G), dim3(256), 0, st, a); break;
+        }
+    };
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int s = 0; s < sets; ++s) launch(args[s]);   // untimed first pass
+    hipError_t e = hipEventRecord(e0, st);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) launch(args[k % sets]);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(PF_ERR_DEVICE, "stream probe failed: %s", hipGetErrorString(e));
+    *mean_us = ms * 1e3 / reps;
     return PF_OK;
 }
 

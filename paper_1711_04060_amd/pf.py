@@ -26,7 +26,8 @@ EXPORTS = ("pf_grid_create", "pf_grid_destroy", "pf_lin_opts_default", "pf_linea
            "pf_residual", "pf_residual_noalloc", "pf_spmv", "pf_spmv_f32", "pf_pf_params_default", "pf_nonlinear_solve",
            "pf_fermi", "pf_linear_solve_batch", "pf_nonlinear_solve_batch", "pf_last_error",
            "pf_set_launch", "pf_timing_enable", "pf_timing_read", "pf_coulomb",
-           "pf_iface_params_default", "pf_interface_setup", "pf_site_model", "pf_site_fill")
+           "pf_iface_params_default", "pf_interface_setup", "pf_site_model", "pf_site_fill",
+           "pf_stream_probe")
 
 
 class pf_grid_desc(C.Structure):
@@ -98,6 +99,7 @@ def load():
         lib.pf_linear_solve.argtypes = [P, P, P, P, C.POINTER(pf_lin_opts), C.POINTER(pf_lin_info)]
         lib.pf_residual.argtypes = [P, P, P, P, C.POINTER(D), P]
         lib.pf_residual_noalloc.argtypes = [P, P, P, P, C.POINTER(D), P]
+        lib.pf_stream_probe.argtypes = [I32, I32, C.c_int64, C.POINTER(P), I32, I32, P, C.POINTER(D)]
         lib.pf_spmv.argtypes = [P, P, P, P, I32]
         lib.pf_spmv_f32.argtypes = [P, P, P, P, I32]
         lib.pf_pf_params_default.argtypes = [C.POINTER(pf_pf_params)]
@@ -230,6 +232,26 @@ def pf_residual_noalloc(g: Grid, sigma, b, x, r) -> float:
                                       _ptr(x, torch.float64, g.N), C.byref(rel), _ptr(r, torch.float64, g.N)),
            "pf_residual_noalloc")
     return rel.value
+
+
+STREAM_MIX = {0: (1, 1), 1: (3, 1), 2: (7, 4)}   # pf_stream_probe kinds: (inputs, outputs)
+
+
+def pf_stream_probe(kind, width, sets, reps=30, stream=None):
+    """Mean launch time (us) of the streaming probe over `sets` lists of
+    device FP64 tensors (inputs first, then outputs), all of one length."""
+    import torch
+    r, w = STREAM_MIX[kind]
+    flat = [t for st in sets for t in st]
+    n = flat[0].numel()
+    if any(len(st) != r + w for st in sets) or any(t.numel() != n or t.dtype != torch.float64 for t in flat):
+        raise ValueError("each set needs %d inputs and %d outputs of equal length" % (r, w))
+    arr = (C.c_void_p * len(flat))(*[t.data_ptr() for t in flat])
+    us = C.c_double()
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(load().pf_stream_probe(int(kind), int(width), n, arr, len(sets), int(reps), st, C.byref(us)),
+           "pf_stream_probe")
+    return us.value
 
 
 def pf_spmv(g: Grid, sigma, x, y, jacobi: int = 0):

@@ -1,7 +1,7 @@
 """Host-side logic of bench.py (no GPU): the one-GPU guard, the counter
 summary's arithmetic on synthetic rocprofv3 CSVs, and the rule that the
 roofline's traffic figure is only taken from a summary of the current kernel
-source and workload."""
+source."""
 import csv
 import json
 import os
@@ -30,61 +30,48 @@ def _write_csv(path, counter, rows):
             w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": kib})
 
 
-def test_counter_summary_scales_selects_and_filters(tmp_path):
-    n = 1000
-    alg_a, alg_b = 12 * n * 8, 7 * n * 8
+def test_batch_counter_summary_scales_and_selects(tmp_path):
     copy_bytes = 1 << 20
-    A = "void pfk::k_zmarch<3, double, false, 512, 1, false, 1>(pfk::ZArgs<double>)"
-    A_other = "void pfk::k_zmarch<3, double, false, 256, 2, false, 1>(pfk::ZArgs<double>)"
-    B = "void pfk::k_zmarch<4, double, false, 512, 1, false, 1>(pfk::ZArgs<double>)"
+    A = "void pfk::k_zmarch_batch<3, double, false, true, 512, 1, false, 1>(pfk::ZArgs<double> const*, int const*, int)"
+    B = "void pfk::k_zmarch_batch<4, double, false, true, 512, 1, false, 1>(pfk::ZArgs<double> const*, int const*, int)"
+    single = "void pfk::k_zmarch<3, double, false, true, 512, 1, false, 1>(pfk::ZArgs<double>)"
     copy = "__amd_rocclr_copyBuffer"
     # FETCH reads half the copied bytes (scale 2), WRITE all of them (scale 1)
     f_rows = [(copy, copy_bytes / 2 / 1024)]
     w_rows = [(copy, copy_bytes / 1024)]
-    # step A: three launches that ran (raw fetch 0.40-0.44 of the algorithmic bytes, 0.80-0.88 scaled)
-    for fa, wa in ((0.40, 0.25), (0.42, 0.26), (0.44, 0.27)):
-        f_rows.append((A, fa * alg_a / 1024))
-        w_rows.append((A, wa * alg_a / 1024))
-    # one launch that exited early: excluded by the half-the-bytes filter
-    f_rows.append((A, 0.01 * alg_a / 1024))
-    w_rows.append((A, 0.0))
-    # a tuner candidate with one launch: not the most frequent instance
-    f_rows.append((A_other, 5.0 * alg_a / 1024))
-    w_rows.append((A_other, 5.0 * alg_a / 1024))
-    f_rows.append((B, 0.45 * alg_b / 1024))
-    w_rows.append((B, 0.3 * alg_b / 1024))
-    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    alg = [9000.0, 6000.0, 3000.0]                 # members drop out: fewer bytes per launch
+    for a in alg:
+        f_rows.append((A, 0.40 * a / 1024))        # 0.80 of the algorithmic bytes once scaled
+        w_rows.append((A, 0.30 * a / 1024))
+    f_rows += [(B, 99.0), (single, 77.0)]          # other kernels are not counted
+    w_rows += [(B, 99.0), (single, 77.0)]
+    fp, wp, log = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "run.log"
     _write_csv(fp, "FETCH_SIZE", f_rows)
     _write_csv(wp, "WRITE_SIZE", w_rows)
-    out = bench.pmc_summary_families(str(fp), str(wp), "synthetic", copy_bytes, n)
-    a = out["kernels"]["step_a_fp64"]
-    assert a["kernel"] == "pfk::k_zmarch<3, double, false, 512, 1, false, 1>"
-    assert a["dispatches"] == 4 and a["dispatches_counted"] == 3 and a["runs_aligned"]
-    assert a["FETCH_SIZE_scale"] == pytest.approx(2.0) and a["WRITE_SIZE_scale"] == pytest.approx(1.0)
-    assert a["FETCH_SIZE"] == pytest.approx(2.0 * 0.42 * alg_a)
-    assert a["WRITE_SIZE"] == pytest.approx(0.26 * alg_a)
-    assert a["counter_over_algorithmic"] == pytest.approx(0.84 + 0.26)
-    assert out["hbm_bytes_per_launch"] == pytest.approx(a["counter_bytes"])
-    b = out["kernels"]["step_b_fp64"]
-    assert b["counter_bytes"] == pytest.approx((0.9 + 0.3) * alg_b)
-    assert "step_a_fp32" not in out["kernels"]
+    log.write_text("[bench] noise\n" + json.dumps({"pmc_run": {"launches_timed": 3, "bytes_timed": sum(alg),
+                                                                "mean_us": 1.0}}) + "\n")
+    out = bench.pmc_summary_batch(str(fp), str(wp), copy_bytes, str(log))
+    assert out["FETCH_SIZE_scale"] == pytest.approx(2.0) and out["WRITE_SIZE_scale"] == pytest.approx(1.0)
+    assert out["FETCH_SIZE_dispatches"] == 3 and out["dispatches_match"]
+    assert out["counter_bytes_per_launch"] == pytest.approx(1.1 * sum(alg) / 3)
+    assert out["algorithmic_bytes_per_launch"] == pytest.approx(sum(alg) / 3)
+    assert out["counter_over_algorithmic"] == pytest.approx(1.1)
 
 
-def test_traffic_only_from_current_source_and_workload(tmp_path, monkeypatch):
+def test_traffic_only_from_current_source(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.traffic_from_profiles("membrane_pore_97") is None          # no summary
+    monkeypatch.setattr(bench, "PMC_BATCH_FILE", str(prof / "pmc_batch64_step_a.json"))
+    assert bench.traffic_from_profiles(1000.0) is None                      # no summary
     csrc = tmp_path / "paper_1711_04060_amd" / "csrc"
     csrc.mkdir(parents=True)
     (csrc / "pf_kernels.h").write_text("// kernel source\n")
     h = bench.kernel_source_hash()
-    (prof / "pmc_bicg_step_a.json").write_text(json.dumps(
-        {"workload": "membrane_pore_97", "source_hash": h, "hbm_bytes_per_launch": 123.0}))
-    assert bench.traffic_from_profiles("membrane_pore_97") == 123.0
-    assert bench.traffic_from_profiles("membrane_pore_49") is None          # other workload
+    (prof / "pmc_batch64_step_a.json").write_text(json.dumps({"source_hash": h, "counter_over_algorithmic": 1.25}))
+    assert bench.traffic_from_profiles(1000.0) == pytest.approx(1250.0)
     (csrc / "pf_kernels.h").write_text("// kernel source, changed\n")
-    assert bench.traffic_from_profiles("membrane_pore_97") is None          # kernel changed
+    assert bench.traffic_from_profiles(1000.0) is None                      # kernel changed
 
 
 def test_trace_summary_busy_idle_and_gaps(tmp_path):
