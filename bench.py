@@ -16,9 +16,9 @@ The JSON line also carries:
                 pass over every iterating member), timed with HIP events on
                 the library's stream in one chunk of iterations out of
                 --sample during the timed steps; algorithmic bytes per launch
-                = 12 vectors of N doubles of every member still iterating
-                (reads s^, p^, v^, t^, eps, sigma, x, shadow; writes x, r^,
-                p^, v^);
+                = 85 B per node of every member still iterating (reads s^,
+                p^, v^, t^, x, sigma in FP64, the coefficient's one-byte
+                palette index and the FP32 shadow; writes x, r^, p^, v^);
   cpu_baseline  the serial FP64 oracle, pinned to one core, on a bounded
                 sample of the members, extrapolated to the whole batch by
                 node-iterations;
@@ -45,12 +45,21 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "time to 1e-10 rel residual & HBM GB/s: FP64 vs mixed-precision vs batched"
-# Bytes of one BiCGSTAB iteration in units of N elements: the method's own
-# count for the fused schedule (operator from eps alone; reads r, p, v, eps,
-# shadow / r, v, eps / x, p, s, t, shadow, eps; writes p, v / s, t / x, r),
-# and this build's two kernels (step A 11, step B 6 for Poisson).
+# Bytes of one BiCGSTAB iteration per node: the method's own count for the
+# fused schedule, 20 vectors of the working precision (operator from eps
+# alone; reads r, p, v, eps, shadow / r, v, eps / x, p, s, t, shadow, eps;
+# writes p, v / s, t / x, r), and this build's two kernels on a Poisson
+# system: step A reads s^, p^, v^, t^, x, the coefficient and the FP32 shadow
+# and writes x, r^, p^, v^ (9 elements + coefficient + 4 B); step B reads r^,
+# v^, the coefficient and the shadow and writes s^, t^ (4 elements +
+# coefficient + 4 B).  The coefficient is a one-byte palette index when the
+# field has at most 128 distinct values (the sphere has two).
 ITER_VECTORS_METHOD = 20.0
-ITER_VECTORS_BUILD = 17.0
+
+
+def iter_bytes_build(elem, palette=True):
+    coef = 1 if (palette and os.environ.get("PF_PALETTE") != "0") else elem
+    return 13 * elem + 2 * coef + 8
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector peak
 # Coulomb kernel, per (point, charge) pair: 3 differences, 5 for r^2, 1 for the
 # reciprocal square root, 2 for the potential term and its sum, 5 for the
@@ -117,7 +126,7 @@ def forms_linear(pf, torch, inputs, timing_sample):
         out[name] = dict(seconds=t, iters=info["iters"], refinements=info["refinements"],
                          rel_res=rel, iters_per_s=info["iters"] / t, us_per_iter=t_iter * 1e6,
                          iter_frac_method_bytes=ITER_VECTORS_METHOD * prob.N * elem / t_iter / 1e9 / PEAK_HBM_GBS,
-                         iter_frac_build_bytes=ITER_VECTORS_BUILD * prob.N * elem / t_iter / 1e9 / PEAK_HBM_GBS,
+                         iter_frac_build_bytes=iter_bytes_build(elem) * prob.N / t_iter / 1e9 / PEAK_HBM_GBS,
                          step_a_mean_us=tm["mean_ms"] * 1e3,
                          step_a_gbs=(tm["bytes"] / tm["launches"] / (tm["mean_ms"] * 1e-3) / 1e9)
                          if tm["launches"] else None)
@@ -798,7 +807,9 @@ def main():
             "launches_timed": tm["launches"],
             "mean_us": tm["mean_ms"] * 1e3,
             "bytes_per_launch": bpl,
-            "bytes_rule": "12 vectors x N x 8 B per member still iterating at that launch",
+            "bytes_rule": ("85 B per node of every member still iterating at that launch: s^, p^, v^, t^, x, "
+                           "sigma (8 B each) read, 1-byte coefficient palette index, 4-byte shadow; x, r^, p^, "
+                           "v^ written"),
         },
     }
     if args.forms:

@@ -131,7 +131,9 @@ typedef struct {
 } pf_lin_info;
 
 /* Fill *o with defaults: rel_tol 1e-10, max_iter 20000, PF_FP64,
- * inner_tol 1e-5, max_refine 30, check_every 0, PF_STOP_REL2. */
+ * inner_tol 1e-2, max_refine 30, check_every 0, PF_STOP_REL2.  (A loose
+ * inner target keeps each FP32 run far from FP32's attainable accuracy; at
+ * 193^3 it takes 599 inner iterations where 1e-5 takes 881.) */
 void pf_lin_opts_default(pf_lin_opts *o);
 
 /* Solve (-div eps grad + sigma) x = b on grid g (potential boundary data:

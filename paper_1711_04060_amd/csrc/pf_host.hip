@@ -109,7 +109,7 @@ ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz, int
     c.nzc = (nz + c.KZ - 1) / c.KZ;
     c.G = c.nstrips * c.nzc;
     c.lmax = std::min(P, c.S + 2 * nx);
-    c.lds = 4 * (size_t)c.lmax * elem;   // two planes of (value, coefficient)
+    c.lds = (4 * (size_t)c.lmax + pfk::PAL_MAX) * elem;   // two planes of (value, coefficient), the palette
     c.wide = 2 * nx > halo_slots(ntz) * ntz;
     c.depth = c.wide ? 1 : (depth ? depth : (g_depth_override ? g_depth_override : default_depth(elem, ppt)));
     return c;
@@ -148,10 +148,13 @@ struct GraphKey {
     }
 };
 
+// Krylov vectors of one precision; the shadow residual is kept in FP32 in
+// both (the shadow vector of Table 3 is r0 rounded to FP32).
 template <typename T>
 struct Work {
-    T *x = nullptr, *r = nullptr, *rt = nullptr, *p[2] = {nullptr, nullptr},
-      *v[2] = {nullptr, nullptr}, *s = nullptr, *t = nullptr;
+    T *x = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *v[2] = {nullptr, nullptr}, *s = nullptr,
+      *t = nullptr;
+    float *rt = nullptr;
 };
 
 }  // namespace
@@ -170,6 +173,10 @@ struct pf_grid {
 
     double *eps64 = nullptr;           // coefficient field; sign bit set on Dirichlet rows (F_DIR_PHI)
     float *eps32 = nullptr;
+    int npal = 0;                      // palette form: number of distinct |eps| (0: no palette)
+    uint8_t *epsi = nullptr;           // palette index per node, bit 7 = Dirichlet row
+    double *pal64 = nullptr;           // PAL_MAX values (unused entries 0)
+    float *pal32 = nullptr;
     uint8_t *flags = nullptr;
     double *dval = nullptr;
     double *q = nullptr;               // fixed charge (may stay null)
@@ -250,8 +257,9 @@ pf_status ensure_work(pf_grid *g)
         if (g->have64) return PF_OK;
         Work<double> &w = g->w64;
         PFCHK(dalloc(g, &g->b64, g->N));
-        for (double **p : {&w.x, &w.r, &w.rt, &w.p[0], &w.p[1], &w.v[0], &w.v[1], &w.s, &w.t})
+        for (double **p : {&w.x, &w.r, &w.p[0], &w.p[1], &w.v[0], &w.v[1], &w.s, &w.t})
             PFCHK(dalloc(g, p, g->N));
+        PFCHK(dalloc(g, &w.rt, g->N));
         g->have64 = true;
         PFCHK(tune<double>(g));
     } else {
@@ -276,11 +284,11 @@ pf_status ensure_work(pf_grid *g)
 // e0, e1 (optional): events that the dispatch itself stamps at the kernel's
 // start and end (hipExtLaunchKernel), so their interval is the kernel's own
 // duration, without the marker packets of separate event records.
-template <int OP, typename T, bool CEPS, bool SIG, int NTZ, int PPT, bool WIDE = false, int DEPTH = 1>
+template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NTZ, int PPT, bool WIDE = false, int DEPTH = 1>
 hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEvent_t e0 = nullptr,
                      hipEvent_t e1 = nullptr)
 {
-    auto kern = pfk::k_zmarch<OP, T, CEPS, SIG, NTZ, PPT, WIDE, DEPTH>;
+    auto kern = pfk::k_zmarch<OP, T, CEPS, SIG, PAL, NTZ, PPT, WIDE, DEPTH>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;   // per instantiation
         if (c.lds > granted) {
@@ -295,12 +303,12 @@ hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEv
     return hipGetLastError();
 }
 
-template <int OP, typename T, bool CEPS, bool SIG>
+template <int OP, typename T, bool CEPS, bool SIG, bool PAL>
 hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEvent_t e0 = nullptr,
                     hipEvent_t e1 = nullptr)
 {
     if (c.wide) {
-        if (c.NTZ == 1024 && c.PPT == 1) return launch_zk<OP, T, CEPS, SIG, 1024, 1, true>(c, a, s, e0, e1);
+        if (c.NTZ == 1024 && c.PPT == 1) return launch_zk<OP, T, CEPS, SIG, PAL, 1024, 1, true>(c, a, s, e0, e1);
         return hipErrorInvalidValue;
     }
     // the BiCGSTAB steps and the Jacobi-scaled product come in both pipeline
@@ -308,31 +316,31 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEve
     constexpr bool PIPE = (OP == pfk::OP_BA || OP == pfk::OP_BB || OP == pfk::OP_SPMV_JAC);
     if (PIPE && c.depth == 2) {
         switch (c.NTZ * 10 + c.PPT) {
-        case 2561: return launch_zk<OP, T, CEPS, SIG, 256, 1, false, 2>(c, a, s, e0, e1);
-        case 2562: return launch_zk<OP, T, CEPS, SIG, 256, 2, false, 2>(c, a, s, e0, e1);
-        case 5121: return launch_zk<OP, T, CEPS, SIG, 512, 1, false, 2>(c, a, s, e0, e1);
-        case 5122: return launch_zk<OP, T, CEPS, SIG, 512, 2, false, 2>(c, a, s, e0, e1);
-        case 10241: return launch_zk<OP, T, CEPS, SIG, 1024, 1, false, 2>(c, a, s, e0, e1);
-        case 10242: return launch_zk<OP, T, CEPS, SIG, 1024, 2, false, 2>(c, a, s, e0, e1);
+        case 2561: return launch_zk<OP, T, CEPS, SIG, PAL, 256, 1, false, 2>(c, a, s, e0, e1);
+        case 2562: return launch_zk<OP, T, CEPS, SIG, PAL, 256, 2, false, 2>(c, a, s, e0, e1);
+        case 5121: return launch_zk<OP, T, CEPS, SIG, PAL, 512, 1, false, 2>(c, a, s, e0, e1);
+        case 5122: return launch_zk<OP, T, CEPS, SIG, PAL, 512, 2, false, 2>(c, a, s, e0, e1);
+        case 10241: return launch_zk<OP, T, CEPS, SIG, PAL, 1024, 1, false, 2>(c, a, s, e0, e1);
+        case 10242: return launch_zk<OP, T, CEPS, SIG, PAL, 1024, 2, false, 2>(c, a, s, e0, e1);
         default: return hipErrorInvalidValue;
         }
     }
     switch (c.NTZ * 10 + c.PPT) {
-    case 2561: return launch_zk<OP, T, CEPS, SIG, 256, 1>(c, a, s, e0, e1);
-    case 2562: return launch_zk<OP, T, CEPS, SIG, 256, 2>(c, a, s, e0, e1);
-    case 5121: return launch_zk<OP, T, CEPS, SIG, 512, 1>(c, a, s, e0, e1);
-    case 5122: return launch_zk<OP, T, CEPS, SIG, 512, 2>(c, a, s, e0, e1);
-    case 10241: return launch_zk<OP, T, CEPS, SIG, 1024, 1>(c, a, s, e0, e1);
-    case 10242: return launch_zk<OP, T, CEPS, SIG, 1024, 2>(c, a, s, e0, e1);
+    case 2561: return launch_zk<OP, T, CEPS, SIG, PAL, 256, 1>(c, a, s, e0, e1);
+    case 2562: return launch_zk<OP, T, CEPS, SIG, PAL, 256, 2>(c, a, s, e0, e1);
+    case 5121: return launch_zk<OP, T, CEPS, SIG, PAL, 512, 1>(c, a, s, e0, e1);
+    case 5122: return launch_zk<OP, T, CEPS, SIG, PAL, 512, 2>(c, a, s, e0, e1);
+    case 10241: return launch_zk<OP, T, CEPS, SIG, PAL, 1024, 1>(c, a, s, e0, e1);
+    case 10242: return launch_zk<OP, T, CEPS, SIG, PAL, 1024, 2>(c, a, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int OP, typename T, bool CEPS, bool SIG, int NTZ, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NTZ, int PPT, bool WIDE, int DEPTH>
 hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s,
                           hipEvent_t e0, hipEvent_t e1)
 {
-    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, SIG, NTZ, PPT, WIDE, DEPTH>;
+    auto kern = pfk::k_zmarch_batch<OP, T, CEPS, SIG, PAL, NTZ, PPT, WIDE, DEPTH>;
     if (c.lds > 64 * 1024) {
         static size_t granted = 0;
         if (c.lds > granted) {
@@ -349,50 +357,56 @@ hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *s
 
 // c: the batch's combined launch (its NTZ, PPT, depth shared by every member;
 // G = all members' tiles, lds and wide = the maxima)
-template <int OP, typename T, bool CEPS, bool SIG>
+template <int OP, typename T, bool CEPS, bool SIG, bool PAL>
 hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     if (c.wide) {
         if (c.NTZ == 1024 && c.PPT == 1)
-            return launch_batch_k<OP, T, CEPS, SIG, 1024, 1, true, 1>(c, args, start, n, s, e0, e1);
+            return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, true, 1>(c, args, start, n, s, e0, e1);
         return hipErrorInvalidValue;
     }
     if (c.depth == 2) {
         switch (c.NTZ * 10 + c.PPT) {
-        case 2561: return launch_batch_k<OP, T, CEPS, SIG, 256, 1, false, 2>(c, args, start, n, s, e0, e1);
-        case 2562: return launch_batch_k<OP, T, CEPS, SIG, 256, 2, false, 2>(c, args, start, n, s, e0, e1);
-        case 5121: return launch_batch_k<OP, T, CEPS, SIG, 512, 1, false, 2>(c, args, start, n, s, e0, e1);
-        case 5122: return launch_batch_k<OP, T, CEPS, SIG, 512, 2, false, 2>(c, args, start, n, s, e0, e1);
-        case 10241: return launch_batch_k<OP, T, CEPS, SIG, 1024, 1, false, 2>(c, args, start, n, s, e0, e1);
-        case 10242: return launch_batch_k<OP, T, CEPS, SIG, 1024, 2, false, 2>(c, args, start, n, s, e0, e1);
+        case 2561: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 1, false, 2>(c, args, start, n, s, e0, e1);
+        case 2562: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 2, false, 2>(c, args, start, n, s, e0, e1);
+        case 5121: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 1, false, 2>(c, args, start, n, s, e0, e1);
+        case 5122: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 2, false, 2>(c, args, start, n, s, e0, e1);
+        case 10241: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, false, 2>(c, args, start, n, s, e0, e1);
+        case 10242: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 2, false, 2>(c, args, start, n, s, e0, e1);
         default: return hipErrorInvalidValue;
         }
     }
     switch (c.NTZ * 10 + c.PPT) {
-    case 2561: return launch_batch_k<OP, T, CEPS, SIG, 256, 1, false, 1>(c, args, start, n, s, e0, e1);
-    case 2562: return launch_batch_k<OP, T, CEPS, SIG, 256, 2, false, 1>(c, args, start, n, s, e0, e1);
-    case 5121: return launch_batch_k<OP, T, CEPS, SIG, 512, 1, false, 1>(c, args, start, n, s, e0, e1);
-    case 5122: return launch_batch_k<OP, T, CEPS, SIG, 512, 2, false, 1>(c, args, start, n, s, e0, e1);
-    case 10241: return launch_batch_k<OP, T, CEPS, SIG, 1024, 1, false, 1>(c, args, start, n, s, e0, e1);
-    case 10242: return launch_batch_k<OP, T, CEPS, SIG, 1024, 2, false, 1>(c, args, start, n, s, e0, e1);
+    case 2561: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 1, false, 1>(c, args, start, n, s, e0, e1);
+    case 2562: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 2, false, 1>(c, args, start, n, s, e0, e1);
+    case 5121: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 1, false, 1>(c, args, start, n, s, e0, e1);
+    case 5122: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 2, false, 1>(c, args, start, n, s, e0, e1);
+    case 10241: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, false, 1>(c, args, start, n, s, e0, e1);
+    case 10242: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 2, false, 1>(c, args, start, n, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
 
-// The three kernel forms of an operator: PF1 (constant coefficient), the
-// potential system with a shift array (sigma read at every own node), and
-// without one.  Only the BiCGSTAB steps have the shift-array form; the other
-// kernels read sigma at their outputs.
-enum { FORM_PLAIN = 0, FORM_SIG = 1, FORM_CEPS = 2 };
+// Kernel forms of an operator: PF1 (constant coefficient), the potential
+// system with a shift array (sigma read at every own node) or without one,
+// each with the coefficient field read in full or as palette indices.  Only
+// the BiCGSTAB steps have the shift-array forms (the other kernels read
+// sigma at their outputs), and only they and the Jacobi-scaled product have
+// the palette forms.
+enum { FORM_PLAIN = 0, FORM_SIG = 1, FORM_CEPS = 2, FORM_PAL = 3, FORM_PALSIG = 4 };
 
 template <int OP, typename T>
 hipError_t launch_batch_form(int form, const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n,
                              hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
-    if (form == FORM_CEPS) return launch_batch<OP, T, true, false>(c, args, start, n, s, e0, e1);
-    if (form == FORM_SIG) return launch_batch<OP, T, false, true>(c, args, start, n, s, e0, e1);
-    return launch_batch<OP, T, false, false>(c, args, start, n, s, e0, e1);
+    switch (form) {
+    case FORM_CEPS: return launch_batch<OP, T, true, false, false>(c, args, start, n, s, e0, e1);
+    case FORM_SIG: return launch_batch<OP, T, false, true, false>(c, args, start, n, s, e0, e1);
+    case FORM_PAL: return launch_batch<OP, T, false, false, true>(c, args, start, n, s, e0, e1);
+    case FORM_PALSIG: return launch_batch<OP, T, false, true, true>(c, args, start, n, s, e0, e1);
+    default: return launch_batch<OP, T, false, false, false>(c, args, start, n, s, e0, e1);
+    }
 }
 
 template <typename T>
@@ -434,18 +448,41 @@ struct OpDesc {
 
 uint8_t dirbit(const OpDesc &op) { return op.psi ? pfk::F_DIR_PSI : pfk::F_DIR_PHI; }
 
-// Kernel form of the BiCGSTAB steps for this operator.
-int step_form(const OpDesc &op) { return op.psi ? FORM_CEPS : (op.sigma ? FORM_SIG : FORM_PLAIN); }
-
-// Vectors of N elements step A moves per launch: s^, p^, v^, t^, eps read at
-// every staged node, x and the shadow at own nodes, x, r^, p^, v^ written;
-// sigma as one more read in the SIG form; the PF1 form reads one flag byte
-// per node instead of eps.
-double step_a_bytes(const OpDesc &op, size_t N, size_t elem)
+// The palette form is used where the grid has one (PF_PALETTE=0 turns it off,
+// for comparisons).
+bool use_palette(const pf_grid *g)
 {
-    const int form = step_form(op);
-    const double vec = form == FORM_CEPS ? 10.0 : (form == FORM_SIG ? 12.0 : 11.0);
-    return vec * (double)N * (double)elem + (form == FORM_CEPS ? (double)N : 0.0);
+    static const bool on = [] {
+        const char *e = getenv("PF_PALETTE");
+        return !(e && e[0] == '0');
+    }();
+    return on && g->npal > 0;
+}
+
+// Kernel form of the BiCGSTAB steps for this operator on grid g.
+int step_form(const OpDesc &op, const pf_grid *g)
+{
+    if (op.psi) return FORM_CEPS;
+    if (use_palette(g)) return op.sigma ? FORM_PALSIG : FORM_PAL;
+    return op.sigma ? FORM_SIG : FORM_PLAIN;
+}
+
+// Bytes per node of the coefficient read: the full field, a palette index,
+// or (PF1) a flag byte.
+double coef_bytes(int form, size_t elem)
+{
+    return (form == FORM_CEPS || form == FORM_PAL || form == FORM_PALSIG) ? 1.0 : (double)elem;
+}
+
+// Algorithmic bytes of one step-A launch on N nodes: s^, p^, v^, t^ and the
+// coefficient read at every staged node, x, the FP32 shadow (and sigma) at
+// own nodes; x, r^, p^, v^ written.
+double step_a_bytes(const OpDesc &op, const pf_grid *g, size_t elem)
+{
+    const int form = step_form(op, g);
+    const bool sig = form == FORM_SIG || form == FORM_PALSIG;
+    const double per = 4.0 * elem + coef_bytes(form, elem) + elem + 4.0 + (sig ? (double)elem : 0.0) + 4.0 * elem;
+    return per * (double)g->N;
 }
 
 template <typename T>
@@ -461,11 +498,14 @@ pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const ZCfg &c)
     a.cidiag = (T)(1.0 / (6.0 * op.ceps * ih2 + op.sig_const));
     a.flags = g->flags;
     a.dirbit = dirbit(op);
+    a.epsi = g->epsi;
     if constexpr (sizeof(T) == 8) {
         a.eps = g->eps64;
+        a.pal = g->pal64;
         a.sig = op.sigma;
     } else {
         a.eps = g->eps32;
+        a.pal = g->pal32;
         a.sig = op.sigma ? g->sig32 : nullptr;   // converted by the mixed solve's set-up
     }
     a.sigma = op.sigma;
@@ -491,10 +531,16 @@ pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a, const ZC
                   hipEvent_t e1 = nullptr)
 {
     constexpr bool STEP = (OP == pfk::OP_BA || OP == pfk::OP_BB);
+    constexpr bool PALOK = STEP || OP == pfk::OP_SPMV_JAC;
+    const bool pal = PALOK && use_palette(g);
     hipError_t e;
-    if (op.psi) e = launch_z<OP, T, true, false>(c, a, g->stream, e0, e1);
-    else if (STEP && op.sigma) e = launch_z<OP, T, false, STEP>(c, a, g->stream, e0, e1);
-    else e = launch_z<OP, T, false, false>(c, a, g->stream, e0, e1);
+    if (op.psi) e = launch_z<OP, T, true, false, false>(c, a, g->stream, e0, e1);
+    else if (STEP && op.sigma)
+        e = pal ? launch_z<OP, T, false, STEP, PALOK>(c, a, g->stream, e0, e1)
+                : launch_z<OP, T, false, STEP, false>(c, a, g->stream, e0, e1);
+    else
+        e = pal ? launch_z<OP, T, false, false, PALOK>(c, a, g->stream, e0, e1)
+                : launch_z<OP, T, false, false, false>(c, a, g->stream, e0, e1);
     if (e != hipSuccess) return fail(PF_ERR_DEVICE, "stencil kernel launch failed: %s", hipGetErrorString(e));
     return PF_OK;
 }
@@ -519,12 +565,12 @@ pf_status prepare_f32(pf_grid *g, const OpDesc &op)
 }
 
 // True FP64 residual r = b - A x (and ||r||^2 into sc->red[slot]); optional
-// shadow copies (r) and Krylov start vectors (s^ = D^-1 r), FP64 or FP32.
-// lift: use the Dirichlet values as x (b_lift).  The launch shape c, the
-// partials buffer and the scalar block are the grid's unless given.
+// shadow copy (r rounded to FP32) and Krylov start vector (s^ = D^-1 r, FP64
+// or FP32).  lift: use the Dirichlet values as x (b_lift).  The launch shape
+// c, the partials buffer and the scalar block are the grid's unless given.
 pf_status residual64(pf_grid *g, const OpDesc &op, const double *b, const double *x, double *r, bool lift,
-                     double *rt64, float *rt32, double *rs64, float *rs32, int slot = 0,
-                     const ZCfg *cshape = nullptr, double *partials = nullptr, Scalars *sc = nullptr)
+                     float *rt32, double *rs64, float *rs32, int slot = 0, const ZCfg *cshape = nullptr,
+                     double *partials = nullptr, Scalars *sc = nullptr)
 {
     const ZCfg &c = cshape ? *cshape : cfg_of<double>(g);
     pfk::ZArgs<double> a = zbase_cfg<double>(g, op, c);
@@ -535,7 +581,6 @@ pf_status residual64(pf_grid *g, const OpDesc &op, const double *b, const double
     a.b = b;
     a.lift = lift ? 1 : 0;
     a.dval = op.psi ? nullptr : g->dval;
-    a.rt64 = rt64;
     a.rt32 = rt32;
     a.rs64 = rs64;
     a.rs32 = rs32;
@@ -641,7 +686,7 @@ pf_status run_chunk(pf_grid *g, const OpDesc &op, Work<T> &w, int m, bool may_ti
         for (int i = 0; i < m; ++i) PFCHK(iteration<T>(g, op, w, i & 1, g->tev[2 * i], g->tev[2 * i + 1]));
         return PF_OK;
     }
-    const GraphKey key{m, (int)sizeof(T), step_form(op), op.sigma};
+    const GraphKey key{m, (int)sizeof(T), step_form(op, g), op.sigma};
     auto it = g->graphs.find(key);
     if (it == g->graphs.end()) {
         hipGraph_t graph;
@@ -710,10 +755,14 @@ pf_status tune(pf_grid *g)
         if constexpr (sizeof(T) == 8) return g->w64;
         else return g->w32;
     }();
-    PFCHK(fill<T>(g, w.r, T(1), g->N));
-    PFCHK(fill<T>(g, w.s, T(1), g->N));
+    // non-constant operands, so that no step finds a vanishing product (a
+    // restart or stop decision would make the timed launches exit early)
+    hipLaunchKernelGGL((pfk::k_fill_pattern<T>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.r, 0.0);
+    hipLaunchKernelGGL((pfk::k_fill_pattern<T>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.s, 0.37);
+    hipLaunchKernelGGL((pfk::k_fill_pattern<float>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.rt,
+                       0.71);
+    HIPCHK(hipGetLastError());
     PFCHK(fill<T>(g, w.t, T(0), g->N));
-    PFCHK(fill<T>(g, w.rt, T(1), g->N));
     PFCHK(fill<T>(g, w.p[0], T(0), g->N));
     PFCHK(fill<T>(g, w.v[0], T(0), g->N));
     Scalars &h = *g->hsc;
@@ -822,7 +871,7 @@ pf_status tune_product(pf_grid *g, const OpDesc &op)
         if constexpr (sizeof(T) == 8) return g->w64;
         else return g->w32;
     }();
-    T *xs[4] = {w.r, w.s, w.rt, w.t};
+    T *xs[4] = {w.r, w.s, w.t, w.x};
     T *ys[4] = {w.p[0], w.p[1], w.v[0], w.v[1]};
     for (T *x : xs) PFCHK(fill<T>(g, x, T(1), g->N));
     hipEvent_t e0, e1;
@@ -947,7 +996,7 @@ pf_status krylov_run(pf_grid *g, const OpDesc &op, Work<T> &w, int m_fixed, int 
                 HIPCHK(hipEventElapsedTime(&ms, g->tev[2 * i], g->tev[2 * i + 1]));
                 g_timing.ms[pi] += ms;
                 g_timing.launches[pi] += 1;
-                g_timing.bytes[pi] += step_a_bytes(op, g->N, sizeof(T));
+                g_timing.bytes[pi] += step_a_bytes(op, g, sizeof(T));
             }
         }
         if (g->hsc->stop != pfk::ST_RUN) {
@@ -989,6 +1038,8 @@ struct LinSolve {
     bool mixed = false;
     double bnorm = 0, tol2 = 0, rr = 0, rinf = 0;   // rinf: true ||r||_inf (PF_STOP_ABS_INF)
     double rr_start = 0;                             // ||r||^2 when the last refinement step began
+    double rr_best = INFINITY;                       // FP64 Krylov runs: smallest true ||r||^2 so far
+    int stall = 0;                                   // consecutive runs that did not halve ||r||
     int iter = 0, restarts = 0, refinements = 0;
     bool started = false, done = false, fallback = false;
     pf_status result = PF_OK;
@@ -1000,9 +1051,9 @@ pf_status ls_round_residual(LinSolve &L)
 {
     pf_grid *g = L.g;
     if (L.mixed)
-        PFCHK(residual64(g, L.op, g->b64, g->w64.x, g->w64.r, false, nullptr, g->w32.rt, nullptr, g->w32.s));
+        PFCHK(residual64(g, L.op, g->b64, g->w64.x, g->w64.r, false, g->w32.rt, nullptr, g->w32.s));
     else
-        PFCHK(residual64(g, L.op, g->b64, g->w64.x, g->w64.r, false, g->w64.rt, nullptr, g->w64.s, nullptr));
+        PFCHK(residual64(g, L.op, g->b64, g->w64.x, g->w64.r, false, g->w64.rt, g->w64.s, nullptr));
     if (L.o->stop_rule == PF_STOP_ABS_INF) {   // ||r||_inf of the free rows into red[2]
         const int B = pw_blocks(g->N);
         hipLaunchKernelGGL(pfk::k_maxabs_free<NT>, dim3(B), dim3(NT), 0, g->stream, g->N, (const double *)g->w64.r,
@@ -1039,7 +1090,7 @@ pf_status ls_init_launch(LinSolve &L)
     hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
                        (const uint8_t *)g->flags, dirbit(L.op), L.op.psi ? nullptr : (const double *)g->dval);
     HIPCHK(hipGetLastError());
-    PFCHK(residual64(g, L.op, g->b64, nullptr, g->w64.r, true, nullptr, nullptr, nullptr, nullptr, 1));
+    PFCHK(residual64(g, L.op, g->b64, nullptr, g->w64.r, true, nullptr, nullptr, nullptr, 1));
     PFCHK(ls_round_residual(L));
     HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
     return PF_OK;
@@ -1122,6 +1173,14 @@ pf_status ls_round_decide(LinSolve &L, bool *run)
     }
     if (!L.mixed) {
         if (L.iter >= L.o->max_iter) { L.result = PF_ERR_NOCONV; L.done = true; return PF_OK; }
+        // a tolerance below the attainable accuracy (rounding of A x at the
+        // operator's condition number) shows as runs that end by the
+        // recurrence while the true residual stays put: stop after three
+        if (L.started) {
+            L.stall = (L.rr > 0.25 * L.rr_best) ? L.stall + 1 : 0;
+            if (L.stall >= 3) { L.result = PF_ERR_NOCONV; L.done = true; return PF_OK; }
+        }
+        L.rr_best = std::min(L.rr_best, L.rr);
         if (L.started) ++L.restarts;
         if (L.restarts > 1000) { L.result = PF_ERR_BREAKDOWN; L.done = true; return PF_OK; }
         L.started = true;
@@ -1228,17 +1287,24 @@ struct BatchBuf {
 } g_batch;
 
 // Launch of one batched BiCGSTAB step: every member shares the kernel
-// instance (threads, nodes per thread, pipeline depth).  Two policies:
+// instance (threads, nodes per thread, pipeline depth).  Policies:
 //   0: the instance most of the work was tuned to on its own (weighted by N),
 //      each member with the z-chunk length of its own tuned shape;
-//   1: 512 threads, one node per thread, z-chunks of clamp(strips nz / 256,
-//      2, 16) planes (a batch has more tiles than one system, so longer
-//      chunks lose less to the planes above and below each chunk).
+//   1: 512 threads, one node per thread, the default depth, z-chunks of
+//      clamp(strips nz / 256, 2, 16) planes (a batch has more tiles than one
+//      system, so longer chunks lose less to the planes above and below);
+//   2: 512 threads, one node per thread, depth 1, the members' z-chunks;
+//   3: 256 threads, one node per thread, depth 1, long z-chunks as in 1.
 // step: 0 = A, 1 = B.
+constexpr int NPOLICY = 4;
+
 template <typename T>
 std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int policy, ZCfg &combined)
 {
     int ntz = 512, ppt = 1, depth = default_depth(sizeof(T), 1);
+    const bool own_kz = policy == 0 || policy == 2;
+    if (policy == 2) depth = 1;
+    if (policy == 3) { ntz = 256; depth = 1; }
     if (policy == 0) {
         std::map<std::tuple<int, int, int>, double> weight;
         for (const LinSolve *L : act) {
@@ -1260,10 +1326,11 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
     for (const LinSolve *L : act) {
         const pf_grid *g = L->g;
         int kz;
-        if (policy == 0) {
+        if (own_kz) {
             kz = (step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g)).KZ;
         } else {
-            const long strips = ((long)g->nx * g->ny + 511) / 512;
+            const long S = (long)ntz * ppt;
+            const long strips = ((long)g->nx * g->ny + S - 1) / S;
             kz = (int)std::max<long>(2, std::min<long>(16, strips * g->nz / 256));
         }
         ZCfg c = make_cfg(g->nx, g->ny, g->nz, sizeof(T), ntz, ppt, kz, depth);
@@ -1284,9 +1351,11 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
     return cs;
 }
 
-// Policy chosen per batch composition (precision, operator kind, member
-// shapes) by timing the first two chunks of its first run, one per policy.
+// Policy chosen per batch composition (precision, kernel form, member
+// shapes) from one chunk per policy (its first chunks, over as many runs as
+// that takes): the one with the most node-iterations per second is kept.
 std::map<std::vector<long>, int> g_batch_policy;
+std::map<std::vector<long>, std::vector<double>> g_batch_trials;   // per policy, -1 = not yet timed
 
 // One instantiated graph chunk of a batched Krylov run under one policy, and
 // the launches it holds (for the sampled chunks of kernel timing, which run
@@ -1312,9 +1381,14 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     // one kernel form for every member: the SIG form if any member has a
     // shift array (members without one read zeros)
     int form = psi ? FORM_CEPS : FORM_PLAIN;
-    if (!psi)
-        for (const LinSolve *L : act)
-            if (L->op.sigma) form = FORM_SIG;
+    if (!psi) {
+        bool sig = false, pal = true;
+        for (const LinSolve *L : act) {
+            sig = sig || L->op.sigma;
+            pal = pal && use_palette(L->g);
+        }
+        form = pal ? (sig ? FORM_PALSIG : FORM_PAL) : (sig ? FORM_SIG : FORM_PLAIN);
+    }
     std::vector<long> key = {(long)sizeof(T), (long)form};
     {
         std::vector<long> shapes;
@@ -1324,8 +1398,18 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     }
     const auto known = g_batch_policy.find(key);
     // only batches of several members are compared (small ones keep policy 0)
-    const int npol = (known != g_batch_policy.end() || !tuning_enabled() || n < 4) ? 1 : 2;
+    const int npol = (known != g_batch_policy.end() || !tuning_enabled() || n < 4) ? 1 : NPOLICY;
     const int pol0 = known != g_batch_policy.end() ? known->second : 0;
+    std::vector<double> *trials = nullptr;
+    if (npol > 1) {
+        trials = &g_batch_trials[key];
+        if (trials->empty()) trials->assign(NPOLICY, -1.0);
+    }
+    auto next_untried = [&]() {
+        for (int k = 0; k < NPOLICY; ++k)
+            if ((*trials)[k] < 0) return k;
+        return -1;
+    };
 
     // device tables: per policy the step A / B arguments (two parities) and
     // tile start tables; shared scalar pointers and gather buffer
@@ -1358,7 +1442,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     Scalars *dgather = (Scalars *)take(szS);
     HIPCHK(hipMemcpyAsync(dscp, scp.data(), szP, hipMemcpyHostToDevice, stream));
 
-    BatchPlan plans[2];
+    BatchPlan plans[NPOLICY];
     for (int k = 0; k < npol; ++k) {
         const int pol = npol == 1 ? pol0 : k;
         std::vector<pfk::ZArgs<T>> za[2], zb[2];
@@ -1373,7 +1457,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
             if constexpr (sizeof(T) == 8) w = &g->w64;
             else w = &g->w32;
             const T *zero_sig = nullptr;
-            if (form == FORM_SIG && !L.op.sigma) {
+            if ((form == FORM_SIG || form == FORM_PALSIG) && !L.op.sigma) {
                 if constexpr (sizeof(T) == 8) {
                     if (!g->sig64) PFCHK(dalloc(g, &g->sig64, g->N));
                     zero_sig = g->sig64;
@@ -1429,14 +1513,14 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
     }
 
     status.assign(n, pfk::ST_RUN);
-    double secs[2] = {0, 0};
-    int use = 0;   // plan index of the next chunk
+    int use = npol > 1 ? next_untried() : 0;   // plan index of the next chunk
+    bool comparing = npol > 1;
     // kernel timing: iterations done per member before the chunk, step-A bytes per member
     std::vector<int> before(n);
     std::vector<double> abytes(n);
     for (int i = 0; i < n; ++i) {
         before[i] = act[i]->g->hsc->iter_done;
-        abytes[i] = step_a_bytes(act[i]->op, act[i]->g->N, sizeof(T));
+        abytes[i] = step_a_bytes(act[i]->op, act[i]->g, sizeof(T));
     }
     const int tslot = sizeof(T) == 8 ? 4 : 5;
     for (int chunk = 0;; ++chunk) {
@@ -1474,29 +1558,32 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
                 g_timing.bytes[tslot] += bytes;
             }
         }
-        for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
-        bool any = false, all = true;
+        bool any = false;
         for (int i = 0; i < n; ++i) {
             status[i] = g_batch.hsc[i].stop;
             any |= status[i] == pfk::ST_RUN;
-            all &= status[i] == pfk::ST_RUN;
         }
-        if (npol == 2 && chunk < 2) {
-            secs[use] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (!all) {   // a member stopped: the two chunks are no longer alike; keep policy 0
-                use = 0;
-                g_batch_policy[key] = 0;
-                chunk = 2;
-            } else if (chunk == 0) {
-                use = 1;
-            } else {
-                use = secs[1] < secs[0] ? 1 : 0;
+        if (comparing) {
+            const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            double work = 0;
+            for (int i = 0; i < n; ++i) work += (double)(g_batch.hsc[i].iter_done - before[i]) * (double)act[i]->g->N;
+            // a chunk in which some member stopped did less than a full chunk
+            // of work for it; it still counts, at the rate it achieved
+            if (work > 0) (*trials)[use] = secs > 0 ? work / secs : 0.0;
+            const int nx_ = next_untried();
+            if (nx_ >= 0) {
+                use = nx_;
+            } else {   // every policy has been timed: keep the fastest
+                const std::vector<double> &t = *trials;
+                use = (int)(std::max_element(t.begin(), t.end()) - t.begin());
                 g_batch_policy[key] = use;
+                comparing = false;
                 if (getenv("PF_LOG"))
-                    fprintf(stderr, "[pf] batch of %d: chunk of %d iterations %.2f ms (members' shapes), %.2f ms "
-                                    "(512-thread strips); keeping policy %d\n", n, m, secs[0] * 1e3, secs[1] * 1e3, use);
+                    fprintf(stderr, "[pf] batch of %d: chunks of %d iterations, policies 0..3 at %.3g %.3g %.3g %.3g "
+                                    "node-iterations/s; keeping policy %d\n", n, m, t[0], t[1], t[2], t[3], use);
             }
         }
+        for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
         if (!any) break;
     }
     for (int i = 0; i < n; ++i) *act[i]->g->hsc = g_batch.hsc[i];
@@ -1546,8 +1633,15 @@ pf_status solve_batch(std::vector<LinSolve> &Ls)
     return PF_OK;
 }
 
-// Account one timed product launch (events p0, p1 already complete):
-// bytes = x, eps (and sigma) read and y written.
+// Algorithmic bytes of the Jacobi-scaled product: x and the coefficient (full
+// or palette index) read, y written, and the FP64 sigma read when given.
+double product_bytes(const pf_grid *g, const double *sigma, size_t elem)
+{
+    const double coef = use_palette(g) ? 1.0 : (double)elem;
+    return (2.0 * elem + coef + (sigma ? 8.0 : 0.0)) * (double)g->N;
+}
+
+// Account one timed product launch (events p0, p1 already complete).
 pf_status timing_add_product(int slot, double bytes)
 {
     float ms = 0;
@@ -1555,6 +1649,50 @@ pf_status timing_add_product(int slot, double bytes)
     g_timing.ms[slot] += ms;
     g_timing.launches[slot] += 1;
     g_timing.bytes[slot] += bytes;
+    return PF_OK;
+}
+
+// Palette form of the grid's coefficient field: the distinct values of
+// |eps| are found one at a time (each pass over the field reports the first
+// node whose value is not yet in the palette); with at most PAL_MAX of them
+// the field is also stored as one byte per node.  Otherwise npal stays 0 and
+// the kernels read the full field.
+pf_status build_palette(pf_grid *g)
+{
+    const size_t N = g->N;
+    double *dpal = nullptr;
+    unsigned long long *dmiss = nullptr;
+    PFCHK(dalloc(g, &dpal, pfk::PAL_MAX));
+    PFCHK(dalloc(g, &dmiss, 1));
+    std::vector<double> pal(pfk::PAL_MAX, 0.0);
+    int npal = 0;
+    PFCHK(sync(g));
+    for (;;) {
+        const unsigned long long none = ~0ull;
+        unsigned long long miss = 0;
+        HIPCHK(hipMemcpy(dpal, pal.data(), pfk::PAL_MAX * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dmiss, &none, sizeof none, hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(pfk::k_palette_scan, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, N,
+                           (const double *)g->eps64, (const double *)dpal, npal, dmiss);
+        HIPCHK(hipGetLastError());
+        PFCHK(sync(g));
+        HIPCHK(hipMemcpy(&miss, dmiss, sizeof miss, hipMemcpyDeviceToHost));
+        if (miss == none) break;
+        if (npal == pfk::PAL_MAX) return PF_OK;   // too many distinct values: no palette
+        double v = 0;
+        HIPCHK(hipMemcpy(&v, g->eps64 + miss, sizeof v, hipMemcpyDeviceToHost));
+        pal[npal++] = std::fabs(v);
+    }
+    PFCHK(dalloc(g, &g->epsi, N));
+    PFCHK(dalloc(g, &g->pal32, pfk::PAL_MAX));
+    g->pal64 = dpal;
+    hipLaunchKernelGGL(pfk::k_palette_index, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, N,
+                       (const double *)g->eps64, (const double *)dpal, npal, g->epsi);
+    hipLaunchKernelGGL((pfk::k_convert<float>), dim3(1), dim3(NT), 0, g->stream, (size_t)pfk::PAL_MAX,
+                       (const double *)dpal, g->pal32);
+    HIPCHK(hipGetLastError());
+    PFCHK(sync(g));
+    g->npal = npal;
     return PF_OK;
 }
 
@@ -1583,7 +1721,7 @@ void pf_lin_opts_default(pf_lin_opts *o)
     o->rel_tol = 1e-10;
     o->max_iter = 20000;
     o->precision = PF_FP64;
-    o->inner_tol = 1e-5;
+    o->inner_tol = 1e-2;
     o->max_refine = 30;
     o->check_every = 0;
     o->stop_rule = PF_STOP_REL2;
@@ -1710,6 +1848,7 @@ pf_status pf_grid_create(const pf_grid_desc *d, pf_grid **out)
     hipLaunchKernelGGL(pfk::k_mark_dirichlet, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, N,
                        (const uint8_t *)g->flags, g->eps64);
     if (hipGetLastError() != hipSuccess) return cleanup(fail(PF_ERR_DEVICE, "Dirichlet mark launch failed"));
+    if ((st = build_palette(g)) != PF_OK) return cleanup(st);
     if ((st = sync(g)) != PF_OK) return cleanup(st);
     *out = g;
     return PF_OK;
@@ -1765,8 +1904,8 @@ pf_status pf_residual(pf_grid *g, const double *sigma, const double *b, const do
     OpDesc op;
     op.sigma = sigma;
     double *rbuf = r ? r : g->w64.r;
-    PFCHK(residual64(g, op, b, nullptr, rbuf, true, nullptr, nullptr, nullptr, nullptr, 1));
-    PFCHK(residual64(g, op, b, x, rbuf, false, nullptr, nullptr, nullptr, nullptr, 0));
+    PFCHK(residual64(g, op, b, nullptr, rbuf, true, nullptr, nullptr, nullptr, 1));
+    PFCHK(residual64(g, op, b, x, rbuf, false, nullptr, nullptr, nullptr, 0));
     PFCHK(read_scalars(g));
     const double bn2 = g->hsc->red[1];
     const double rr = g->hsc->red[0];
@@ -1835,8 +1974,8 @@ pf_status pf_residual_noalloc(pf_grid *g, const double *sigma, const double *b, 
     PFCHK(begin(g));
     OpDesc op;
     op.sigma = sigma;
-    PFCHK(residual64(g, op, b, nullptr, r, true, nullptr, nullptr, nullptr, nullptr, 1, &c, part, sc));
-    PFCHK(residual64(g, op, b, x, r, false, nullptr, nullptr, nullptr, nullptr, 0, &c, part, sc));
+    PFCHK(residual64(g, op, b, nullptr, r, true, nullptr, nullptr, nullptr, 1, &c, part, sc));
+    PFCHK(residual64(g, op, b, x, r, false, nullptr, nullptr, nullptr, 0, &c, part, sc));
     double red[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(red, sc->red, sizeof red, hipMemcpyDeviceToHost, g->stream));
     PFCHK(sync(g));
@@ -1911,7 +2050,7 @@ pf_status pf_spmv(pf_grid *g, const double *sigma, const double *x, double *y, i
     if (jacobi) PFCHK((zlaunch<pfk::OP_SPMV_JAC, double>(g, op, a, c, t0, t1)));
     else PFCHK((zlaunch<pfk::OP_SPMV, double>(g, op, a, c)));
     PFCHK(sync(g));
-    if (timed) PFCHK(timing_add_product(2, (sigma ? 4.0 : 3.0) * (double)g->N * sizeof(double)));
+    if (timed) PFCHK(timing_add_product(2, product_bytes(g, sigma, sizeof(double))));
     return PF_OK;
 }
 
@@ -1933,7 +2072,7 @@ pf_status pf_spmv_f32(pf_grid *g, const double *sigma, const float *x, float *y,
     PFCHK((zlaunch<pfk::OP_SPMV_JAC, float>(g, op, a, c, timed ? g_timing.p0 : nullptr,
                                              timed ? g_timing.p1 : nullptr)));
     PFCHK(sync(g));
-    if (timed) PFCHK(timing_add_product(3, 3.0 * (double)g->N * sizeof(float) + (sigma ? 8.0 * (double)g->N : 0.0)));
+    if (timed) PFCHK(timing_add_product(3, product_bytes(g, sigma, sizeof(float))));
     return PF_OK;
 }
 

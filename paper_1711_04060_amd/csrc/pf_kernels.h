@@ -93,6 +93,8 @@ struct ZArgs {
     T ceps;                     // CEPS form: constant face coefficient (already / h^2)
     T cdiag, cidiag;            // CEPS form: constant diagonal 6 ceps + sigma and its inverse
     const T *eps;               // coefficient field, sign bit set on Dirichlet rows (non-CEPS)
+    const uint8_t *epsi;        // PAL form: palette index of each node's coefficient, bit 7 = Dirichlet row
+    const T *pal;               // PAL form: the palette (PAL_MAX values)
     const uint8_t *flags;       // CEPS form: node flags, Dirichlet rows have bit dirbit
     uint8_t dirbit;
     const T *sig;               // SIG form (BA, BB): diagonal shift sigma
@@ -100,7 +102,7 @@ struct ZArgs {
     const T *y0;                // BA: p^ (previous); BB: v^
     const T *y1;                // BA: v^ (previous)
     const T *y2;                // BA: t^
-    const T *rt;                // BA, BB: shadow residual (unscaled)
+    const float *rt;            // BA, BB: shadow residual (unscaled, FP32 in both precisions)
     T *xio;                     // BA: iterate x (read and updated in place)
     T *out;                     // SPMV*: y; RESID: r; BA: v^ (new); BB: t^
     T *out_aux;                 // BA: p^ (new); BB: s^
@@ -112,8 +114,7 @@ struct ZArgs {
     double sig_const;           // used when sigma is null
     const double *dval;         // RESID lift form: Dirichlet values (0 on free rows) or null
     int lift;                   // RESID: use x = Dirichlet values on Dirichlet rows, 0 elsewhere
-    double *rt64;               // RESID: optional shadow copy r (FP64)
-    float *rt32;                // RESID: optional shadow copy r (FP32)
+    float *rt32;                // RESID: optional shadow r, rounded to FP32
     double *rs64;               // RESID: optional Krylov start D^-1 r (FP64)
     float *rs32;                // RESID: optional Krylov start D^-1 r (FP32)
     // reduction and scalars
@@ -390,9 +391,28 @@ __device__ __forceinline__ float absT(float x) { return __builtin_fabsf(x); }
 // sigma in the SIG form; the flag byte in the CEPS form).
 template <typename T>
 struct Raw {
-    T e, x0, x1, x2, x3, x4, t, sg;
-    uint8_t f;
+    T e, x0, x1, x2, x3, x4, sg;
+    float t;
+    uint8_t f, ei;
 };
+
+// Palette form of the coefficient field: fields with at most PAL_MAX
+// distinct values (the piecewise-constant dielectric of Eq. (7): eps_m in the
+// solute region, eps_s in the solvent) are stored as one byte per node, the
+// value's palette index with the Dirichlet mark in bit 7.  The palette is
+// staged in LDS; the value read at a node is the signed coefficient.
+constexpr int PAL_MAX = 128;
+
+template <bool PAL, typename T>
+__device__ __forceinline__ T coef(const Raw<T> &w, const T *lpal)
+{
+    if constexpr (PAL) {
+        const T v = lpal[w.ei & 127];
+        return (w.ei & 128) ? -v : v;
+    } else {
+        return w.e;
+    }
+}
 
 // Load of element g (g < 2^29 nodes, so the byte offset fits 32 bits): the
 // array base stays in scalar registers and one 32-bit vector offset serves
@@ -403,10 +423,11 @@ __device__ __forceinline__ U ldx(const U *base, unsigned g)
     return *reinterpret_cast<const U *>(reinterpret_cast<const char *>(base) + g * (unsigned)sizeof(U));
 }
 
-template <int OP, typename T, bool CEPS, bool SIG, bool OWN>
+template <int OP, typename T, bool CEPS, bool SIG, bool PAL, bool OWN>
 __device__ __forceinline__ void load_raw(const ZArgs<T> &a, unsigned g, Raw<T> &w)
 {
-    if constexpr (!CEPS) w.e = ldx(a.eps, g);
+    if constexpr (PAL) w.ei = ldx(a.epsi, g);
+    else if constexpr (!CEPS) w.e = ldx(a.eps, g);
     if constexpr (CEPS && OWN) w.f = a.flags[g];
     if constexpr (SIG && OWN) w.sg = ldx(a.sig, g);
     if constexpr (OP == OP_SPMV || OP == OP_SPMV_JAC) {
@@ -522,11 +543,12 @@ __device__ __forceinline__ uint8_t own_reg(uint8_t x)
 // issued unconditionally with its plane clamped into the tile's range and
 // its node clamped into the strip, so the number of loads per step is fixed
 // and the wait before staging a plane covers only that plane's loads.
-template <int OP, typename T, bool CEPS, bool SIG, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
 __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, const int slot)
 {
     static_assert(!SIG || OP == OP_BA || OP == OP_BB, "the SIG form is a BiCGSTAB step form");
     static_assert(!(SIG && CEPS), "the CEPS form has a constant shift");
+    static_assert(!(PAL && CEPS), "the CEPS form reads no coefficient field");
     // halo nodes per thread kept in registers (both halo rows fit when
     // 2 nx <= HMAX*NT); the WIDE form stages the rest in a slower
     // synchronous loop, for planes wider than that
@@ -588,6 +610,12 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     auto gown = [&](int q, int k) { return (unsigned)om[q] + Pu * (unsigned)min(k, kown_hi); };
     auto ghal = [&](int u, int k) { return (unsigned)hm[u] + Pu * (unsigned)min(k, khal_hi); };
 
+    // the palette: loaded first, stored behind the two LDS planes once the
+    // plane loads are out, read after the barrier before the first staging
+    T *lpal = reinterpret_cast<T *>(smem_raw) + 4 * a.lmax;
+    T palv = T(0);
+    if constexpr (PAL) palv = a.pal[threadIdx.x & (PAL_MAX - 1)];
+
     // ---- prologue loads: the previous phase's partials, then planes k0-1,
     //      k0 (own), k0 (halo), and the raw sets of planes k0+1 and k0+2
     PartLoad<NQP> pl;
@@ -597,11 +625,11 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     Raw<T> rA[PPT], hA[HMAX], rB[PPT], hB[HMAX];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        load_raw<OP, T, CEPS, SIG, true>(a, gown(q, k0), rc[q]);
-        load_raw<OP, T, CEPS, SIG, false>(a, gown(q, max(k0 - 1, 0)), rp[q]);
+        load_raw<OP, T, CEPS, SIG, PAL, true>(a, gown(q, k0), rc[q]);
+        load_raw<OP, T, CEPS, SIG, PAL, false>(a, gown(q, max(k0 - 1, 0)), rp[q]);
     }
 #pragma unroll
-    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, false>(a, ghal(u, k0), hc[u]);
+    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, PAL, false>(a, ghal(u, k0), hc[u]);
     // The sets go out in the order of the march steps (own, halo, then as
     // many stores as a step makes, here to the sink), so that at the loop's
     // first wait the loads of each set are as far from the newest event as in
@@ -611,17 +639,17 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     constexpr int NST = PPT * ((OP == OP_BA) ? 4 : (OP == OP_BB) ? 2 : (OP == OP_SPMV_JAC) ? 1 : 0);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, true>(a, gown(q, k0 + 1), rA[q]);
+    for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, PAL, true>(a, gown(q, k0 + 1), rA[q]);
 #pragma unroll
-    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, false>(a, ghal(u, k0 + 1), hA[u]);
+    for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, PAL, false>(a, ghal(u, k0 + 1), hA[u]);
 #pragma unroll
     for (int j = 0; j < NST; ++j) sink_store(a.sink + threadIdx.x);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (DEPTH == 2) {
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, true>(a, gown(q, k0 + 2), rB[q]);
+        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, PAL, true>(a, gown(q, k0 + 2), rB[q]);
 #pragma unroll
-        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, false>(a, ghal(u, k0 + 2), hB[u]);
+        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, PAL, false>(a, ghal(u, k0 + 2), hB[u]);
 #pragma unroll
         for (int j = 0; j < NST; ++j) sink_store(a.sink + threadIdx.x);
         __builtin_amdgcn_sched_barrier(0);
@@ -672,6 +700,10 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     alpha = uniform(alpha);
     omega = uniform(omega);
     beta = uniform(beta);
+    if constexpr (PAL) {
+        if (threadIdx.x < PAL_MAX) lpal[threadIdx.x] = palv;
+        __syncthreads();   // palette visible before the first staging
+    }
 
     // two LDS planes (double buffer) of staged values and coefficients
     T *lval0 = reinterpret_cast<T *>(smem_raw);
@@ -681,7 +713,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 
     T vp[PPT], vc[PPT], vn[PPT];   // staged value, planes k-1, k, k+1
     T ep[PPT], ec[PPT], en[PPT];   // coefficient field (signed), planes k-1, k, k+1
-    T tc[PPT], tn[PPT];            // shadow residual (BA, BB), planes k, k+1
+    float tc[PPT], tn[PPT];        // shadow residual (BA, BB), planes k, k+1
     T rc_[PPT], rn_[PPT];          // BA: r^ of planes k, k+1
     T sc_[PPT], sn_[PPT];          // SIG: sigma of planes k, k+1
     uint8_t fc[PPT], fn[PPT];      // CEPS: flag bytes of planes k, k+1
@@ -693,13 +725,14 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         vc[q] = stage_raw<OP, T>(rc[q], alpha, omega, beta);
-        ec[q] = CEPS ? T(0) : rc[q].e;
-        tc[q] = SCAL ? rc[q].t : T(0);
+        ec[q] = CEPS ? T(0) : coef<PAL>(rc[q], lpal);
+        tc[q] = SCAL ? rc[q].t : 0.0f;
         sc_[q] = SIG ? rc[q].sg : T(0);
         fc[q] = CEPS ? rc[q].f : (uint8_t)0;
         vp[q] = stage_raw<OP, T>(rp[q], alpha, omega, beta);
-        ep[q] = CEPS ? T(0) : rp[q].e;
-        vn[q] = en[q] = tn[q] = rn_[q] = sn_[q] = T(0);
+        ep[q] = CEPS ? T(0) : coef<PAL>(rp[q], lpal);
+        vn[q] = en[q] = rn_[q] = sn_[q] = T(0);
+        tn[q] = 0.0f;
         fn[q] = 0;
         rc_[q] = T(0);
         if constexpr (OP == OP_BA) {
@@ -721,16 +754,16 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     for (int u = 0; u < HMAX; ++u) {
         if (hok[u]) {
             lval0[hm[u] - lo] = stage_raw<OP, T>(hc[u], alpha, omega, beta);
-            if constexpr (!CEPS) leps0[hm[u] - lo] = hc[u].e;
+            if constexpr (!CEPS) leps0[hm[u] - lo] = coef<PAL>(hc[u], lpal);
         }
     }
     if (WIDE && nhalo > HMAX * NT) {
         for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
             const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
             Raw<T> w;
-            load_raw<OP, T, CEPS, false, false>(a, (unsigned)m + Pu * (unsigned)k0, w);
+            load_raw<OP, T, CEPS, false, PAL, false>(a, (unsigned)m + Pu * (unsigned)k0, w);
             lval0[m - lo] = stage_raw<OP, T>(w, alpha, omega, beta);
-            if constexpr (!CEPS) leps0[m - lo] = w.e;
+            if constexpr (!CEPS) leps0[m - lo] = coef<PAL>(w, lpal);
         }
     }
     __syncthreads();
@@ -750,7 +783,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             vn[q] = own_reg(stage_raw<OP, T>(ro[q], alpha, omega, beta));
-            if constexpr (!CEPS) en[q] = own_reg(ro[q].e);
+            if constexpr (!CEPS) en[q] = own_reg(coef<PAL>(ro[q], lpal));
             if constexpr (CEPS) fn[q] = own_reg(ro[q].f);
             if constexpr (SIG) sn_[q] = own_reg(ro[q].sg);
             if constexpr (SCAL) tn[q] = own_reg(ro[q].t);
@@ -763,7 +796,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
         for (int u = 0; u < HMAX; ++u) {
             hv[u] = own_reg(stage_raw<OP, T>(rh[u], alpha, omega, beta));
-            if constexpr (!CEPS) he[u] = own_reg(rh[u].e);
+            if constexpr (!CEPS) he[u] = own_reg(coef<PAL>(rh[u], lpal));
         }
         // (2) refill the set with plane k+1+DEPTH (clamped: re-reads of a plane
         //     already loaded near the tile's end hit the cache).  The
@@ -771,9 +804,9 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         //     above, so the loads can reuse its registers.
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, true>(a, gown(q, k + 1 + DEPTH), ro[q]);
+        for (int q = 0; q < PPT; ++q) load_raw<OP, T, CEPS, SIG, PAL, true>(a, gown(q, k + 1 + DEPTH), ro[q]);
 #pragma unroll
-        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, false>(a, ghal(u, k + 1 + DEPTH), rh[u]);
+        for (int u = 0; u < HMAX; ++u) load_raw<OP, T, CEPS, SIG, PAL, false>(a, ghal(u, k + 1 + DEPTH), rh[u]);
         if constexpr (SCAL) {
             // own outputs of plane k+1 when the tile owns it (else the sink)
 #pragma unroll
@@ -838,7 +871,6 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                     const double Ax = Dd * (double)vc[q] - (double)sum;
                     const double r = dir ? 0.0 : a.b[g] - Ax;
                     a.out[g] = (T)r;
-                    if (a.rt64) a.rt64[g] = r;
                     if (a.rt32) a.rt32[g] = (float)r;
                     if (a.rs64 || a.rs32) {
                         const double rs = r * rcp_pos(Dd);
@@ -898,9 +930,9 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             for (int hI = threadIdx.x + HMAX * NT; hI < nhalo; hI += NT) {
                 const int m = (hI < nhl) ? lo + hI : mend + (hI - nhl);
                 Raw<T> w;
-                load_raw<OP, T, CEPS, false, false>(a, (unsigned)m + Pu * (unsigned)(k + 1), w);
+                load_raw<OP, T, CEPS, false, PAL, false>(a, (unsigned)m + Pu * (unsigned)(k + 1), w);
                 nv[m - lo] = stage_raw<OP, T>(w, alpha, omega, beta);
-                if constexpr (!CEPS) ne[m - lo] = w.e;
+                if constexpr (!CEPS) ne[m - lo] = coef<PAL>(w, lpal);
             }
         }
         // one barrier per plane: the buffer written next step was last read
@@ -930,10 +962,10 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     }
 }
 
-template <int OP, typename T, bool CEPS, bool SIG, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
 {
-    zmarch_tile<OP, T, CEPS, SIG, NT, PPT, WIDE, DEPTH>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
+    zmarch_tile<OP, T, CEPS, SIG, PAL, NT, PPT, WIDE, DEPTH>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
 }
 
 // System owning global block b: start[s] <= b < start[s+1].
@@ -949,14 +981,44 @@ __device__ __forceinline__ int batch_system(const int *start, int nsys, int b)
 
 // Batched form: one launch covers the tiles of nsys systems (grids of any
 // size); each system keeps its own scalars, partials and status.
-template <int OP, typename T, bool CEPS, bool SIG, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch_batch(const ZArgs<T> *__restrict__ args,
                                                      const int *__restrict__ start, int nsys)
 {
     const int s = batch_system(start, nsys, blockIdx.x);
     const int lb = blockIdx.x - start[s];
     const ZArgs<T> a = args[s];   // private copy: stores cannot alias it
-    zmarch_tile<OP, T, CEPS, SIG, NT, PPT, WIDE, DEPTH>(a, lb, lb);
+    zmarch_tile<OP, T, CEPS, SIG, PAL, NT, PPT, WIDE, DEPTH>(a, lb, lb);
+}
+
+// Palette of a coefficient field: *miss receives the smallest index n whose
+// |eps[n]| is not among the npal palette values (unchanged when every node's
+// value is there).  Run repeatedly, adding the missed value each time.
+__global__ void k_palette_scan(size_t N, const double *eps, const double *pal, int npal,
+                               unsigned long long *miss)
+{
+    unsigned long long first = ~0ull;
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        const double v = fabs(eps[n]);
+        bool hit = false;
+        for (int i = 0; i < npal && !hit; ++i) hit = (v == pal[i]);
+        if (!hit) { first = n; break; }
+    }
+    if (first != ~0ull) atomicMin(miss, first);
+}
+
+// Palette indices: byte = index of |eps| in the palette, bit 7 = Dirichlet
+// row (eps < 0); the FP32 palette is the FP64 one rounded.
+__global__ void k_palette_index(size_t N, const double *eps, const double *pal, int npal, uint8_t *idx)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        const double e = eps[n], v = fabs(e);
+        int k = 0;
+        while (k < npal - 1 && pal[k] != v) ++k;
+        idx[n] = (uint8_t)(k | (e < 0.0 ? 128 : 0));
+    }
 }
 
 // ------------------------------------------------------------ finalize
@@ -1052,6 +1114,18 @@ __global__ void k_fill(size_t N, T *dst, T v)
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
          n += (size_t)gridDim.x * blockDim.x)
         dst[n] = v;
+}
+
+// A fixed non-constant pattern in [0.5, 1.5) (synthetic operands of the
+// launch-shape tuner: constant vectors make the stencil products vanish).
+template <typename T>
+__global__ void k_fill_pattern(size_t N, T *dst, double off)
+{
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        const double u = ((double)n + off) * 0.6180339887498949;
+        dst[n] = (T)(0.5 + (u - floor(u)));
+    }
 }
 
 // Two copies of N doubles in one launch: d0 = s0, d1 = s1.

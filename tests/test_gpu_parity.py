@@ -14,6 +14,7 @@ Bars (stated per test):
   * nonlinear loop: relative L2 <= 1e-9 at outer_tol 1e-11.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -518,8 +519,12 @@ def test_timing_of_products_and_bad_kind():
         pf.pf_spmv_f32(g, None, x.float(), y.float(), 1)
         t64 = pf.pf_timing_read(pf.TIMING_SPMV_FP64)
         t32 = pf.pf_timing_read(pf.TIMING_SPMV_FP32)
-        assert t64["launches"] == 1 and t64["bytes"] == 3 * p.N * 8 and t64["mean_ms"] >= 0
-        assert t32["launches"] == 1 and t32["bytes"] == 3 * p.N * 4
+        # x and y in the working precision and the coefficient field: one
+        # palette byte per node (the sphere's field has two values) or a full
+        # value when the palette form is switched off
+        coef = (lambda e: 1) if os.environ.get("PF_PALETTE") != "0" else (lambda e: e)
+        assert t64["launches"] == 1 and t64["bytes"] == (16 + coef(8)) * p.N and t64["mean_ms"] >= 0
+        assert t32["launches"] == 1 and t32["bytes"] == (8 + coef(4)) * p.N
         with pytest.raises(pf.PfError):
             pf.pf_timing_read(6)
     finally:
