@@ -109,7 +109,7 @@ ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz, int
     c.nzc = (nz + c.KZ - 1) / c.KZ;
     c.G = c.nstrips * c.nzc;
     c.lmax = std::min(P, c.S + 2 * nx);
-    c.lds = (4 * (size_t)c.lmax + pfk::PAL_MAX) * elem;   // two planes of (value, coefficient), the palette
+    c.lds = (4 * (size_t)c.lmax + pfk::FTAB) * elem;   // two planes of (value, coefficient), the face table
     c.wide = 2 * nx > halo_slots(ntz) * ntz;
     c.depth = c.wide ? 1 : (depth ? depth : (g_depth_override ? g_depth_override : default_depth(elem, ppt)));
     return c;
@@ -175,8 +175,8 @@ struct pf_grid {
     float *eps32 = nullptr;
     int npal = 0;                      // palette form: number of distinct |eps| (0: no palette)
     uint8_t *epsi = nullptr;           // palette index per node, bit 7 = Dirichlet row
-    double *pal64 = nullptr;           // PAL_MAX values (unused entries 0)
-    float *pal32 = nullptr;
+    double *ftab64 = nullptr;          // face coefficients of palette pairs (FTAB values, / h^2)
+    float *ftab32 = nullptr;
     uint8_t *flags = nullptr;
     double *dval = nullptr;
     double *q = nullptr;               // fixed charge (may stay null)
@@ -501,11 +501,11 @@ pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const ZCfg &c)
     a.epsi = g->epsi;
     if constexpr (sizeof(T) == 8) {
         a.eps = g->eps64;
-        a.pal = g->pal64;
+        a.ftab = g->ftab64;
         a.sig = op.sigma;
     } else {
         a.eps = g->eps32;
-        a.pal = g->pal32;
+        a.ftab = g->ftab32;
         a.sig = op.sigma ? g->sig32 : nullptr;   // converted by the mixed solve's set-up
     }
     a.sigma = op.sigma;
@@ -1655,8 +1655,10 @@ pf_status timing_add_product(int slot, double bytes)
 // Palette form of the grid's coefficient field: the distinct values of
 // |eps| are found one at a time (each pass over the field reports the first
 // node whose value is not yet in the palette); with at most PAL_MAX of them
-// the field is also stored as one byte per node.  Otherwise npal stays 0 and
-// the kernels read the full field.
+// the field is also stored as one byte per node, and the face coefficient
+// 2 e_a e_b / (e_a + e_b) / h^2 of every pair of palette values is tabulated
+// (FP64, rounded to FP32 for the FP32 table).  Otherwise npal stays 0 and the
+// kernels read the full field.
 pf_status build_palette(pf_grid *g)
 {
     const size_t N = g->N;
@@ -1684,12 +1686,20 @@ pf_status build_palette(pf_grid *g)
         pal[npal++] = std::fabs(v);
     }
     PFCHK(dalloc(g, &g->epsi, N));
-    PFCHK(dalloc(g, &g->pal32, pfk::PAL_MAX));
-    g->pal64 = dpal;
+    PFCHK(dalloc(g, &g->ftab64, pfk::FTAB));
+    PFCHK(dalloc(g, &g->ftab32, pfk::FTAB));
+    std::vector<double> ft(pfk::FTAB, 0.0);
+    std::vector<float> ft32(pfk::FTAB, 0.0f);
+    const double ih2 = 1.0 / (g->h * g->h);
+    for (int a = 0; a < npal; ++a)
+        for (int b = 0; b < npal; ++b) {
+            ft[a * pfk::PAL_MAX + b] = (2.0 * pal[a] * pal[b]) / (pal[a] + pal[b]) * ih2;
+            ft32[a * pfk::PAL_MAX + b] = (float)ft[a * pfk::PAL_MAX + b];
+        }
+    HIPCHK(hipMemcpy(g->ftab64, ft.data(), pfk::FTAB * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->ftab32, ft32.data(), pfk::FTAB * sizeof(float), hipMemcpyHostToDevice));
     hipLaunchKernelGGL(pfk::k_palette_index, dim3(pw_blocks(N)), dim3(NT), 0, g->stream, N,
                        (const double *)g->eps64, (const double *)dpal, npal, g->epsi);
-    hipLaunchKernelGGL((pfk::k_convert<float>), dim3(1), dim3(NT), 0, g->stream, (size_t)pfk::PAL_MAX,
-                       (const double *)dpal, g->pal32);
     HIPCHK(hipGetLastError());
     PFCHK(sync(g));
     g->npal = npal;

@@ -94,7 +94,7 @@ struct ZArgs {
     T cdiag, cidiag;            // CEPS form: constant diagonal 6 ceps + sigma and its inverse
     const T *eps;               // coefficient field, sign bit set on Dirichlet rows (non-CEPS)
     const uint8_t *epsi;        // PAL form: palette index of each node's coefficient, bit 7 = Dirichlet row
-    const T *pal;               // PAL form: the palette (PAL_MAX values)
+    const T *ftab;              // PAL form: face coefficients of every palette pair (PAL_MAX^2, / h^2)
     const uint8_t *flags;       // CEPS form: node flags, Dirichlet rows have bit dirbit
     uint8_t dirbit;
     const T *sig;               // SIG form (BA, BB): diagonal shift sigma
@@ -399,16 +399,19 @@ struct Raw {
 // Palette form of the coefficient field: fields with at most PAL_MAX
 // distinct values (the piecewise-constant dielectric of Eq. (7): eps_m in the
 // solute region, eps_s in the solvent) are stored as one byte per node, the
-// value's palette index with the Dirichlet mark in bit 7.  The palette is
-// staged in LDS; the value read at a node is the signed coefficient.
-constexpr int PAL_MAX = 128;
+// value's palette index with the Dirichlet mark in bit 7, and the face
+// coefficient of each pair of palette values is precomputed (a table staged
+// in LDS).  The stencil then stages a code per node instead of the value:
+// +-(index + 1), negative on Dirichlet rows.
+constexpr int PAL_MAX = 16;
+constexpr int FTAB = PAL_MAX * PAL_MAX;
 
 template <bool PAL, typename T>
-__device__ __forceinline__ T coef(const Raw<T> &w, const T *lpal)
+__device__ __forceinline__ T coef(const Raw<T> &w)
 {
     if constexpr (PAL) {
-        const T v = lpal[w.ei & 127];
-        return (w.ei & 128) ? -v : v;
+        const T c = (T)((w.ei & (PAL_MAX - 1)) + 1);
+        return (w.ei & 128) ? -c : c;
     } else {
         return w.e;
     }
@@ -610,11 +613,11 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     auto gown = [&](int q, int k) { return (unsigned)om[q] + Pu * (unsigned)min(k, kown_hi); };
     auto ghal = [&](int u, int k) { return (unsigned)hm[u] + Pu * (unsigned)min(k, khal_hi); };
 
-    // the palette: loaded first, stored behind the two LDS planes once the
-    // plane loads are out, read after the barrier before the first staging
-    T *lpal = reinterpret_cast<T *>(smem_raw) + 4 * a.lmax;
-    T palv = T(0);
-    if constexpr (PAL) palv = a.pal[threadIdx.x & (PAL_MAX - 1)];
+    // the face table: loaded first, stored behind the two LDS planes once
+    // the plane loads are out, read after the barrier before the first output
+    T *lftab = reinterpret_cast<T *>(smem_raw) + 4 * a.lmax;
+    T ftv = T(0);
+    if constexpr (PAL) ftv = a.ftab[threadIdx.x & (FTAB - 1)];
 
     // ---- prologue loads: the previous phase's partials, then planes k0-1,
     //      k0 (own), k0 (halo), and the raw sets of planes k0+1 and k0+2
@@ -701,8 +704,8 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     omega = uniform(omega);
     beta = uniform(beta);
     if constexpr (PAL) {
-        if (threadIdx.x < PAL_MAX) lpal[threadIdx.x] = palv;
-        __syncthreads();   // palette visible before the first staging
+        if (threadIdx.x < FTAB) lftab[threadIdx.x] = ftv;
+        __syncthreads();   // table visible before the first output
     }
 
     // two LDS planes (double buffer) of staged values and coefficients
@@ -725,12 +728,12 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         vc[q] = stage_raw<OP, T>(rc[q], alpha, omega, beta);
-        ec[q] = CEPS ? T(0) : coef<PAL>(rc[q], lpal);
+        ec[q] = CEPS ? T(0) : coef<PAL>(rc[q]);
         tc[q] = SCAL ? rc[q].t : 0.0f;
         sc_[q] = SIG ? rc[q].sg : T(0);
         fc[q] = CEPS ? rc[q].f : (uint8_t)0;
         vp[q] = stage_raw<OP, T>(rp[q], alpha, omega, beta);
-        ep[q] = CEPS ? T(0) : coef<PAL>(rp[q], lpal);
+        ep[q] = CEPS ? T(0) : coef<PAL>(rp[q]);
         vn[q] = en[q] = rn_[q] = sn_[q] = T(0);
         tn[q] = 0.0f;
         fn[q] = 0;
@@ -754,7 +757,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     for (int u = 0; u < HMAX; ++u) {
         if (hok[u]) {
             lval0[hm[u] - lo] = stage_raw<OP, T>(hc[u], alpha, omega, beta);
-            if constexpr (!CEPS) leps0[hm[u] - lo] = coef<PAL>(hc[u], lpal);
+            if constexpr (!CEPS) leps0[hm[u] - lo] = coef<PAL>(hc[u]);
         }
     }
     if (WIDE && nhalo > HMAX * NT) {
@@ -763,7 +766,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             Raw<T> w;
             load_raw<OP, T, CEPS, false, PAL, false>(a, (unsigned)m + Pu * (unsigned)k0, w);
             lval0[m - lo] = stage_raw<OP, T>(w, alpha, omega, beta);
-            if constexpr (!CEPS) leps0[m - lo] = coef<PAL>(w, lpal);
+            if constexpr (!CEPS) leps0[m - lo] = coef<PAL>(w);
         }
     }
     __syncthreads();
@@ -783,7 +786,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             vn[q] = own_reg(stage_raw<OP, T>(ro[q], alpha, omega, beta));
-            if constexpr (!CEPS) en[q] = own_reg(coef<PAL>(ro[q], lpal));
+            if constexpr (!CEPS) en[q] = own_reg(coef<PAL>(ro[q]));
             if constexpr (CEPS) fn[q] = own_reg(ro[q].f);
             if constexpr (SIG) sn_[q] = own_reg(ro[q].sg);
             if constexpr (SCAL) tn[q] = own_reg(ro[q].t);
@@ -796,7 +799,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
 #pragma unroll
         for (int u = 0; u < HMAX; ++u) {
             hv[u] = own_reg(stage_raw<OP, T>(rh[u], alpha, omega, beta));
-            if constexpr (!CEPS) he[u] = own_reg(coef<PAL>(rh[u], lpal));
+            if constexpr (!CEPS) he[u] = own_reg(coef<PAL>(rh[u]));
         }
         // (2) refill the set with plane k+1+DEPTH (clamped: re-reads of a plane
         //     already loaded near the tile's end hit the cache).  The
@@ -843,6 +846,16 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                 sum = c * (lv[oxm[q]] + lv[oxp[q]] + lv[oym[q]] + lv[oyp[q]] + vu[q] + vp[q]);
                 D = a.cdiag;
                 dir = (fc[q] & a.dirbit) != 0;
+            } else if constexpr (PAL) {
+                const T *row = lftab + ((int)absT(ec[q]) - 1) * PAL_MAX;
+                const T c0 = row[(int)absT(le[oxm[q]]) - 1], c1 = row[(int)absT(le[oxp[q]]) - 1];
+                const T c2 = row[(int)absT(le[oym[q]]) - 1], c3 = row[(int)absT(le[oyp[q]]) - 1];
+                const T c4 = row[(int)absT(ep[q]) - 1], c5 = row[(int)absT(eu[q]) - 1];
+                sum = c0 * lv[oxm[q]] + c1 * lv[oxp[q]] + c2 * lv[oym[q]] + c3 * lv[oyp[q]] + c4 * vp[q] +
+                      c5 * vu[q];
+                D = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
+                if constexpr (SIG) D += sc_[q];
+                dir = ec[q] < T(0);
             } else {
                 const T e = absT(ec[q]);
                 const T c0 = face(e, absT(le[oxm[q]]), ih2), c1 = face(e, absT(le[oxp[q]]), ih2);
@@ -932,7 +945,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                 Raw<T> w;
                 load_raw<OP, T, CEPS, false, PAL, false>(a, (unsigned)m + Pu * (unsigned)(k + 1), w);
                 nv[m - lo] = stage_raw<OP, T>(w, alpha, omega, beta);
-                if constexpr (!CEPS) ne[m - lo] = coef<PAL>(w, lpal);
+                if constexpr (!CEPS) ne[m - lo] = coef<PAL>(w);
             }
         }
         // one barrier per plane: the buffer written next step was last read
@@ -1009,7 +1022,7 @@ __global__ void k_palette_scan(size_t N, const double *eps, const double *pal, i
 }
 
 // Palette indices: byte = index of |eps| in the palette, bit 7 = Dirichlet
-// row (eps < 0); the FP32 palette is the FP64 one rounded.
+// row (eps < 0).
 __global__ void k_palette_index(size_t N, const double *eps, const double *pal, int npal, uint8_t *idx)
 {
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
