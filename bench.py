@@ -697,8 +697,9 @@ def main():
                     help="summarise two rocprofv3 --pmc CSVs of a --pmc-run (and its printed algorithmic "
                          "bytes) into the traffic file and exit")
     ap.add_argument("--pmc-run", type=int, default=0,
-                    help="counter run: the headline steps only, every chunk timed (--sample 1), launch shapes "
-                         "pinned, and the algorithmic bytes of the timed launches printed")
+                    help="counter run: the headline steps only, every chunk timed (--sample 1), and the "
+                         "algorithmic bytes of the timed launches printed (run it with PF_BATCH_POLICY set "
+                         "to the policy an uninstrumented run keeps, and --warmup 0)")
     ap.add_argument("--trace-summary", nargs="+", metavar="CSV",
                     help="summarise rocprofv3 kernel / memory-copy trace CSVs (busy, idle gaps) and exit")
     ap.add_argument("--copy-ceiling", type=int, default=0,

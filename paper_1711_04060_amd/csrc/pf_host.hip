@@ -1373,8 +1373,11 @@ struct BatchPlan {
 // Run the Krylov iterations of all listed systems (same precision, same
 // operator kind) together: one launch per kernel per iteration covers every
 // system, captured as a graph chunk and replayed until no system is RUN.
+// members: shapes of the whole batch (the policy is chosen for the batch
+// and kept for every subset of its members that still iterates).
 template <typename T>
-pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int m, std::vector<int> &status)
+pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long> &members, hipStream_t stream, int m,
+                           std::vector<int> &status)
 {
     const int n = (int)act.size();
     const bool psi = act[0]->op.psi;
@@ -1390,16 +1393,16 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         form = pal ? (sig ? FORM_PALSIG : FORM_PAL) : (sig ? FORM_SIG : FORM_PLAIN);
     }
     std::vector<long> key = {(long)sizeof(T), (long)form};
-    {
-        std::vector<long> shapes;
-        for (const LinSolve *L : act) shapes.push_back(((long)L->g->nx * 4096 + L->g->ny) * 4096 + L->g->nz);
-        std::sort(shapes.begin(), shapes.end());
-        key.insert(key.end(), shapes.begin(), shapes.end());
-    }
+    key.insert(key.end(), members.begin(), members.end());
     const auto known = g_batch_policy.find(key);
+    // PF_BATCH_POLICY=k forces policy k (profiler runs, whose serialised
+    // launches would distort the comparison)
+    const char *forced_env = getenv("PF_BATCH_POLICY");
+    const int forced = forced_env ? std::min(NPOLICY - 1, std::max(0, atoi(forced_env))) : -1;
     // only batches of several members are compared (small ones keep policy 0)
-    const int npol = (known != g_batch_policy.end() || !tuning_enabled() || n < 4) ? 1 : NPOLICY;
-    const int pol0 = known != g_batch_policy.end() ? known->second : 0;
+    const int npol = (forced >= 0 || known != g_batch_policy.end() || !tuning_enabled() || members.size() < 4)
+                         ? 1 : NPOLICY;
+    const int pol0 = forced >= 0 ? forced : (known != g_batch_policy.end() ? known->second : 0);
     std::vector<double> *trials = nullptr;
     if (npol > 1) {
         trials = &g_batch_trials[key];
@@ -1545,12 +1548,14 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, hipStream_t stream, int
         if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched chunk failed: %s", hipGetErrorString(e));
         if (timed) {
             // launch j of the chunk did a member's whole step A while the
-            // member still iterated: j <= the iterations it completed here
+            // member still iterated: j <= the iterations it completed here.
+            // Every launch of the chunk counts (those after the last member
+            // stopped exit at once and add time but no bytes), as in a
+            // profiler's mean over all launches of the kernel.
             for (int j = 0; j < m; ++j) {
                 double bytes = 0;
                 for (int i = 0; i < n; ++i)
                     if (status[i] == pfk::ST_RUN && j <= g_batch.hsc[i].iter_done - before[i]) bytes += abytes[i];
-                if (bytes == 0) break;
                 float ms = 0;
                 HIPCHK(hipEventElapsedTime(&ms, g_batch.ev[2 * j], g_batch.ev[2 * j + 1]));
                 g_timing.ms[tslot] += ms;
@@ -1601,6 +1606,9 @@ pf_status solve_batch(std::vector<LinSolve> &Ls)
     hipStream_t bs = Ls[0].g->stream;
     int m = 16;
     for (auto &L : Ls) m = std::max(m, chunk_len(L.g, L.o));
+    std::vector<long> members;
+    for (auto &L : Ls) members.push_back(((long)L.g->nx * 4096 + L.g->ny) * 4096 + L.g->nz);
+    std::sort(members.begin(), members.end());
     for (bool first = true;; first = false) {
         if (!first) {   // the first true residuals came with the init read
             for (auto &L : Ls)
@@ -1621,11 +1629,11 @@ pf_status solve_batch(std::vector<LinSolve> &Ls)
         for (LinSolve *L : act) (L->mixed ? a32 : a64).push_back(L);
         std::vector<int> st;
         if (!a32.empty()) {
-            PFCHK(batch_krylov_run<float>(a32, bs, m, st));
+            PFCHK(batch_krylov_run<float>(a32, members, bs, m, st));
             for (size_t i = 0; i < a32.size(); ++i) PFCHK(ls_after(*a32[i], st[i]));
         }
         if (!a64.empty()) {
-            PFCHK(batch_krylov_run<double>(a64, bs, m, st));
+            PFCHK(batch_krylov_run<double>(a64, members, bs, m, st));
             for (size_t i = 0; i < a64.size(); ++i) PFCHK(ls_after(*a64[i], st[i]));
         }
     }

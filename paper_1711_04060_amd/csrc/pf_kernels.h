@@ -994,12 +994,30 @@ __device__ __forceinline__ int batch_system(const int *start, int nsys, int b)
 
 // Batched form: one launch covers the tiles of nsys systems (grids of any
 // size); each system keeps its own scalars, partials and status.
+// Batched launches hold tiles of very different cost (members of other
+// sizes take other z-chunk lengths), so contiguous per-XCD ranges would load
+// the XCDs unevenly.  Instead runs of C consecutive tiles go to one XCD and
+// the runs are dealt to the XCDs in turn: neighbouring strips of a run share
+// that XCD's L2 for their halo rows, and every XCD gets a slice of every
+// part of the batch.  Blocks past the last whole round of runs keep their
+// order.
+template <int C>
+__device__ __forceinline__ int xcd_runs(int b, int G)
+{
+    const int X = 8;
+    const int full = (G / (X * C)) * (X * C);
+    if (b >= full) return b;
+    const int x = b % X, i = b / X;
+    return ((i / C) * X + x) * C + i % C;
+}
+
 template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch_batch(const ZArgs<T> *__restrict__ args,
                                                      const int *__restrict__ start, int nsys)
 {
-    const int s = batch_system(start, nsys, blockIdx.x);
-    const int lb = blockIdx.x - start[s];
+    const int t = xcd_runs<16>(blockIdx.x, start[nsys]);
+    const int s = batch_system(start, nsys, t);
+    const int lb = t - start[s];
     const ZArgs<T> a = args[s];   // private copy: stores cannot alias it
     zmarch_tile<OP, T, CEPS, SIG, PAL, NT, PPT, WIDE, DEPTH>(a, lb, lb);
 }
