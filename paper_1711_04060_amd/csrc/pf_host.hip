@@ -336,54 +336,56 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEve
     }
 }
 
+// Batched step over the active members' tiles: the grid covers every
+// member's tiles (c.G); the kernel maps the first workgroups to the active
+// ones.
 template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NTZ, int PPT, bool WIDE, int DEPTH>
-hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s,
-                          hipEvent_t e0, hipEvent_t e1)
+hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *act, const int *pref, const int *na,
+                          hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     auto kern = pfk::k_zmarch_batch<OP, T, CEPS, SIG, PAL, NTZ, PPT, WIDE, DEPTH>;
-    if (c.lds > 64 * 1024) {
-        static size_t granted = 0;
-        if (c.lds > granted) {
-            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)c.lds);
-            if (e != hipSuccess) return e;
-            granted = c.lds;
-        }
+    static size_t granted = 0;
+    if (c.lds > 64 * 1024 && c.lds > granted) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)c.lds);
+        if (e != hipSuccess) return e;
+        granted = c.lds;
     }
-    if (e0 || e1) hipExtLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), (std::uint32_t)c.lds, s, e0, e1, 0u, args, start, n);
-    else hipLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), c.lds, s, args, start, n);
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), (std::uint32_t)c.lds, s, e0, e1, 0u, args, act, pref, na);
+    else hipLaunchKernelGGL(kern, dim3(c.G), dim3(NTZ), c.lds, s, args, act, pref, na);
     return hipGetLastError();
 }
 
 // c: the batch's combined launch (its NTZ, PPT, depth shared by every member;
 // G = all members' tiles, lds and wide = the maxima)
 template <int OP, typename T, bool CEPS, bool SIG, bool PAL>
-hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n, hipStream_t s,
-                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *act, const int *pref, const int *na,
+                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     if (c.wide) {
         if (c.NTZ == 1024 && c.PPT == 1)
-            return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, true, 1>(c, args, start, n, s, e0, e1);
+            return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, true, 1>(c, args, act, pref, na, s, e0, e1);
         return hipErrorInvalidValue;
     }
     if (c.depth == 2) {
         switch (c.NTZ * 10 + c.PPT) {
-        case 2561: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 1, false, 2>(c, args, start, n, s, e0, e1);
-        case 2562: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 2, false, 2>(c, args, start, n, s, e0, e1);
-        case 5121: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 1, false, 2>(c, args, start, n, s, e0, e1);
-        case 5122: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 2, false, 2>(c, args, start, n, s, e0, e1);
-        case 10241: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, false, 2>(c, args, start, n, s, e0, e1);
-        case 10242: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 2, false, 2>(c, args, start, n, s, e0, e1);
+        case 2561: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 1, false, 2>(c, args, act, pref, na, s, e0, e1);
+        case 2562: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 2, false, 2>(c, args, act, pref, na, s, e0, e1);
+        case 5121: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 1, false, 2>(c, args, act, pref, na, s, e0, e1);
+        case 5122: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 2, false, 2>(c, args, act, pref, na, s, e0, e1);
+        case 10241: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, false, 2>(c, args, act, pref, na, s, e0, e1);
+        case 10242: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 2, false, 2>(c, args, act, pref, na, s, e0, e1);
         default: return hipErrorInvalidValue;
         }
     }
     switch (c.NTZ * 10 + c.PPT) {
-    case 2561: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 1, false, 1>(c, args, start, n, s, e0, e1);
-    case 2562: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 2, false, 1>(c, args, start, n, s, e0, e1);
-    case 5121: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 1, false, 1>(c, args, start, n, s, e0, e1);
-    case 5122: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 2, false, 1>(c, args, start, n, s, e0, e1);
-    case 10241: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, false, 1>(c, args, start, n, s, e0, e1);
-    case 10242: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 2, false, 1>(c, args, start, n, s, e0, e1);
+    case 2561: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 1, false, 1>(c, args, act, pref, na, s, e0, e1);
+    case 2562: return launch_batch_k<OP, T, CEPS, SIG, PAL, 256, 2, false, 1>(c, args, act, pref, na, s, e0, e1);
+    case 5121: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 1, false, 1>(c, args, act, pref, na, s, e0, e1);
+    case 5122: return launch_batch_k<OP, T, CEPS, SIG, PAL, 512, 2, false, 1>(c, args, act, pref, na, s, e0, e1);
+    case 10241: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 1, false, 1>(c, args, act, pref, na, s, e0, e1);
+    case 10242: return launch_batch_k<OP, T, CEPS, SIG, PAL, 1024, 2, false, 1>(c, args, act, pref, na, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -397,15 +399,15 @@ hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *sta
 enum { FORM_PLAIN = 0, FORM_SIG = 1, FORM_CEPS = 2, FORM_PAL = 3, FORM_PALSIG = 4 };
 
 template <int OP, typename T>
-hipError_t launch_batch_form(int form, const ZCfg &c, const pfk::ZArgs<T> *args, const int *start, int n,
-                             hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+hipError_t launch_batch_form(int form, const ZCfg &c, const pfk::ZArgs<T> *args, const int *act, const int *pref,
+                             const int *na, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     switch (form) {
-    case FORM_CEPS: return launch_batch<OP, T, true, false, false>(c, args, start, n, s, e0, e1);
-    case FORM_SIG: return launch_batch<OP, T, false, true, false>(c, args, start, n, s, e0, e1);
-    case FORM_PAL: return launch_batch<OP, T, false, false, true>(c, args, start, n, s, e0, e1);
-    case FORM_PALSIG: return launch_batch<OP, T, false, true, true>(c, args, start, n, s, e0, e1);
-    default: return launch_batch<OP, T, false, false, false>(c, args, start, n, s, e0, e1);
+    case FORM_CEPS: return launch_batch<OP, T, true, false, false>(c, args, act, pref, na, s, e0, e1);
+    case FORM_SIG: return launch_batch<OP, T, false, true, false>(c, args, act, pref, na, s, e0, e1);
+    case FORM_PAL: return launch_batch<OP, T, false, false, true>(c, args, act, pref, na, s, e0, e1);
+    case FORM_PALSIG: return launch_batch<OP, T, false, true, true>(c, args, act, pref, na, s, e0, e1);
+    default: return launch_batch<OP, T, false, false, false>(c, args, act, pref, na, s, e0, e1);
     }
 }
 
@@ -1419,7 +1421,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
     const size_t szZ = sizeof(pfk::ZArgs<T>) * n;
     const size_t szI = sizeof(int) * (n + 1), szP = sizeof(void *) * n, szS = sizeof(Scalars) * n;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t per_pol = 4 * al(szZ) + 2 * al(szI);
+    const size_t per_pol = 4 * al(szZ) + 4 * al(szI) + al(sizeof(int) * n) + al(sizeof(int));
     const size_t need = npol * per_pol + al(szP) + al(szS);
     if (need > g_batch.bytes) {
         if (g_batch.dev) (void)hipFree(g_batch.dev);
@@ -1481,6 +1483,9 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         pfk::ZArgs<T> *dA[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
         pfk::ZArgs<T> *dB[2] = {(pfk::ZArgs<T> *)take(szZ), (pfk::ZArgs<T> *)take(szZ)};
         int *das = (int *)take(szI), *dbs = (int *)take(szI);
+        // the active members' list and tile prefixes (k_batch_active)
+        int *dpa = (int *)take(szI), *dpb = (int *)take(szI), *dact = (int *)take(sizeof(int) * n);
+        int *dna = (int *)take(sizeof(int));
         for (int par = 0; par < 2; ++par) {
             HIPCHK(hipMemcpyAsync(dA[par], za[par].data(), szZ, hipMemcpyHostToDevice, stream));
             HIPCHK(hipMemcpyAsync(dB[par], zb[par].data(), szZ, hipMemcpyHostToDevice, stream));
@@ -1490,9 +1495,13 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         HIPCHK(hipStreamSynchronize(stream));   // the host vectors above go out of scope
 
         plans[k].launch_iter = [=](int par, hipEvent_t e0, hipEvent_t e1) -> pf_status {
-            hipError_t e = launch_batch_form<pfk::OP_BA, T>(form, ca, dA[par], das, n, stream, e0, e1);
+            hipLaunchKernelGGL(pfk::k_batch_active, dim3(1), dim3(pfk::ACT_NT), 0, stream, dscp, (const int *)das,
+                               (const int *)dbs, n, dact, dpa, dpb, dna);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return fail(PF_ERR_DEVICE, "active-member list launch failed: %s", hipGetErrorString(e));
+            e = launch_batch_form<pfk::OP_BA, T>(form, ca, dA[par], dact, dpa, dna, stream, e0, e1);
             if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
-            e = launch_batch_form<pfk::OP_BB, T>(form, cb, dB[par], dbs, n, stream);
+            e = launch_batch_form<pfk::OP_BB, T>(form, cb, dB[par], dact, dpb, dna, stream);
             if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
             return PF_OK;
         };

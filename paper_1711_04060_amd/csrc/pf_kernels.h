@@ -566,7 +566,16 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     Scalars *sc = a.sc;
     int fresh = 0;
     if constexpr (SCAL) {
-        if (sc->stop != ST_RUN) return;
+        // One read of the stop state for the whole workgroup: step B's
+        // leading workgroup may set it while another workgroup of the same
+        // system starts, and waves that read different values would leave
+        // the tile apart (in the persistent batched walk the next barrier
+        // they meet belongs to another tile).
+        __shared__ int stop_seen;
+        __syncthreads();   // the previous tile of this workgroup is done with stop_seen
+        if (threadIdx.x == 0) stop_seen = sc->stop;
+        __syncthreads();
+        if (stop_seen != ST_RUN) return;
         if constexpr (OP == OP_BA) fresh = sc->fresh;
     }
 
@@ -999,8 +1008,8 @@ __device__ __forceinline__ int batch_system(const int *start, int nsys, int b)
 // the XCDs unevenly.  Instead runs of C consecutive tiles go to one XCD and
 // the runs are dealt to the XCDs in turn: neighbouring strips of a run share
 // that XCD's L2 for their halo rows, and every XCD gets a slice of every
-// part of the batch.  Blocks past the last whole round of runs keep their
-// order.
+// part of the batch.  Indices past the last whole round of runs keep their
+// order.  (A permutation of [0, G).)
 template <int C>
 __device__ __forceinline__ int xcd_runs(int b, int G)
 {
@@ -1011,14 +1020,81 @@ __device__ __forceinline__ int xcd_runs(int b, int G)
     return ((i / C) * X + x) * C + i % C;
 }
 
+// Active members of a batched Krylov run: before each iteration one
+// workgroup lists the members still iterating (stop == RUN) and the prefix
+// sums of their tile counts for steps A and B, so that the step kernels
+// walk only those members' tiles.  act[0..na) = member indices, pa/pb
+// [0..na] = tile prefixes (pa[na] = step A's tile total), *na_out = na.
+constexpr int ACT_NT = 256;
+
+__global__ __launch_bounds__(ACT_NT) void k_batch_active(const Scalars *const *sc, const int *startA,
+                                                         const int *startB, int n, int *act, int *pa, int *pb,
+                                                         int *na_out)
+{
+    __shared__ int sa[ACT_NT], sb[ACT_NT], sf[ACT_NT];
+    __shared__ int base[3];   // running member count and tile totals
+    if (threadIdx.x == 0) base[0] = base[1] = base[2] = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += ACT_NT) {
+        const int i = c0 + threadIdx.x;
+        const bool on = i < n && sc[i]->stop == ST_RUN;
+        sf[threadIdx.x] = on ? 1 : 0;
+        sa[threadIdx.x] = on ? startA[i + 1] - startA[i] : 0;
+        sb[threadIdx.x] = on ? startB[i + 1] - startB[i] : 0;
+        __syncthreads();
+        // inclusive scans of the three counts (Hillis-Steele)
+        for (int off = 1; off < ACT_NT; off <<= 1) {
+            const int f = threadIdx.x >= off ? sf[threadIdx.x - off] : 0;
+            const int a = threadIdx.x >= off ? sa[threadIdx.x - off] : 0;
+            const int b = threadIdx.x >= off ? sb[threadIdx.x - off] : 0;
+            __syncthreads();
+            sf[threadIdx.x] += f;
+            sa[threadIdx.x] += a;
+            sb[threadIdx.x] += b;
+            __syncthreads();
+        }
+        if (on) {
+            const int k = base[0] + sf[threadIdx.x] - 1;   // this member's slot
+            act[k] = i;
+            pa[k + 1] = base[1] + sa[threadIdx.x];
+            pb[k + 1] = base[2] + sb[threadIdx.x];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            base[0] += sf[ACT_NT - 1];
+            base[1] += sa[ACT_NT - 1];
+            base[2] += sb[ACT_NT - 1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pa[0] = 0;
+        pb[0] = 0;
+        *na_out = base[0];
+    }
+}
+
+// Batched form: one launch over the tiles of the members still iterating,
+// listed by k_batch_active and numbered densely from 0 (the tiles of members
+// that stopped are not in the list).  The grid is sized for every member's
+// tiles when the launch is captured; workgroups past the active total leave
+// after reading it.  Tiles go to the XCDs in runs (xcd_runs), and the
+// hardware hands each workgroup slot the next tile as one finishes.  Each
+// member keeps its own scalars, partials and status.
 template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch_batch(const ZArgs<T> *__restrict__ args,
-                                                     const int *__restrict__ start, int nsys)
+                                                     const int *__restrict__ act,
+                                                     const int *__restrict__ pref,
+                                                     const int *__restrict__ na_ptr)
 {
-    const int t = xcd_runs<16>(blockIdx.x, start[nsys]);
-    const int s = batch_system(start, nsys, t);
-    const int lb = t - start[s];
-    const ZArgs<T> a = args[s];   // private copy: stores cannot alias it
+    const int na = *na_ptr;
+    const int total = pref[na];
+    const int v = blockIdx.x;
+    if (v >= total) return;
+    const int t = xcd_runs<16>(v, total);
+    const int k = batch_system(pref, na, t);
+    const int lb = t - pref[k];
+    const ZArgs<T> a = args[act[k]];   // private copy: stores cannot alias it
     zmarch_tile<OP, T, CEPS, SIG, PAL, NT, PPT, WIDE, DEPTH>(a, lb, lb);
 }
 
