@@ -109,7 +109,8 @@ ZCfg make_cfg(int nx, int ny, int nz, size_t elem, int ntz, int ppt, int kz, int
     c.nzc = (nz + c.KZ - 1) / c.KZ;
     c.G = c.nstrips * c.nzc;
     c.lmax = std::min(P, c.S + 2 * nx);
-    c.lds = (4 * (size_t)c.lmax + pfk::FTAB) * elem;   // two planes of (value, coefficient), the face table
+    // two planes of (value, coefficient), the face table, the class shifts
+    c.lds = (4 * (size_t)c.lmax + pfk::FTAB + pfk::PAL_MAX) * elem;
     c.wide = 2 * nx > halo_slots(ntz) * ntz;
     c.depth = c.wide ? 1 : (depth ? depth : (g_depth_override ? g_depth_override : default_depth(elem, ppt)));
     return c;
@@ -177,6 +178,9 @@ struct pf_grid {
     uint8_t *epsi = nullptr;           // palette index per node, bit 7 = Dirichlet row
     double *ftab64 = nullptr;          // face coefficients of palette pairs (FTAB values, / h^2)
     float *ftab32 = nullptr;
+    double *stab64 = nullptr;          // shift of each palette class (SIG_CLASS form, per solve)
+    float *stab32 = nullptr;
+    unsigned long long *smm = nullptr; // per-class extremes of the shift (2 PAL_MAX)
     uint8_t *flags = nullptr;
     double *dval = nullptr;
     double *q = nullptr;               // fixed charge (may stay null)
@@ -284,7 +288,7 @@ pf_status ensure_work(pf_grid *g)
 // e0, e1 (optional): events that the dispatch itself stamps at the kernel's
 // start and end (hipExtLaunchKernel), so their interval is the kernel's own
 // duration, without the marker packets of separate event records.
-template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NTZ, int PPT, bool WIDE = false, int DEPTH = 1>
+template <int OP, typename T, bool CEPS, int SIG, bool PAL, int NTZ, int PPT, bool WIDE = false, int DEPTH = 1>
 hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEvent_t e0 = nullptr,
                      hipEvent_t e1 = nullptr)
 {
@@ -303,7 +307,7 @@ hipError_t launch_zk(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEv
     return hipGetLastError();
 }
 
-template <int OP, typename T, bool CEPS, bool SIG, bool PAL>
+template <int OP, typename T, bool CEPS, int SIG, bool PAL>
 hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEvent_t e0 = nullptr,
                     hipEvent_t e1 = nullptr)
 {
@@ -339,7 +343,7 @@ hipError_t launch_z(const ZCfg &c, const pfk::ZArgs<T> &a, hipStream_t s, hipEve
 // Batched step over the active members' tiles: the grid covers every
 // member's tiles (c.G); the kernel maps the first workgroups to the active
 // ones.
-template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NTZ, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, int SIG, bool PAL, int NTZ, int PPT, bool WIDE, int DEPTH>
 hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *act, const int *pref, const int *na,
                           hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
@@ -359,7 +363,7 @@ hipError_t launch_batch_k(const ZCfg &c, const pfk::ZArgs<T> *args, const int *a
 
 // c: the batch's combined launch (its NTZ, PPT, depth shared by every member;
 // G = all members' tiles, lds and wide = the maxima)
-template <int OP, typename T, bool CEPS, bool SIG, bool PAL>
+template <int OP, typename T, bool CEPS, int SIG, bool PAL>
 hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *act, const int *pref, const int *na,
                         hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
@@ -392,22 +396,24 @@ hipError_t launch_batch(const ZCfg &c, const pfk::ZArgs<T> *args, const int *act
 
 // Kernel forms of an operator: PF1 (constant coefficient), the potential
 // system with a shift array (sigma read at every own node) or without one,
-// each with the coefficient field read in full or as palette indices.  Only
-// the BiCGSTAB steps have the shift-array forms (the other kernels read
-// sigma at their outputs), and only they and the Jacobi-scaled product have
-// the palette forms.
-enum { FORM_PLAIN = 0, FORM_SIG = 1, FORM_CEPS = 2, FORM_PAL = 3, FORM_PALSIG = 4 };
+// each with the coefficient field read in full or as palette indices, and
+// the palette form whose shift is one value per palette class (a table).
+// Only the BiCGSTAB steps have the shift forms (the other kernels read sigma
+// at their outputs), and only they and the Jacobi-scaled product have the
+// palette forms.
+enum { FORM_PLAIN = 0, FORM_SIG = 1, FORM_CEPS = 2, FORM_PAL = 3, FORM_PALSIG = 4, FORM_PALTAB = 5 };
 
 template <int OP, typename T>
 hipError_t launch_batch_form(int form, const ZCfg &c, const pfk::ZArgs<T> *args, const int *act, const int *pref,
                              const int *na, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     switch (form) {
-    case FORM_CEPS: return launch_batch<OP, T, true, false, false>(c, args, act, pref, na, s, e0, e1);
-    case FORM_SIG: return launch_batch<OP, T, false, true, false>(c, args, act, pref, na, s, e0, e1);
-    case FORM_PAL: return launch_batch<OP, T, false, false, true>(c, args, act, pref, na, s, e0, e1);
-    case FORM_PALSIG: return launch_batch<OP, T, false, true, true>(c, args, act, pref, na, s, e0, e1);
-    default: return launch_batch<OP, T, false, false, false>(c, args, act, pref, na, s, e0, e1);
+    case FORM_CEPS: return launch_batch<OP, T, true, pfk::SIG_NONE, false>(c, args, act, pref, na, s, e0, e1);
+    case FORM_SIG: return launch_batch<OP, T, false, pfk::SIG_NODE, false>(c, args, act, pref, na, s, e0, e1);
+    case FORM_PAL: return launch_batch<OP, T, false, pfk::SIG_NONE, true>(c, args, act, pref, na, s, e0, e1);
+    case FORM_PALSIG: return launch_batch<OP, T, false, pfk::SIG_NODE, true>(c, args, act, pref, na, s, e0, e1);
+    case FORM_PALTAB: return launch_batch<OP, T, false, pfk::SIG_CLASS, true>(c, args, act, pref, na, s, e0, e1);
+    default: return launch_batch<OP, T, false, pfk::SIG_NONE, false>(c, args, act, pref, na, s, e0, e1);
     }
 }
 
@@ -446,12 +452,21 @@ struct OpDesc {
     double ceps = 0;           // PF1 face coefficient eps_s lc^2 (before / h^2)
     const double *sigma = nullptr;
     double sig_const = 0;
+    bool sig_class = false;    // sigma is one value per palette class on the free rows (table in the grid)
 };
 
 uint8_t dirbit(const OpDesc &op) { return op.psi ? pfk::F_DIR_PSI : pfk::F_DIR_PHI; }
 
 // The palette form is used where the grid has one (PF_PALETTE=0 turns it off,
 // for comparisons).
+// The shift-per-class table replaces a per-node shift where it holds
+// (PF_SHIFT_CLASS=0 turns it off, read at each solve, for comparisons).
+bool shift_class_enabled()
+{
+    const char *e = getenv("PF_SHIFT_CLASS");
+    return !(e && e[0] == '0');
+}
+
 bool use_palette(const pf_grid *g)
 {
     static const bool on = [] {
@@ -465,7 +480,7 @@ bool use_palette(const pf_grid *g)
 int step_form(const OpDesc &op, const pf_grid *g)
 {
     if (op.psi) return FORM_CEPS;
-    if (use_palette(g)) return op.sigma ? FORM_PALSIG : FORM_PAL;
+    if (use_palette(g)) return op.sigma ? (op.sig_class ? FORM_PALTAB : FORM_PALSIG) : FORM_PAL;
     return op.sigma ? FORM_SIG : FORM_PLAIN;
 }
 
@@ -473,12 +488,12 @@ int step_form(const OpDesc &op, const pf_grid *g)
 // or (PF1) a flag byte.
 double coef_bytes(int form, size_t elem)
 {
-    return (form == FORM_CEPS || form == FORM_PAL || form == FORM_PALSIG) ? 1.0 : (double)elem;
+    return (form == FORM_CEPS || form == FORM_PAL || form == FORM_PALSIG || form == FORM_PALTAB) ? 1.0 : (double)elem;
 }
 
 // Algorithmic bytes of one step-A launch on N nodes: s^, p^, v^, t^ and the
-// coefficient read at every staged node, x, the FP32 shadow (and sigma) at
-// own nodes; x, r^, p^, v^ written.
+// coefficient read at every staged node, x, the FP32 shadow (and a per-node
+// sigma) at own nodes; x, r^, p^, v^ written.
 double step_a_bytes(const OpDesc &op, const pf_grid *g, size_t elem)
 {
     const int form = step_form(op, g);
@@ -505,10 +520,12 @@ pfk::ZArgs<T> zbase_cfg(pf_grid *g, const OpDesc &op, const ZCfg &c)
         a.eps = g->eps64;
         a.ftab = g->ftab64;
         a.sig = op.sigma;
+        a.stab = g->stab64;
     } else {
         a.eps = g->eps32;
         a.ftab = g->ftab32;
         a.sig = op.sigma ? g->sig32 : nullptr;   // converted by the mixed solve's set-up
+        a.stab = g->stab32;
     }
     a.sigma = op.sigma;
     a.sig_const = op.sig_const;
@@ -535,14 +552,16 @@ pf_status zlaunch(pf_grid *g, const OpDesc &op, const pfk::ZArgs<T> &a, const ZC
     constexpr bool STEP = (OP == pfk::OP_BA || OP == pfk::OP_BB);
     constexpr bool PALOK = STEP || OP == pfk::OP_SPMV_JAC;
     const bool pal = PALOK && use_palette(g);
+    constexpr int SN = STEP ? pfk::SIG_NODE : pfk::SIG_NONE, SC = STEP ? pfk::SIG_CLASS : pfk::SIG_NONE;
     hipError_t e;
-    if (op.psi) e = launch_z<OP, T, true, false, false>(c, a, g->stream, e0, e1);
+    if (op.psi) e = launch_z<OP, T, true, pfk::SIG_NONE, false>(c, a, g->stream, e0, e1);
     else if (STEP && op.sigma)
-        e = pal ? launch_z<OP, T, false, STEP, PALOK>(c, a, g->stream, e0, e1)
-                : launch_z<OP, T, false, STEP, false>(c, a, g->stream, e0, e1);
+        e = pal ? (op.sig_class ? launch_z<OP, T, false, SC, PALOK>(c, a, g->stream, e0, e1)
+                                : launch_z<OP, T, false, SN, PALOK>(c, a, g->stream, e0, e1))
+                : launch_z<OP, T, false, SN, false>(c, a, g->stream, e0, e1);
     else
-        e = pal ? launch_z<OP, T, false, false, PALOK>(c, a, g->stream, e0, e1)
-                : launch_z<OP, T, false, false, false>(c, a, g->stream, e0, e1);
+        e = pal ? launch_z<OP, T, false, pfk::SIG_NONE, PALOK>(c, a, g->stream, e0, e1)
+                : launch_z<OP, T, false, pfk::SIG_NONE, false>(c, a, g->stream, e0, e1);
     if (e != hipSuccess) return fail(PF_ERR_DEVICE, "stencil kernel launch failed: %s", hipGetErrorString(e));
     return PF_OK;
 }
@@ -1044,6 +1063,7 @@ struct LinSolve {
     int stall = 0;                                   // consecutive runs that did not halve ||r||
     int iter = 0, restarts = 0, refinements = 0;
     bool started = false, done = false, fallback = false;
+    bool class_probe = false;   // the shift-per-class test ran in the set-up
     pf_status result = PF_OK;
 };
 
@@ -1089,6 +1109,25 @@ pf_status ls_init_launch(LinSolve &L)
         L.op.sigma = g->sig64;
     }
     if (L.mixed) PFCHK(prepare_f32(g, L.op));
+    L.op.sig_class = false;
+    // (not for the outer loop's own shift, the Fermi derivative, which
+    // varies over the solvent)
+    L.class_probe = L.op.sigma && L.op.sigma != g->sig && !L.op.psi && use_palette(g) && shift_class_enabled();
+    if (L.class_probe) {   // is sigma one value per palette class?  read back with ||b_lift||
+        if (!g->smm) {
+            PFCHK(dalloc(g, &g->smm, 2 * pfk::PAL_MAX));
+            PFCHK(dalloc(g, &g->stab64, pfk::PAL_MAX));
+            PFCHK(dalloc(g, &g->stab32, pfk::PAL_MAX));
+        }
+        PFCHK(fill<unsigned long long>(g, g->smm, ~0ull, pfk::PAL_MAX));
+        PFCHK(fill<unsigned long long>(g, g->smm + pfk::PAL_MAX, 0ull, pfk::PAL_MAX));
+        hipLaunchKernelGGL(pfk::k_shift_classes, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, L.op.sigma,
+                           (const uint8_t *)g->epsi, g->smm);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(pfk::k_shift_table, dim3(1), dim3(64), 0, g->stream, (const unsigned long long *)g->smm,
+                           g->stab64, g->stab32, &g->sc->shift_class);
+        HIPCHK(hipGetLastError());
+    }
     hipLaunchKernelGGL(pfk::k_set_dirichlet, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
                        (const uint8_t *)g->flags, dirbit(L.op), L.op.psi ? nullptr : (const double *)g->dval);
     HIPCHK(hipGetLastError());
@@ -1107,6 +1146,7 @@ pf_status ls_init_decide(LinSolve &L)
         L.result = PF_ERR_ARG;
         return PF_OK;
     }
+    L.op.sig_class = L.class_probe && g->hsc->shift_class;
     L.bnorm = std::sqrt(g->hsc->red[1]);
     if (!std::isfinite(L.bnorm)) {
         L.done = true;
@@ -1387,12 +1427,13 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
     // shift array (members without one read zeros)
     int form = psi ? FORM_CEPS : FORM_PLAIN;
     if (!psi) {
-        bool sig = false, pal = true;
+        bool sig = false, pal = true, cls = true;
         for (const LinSolve *L : act) {
             sig = sig || L->op.sigma;
             pal = pal && use_palette(L->g);
+            cls = cls && L->op.sigma && L->op.sig_class;
         }
-        form = pal ? (sig ? FORM_PALSIG : FORM_PAL) : (sig ? FORM_SIG : FORM_PLAIN);
+        form = pal ? (sig ? (cls ? FORM_PALTAB : FORM_PALSIG) : FORM_PAL) : (sig ? FORM_SIG : FORM_PLAIN);
     }
     std::vector<long> key = {(long)sizeof(T), (long)form};
     key.insert(key.end(), members.begin(), members.end());

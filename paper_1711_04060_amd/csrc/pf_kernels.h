@@ -78,11 +78,19 @@ struct Scalars {
     int stop_a;        // state decided by the last step A, published by the step B after it
     int fresh;         // 1 from a (re)start until step B of the first iteration
     int neg_shift;     // set when a free row of the operator has sigma < 0
+    int shift_class;   // set when sigma is one value per palette class on the free rows
 };
 enum { ST_RUN = 0, ST_CONV = 1, ST_RESTART = 3, ST_NONFINITE = 4, ST_MAXIT = 5 };
 
 // stencil operation selector
 enum { OP_SPMV = 0, OP_SPMV_JAC = 1, OP_RESID = 2, OP_BA = 3, OP_BB = 4 };
+
+// how the BiCGSTAB steps get the diagonal shift sigma of the own node: none,
+// read from a per-node array, or (palette form) from a table by the node's
+// palette class, where sigma is one value per class on the free rows (the
+// linearised systems, whose shift is uniform in the solvent and zero in the
+// solute)
+enum { SIG_NONE = 0, SIG_NODE = 1, SIG_CLASS = 2 };
 
 template <typename T>
 struct ZArgs {
@@ -97,7 +105,8 @@ struct ZArgs {
     const T *ftab;              // PAL form: face coefficients of every palette pair (PAL_MAX^2, / h^2)
     const uint8_t *flags;       // CEPS form: node flags, Dirichlet rows have bit dirbit
     uint8_t dirbit;
-    const T *sig;               // SIG form (BA, BB): diagonal shift sigma
+    const T *sig;               // SIG_NODE form (BA, BB): diagonal shift sigma
+    const T *stab;              // SIG_CLASS form (BA, BB): sigma of each palette class (PAL_MAX)
     const T *x;                 // SPMV*/RESID operand; BA: s^; BB: r^
     const T *y0;                // BA: p^ (previous); BB: v^
     const T *y1;                // BA: v^ (previous)
@@ -426,13 +435,13 @@ __device__ __forceinline__ U ldx(const U *base, unsigned g)
     return *reinterpret_cast<const U *>(reinterpret_cast<const char *>(base) + g * (unsigned)sizeof(U));
 }
 
-template <int OP, typename T, bool CEPS, bool SIG, bool PAL, bool OWN>
+template <int OP, typename T, bool CEPS, int SIG, bool PAL, bool OWN>
 __device__ __forceinline__ void load_raw(const ZArgs<T> &a, unsigned g, Raw<T> &w)
 {
     if constexpr (PAL) w.ei = ldx(a.epsi, g);
     else if constexpr (!CEPS) w.e = ldx(a.eps, g);
     if constexpr (CEPS && OWN) w.f = a.flags[g];
-    if constexpr (SIG && OWN) w.sg = ldx(a.sig, g);
+    if constexpr (SIG == SIG_NODE && OWN) w.sg = ldx(a.sig, g);
     if constexpr (OP == OP_SPMV || OP == OP_SPMV_JAC) {
         w.x0 = ldx(a.x, g);
     } else if constexpr (OP == OP_RESID) {
@@ -546,12 +555,13 @@ __device__ __forceinline__ uint8_t own_reg(uint8_t x)
 // issued unconditionally with its plane clamped into the tile's range and
 // its node clamped into the strip, so the number of loads per step is fixed
 // and the wait before staging a plane covers only that plane's loads.
-template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, int SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
 __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, const int slot)
 {
     static_assert(!SIG || OP == OP_BA || OP == OP_BB, "the SIG form is a BiCGSTAB step form");
     static_assert(!(SIG && CEPS), "the CEPS form has a constant shift");
     static_assert(!(PAL && CEPS), "the CEPS form reads no coefficient field");
+    static_assert(SIG != SIG_CLASS || PAL, "the class shift is indexed by the palette");
     // halo nodes per thread kept in registers (both halo rows fit when
     // 2 nx <= HMAX*NT); the WIDE form stages the rest in a slower
     // synchronous loop, for planes wider than that
@@ -625,8 +635,10 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     // the face table: loaded first, stored behind the two LDS planes once
     // the plane loads are out, read after the barrier before the first output
     T *lftab = reinterpret_cast<T *>(smem_raw) + 4 * a.lmax;
-    T ftv = T(0);
+    T *lstab = lftab + FTAB;   // SIG_CLASS: the shift of each palette class
+    T ftv = T(0), stv = T(0);
     if constexpr (PAL) ftv = a.ftab[threadIdx.x & (FTAB - 1)];
+    if constexpr (SIG == SIG_CLASS) stv = a.stab[threadIdx.x & (PAL_MAX - 1)];
 
     // ---- prologue loads: the previous phase's partials, then planes k0-1,
     //      k0 (own), k0 (halo), and the raw sets of planes k0+1 and k0+2
@@ -714,6 +726,9 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     beta = uniform(beta);
     if constexpr (PAL) {
         if (threadIdx.x < FTAB) lftab[threadIdx.x] = ftv;
+        if constexpr (SIG == SIG_CLASS) {
+            if (threadIdx.x < PAL_MAX) lstab[threadIdx.x] = stv;
+        }
         __syncthreads();   // table visible before the first output
     }
 
@@ -727,7 +742,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     T ep[PPT], ec[PPT], en[PPT];   // coefficient field (signed), planes k-1, k, k+1
     float tc[PPT], tn[PPT];        // shadow residual (BA, BB), planes k, k+1
     T rc_[PPT], rn_[PPT];          // BA: r^ of planes k, k+1
-    T sc_[PPT], sn_[PPT];          // SIG: sigma of planes k, k+1
+    T sc_[PPT], sn_[PPT];          // SIG_NODE: sigma of planes k, k+1
     uint8_t fc[PPT], fn[PPT];      // CEPS: flag bytes of planes k, k+1
     double acc[NQ];
 #pragma unroll
@@ -739,7 +754,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
         vc[q] = stage_raw<OP, T>(rc[q], alpha, omega, beta);
         ec[q] = CEPS ? T(0) : coef<PAL>(rc[q]);
         tc[q] = SCAL ? rc[q].t : 0.0f;
-        sc_[q] = SIG ? rc[q].sg : T(0);
+        sc_[q] = SIG == SIG_NODE ? rc[q].sg : T(0);
         fc[q] = CEPS ? rc[q].f : (uint8_t)0;
         vp[q] = stage_raw<OP, T>(rp[q], alpha, omega, beta);
         ep[q] = CEPS ? T(0) : coef<PAL>(rp[q]);
@@ -797,7 +812,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
             vn[q] = own_reg(stage_raw<OP, T>(ro[q], alpha, omega, beta));
             if constexpr (!CEPS) en[q] = own_reg(coef<PAL>(ro[q]));
             if constexpr (CEPS) fn[q] = own_reg(ro[q].f);
-            if constexpr (SIG) sn_[q] = own_reg(ro[q].sg);
+            if constexpr (SIG == SIG_NODE) sn_[q] = own_reg(ro[q].sg);
             if constexpr (SCAL) tn[q] = own_reg(ro[q].t);
             if constexpr (OP == OP_BA) {
                 stage_xr<T>(ro[q], xn[q], rn_[q], alpha, omega);
@@ -856,14 +871,16 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                 D = a.cdiag;
                 dir = (fc[q] & a.dirbit) != 0;
             } else if constexpr (PAL) {
-                const T *row = lftab + ((int)absT(ec[q]) - 1) * PAL_MAX;
+                const int own = (int)absT(ec[q]) - 1;
+                const T *row = lftab + own * PAL_MAX;
                 const T c0 = row[(int)absT(le[oxm[q]]) - 1], c1 = row[(int)absT(le[oxp[q]]) - 1];
                 const T c2 = row[(int)absT(le[oym[q]]) - 1], c3 = row[(int)absT(le[oyp[q]]) - 1];
                 const T c4 = row[(int)absT(ep[q]) - 1], c5 = row[(int)absT(eu[q]) - 1];
                 sum = c0 * lv[oxm[q]] + c1 * lv[oxp[q]] + c2 * lv[oym[q]] + c3 * lv[oyp[q]] + c4 * vp[q] +
                       c5 * vu[q];
                 D = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
-                if constexpr (SIG) D += sc_[q];
+                if constexpr (SIG == SIG_NODE) D += sc_[q];
+                if constexpr (SIG == SIG_CLASS) D += lstab[own];
                 dir = ec[q] < T(0);
             } else {
                 const T e = absT(ec[q]);
@@ -873,7 +890,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
                 sum = c0 * lv[oxm[q]] + c1 * lv[oxp[q]] + c2 * lv[oym[q]] + c3 * lv[oyp[q]] + c4 * vp[q] +
                       c5 * vu[q];
                 D = ((c0 + c1) + (c2 + c3)) + (c4 + c5);
-                if constexpr (SIG) D += sc_[q];
+                if constexpr (SIG == SIG_NODE) D += sc_[q];
                 dir = ec[q] < T(0);
             }
             if constexpr (OP == OP_SPMV) {
@@ -984,7 +1001,7 @@ __device__ __forceinline__ void zmarch_tile(const ZArgs<T> &a, const int lb, con
     }
 }
 
-template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, int SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch(ZArgs<T> a)
 {
     zmarch_tile<OP, T, CEPS, SIG, PAL, NT, PPT, WIDE, DEPTH>(a, xcd_remap(blockIdx.x, a.G), blockIdx.x);
@@ -1081,7 +1098,7 @@ __global__ __launch_bounds__(ACT_NT) void k_batch_active(const Scalars *const *s
 // after reading it.  Tiles go to the XCDs in runs (xcd_runs), and the
 // hardware hands each workgroup slot the next tile as one finishes.  Each
 // member keeps its own scalars, partials and status.
-template <int OP, typename T, bool CEPS, bool SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
+template <int OP, typename T, bool CEPS, int SIG, bool PAL, int NT, int PPT, bool WIDE, int DEPTH>
 __global__ __launch_bounds__(NT) void k_zmarch_batch(const ZArgs<T> *__restrict__ args,
                                                      const int *__restrict__ act,
                                                      const int *__restrict__ pref,
@@ -1126,6 +1143,75 @@ __global__ void k_palette_index(size_t N, const double *eps, const double *pal, 
         while (k < npal - 1 && pal[k] != v) ++k;
         idx[n] = (uint8_t)(k | (e < 0.0 ? 128 : 0));
     }
+}
+
+// Shift per palette class: the smallest and largest bit pattern of sigma on
+// the free rows of each class (sigma >= 0 there, so the patterns order as the
+// values; a negative zero or a NaN reads as a second value).  mm holds
+// PAL_MAX minima, then PAL_MAX maxima, preset to ~0 and 0.  Each wave takes
+// the classes of its lanes one at a time.
+__global__ __launch_bounds__(256) void k_shift_classes(size_t N, const double *sigma, const uint8_t *epsi,
+                                                       unsigned long long *mm)
+{
+    __shared__ unsigned long long smin[PAL_MAX], smax[PAL_MAX];
+    if (threadIdx.x < PAL_MAX) {
+        smin[threadIdx.x] = ~0ull;
+        smax[threadIdx.x] = 0ull;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (size_t base = (size_t)blockIdx.x * blockDim.x; base < N; base += (size_t)gridDim.x * blockDim.x) {
+        const size_t n = base + threadIdx.x;
+        int c = PAL_MAX;   // none
+        unsigned long long u = 0;
+        if (n < N) {
+            const uint8_t e = epsi[n];
+            if (!(e & 128)) {
+                c = e & (PAL_MAX - 1);
+                u = (unsigned long long)__double_as_longlong(sigma[n]);
+            }
+        }
+        for (;;) {
+            const unsigned long long pending = __ballot(c < PAL_MAX);
+            if (pending == 0ull) break;
+            const int lead = __ffsll((long long)pending) - 1;
+            const int cl = __shfl(c, lead);
+            unsigned long long lo = (c == cl) ? u : ~0ull, hi = (c == cl) ? u : 0ull;
+            for (int o = 32; o > 0; o >>= 1) {
+                lo = min(lo, (unsigned long long)__shfl_xor(lo, o));
+                hi = max(hi, (unsigned long long)__shfl_xor(hi, o));
+            }
+            if (lane == lead) {
+                atomicMin(&smin[cl], lo);
+                atomicMax(&smax[cl], hi);
+            }
+            if (c == cl) c = PAL_MAX;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < PAL_MAX && smin[threadIdx.x] != ~0ull) {
+        atomicMin(&mm[threadIdx.x], smin[threadIdx.x]);
+        atomicMax(&mm[PAL_MAX + threadIdx.x], smax[threadIdx.x]);
+    }
+}
+
+// The class table (FP64 and its FP32 rounding; 0 for classes without free
+// rows) and the verdict: 1 when every class holds a single value.
+__global__ void k_shift_table(const unsigned long long *mm, double *t64, float *t32, int *one_per_class)
+{
+    if (threadIdx.x != 0) return;
+    int ok = 1;
+    for (int c = 0; c < PAL_MAX; ++c) {
+        const unsigned long long lo = mm[c], hi = mm[PAL_MAX + c];
+        double v = 0.0;
+        if (lo != ~0ull) {
+            ok &= lo == hi;
+            v = __longlong_as_double((long long)lo);
+        }
+        t64[c] = v;
+        t32[c] = (float)v;
+    }
+    *one_per_class = ok;
 }
 
 // ------------------------------------------------------------ finalize

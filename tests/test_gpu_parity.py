@@ -466,6 +466,92 @@ def test_linear_batch_matches_single_solves():
             assert _rel(host(x), ref) <= bar, (p.name, prec)
 
 
+def _small_linearised(count):
+    """Linearised systems of the 64-system workload with at most 57^3 nodes."""
+    return [p for p in inputs.batch_systems(n_sys=16) if p.nx <= 57][:count]
+
+
+def _solve_with(pf, g, s, b, prec, shift_class, batched=False):
+    """Solve(s) with the shift-per-class table allowed or not; returns the
+    solutions and the step-A bytes per launch the library accounted."""
+    os.environ["PF_SHIFT_CLASS"] = "1" if shift_class else "0"
+    pf.pf_timing_enable(1, 1)
+    try:
+        opts = pf.pf_lin_opts_default(rel_tol=1e-12 if prec == 0 else 1e-10, precision=prec)
+        if batched:
+            xs = [torch.zeros_like(bb) for bb in b]
+            infos = pf.pf_linear_solve_batch(g, s, b, xs, opts)
+            kind = pf.TIMING_BATCH_FP64 if prec == 0 else pf.TIMING_BATCH_FP32
+        else:
+            xs = [torch.zeros_like(b)]
+            infos = [pf.pf_linear_solve(g, s, b, xs[0], opts)]
+            kind = prec
+        t = pf.pf_timing_read(kind)
+    finally:
+        pf.pf_timing_enable(0, 1)
+        os.environ.pop("PF_SHIFT_CLASS", None)
+    return xs, infos, t
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_shift_per_class_table_matches_per_node_shift(prec):
+    """A linearised system's shift is one value per coefficient class (zero in
+    the solute, uniform in the solvent): the step kernels then take it from a
+    per-class table instead of reading it per node.  The diagonal is summed
+    in the same order, so both forms give the same iterates bit for bit; the
+    table form reads 8 (FP64) or 4 (FP32) bytes per node less in step A.  A
+    shift that differs at one free node keeps the per-node form and still
+    matches the oracle."""
+    pf = _pf()
+    if os.environ.get("PF_PALETTE") == "0":
+        pytest.skip("the class table needs the palette form")
+    p = _small_linearised(1)[0]
+    g = pf.grid_from_problem(p)
+    s, b = dev(p.sigma), dev(p.b)
+    elem = 8 if prec == 0 else 4
+    xt, it, tt = _solve_with(pf, g, s, b, prec, True)
+    xn, inn, tn = _solve_with(pf, g, s, b, prec, False)
+    assert it[0]["status"] == 0 and inn[0]["status"] == 0
+    assert it[0]["iters"] == inn[0]["iters"]
+    assert torch.equal(xt[0], xn[0])
+    per_t, per_n = tt["bytes"] / tt["launches"], tn["bytes"] / tn["launches"]
+    assert per_n - per_t == elem * p.N
+    ref = oracle.linear_solve(p, p.sigma, p.b, tol=1e-13)[0]
+    assert _rel(host(xt[0]), ref) <= (1e-9 if prec == 0 else 1e-8)
+    # one free solvent node with a different shift: per-node form, same bar
+    sig2 = p.sigma.copy()
+    isd, _ = oracle.dirichlet(p)
+    free_solvent = np.flatnonzero((isd == 0) & (sig2 > 0))
+    k = int(free_solvent[len(free_solvent) // 2])
+    sig2[k] *= 1.5
+    x2, i2, t2 = _solve_with(pf, g, dev(sig2), b, prec, True)
+    assert i2[0]["status"] == 0 and t2["bytes"] / t2["launches"] == per_n
+    ref2 = oracle.linear_solve(p, sig2, p.b, tol=1e-13)[0]
+    assert _rel(host(x2[0]), ref2) <= (1e-9 if prec == 0 else 1e-8)
+    assert _rel(ref2, ref) > 1e-12   # the perturbation is visible in the solution
+
+
+def test_batch_shift_per_class_table_matches_oracle():
+    """A batch whose members all have a shift per class runs the table form
+    (step-A bytes counted without the shift); each member matches the oracle."""
+    pf = _pf()
+    if os.environ.get("PF_PALETTE") == "0":
+        pytest.skip("the class table needs the palette form")
+    probs = _small_linearised(3)
+    grids = [pf.grid_from_problem(p) for p in probs]
+    sg, bs = [dev(p.sigma) for p in probs], [dev(p.b) for p in probs]
+    refs = [oracle.linear_solve(p, p.sigma, p.b, tol=1e-13)[0] for p in probs]
+    for prec, bar in ((0, 1e-9), (1, 1e-8)):
+        elem = 8 if prec == 0 else 4
+        xs, infos, t = _solve_with(pf, grids, sg, bs, prec, True, batched=True)
+        for p, x, ref, info in zip(probs, xs, refs, infos):
+            assert info["status"] == 0
+            assert _rel(host(x), ref) <= bar, (p.name, prec)
+        # every launch counted moved at most the members' table-form bytes
+        full = sum((9 * elem + 1 + 4) * p.N for p in probs)
+        assert 0 < t["bytes"] / t["launches"] <= full
+
+
 def test_linear_batch_rejects_shared_grid():
     pf = _pf()
     p = inputs.sphere_poisson(33)
