@@ -16,9 +16,10 @@ The JSON line also carries:
                 pass over every iterating member), timed with HIP events on
                 the library's stream in one chunk of iterations out of
                 --sample during the timed steps; algorithmic bytes per launch
-                = 85 B per node of every member still iterating (reads s^,
-                p^, v^, t^, x, sigma in FP64, the coefficient's one-byte
-                palette index and the FP32 shadow; writes x, r^, p^, v^);
+                = 77 B per node of every member still iterating (reads s^,
+                p^, v^, t^, x in FP64, the coefficient's one-byte palette
+                index, which also selects the member's shift from its
+                per-class table, and the FP32 shadow; writes x, r^, p^, v^);
   cpu_baseline  the serial FP64 oracle, pinned to one core, on a bounded
                 sample of the members, extrapolated to the whole batch by
                 node-iterations;
@@ -560,7 +561,7 @@ def copy_reference(torch, mib=512):
     return n * 8
 
 
-PMC_BATCH_KERNEL = "k_zmarch_batch<3, double, false, true"   # batched step A, FP64, shift-array form
+PMC_BATCH_KERNEL = "k_zmarch_batch<3, double, false, 2, true"   # batched step A, FP64, shift per class
 
 
 def _counter_rows(path, counter):
@@ -798,8 +799,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("batched BiCGSTAB step A, FP64, shift-array form (previous x, r^ update + p^ update + "
-                       "v^ = D^-1 A p^ + 2 dots over every iterating member)"),
+            "kernel": ("batched BiCGSTAB step A, FP64, palette form with the shift per class (previous x, "
+                       "r^ update + p^ update + v^ = D^-1 A p^ + 2 dots over every iterating member)"),
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
@@ -808,9 +809,9 @@ def main():
             "launches_timed": tm["launches"],
             "mean_us": tm["mean_ms"] * 1e3,
             "bytes_per_launch": bpl,
-            "bytes_rule": ("85 B per node of every member still iterating at that launch: s^, p^, v^, t^, x, "
-                           "sigma (8 B each) read, 1-byte coefficient palette index, 4-byte shadow; x, r^, p^, "
-                           "v^ written"),
+            "bytes_rule": ("77 B per node of every member still iterating at that launch: s^, p^, v^, t^, x "
+                           "(8 B each) read, 1-byte coefficient palette index (it also selects the shift from "
+                           "the member's per-class table), 4-byte shadow; x, r^, p^, v^ written"),
         },
     }
     if args.forms:

@@ -32,8 +32,8 @@ def _write_csv(path, counter, rows):
 
 def test_batch_counter_summary_scales_and_selects(tmp_path):
     copy_bytes = 1 << 20
-    A = "void pfk::k_zmarch_batch<3, double, false, true, 512, 1, false, 1>(pfk::ZArgs<double> const*, int const*, int)"
-    B = "void pfk::k_zmarch_batch<4, double, false, true, 512, 1, false, 1>(pfk::ZArgs<double> const*, int const*, int)"
+    A = "void pfk::k_zmarch_batch<3, double, false, 2, true, 512, 1, false, 1>(pfk::ZArgs<double> const*, int const*, int)"
+    B = "void pfk::k_zmarch_batch<4, double, false, 2, true, 512, 1, false, 1>(pfk::ZArgs<double> const*, int const*, int)"
     single = "void pfk::k_zmarch<3, double, false, true, 512, 1, false, 1>(pfk::ZArgs<double>)"
     copy = "__amd_rocclr_copyBuffer"
     # FETCH reads half the copied bytes (scale 2), WRITE all of them (scale 1)
