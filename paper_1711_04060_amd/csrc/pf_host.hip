@@ -2253,6 +2253,7 @@ struct NlSys {
     double delta = INFINITY;
     pf_status st = PF_OK;
     bool done = false;
+    bool pre = false;   // the last relaxation launch already did the next iteration's point-wise steps
     std::chrono::steady_clock::time_point t0;
 };
 
@@ -2307,6 +2308,9 @@ pf_status nl_linear_phase(std::vector<NlSys *> &sys, const std::vector<OpDesc> &
 //   step 3   Fermi update at Phi_0 (Eq. (1)) and PF1 (Eq. (12), (14));
 //   step 4   PF2 (Eq. (13)) warm-started from Phi_0;
 //   step 5   Phi := omega Phi_0 + (1 - omega) Phi, stop on the max norm.
+// From the second outer iteration on, step 5's kernel also does step 3's
+// Fermi update (and, for the local PF1, Psi and the PF2 right-hand side) at
+// the relaxed Phi_0, so the point-wise work of an outer iteration is one pass.
 pf_status nl_drive(std::vector<NlSys> &S, bool batched)
 {
     for (auto &s : S) {
@@ -2353,6 +2357,7 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
         for (NlSys *s : act) {
             pf_grid *g = s->g;
             ++s->it;
+            if (s->pre) continue;
             hipLaunchKernelGGL(pfk::k_fermi, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
                                (const double *)g->phi0, (const uint8_t *)g->flags, s->sp, g->rhs1, (double *)nullptr,
                                g->sig, (double *)nullptr, (double *)nullptr);
@@ -2376,7 +2381,7 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
                     bs.push_back(g->rhs1);
                     x0s.push_back(g->psi);
                     xs.push_back(g->psi);
-                } else {
+                } else if (!s->pre) {
                     hipLaunchKernelGGL(pfk::k_psi_local, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
                                        (const double *)g->rhs1, (const uint8_t *)g->flags, 1.0 / s->p->eps_s, g->psi);
                     HIPCHK(hipGetLastError());
@@ -2393,10 +2398,12 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
             for (NlSys *s : act) {
                 if (s->done) continue;
                 pf_grid *g = s->g;
-                hipLaunchKernelGGL(pfk::k_rhs_pf2, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
-                                   (const double *)g->psi, (const double *)g->sig, (const double *)g->phi0,
-                                   (const double *)g->src, s->p->eps_s, g->rhs2);
-                HIPCHK(hipGetLastError());
+                if (!s->pre || s->p->lc > 0) {   // else written by the relaxation kernel
+                    hipLaunchKernelGGL(pfk::k_rhs_pf2, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N,
+                                       (const double *)g->psi, (const double *)g->sig, (const double *)g->phi0,
+                                       (const double *)g->src, s->p->eps_s, g->rhs2);
+                    HIPCHK(hipGetLastError());
+                }
                 OpDesc op;
                 op.sigma = g->sig;
                 pf2.push_back(s);
@@ -2412,9 +2419,13 @@ pf_status nl_drive(std::vector<NlSys> &S, bool batched)
             if (s->done) continue;
             pf_grid *g = s->g;
             const int B = pw_blocks(g->N);
-            hipLaunchKernelGGL((pfk::k_relax<NT>), dim3(B), dim3(NT), 0, g->stream, g->N, g->phi0, g->phi,
-                               s->p->omega, g->partials);
+            const bool local = !(s->p->lc > 0);
+            hipLaunchKernelGGL((pfk::k_relax_fermi<NT>), dim3(B), dim3(NT), 0, g->stream, g->N, g->phi0, g->phi,
+                               s->p->omega, g->partials, (const uint8_t *)g->flags, s->sp,
+                               local ? nullptr : g->rhs1, g->sig, (const double *)g->src, s->p->eps_s,
+                               1.0 / s->p->eps_s, local ? g->rhs2 : nullptr);
             HIPCHK(hipGetLastError());
+            s->pre = true;
             PFCHK(finalize<pfk::FIN_MAX>(g, B));
             HIPCHK(hipMemcpyAsync(g->hsc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, g->stream));
         }

@@ -1436,6 +1436,25 @@ __device__ __forceinline__ double steric_root(double phi, const SpeciesDev &sp)
     return S;
 }
 
+// Fermi update at one solvent node of potential ph: rho_hat into rh,
+// lambda sum z_i^2 C_i (= -rho_hat' of Eq. (11)) into sg, the steric
+// potential into S, and C_i into conc[i*N + n] when conc is given.
+__device__ __forceinline__ void fermi_at(double ph, const SpeciesDev &sp, double &rh, double &sg, double &S,
+                                         double *conc, size_t n, size_t N)
+{
+    rh = 0.0;
+    sg = 0.0;
+    S = sp.steric ? steric_root(ph, sp) : 0.0;
+    for (int i = 0; i < sp.nsp; ++i) {
+        const double C = exp(sp.lncb[i] - sp.z[i] * ph + sp.p[i] * S);
+        rh += sp.z[i] * C;
+        sg += sp.z[i] * sp.z[i] * C;
+        if (conc) conc[(size_t)i * N + n] = C;
+    }
+    rh *= sp.lam;
+    sg *= sp.lam;
+}
+
 // Fermi update at every node; zeros off the solvent.  Writes any of:
 // rhs1 = -rho_hat (the PF1 right-hand side), rho = rho_hat,
 // sigma = lambda sum z_i^2 C_i (= -rho_hat' of Eq. (11)), conc[i*N + n], S.
@@ -1447,16 +1466,7 @@ __global__ void k_fermi(size_t N, const double *phi, const uint8_t *flags, Speci
         double rh = 0.0, sg = 0.0, S = 0.0;
         const bool solvent = flags[n] & F_SOLVENT;
         if (solvent) {
-            const double ph = phi[n];
-            if (sp.steric) S = steric_root(ph, sp);
-            for (int i = 0; i < sp.nsp; ++i) {
-                const double C = exp(sp.lncb[i] - sp.z[i] * ph + sp.p[i] * S);
-                rh += sp.z[i] * C;
-                sg += sp.z[i] * sp.z[i] * C;
-                if (conc) conc[(size_t)i * N + n] = C;
-            }
-            rh *= sp.lam;
-            sg *= sp.lam;
+            fermi_at(phi[n], sp, rh, sg, S, conc, n, N);
         } else if (conc) {
             for (int i = 0; i < sp.nsp; ++i) conc[(size_t)i * N + n] = 0.0;
         }
@@ -1516,8 +1526,20 @@ __global__ __launch_bounds__(NT) void k_maxabs_free(size_t N, const double *r, c
     store_partials<1>(acc, partials, blockIdx.x);
 }
 
+// Relaxation (Table 2 step 5) fused with the point-wise steps that open the
+// next outer iteration: Phi_0 := omega Phi_0 + (1 - omega) Phi (also into
+// Phi; max |change| into the partials), then at the new Phi_0 the Fermi
+// update (Eq. (1)): sig = -rho_hat', and
+//   rhs2 == null (a PF1 solve follows): rhs1 = -rho_hat;
+//   rhs2 != null (local PF1, lc = 0): Psi = -rho_hat / eps_s (0 on PF1
+//   Dirichlet rows) and the PF2 right-hand side of Eq. (13),
+//   rhs2 = -eps_s Psi + sig Phi_0 + src, neither Psi nor rhs1 stored.
+// Each value is the one the separate kernels compute, in the same order.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_relax(size_t N, double *phi0, double *phi, double omega, double *partials)
+__global__ __launch_bounds__(NT) void k_relax_fermi(size_t N, double *phi0, double *phi, double omega,
+                                                    double *partials, const uint8_t *flags, SpeciesDev sp,
+                                                    double *rhs1, double *sig, const double *src, double eps_s,
+                                                    double inv_eps_s, double *rhs2)
 {
     double acc[1] = {0.0};
     const size_t stride = (size_t)gridDim.x * NT;
@@ -1529,6 +1551,16 @@ __global__ __launch_bounds__(NT) void k_relax(size_t N, double *phi0, double *ph
         acc[0] = fmax(acc[0], d);
         phi0[n] = nv;
         phi[n] = nv;
+        const uint8_t f = flags[n];
+        double rh = 0.0, sg = 0.0, S = 0.0;
+        if (f & F_SOLVENT) fermi_at(nv, sp, rh, sg, S, nullptr, n, N);
+        sig[n] = sg;
+        if (rhs2) {
+            const double ps = (f & F_DIR_PSI) ? 0.0 : -rh * inv_eps_s;
+            rhs2[n] = -eps_s * ps + sg * nv + src[n];
+        } else {
+            rhs1[n] = -rh;
+        }
     }
     block_reduce<1, NT, true>(acc);
     store_partials<1>(acc, partials, blockIdx.x);

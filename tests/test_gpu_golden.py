@@ -21,8 +21,9 @@ Bars (relative L2 on the subsample):
 Workloads: the 193^3 dielectric sphere (the mixed-precision linear
 workload), the 97^3 membrane pore (the full PF workload) in FP64 and with
 mixed-precision linear solves, and the 16-bias sweep of the membrane at 33^3
-batched with mixed-precision linear solves (the bias-sweep form), plus the
-mixed-precision nonlinear solve at 17^3 and 25^3 against the oracle run here.
+batched with mixed-precision linear solves (the bias-sweep form) and one of
+its members solved alone, plus the mixed-precision nonlinear solve at 17^3
+and 25^3 against the oracle run here.
 """
 import os
 
@@ -139,6 +140,26 @@ def test_nonlinear_mixed_linear_solves_match_oracle(n, nc):
     info = pf.pf_nonlinear_solve(g, prm, phi)
     assert info["status"] == 0
     assert _rel(phi.cpu().numpy(), ref) <= 1e-8
+
+
+def test_nonlinear_mixed_33_matches_stored_oracle():
+    """The 33^3 membrane at one bias of the sweep, solved alone (not batched)
+    with mixed-precision linear solves, against its stored oracle solution."""
+    pf = _pf()
+    m = 7
+    vt = inputs.thermal_voltage_mV()
+    p = inputs.membrane_pore(33, bias_phi=inputs.bias_sweep_mV()[m] / vt)
+    gold = _golden(f"bias33_{m:02d}")
+    assert abs(float(gold["bias_phi"]) - p.bc_value[4]) == 0.0
+    g = pf.grid_from_problem(p)
+    prm = pf.params_for(p, outer_tol=float(gold["outer_tol"]),
+                        lin={"rel_tol": float(gold["lin_tol"]), "precision": pf.PF_MIXED})
+    phi = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    info = pf.pf_nonlinear_solve(g, prm, phi)
+    assert info["status"] == 0
+    e = _rel(_sub(phi.cpu().numpy(), gold), gold["x_sub"])
+    print(f"membrane33 bias {m} mixed: rel L2 {e:.2e}, outer {info['outer_iters']} (oracle {int(gold['outer_iters'])})")
+    assert e <= 1e-8
 
 
 def test_bias_sweep_33_batched_mixed_matches_oracle():
