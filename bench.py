@@ -407,19 +407,28 @@ def forms_loop_settings(pf, torch, inputs, n=49):
     return dict(workload=f"membrane_pore {n}^3", runs=runs)
 
 
-def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0):
+BIAS_MODES = ("batched_mixed", "sequential_fp64")
+
+
+def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0, modes=BIAS_MODES, members=None):
     """Configuration 5: 16 bias voltages on the membrane workload, full PF
     nonlinear solves, batched (shared launches, mixed-precision linear
     solves) vs 16 sequential FP64 solves.  Each run is driven in chunks of
-    `chunk` outer iterations (warm-started from the last iterate, which is the
-    whole state of the outer loop) so that progress is printed.  outer_cap > 0
-    stops every bias after that many outer iterations (equal work in both
-    modes: a throughput comparison instead of time to convergence)."""
+    `chunk` outer iterations (warm-started from the last iterate; the PF1
+    initial guess restarts from zero) so that progress is printed.
+    outer_cap > 0 stops every bias after that many outer iterations (equal
+    work in both modes: a throughput comparison instead of time to
+    convergence).  modes and members (indices into the 16 biases) select
+    part of the sweep, for runs split over several invocations."""
     vt = inputs.thermal_voltage_mV()
-    probs = [inputs.membrane_pore(n, bias_phi=v / vt) for v in inputs.bias_sweep_mV()]
+    sweep = inputs.bias_sweep_mV()
+    members = list(range(len(sweep))) if members is None else list(members)
+    probs = [inputs.membrane_pore(n, bias_phi=sweep[m] / vt) for m in members]
     grids = [pf.grid_from_problem(p) for p in probs]
-    res = {}
+    res = {"members": members, "bias_mV": [sweep[m] for m in members]}
     for name, prec, batched in (("batched_mixed", pf.PF_MIXED, True), ("sequential_fp64", pf.PF_FP64, False)):
+        if name not in modes:
+            continue
         step = min(chunk, outer_cap) if outer_cap else chunk
         prms = [pf.params_for(p, outer_tol=1e-8, max_outer=step, lin={"rel_tol": 1e-10, "precision": prec})
                 for p in probs]
@@ -453,11 +462,14 @@ def forms_bias_sweep(pf, torch, inputs, n=129, chunk=400, outer_cap=0):
                 log(f"[bench]   {name}: {len(todo)} of {len(grp)} still running, "
                     f"{time.perf_counter() - t0:.1f} s")
         torch.cuda.synchronize()
-        res[name] = dict(seconds=time.perf_counter() - t0, outer_iters=outer, total_lin_iters=lin)
+        res[name] = dict(seconds=time.perf_counter() - t0, outer_iters=outer, total_lin_iters=lin,
+                         converged=not outer_cap)
         log(f"[bench] bias sweep {name}: {res[name]['seconds']:.1f} s")
-    res["speedup"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
-    res["workload"] = (f"membrane_pore {n}^3, 16 biases -150..+150 mV on -z, outer 1e-8, BiCGSTAB 1e-10"
-                       + (f", every bias stopped after {outer_cap} outer iterations" if outer_cap else ""))
+    if all(m in res for m in BIAS_MODES):
+        res["speedup"] = res["sequential_fp64"]["seconds"] / res["batched_mixed"]["seconds"]
+    res["workload"] = (f"membrane_pore {n}^3, {len(members)} of the 16 biases -150..+150 mV on -z, outer 1e-8, "
+                       "BiCGSTAB 1e-10"
+                       + (f", every bias stopped after {outer_cap} outer iterations" if outer_cap else ", converged"))
     return res
 
 
@@ -691,6 +703,10 @@ def main():
                     help="configuration 5: stop every bias after this many outer iterations (0: converge)")
     ap.add_argument("--bias-sweep", type=int, default=1, help="run configuration 5 (16 biases, 129^3)")
     ap.add_argument("--bias-n", type=int, default=129)
+    ap.add_argument("--bias-modes", type=str, default=",".join(BIAS_MODES),
+                    help="bias sweep modes to run (comma list of batched_mixed, sequential_fp64)")
+    ap.add_argument("--bias-members", type=str, default="",
+                    help="first:last (exclusive) of the 16 biases; default all")
     ap.add_argument("--tps", type=int, default=0, help="also run the five exchange-cycle states at 97^3")
     ap.add_argument("--loop-settings", type=int, default=0, help="also sweep omega and ErrTol at 49^3")
     ap.add_argument("--copy-ref", type=int, default=0, help="run the copy reference kernel (counter scale)")
@@ -829,8 +845,10 @@ def main():
         result["forms"]["interface_97"] = forms_interface(pf, torch, inputs)
     if args.bias_sweep:
         log(f"[bench] forms: 16-bias sweep at {args.bias_n}^3")
-        result.setdefault("forms", {})["bias_sweep"] = forms_bias_sweep(pf, torch, inputs, n=args.bias_n,
-                                                                        outer_cap=args.bias_outer)
+        sel = [int(v) for v in args.bias_members.split(":")] if args.bias_members else None
+        result.setdefault("forms", {})["bias_sweep"] = forms_bias_sweep(
+            pf, torch, inputs, n=args.bias_n, outer_cap=args.bias_outer,
+            modes=tuple(args.bias_modes.split(",")), members=range(sel[0], sel[1]) if sel else None)
     if args.loop_settings:
         log("[bench] forms: outer-loop settings at 49^3")
         result.setdefault("forms", {})["loop_settings_49"] = forms_loop_settings(pf, torch, inputs)
