@@ -12,6 +12,8 @@ benchmark uses (autotuned), where the oracle cannot afford a whole solve:
   * 97^3 membrane PF solve: the returned potential satisfies the discrete PF
     system (PF2 with the rho' terms cancelled, Psi from PF1) evaluated by the
     oracle's assembly, Fermi and BiCGSTAB;
+  * the two ends of the 16-bias sweep at 129^3, batched with mixed-precision
+    linear solves to convergence: the same property for both members;
   * 97^3 membrane through the singular-charge decomposition with its 2000
     charges: the interface terms and phi* + phi^L against the whole oracle
     computation, and the Coulomb kernel over every Omega_m node (the launch
@@ -126,16 +128,11 @@ def test_fermi_97_sampled_nodes(membrane97):
     np.testing.assert_allclose(S.cpu().numpy()[idx], oS, rtol=1e-12, atol=1e-12)
 
 
-def test_pf_solve_97_satisfies_discrete_system(membrane97):
-    pf = _pf()
-    p = membrane97
+def _discrete_pf_residual(p, phi):
+    """Relative L2 residual of the discrete PF2 equation at phi (rho' terms
+    cancelled), with Psi from the oracle's PF1 solve and rho from its Fermi
+    update, on the free rows."""
     eps_s, lc = 78.45, p.meta["lc_A"]
-    g = pf.grid_from_problem(p)
-    prm = pf.params_for(p, outer_tol=1e-8, lin={"rel_tol": 1e-10})
-    phi_t = torch.zeros(p.N, dtype=torch.float64, device="cuda")
-    info = pf.pf_nonlinear_solve(g, prm, phi_t)
-    assert info["status"] == 0 and info["last_delta"] <= 1e-8
-    phi = phi_t.cpu().numpy()
     ms = p.meta["species"]
     sp = oracle.species_from_molar(ms["valence"], ms["radius_A"], ms["bath_M"])
     rho, _, _, _ = oracle.fermi(phi, sp, p.node_type, want_conc=False)
@@ -148,10 +145,41 @@ def test_pf_solve_97_satisfies_discrete_system(membrane97):
     A = oracle.assemble(p.nx, p.ny, p.nz, p.h, p.eps, None, isd, p.bc_phi)
     rhs = -eps_s * psi + sp.lam * p.fixed_charge / p.h ** 3
     r = (oracle.dia_matvec(p.nx, p.ny, p.nz, A, phi) - rhs)[isd == 0]
+    return float(np.linalg.norm(r) / np.linalg.norm(rhs[isd == 0]))
+
+
+def test_pf_solve_97_satisfies_discrete_system(membrane97):
+    pf = _pf()
+    p = membrane97
+    g = pf.grid_from_problem(p)
+    prm = pf.params_for(p, outer_tol=1e-8, lin={"rel_tol": 1e-10})
+    phi_t = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    info = pf.pf_nonlinear_solve(g, prm, phi_t)
+    assert info["status"] == 0 and info["last_delta"] <= 1e-8
     # the outer loop stops on the size of its last update (1e-8), not on this
     # residual; its contraction near the fixed point is slow (~0.996 per outer
     # iteration), so the potential can still be ~2.5e-6 from the fixed point
-    assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(rhs[isd == 0])
+    assert _discrete_pf_residual(p, phi_t.cpu().numpy()) <= 1e-5
+
+
+def test_bias_sweep_129_batched_mixed_satisfies_discrete_system():
+    """The two ends of the 16-bias sweep (-150 and +150 mV on the -z face) at
+    129^3, batched with mixed-precision linear solves and run to convergence
+    (outer 1e-8, BiCGSTAB 1e-10) as the bias-sweep form does: each potential
+    satisfies the discrete PF system to the bar of the 97^3 solve."""
+    pf = _pf()
+    vt = inputs.thermal_voltage_mV()
+    sweep = inputs.bias_sweep_mV()
+    probs = [inputs.membrane_pore(129, bias_phi=sweep[m] / vt) for m in (0, len(sweep) - 1)]
+    grids = [pf.grid_from_problem(p) for p in probs]
+    prms = [pf.params_for(p, outer_tol=1e-8, lin={"rel_tol": 1e-10, "precision": pf.PF_MIXED}) for p in probs]
+    phis = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
+    infos = pf.pf_nonlinear_solve_batch(grids, prms, phis)
+    for p, phi, info in zip(probs, phis, infos):
+        assert info["status"] == 0 and info["last_delta"] <= 1e-8
+        res = _discrete_pf_residual(p, phi.cpu().numpy())
+        print(f"129^3 bias {p.bc_value[4] * vt:+.0f} mV: outer {info['outer_iters']}, discrete residual {res:.2e}")
+        assert res <= 1e-5
 
 
 def test_decomposition_97_against_oracle():
