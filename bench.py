@@ -577,12 +577,61 @@ PMC_BATCH_KERNEL = "k_zmarch_batch<3, double, false, 2, true"   # batched step A
 
 
 def _counter_rows(path, counter):
+    """Counter values (bytes) per kernel name, in dispatch order."""
     import csv
     vals = {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
-            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
-    return vals
+            vals.setdefault(r["Kernel_Name"], []).append((int(r.get("Dispatch_Id") or 0),
+                                                          float(r["Counter_Value"]) * 1024.0))
+    return {k: [v for _, v in sorted(xs, key=lambda t: t[0])] for k, xs in vals.items()}
+
+
+# The 193^3 Poisson steps in the pinned launch shapes (SHAPE_193) and their
+# algorithmic bytes per node (palette form, no shift): step A reads s^, p^,
+# v^, t^, x, the palette byte and the FP32 shadow and writes x, r^, p^, v^;
+# step B reads r^, v^, the palette byte and the shadow and writes s^, t^.
+PMC_193_KERNELS = {
+    "step_a_fp64": ("k_zmarch<3, double, false, 0, true, 512, 1, false, 1>", 9 * 8 + 1 + 4),
+    "step_b_fp64": ("k_zmarch<4, double, false, 0, true, 512, 1, false, 1>", 4 * 8 + 1 + 4),
+    "step_a_fp32": ("k_zmarch<3, float, false, 0, true, 1024, 2, false, 1>", 9 * 4 + 1 + 4),
+    "step_b_fp32": ("k_zmarch<4, float, false, 0, true, 1024, 2, false, 1>", 4 * 4 + 1 + 4),
+}
+
+
+def pmc_summary_193(fetch_csv, write_csv, copy_bytes, n=193):
+    """Counter traffic of the 193^3 BiCGSTAB steps from two rocprofv3 --pmc
+    runs of `bench.py --linear193-only 1 --copy-ref 1`: per kernel, the
+    dispatches that did a whole step (those queued after convergence exit at
+    once and fetch almost nothing: counted are the ones fetching at least a
+    fifth of the algorithmic bytes, the same dispatches in both runs), the
+    counters scaled by their reading on the copy kernel of known size, and
+    their ratio to the algorithmic bytes."""
+    N = n ** 3
+    rows = {c: _counter_rows(p, c) for c, p in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv))}
+    scale = {}
+    for c, r in rows.items():
+        copy = [x for k, xs in r.items() if "copy" in k.lower() for x in xs]
+        scale[c] = copy_bytes / max(copy) if copy else None
+    out = {"workload": f"sphere_poisson_{n}", "source_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
+           "FETCH_SIZE_scale": scale["FETCH_SIZE"], "WRITE_SIZE_scale": scale["WRITE_SIZE"], "kernels": {}}
+    if not all(scale.values()):
+        return out
+    for key, (name, per_node) in PMC_193_KERNELS.items():
+        alg = per_node * N
+        f = [x * scale["FETCH_SIZE"] for k, xs in rows["FETCH_SIZE"].items() if name in k for x in xs]
+        w = [x * scale["WRITE_SIZE"] for k, xs in rows["WRITE_SIZE"].items() if name in k for x in xs]
+        e = {"kernel": name, "algorithmic_bytes": alg, "dispatches": len(f), "runs_aligned": len(f) == len(w)}
+        if f and len(f) == len(w):
+            full = [i for i, x in enumerate(f) if x >= 0.2 * alg]
+            e["dispatches_counted"] = len(full)
+            if full:
+                e["FETCH_SIZE"] = sum(f[i] for i in full) / len(full)
+                e["WRITE_SIZE"] = sum(w[i] for i in full) / len(full)
+                e["counter_bytes"] = e["FETCH_SIZE"] + e["WRITE_SIZE"]
+                e["counter_over_algorithmic"] = e["counter_bytes"] / alg
+        out["kernels"][key] = e
+    return out
 
 
 def pmc_summary_batch(fetch_csv, write_csv, copy_bytes, alg_log):
@@ -724,6 +773,8 @@ def main():
     ap.add_argument("--pin-shape", type=str, default="",
                     help="threads,strip,zplanes,depth: launch shape of every stencil kernel instead of the "
                          "autotuner's (for counter runs, whose serialised launches distort the tuner)")
+    ap.add_argument("--pmc-summary-193", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs of --linear193-only 1 --copy-ref 1 and exit")
     ap.add_argument("--linear193-only", type=int, default=0,
                     help="run only the 193^3 FP64 and mixed linear solves (for traces and counters) and exit")
     ap.add_argument("--cpu-sample-job", type=str, default="", help=argparse.SUPPRESS)
@@ -737,6 +788,10 @@ def main():
     if args.pmc_summary:
         print(json.dumps(pmc_summary_batch(args.pmc_summary[0], args.pmc_summary[1], 512 * (1 << 20),
                                            args.pmc_summary[2]), indent=1))
+        return
+    if args.pmc_summary_193:
+        print(json.dumps(pmc_summary_193(args.pmc_summary_193[0], args.pmc_summary_193[1], 512 * (1 << 20)),
+                         indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path "

@@ -58,6 +58,30 @@ def test_batch_counter_summary_scales_and_selects(tmp_path):
     assert out["counter_over_algorithmic"] == pytest.approx(1.1)
 
 
+def test_193_counter_summary_counts_whole_steps(tmp_path):
+    copy_bytes = 1 << 20
+    n = 5
+    N = n ** 3
+    name, per = bench.PMC_193_KERNELS["step_a_fp64"]
+    A = f"void pfk::{name}(pfk::ZArgs<double>)"
+    alg = per * N
+    copy = "__amd_rocclr_copyBuffer"
+    f_rows = [(copy, copy_bytes / 2 / 1024)]       # FETCH scale 2, WRITE scale 1
+    w_rows = [(copy, copy_bytes / 1024)]
+    for frac in (0.6, 0.6, 0.001):                 # two whole steps, one exit after convergence
+        f_rows.append((A, 0.5 * frac * alg / 1024))
+        w_rows.append((A, 0.5 * frac * alg / 1024))
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    _write_csv(fp, "FETCH_SIZE", f_rows)
+    _write_csv(wp, "WRITE_SIZE", w_rows)
+    out = bench.pmc_summary_193(str(fp), str(wp), copy_bytes, n=n)
+    e = out["kernels"]["step_a_fp64"]
+    assert e["dispatches"] == 3 and e["runs_aligned"] and e["dispatches_counted"] == 2
+    assert e["FETCH_SIZE"] == pytest.approx(0.6 * alg) and e["WRITE_SIZE"] == pytest.approx(0.3 * alg)
+    assert e["counter_over_algorithmic"] == pytest.approx(0.9)
+    assert out["kernels"]["step_b_fp64"]["dispatches"] == 0
+
+
 def test_traffic_only_from_current_source(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
