@@ -634,32 +634,38 @@ def pmc_summary_193(fetch_csv, write_csv, copy_bytes, n=193):
     return out
 
 
-def pmc_summary_batch(fetch_csv, write_csv, copy_bytes, alg_log):
+def pmc_summary_batch(fetch_csv, write_csv, copy_bytes, fetch_log, write_log):
     """Counter traffic of the batched FP64 step A from two rocprofv3 --pmc
     runs (CSV) of `bench.py --pmc-run 1`: FETCH_SIZE and WRITE_SIZE summed
     over every dispatch of that kernel (the run times every chunk, so each
-    dispatch is also in the algorithmic count the run printed to alg_log),
-    each counter scaled by its reading on the copy kernel of known size."""
-    alg = None
-    for line in open(alg_log):
-        if line.startswith("{") and "pmc_run" in line:
-            alg = json.loads(line)["pmc_run"]
-    out = {"kernel": PMC_BATCH_KERNEL, "source_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
-           "algorithmic": alg}
-    tot = {}
-    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+    dispatch is also in the algorithmic count the run printed to its log),
+    each counter scaled by its reading on the copy kernel of known size and
+    divided by its own run's algorithmic bytes (the two runs can differ by a
+    chunk: the true-residual checks between Krylov runs use autotuned shapes,
+    whose reduction order decides a restart near the tolerance)."""
+    def alg_of(path):
+        alg = None
+        for line in open(path):
+            if line.startswith("{") and "pmc_run" in line:
+                alg = json.loads(line)["pmc_run"]
+        return alg
+
+    out = {"kernel": PMC_BATCH_KERNEL, "source_hash": kernel_source_hash(), "copy_bytes": copy_bytes}
+    ratio = {}
+    for counter, path, log_path in (("FETCH_SIZE", fetch_csv, fetch_log), ("WRITE_SIZE", write_csv, write_log)):
+        alg = alg_of(log_path)
         rows = _counter_rows(path, counter)
         copy = [x for k, xs in rows.items() if "copy" in k.lower() for x in xs]
         scale = copy_bytes / max(copy) if copy else None
         mine = [x for k, xs in rows.items() if PMC_BATCH_KERNEL in k for x in xs]
+        out[counter + "_run"] = alg
         out[counter + "_dispatches"] = len(mine)
         out[counter + "_scale"] = scale
-        tot[counter] = sum(mine) * scale if (mine and scale) else None
-    if alg and all(tot.values()) and alg["launches_timed"]:
-        out["dispatches_match"] = out["FETCH_SIZE_dispatches"] == out["WRITE_SIZE_dispatches"] == alg["launches_timed"]
-        out["counter_bytes_per_launch"] = (tot["FETCH_SIZE"] + tot["WRITE_SIZE"]) / out["FETCH_SIZE_dispatches"]
-        out["algorithmic_bytes_per_launch"] = alg["bytes_timed"] / alg["launches_timed"]
-        out["counter_over_algorithmic"] = out["counter_bytes_per_launch"] / out["algorithmic_bytes_per_launch"]
+        if mine and scale and alg and alg["launches_timed"] == len(mine) and alg["bytes_timed"] > 0:
+            out[counter + "_bytes_per_launch"] = sum(mine) * scale / len(mine)
+            ratio[counter] = sum(mine) * scale / alg["bytes_timed"]
+    if len(ratio) == 2:
+        out["counter_over_algorithmic"] = ratio["FETCH_SIZE"] + ratio["WRITE_SIZE"]
     return out
 
 
@@ -759,9 +765,9 @@ def main():
     ap.add_argument("--tps", type=int, default=0, help="also run the five exchange-cycle states at 97^3")
     ap.add_argument("--loop-settings", type=int, default=0, help="also sweep omega and ErrTol at 49^3")
     ap.add_argument("--copy-ref", type=int, default=0, help="run the copy reference kernel (counter scale)")
-    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "RUN_LOG"),
-                    help="summarise two rocprofv3 --pmc CSVs of a --pmc-run (and its printed algorithmic "
-                         "bytes) into the traffic file and exit")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_LOG", "WRITE_LOG"),
+                    help="summarise the rocprofv3 --pmc CSVs of two --pmc-run invocations (and the algorithmic "
+                         "bytes each printed) into the traffic file and exit")
     ap.add_argument("--pmc-run", type=int, default=0,
                     help="counter run: the headline steps only, every chunk timed (--sample 1), and the "
                          "algorithmic bytes of the timed launches printed (run it with PF_BATCH_POLICY set "
@@ -786,8 +792,8 @@ def main():
         print(json.dumps(trace_summary(args.trace_summary), indent=1))
         return
     if args.pmc_summary:
-        print(json.dumps(pmc_summary_batch(args.pmc_summary[0], args.pmc_summary[1], 512 * (1 << 20),
-                                           args.pmc_summary[2]), indent=1))
+        f_csv, w_csv, f_log, w_log = args.pmc_summary
+        print(json.dumps(pmc_summary_batch(f_csv, w_csv, 512 * (1 << 20), f_log, w_log), indent=1))
         return
     if args.pmc_summary_193:
         print(json.dumps(pmc_summary_193(args.pmc_summary_193[0], args.pmc_summary_193[1], 512 * (1 << 20)),

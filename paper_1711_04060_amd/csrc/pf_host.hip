@@ -1336,9 +1336,13 @@ struct BatchBuf {
 //      clamp(strips nz / 256, 2, 16) planes (a batch has more tiles than one
 //      system, so longer chunks lose less to the planes above and below);
 //   2: 512 threads, one node per thread, depth 1, the members' z-chunks;
-//   3: 256 threads, one node per thread, depth 1, long z-chunks as in 1.
+//   3: 256 threads, one node per thread, depth 1, long z-chunks as in 1;
+//   4, 5: 512 threads, one node per thread, the default depth, z-chunks of
+//      8 and 16 planes for every member (fewer planes re-read above and
+//      below a chunk on the small members, fewer tiles once few members are
+//      left).
 // step: 0 = A, 1 = B.
-constexpr int NPOLICY = 4;
+constexpr int NPOLICY = 6;
 
 template <typename T>
 std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int policy, ZCfg &combined)
@@ -1370,6 +1374,8 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
         int kz;
         if (own_kz) {
             kz = (step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g)).KZ;
+        } else if (policy >= 4) {
+            kz = policy == 4 ? 8 : 16;
         } else {
             const long S = (long)ntz * ppt;
             const long strips = ((long)g->nx * g->ny + S - 1) / S;
@@ -1549,6 +1555,10 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         plans[k].gather = [=]() {
             hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
         };
+    }
+    // the chunk graph of plan k, captured on first use
+    auto capture = [&](int k) -> pf_status {
+        if (plans[k].exec) return PF_OK;
         hipGraph_t graph;
         HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
         pf_status st = PF_OK;
@@ -1563,11 +1573,11 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
             plans[k].exec = nullptr;
             return fail(PF_ERR_DEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
         }
-    }
+        return PF_OK;
+    };
 
     status.assign(n, pfk::ST_RUN);
-    int use = npol > 1 ? next_untried() : 0;   // plan index of the next chunk
-    bool comparing = npol > 1;
+    int use = 0;   // plan index of the chunks
     // kernel timing: iterations done per member before the chunk, step-A bytes per member
     std::vector<int> before(n);
     std::vector<double> abytes(n);
@@ -1576,8 +1586,54 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         abytes[i] = step_a_bytes(act[i]->op, act[i]->g, sizeof(T));
     }
     const int tslot = sizeof(T) == 8 ? 4 : 5;
-    for (int chunk = 0;; ++chunk) {
-        const auto t0 = std::chrono::steady_clock::now();
+    // one status read: members' scalars to the host, status updated; false
+    // once no member iterates
+    auto read_status = [&]() -> pf_status {
+        HIPCHK(hipMemcpyAsync(g_batch.hsc, dgather, szS, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        for (int i = 0; i < n; ++i) status[i] = g_batch.hsc[i].stop;
+        return PF_OK;
+    };
+    auto running = [&]() {
+        for (int i = 0; i < n; ++i)
+            if (status[i] == pfk::ST_RUN) return true;
+        return false;
+    };
+    if (npol > 1) {
+        // every policy runs the same few iterations at the start of the run,
+        // while (nearly) every member still iterates: two untimed (first
+        // launches of a kernel instance), then TRIAL timed, each policy in
+        // turn; the node-iterations per second decide
+        constexpr int WARM = 2, TRIAL = 4;
+        std::vector<double> &t = *trials;
+        for (int k = 0; k < NPOLICY && running(); ++k) {
+            for (int i = 0; i < WARM; ++i) PFCHK(plans[k].launch_iter(i & 1, nullptr, nullptr));
+            plans[k].gather();
+            PFCHK(read_status());
+            for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int i = 0; i < TRIAL; ++i) PFCHK(plans[k].launch_iter(i & 1, nullptr, nullptr));
+            plans[k].gather();
+            PFCHK(read_status());
+            const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            double work = 0;
+            for (int i = 0; i < n; ++i) work += (double)(g_batch.hsc[i].iter_done - before[i]) * (double)act[i]->g->N;
+            t[k] = secs > 0 ? work / secs : 0.0;
+            for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
+        }
+        if (next_untried() < 0) {
+            use = (int)(std::max_element(t.begin(), t.end()) - t.begin());
+            g_batch_policy[key] = use;
+            if (getenv("PF_LOG"))
+                fprintf(stderr, "[pf] batch of %d: policies 0..5 at %.3g %.3g %.3g %.3g %.3g %.3g node-iterations/s "
+                                "over %d iterations each; keeping policy %d\n", n, t[0], t[1], t[2], t[3], t[4],
+                        t[5], TRIAL, use);
+        } else {   // the run ended before every policy was timed: compare again next time
+            trials->clear();
+        }
+    }
+    if (running()) PFCHK(capture(use));
+    while (running()) {
         const bool timed = g_timing.enabled && (g_timing.chunk++ % g_timing.sample) == 0;
         hipError_t e = hipSuccess;
         if (timed) {
@@ -1613,33 +1669,10 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
                 g_timing.bytes[tslot] += bytes;
             }
         }
-        bool any = false;
         for (int i = 0; i < n; ++i) {
             status[i] = g_batch.hsc[i].stop;
-            any |= status[i] == pfk::ST_RUN;
+            before[i] = g_batch.hsc[i].iter_done;
         }
-        if (comparing) {
-            const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            double work = 0;
-            for (int i = 0; i < n; ++i) work += (double)(g_batch.hsc[i].iter_done - before[i]) * (double)act[i]->g->N;
-            // a chunk in which some member stopped did less than a full chunk
-            // of work for it; it still counts, at the rate it achieved
-            if (work > 0) (*trials)[use] = secs > 0 ? work / secs : 0.0;
-            const int nx_ = next_untried();
-            if (nx_ >= 0) {
-                use = nx_;
-            } else {   // every policy has been timed: keep the fastest
-                const std::vector<double> &t = *trials;
-                use = (int)(std::max_element(t.begin(), t.end()) - t.begin());
-                g_batch_policy[key] = use;
-                comparing = false;
-                if (getenv("PF_LOG"))
-                    fprintf(stderr, "[pf] batch of %d: chunks of %d iterations, policies 0..3 at %.3g %.3g %.3g %.3g "
-                                    "node-iterations/s; keeping policy %d\n", n, m, t[0], t[1], t[2], t[3], use);
-            }
-        }
-        for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
-        if (!any) break;
     }
     for (int i = 0; i < n; ++i) *act[i]->g->hsc = g_batch.hsc[i];
     return PF_OK;

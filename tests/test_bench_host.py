@@ -34,28 +34,37 @@ def test_batch_counter_summary_scales_and_selects(tmp_path):
     copy_bytes = 1 << 20
     A = "void pfk::k_zmarch_batch<3, double, false, 2, true, 512, 1, false, 1>(pfk::ZArgs<double> const*, int const*, int)"
     B = "void pfk::k_zmarch_batch<4, double, false, 2, true, 512, 1, false, 1>(pfk::ZArgs<double> const*, int const*, int)"
-    single = "void pfk::k_zmarch<3, double, false, true, 512, 1, false, 1>(pfk::ZArgs<double>)"
+    single = "void pfk::k_zmarch<3, double, false, 0, true, 512, 1, false, 1>(pfk::ZArgs<double>)"
     copy = "__amd_rocclr_copyBuffer"
-    # FETCH reads half the copied bytes (scale 2), WRITE all of them (scale 1)
+    # FETCH reads half the copied bytes (scale 2), WRITE all of them (scale 1);
+    # the WRITE run did one dispatch fewer (its own algorithmic count)
     f_rows = [(copy, copy_bytes / 2 / 1024)]
     w_rows = [(copy, copy_bytes / 1024)]
-    alg = [9000.0, 6000.0, 3000.0]                 # members drop out: fewer bytes per launch
-    for a in alg:
+    alg_f = [9000.0, 6000.0, 3000.0]               # members drop out: fewer bytes per launch
+    alg_w = [9000.0, 6000.0]
+    for a in alg_f:
         f_rows.append((A, 0.40 * a / 1024))        # 0.80 of the algorithmic bytes once scaled
-        w_rows.append((A, 0.30 * a / 1024))
+    for a in alg_w:
+        w_rows.append((A, 0.30 * a / 1024))        # 0.30
     f_rows += [(B, 99.0), (single, 77.0)]          # other kernels are not counted
     w_rows += [(B, 99.0), (single, 77.0)]
-    fp, wp, log = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "run.log"
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    flog, wlog = tmp_path / "f.log", tmp_path / "w.log"
     _write_csv(fp, "FETCH_SIZE", f_rows)
     _write_csv(wp, "WRITE_SIZE", w_rows)
-    log.write_text("[bench] noise\n" + json.dumps({"pmc_run": {"launches_timed": 3, "bytes_timed": sum(alg),
-                                                                "mean_us": 1.0}}) + "\n")
-    out = bench.pmc_summary_batch(str(fp), str(wp), copy_bytes, str(log))
+    for path, alg in ((flog, alg_f), (wlog, alg_w)):
+        path.write_text("[bench] noise\n" + json.dumps({"pmc_run": {"launches_timed": len(alg),
+                                                                     "bytes_timed": sum(alg),
+                                                                     "mean_us": 1.0}}) + "\n")
+    out = bench.pmc_summary_batch(str(fp), str(wp), copy_bytes, str(flog), str(wlog))
     assert out["FETCH_SIZE_scale"] == pytest.approx(2.0) and out["WRITE_SIZE_scale"] == pytest.approx(1.0)
-    assert out["FETCH_SIZE_dispatches"] == 3 and out["dispatches_match"]
-    assert out["counter_bytes_per_launch"] == pytest.approx(1.1 * sum(alg) / 3)
-    assert out["algorithmic_bytes_per_launch"] == pytest.approx(sum(alg) / 3)
+    assert out["FETCH_SIZE_dispatches"] == 3 and out["WRITE_SIZE_dispatches"] == 2
+    assert out["FETCH_SIZE_bytes_per_launch"] == pytest.approx(0.8 * sum(alg_f) / 3)
     assert out["counter_over_algorithmic"] == pytest.approx(1.1)
+    # a run whose dispatch count does not match its own log gives no ratio
+    wlog.write_text(json.dumps({"pmc_run": {"launches_timed": 3, "bytes_timed": 1.0, "mean_us": 1.0}}) + "\n")
+    assert "counter_over_algorithmic" not in bench.pmc_summary_batch(str(fp), str(wp), copy_bytes, str(flog),
+                                                                     str(wlog))
 
 
 def test_193_counter_summary_counts_whole_steps(tmp_path):
