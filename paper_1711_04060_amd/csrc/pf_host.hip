@@ -1338,7 +1338,7 @@ struct BatchBuf {
 //   2: 512 threads, one node per thread, depth 1, the members' z-chunks;
 //   3: 256 threads, one node per thread, depth 1, long z-chunks as in 1;
 //   4, 5: 512 threads, one node per thread, the default depth, z-chunks of
-//      8 and 16 planes for every member (fewer planes re-read above and
+//      32 and 16 planes for every member (fewer planes re-read above and
 //      below a chunk on the small members, fewer tiles once few members are
 //      left).
 // step: 0 = A, 1 = B.
@@ -1375,7 +1375,7 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
         if (own_kz) {
             kz = (step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g)).KZ;
         } else if (policy >= 4) {
-            kz = policy == 4 ? 8 : 16;
+            kz = policy == 4 ? 32 : 16;
         } else {
             const long S = (long)ntz * ppt;
             const long strips = ((long)g->nx * g->ny + S - 1) / S;
@@ -1625,9 +1625,9 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
             use = (int)(std::max_element(t.begin(), t.end()) - t.begin());
             g_batch_policy[key] = use;
             if (getenv("PF_LOG"))
-                fprintf(stderr, "[pf] batch of %d: policies 0..5 at %.3g %.3g %.3g %.3g %.3g %.3g node-iterations/s "
-                                "over %d iterations each; keeping policy %d\n", n, t[0], t[1], t[2], t[3], t[4],
-                        t[5], TRIAL, use);
+                fprintf(stderr, "[pf] batch of %d: policies 0..5 at %.3g %.3g %.3g %.3g %.3g %.3g "
+                                "node-iterations/s over %d iterations each; keeping policy %d\n", n, t[0], t[1], t[2],
+                        t[3], t[4], t[5], TRIAL, use);
         } else {   // the run ended before every policy was timed: compare again next time
             trials->clear();
         }
