@@ -14,8 +14,10 @@ The JSON line also carries:
   roofline      the batched BiCGSTAB step-A stencil kernel (the previous
                 iteration's x, r update, the p update and v = A p^ in one
                 pass over every iterating member), timed with HIP events on
-                the library's stream in one chunk of iterations out of
-                --sample during the timed steps; algorithmic bytes per launch
+                the library's stream over every launch of the timed steps
+                (one chunk of iterations out of --sample, default 1: all of
+                them, whose graph launches then become direct launches with
+                dispatch-stamped events); algorithmic bytes per launch
                 = 77 B per node of every member still iterating (reads s^,
                 p^, v^, t^, x in FP64, the coefficient's one-byte palette
                 index, which also selects the member's shift from its
@@ -751,7 +753,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sample", type=int, default=4, help="time step A in one chunk of iterations out of this many")
+    ap.add_argument("--sample", type=int, default=1,
+                    help="time step A in one chunk of iterations out of this many (1: every launch of the timed "
+                         "steps, the set a profiler's mean over them covers)")
     ap.add_argument("--forms", type=int, default=1)
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--bias-outer", type=int, default=100,
