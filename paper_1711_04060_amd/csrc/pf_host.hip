@@ -1340,9 +1340,11 @@ struct BatchBuf {
 //   4, 5: 512 threads, one node per thread, the default depth, z-chunks of
 //      32 and 16 planes for every member (fewer planes re-read above and
 //      below a chunk on the small members, fewer tiles once few members are
-//      left).
+//      left);
+//   6: as 5 for step A; step B with 512 threads x two nodes (its lighter
+//      work per node favours longer strips).
 // step: 0 = A, 1 = B.
-constexpr int NPOLICY = 6;
+constexpr int NPOLICY = 7;
 
 template <typename T>
 std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int policy, ZCfg &combined)
@@ -1351,6 +1353,7 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
     const bool own_kz = policy == 0 || policy == 2;
     if (policy == 2) depth = 1;
     if (policy == 3) { ntz = 256; depth = 1; }
+    if (policy == 6 && step == 1) { ppt = 2; depth = default_depth(sizeof(T), 2); }
     if (policy == 0) {
         std::map<std::tuple<int, int, int>, double> weight;
         for (const LinSolve *L : act) {
@@ -1375,7 +1378,7 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
         if (own_kz) {
             kz = (step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g)).KZ;
         } else if (policy >= 4) {
-            kz = policy == 4 ? 32 : 16;
+            kz = policy == 4 ? 32 : 16;   // 5, 6: 16
         } else {
             const long S = (long)ntz * ppt;
             const long strips = ((long)g->nx * g->ny + S - 1) / S;
@@ -1625,9 +1628,9 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
             use = (int)(std::max_element(t.begin(), t.end()) - t.begin());
             g_batch_policy[key] = use;
             if (getenv("PF_LOG"))
-                fprintf(stderr, "[pf] batch of %d: policies 0..5 at %.3g %.3g %.3g %.3g %.3g %.3g "
+                fprintf(stderr, "[pf] batch of %d: policies 0..6 at %.3g %.3g %.3g %.3g %.3g %.3g %.3g "
                                 "node-iterations/s over %d iterations each; keeping policy %d\n", n, t[0], t[1], t[2],
-                        t[3], t[4], t[5], TRIAL, use);
+                        t[3], t[4], t[5], t[6], TRIAL, use);
         } else {   // the run ended before every policy was timed: compare again next time
             trials->clear();
         }
