@@ -244,7 +244,13 @@ pf_status pf_fermi(pf_grid *g, const pf_pf_params *p, const double *phi, double 
                    double *sigma, double *conc, double *steric);
 
 /* Batched linear solves: n independent systems (grids may differ in size),
- * each as pf_linear_solve with the shared opts.  info: host [n] or NULL. */
+ * each as pf_linear_solve with the shared opts.  info: host [n] or NULL.
+ * The members' BiCGSTAB iterations run in shared launches over the tiles of
+ * the members still iterating.  The first batch of a composition (precision,
+ * kernel form, every member's shape) with four or more members times each
+ * launch policy for a few iterations at the start of its first Krylov run and
+ * keeps the fastest for the process (PF_BATCH_POLICY=k in the environment
+ * pins policy k instead). */
 pf_status pf_linear_solve_batch(int32_t n, pf_grid *const *g, const double *const *sigma,
                                 const double *const *b, double *const *x,
                                 const pf_lin_opts *opts, pf_lin_info *info);
@@ -254,13 +260,13 @@ pf_status pf_linear_solve_batch(int32_t n, pf_grid *const *g, const double *cons
 pf_status pf_nonlinear_solve_batch(int32_t n, pf_grid *const *g, const pf_pf_params *const *p,
                                    double *const *phi, pf_nl_info *info);
 
-/* Kernel timing for measurement: while enabled, one chunk in every `sample`
- * (single solves and batches counted together) records HIP events (on the
- * library's stream, as direct launches) around each launch of the BiCGSTAB
- * step-A stencil kernel (the previous iteration's x, r update fused with the
- * p update and v = A p^: the kernel that moves the most bytes per
- * iteration), and every Jacobi-scaled pf_spmv / pf_spmv_f32 call records
- * events around its kernel.
+/* Kernel timing for measurement: while enabled, one chunk of iterations in
+ * every `sample` (single solves and batches counted together) runs as direct
+ * launches on the library's stream with HIP events that each dispatch stamps
+ * at its kernel's start and end, on every launch of the BiCGSTAB step-A
+ * stencil kernel (the previous iteration's x, r update fused with the p
+ * update and v = A p^: the kernel that moves the most bytes per iteration);
+ * every Jacobi-scaled pf_spmv / pf_spmv_f32 call is timed the same way.
  * enable = 1 clears the accumulators and starts; 0 stops.  Process-wide. */
 pf_status pf_timing_enable(int32_t enable, int32_t sample);
 
@@ -269,13 +275,15 @@ pf_status pf_timing_enable(int32_t enable, int32_t sample);
  * Jacobi-scaled products of pf_spmv and pf_spmv_f32; 4 and 5 = the batched
  * step A (one launch over every member) in FP64 and FP32.  launches timed and
  * their mean duration in ms; bytes is the algorithmic HBM traffic of those
- * launches.  Step A moves 11 vectors of N elements per launch (s^, p^, v^,
- * t^, eps, x and the shadow read; x, r^, p^, v^ written), 12 with a shift
- * array sigma, and for PF1 10 vectors plus one flag byte per node; a batched
- * launch counts the members still iterating.  Products: x, eps (and sigma)
- * read, y written.  The mean is that of the event brackets, which also hold
- * the dispatch and completion of the launch: it bounds the kernel's duration
- * from above.  PF_ERR_ARG for another kind. */
+ * launches.  Step A per node: 9 elements of the working precision (s^, p^,
+ * v^, t^, x read; x, r^, p^, v^ written), the coefficient (one palette byte
+ * where the field has at most 16 distinct values, else one element), the
+ * FP32 shadow (4 bytes), and one more element where the shift sigma is read
+ * per node (not where it is one value per palette class and comes from a
+ * table); PF1 reads one flag byte instead of the coefficient.  A batched
+ * launch counts the members still iterating.  Products: x and the
+ * coefficient (and an FP64 sigma) read, y written.  PF_ERR_ARG for another
+ * kind. */
 pf_status pf_timing_read(int32_t kind, int64_t *launches, double *mean_ms, double *bytes);
 
 /* Streaming-bandwidth probe (a measurement aid, no part of the method): the
