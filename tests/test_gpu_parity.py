@@ -552,6 +552,33 @@ def test_batch_shift_per_class_table_matches_oracle():
         assert 0 < t["bytes"] / t["launches"] <= full
 
 
+@pytest.fixture(scope="module")
+def small_batch_refs():
+    probs = _small_linearised(4)
+    return probs, [oracle.linear_solve(p, p.sigma, p.b, tol=1e-13)[0] for p in probs]
+
+
+@pytest.mark.parametrize("policy", range(7))
+def test_every_batch_launch_policy_matches_oracle(policy, small_batch_refs):
+    """Each of the batched launch policies (kernel instance, z-chunk length,
+    step-B strip) the library may keep, pinned through PF_BATCH_POLICY, gives
+    every member the oracle's solution (FP64 1e-9, mixed 1e-8)."""
+    pf = _pf()
+    probs, refs = small_batch_refs
+    grids = [pf.grid_from_problem(p) for p in probs]
+    sg, bs = [dev(p.sigma) for p in probs], [dev(p.b) for p in probs]
+    os.environ["PF_BATCH_POLICY"] = str(policy)
+    try:
+        for prec, tol, bar in ((0, 1e-12, 1e-9), (1, 1e-10, 1e-8)):
+            xs = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for p in probs]
+            infos = pf.pf_linear_solve_batch(grids, sg, bs, xs, pf.pf_lin_opts_default(rel_tol=tol, precision=prec))
+            for p, x, ref, info in zip(probs, xs, refs, infos):
+                assert info["status"] == 0 and info["rel_res"] <= tol
+                assert _rel(host(x), ref) <= bar, (p.name, prec, policy)
+    finally:
+        os.environ.pop("PF_BATCH_POLICY", None)
+
+
 def test_linear_batch_rejects_shared_grid():
     pf = _pf()
     p = inputs.sphere_poisson(33)
