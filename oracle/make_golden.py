@@ -18,6 +18,9 @@ Cases (each one file ``tests/golden/oracle_<case>.npz``):
   bias33_<m>   The 33^3 membrane with bias m of the 16-point sweep
                (-150..+150 mV on the -z face), Table 2 loop to 1e-11,
                BiCGSTAB 1e-13.  Stored: phi on every second node per axis.
+  batch64      The 64 linearised Poisson-Boltzmann systems (33^3..129^3),
+               each Jacobi-BiCGSTAB (Table 3) to relative residual 1e-13.
+               Stored: each x on every (n-1)/8-th node per axis (9^3 nodes).
 
 Every file also holds the whole vector's L2 norm, the iteration counts, the
 oracle's wall time and the host it ran on.
@@ -25,6 +28,7 @@ oracle's wall time and the host it ran on.
     python -m oracle.make_golden membrane97
     python -m oracle.make_golden sphere193
     python -m oracle.make_golden bias33 [first last]
+    python -m oracle.make_golden batch64
 """
 from __future__ import annotations
 
@@ -120,6 +124,25 @@ def bias33(first: int = 0, last: int = 15) -> list:
     return out
 
 
+def batch64() -> str:
+    probs = inputs.batch_systems()
+    arrays = {}
+    t0 = time.perf_counter()
+    iters = []
+    for b, p in enumerate(probs):
+        x, info = oracle.linear_solve(p, p.sigma, p.b, tol=LIN_TOL)
+        s = (p.nx - 1) // 8
+        arrays[f"x_sub_{b:02d}"] = subsample(x, p.shape, s)
+        arrays[f"stride_{b:02d}"] = np.int64(s)
+        arrays[f"shape_{b:02d}"] = np.array(p.shape, np.int64)
+        iters.append(info["iters"])
+        print(f"[golden] batch64 member {b}: n {p.nx} iters {info['iters']} rel_res {info['rel_res']:.3e}", flush=True)
+    secs = time.perf_counter() - t0
+    return _save("batch64", **arrays, members=np.int64(len(probs)), lin_tol=np.float64(LIN_TOL),
+                 lin_iters=np.array(iters, np.int64), seconds=np.float64(secs), host=np.str_(host_name()),
+                 command=np.str_("python -m oracle.make_golden batch64"))
+
+
 def main(argv) -> None:
     case = argv[0] if argv else ""
     # the OpenMP build of the same source (identical bits, independent loops
@@ -129,6 +152,8 @@ def main(argv) -> None:
         print(membrane97())
     elif case == "sphere193":
         print(sphere193())
+    elif case == "batch64":
+        print(batch64())
     elif case == "bias33":
         lo = int(argv[1]) if len(argv) > 1 else 0
         hi = int(argv[2]) if len(argv) > 2 else 15
