@@ -854,6 +854,7 @@ def main():
                                       "mean_us": tm["mean_ms"] * 1e3}}), flush=True)
         return
     max_res = batch.max_rel_res(pf)
+    traffic = traffic_from_profiles(bpl)
     result = {
         "metric": METRIC,
         "value": sec_per_step,
@@ -876,6 +877,7 @@ def main():
             "bicgstab_iters_total": total_iters,
             "bicgstab_iters_max_member": max(i["iters"] for i in infos),
             "node_iters_per_s": node_iters / sec_per_step,
+            "bicgstab_iters_per_s": total_iters / sec_per_step,
             "max_true_rel_res": max_res,
         },
         "roofline": {
@@ -886,7 +888,8 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": traffic_from_profiles(bpl),
+            "traffic": traffic,
+            "traffic_gbs": traffic / (tm["mean_ms"] * 1e-3) / 1e9 if (traffic and tm["launches"]) else None,
             "launches_timed": tm["launches"],
             "mean_us": tm["mean_ms"] * 1e3,
             "bytes_per_launch": bpl,
