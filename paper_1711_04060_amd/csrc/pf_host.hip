@@ -1544,11 +1544,21 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         HIPCHK(hipMemcpyAsync(dbs, bstart.data(), szI, hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));   // the host vectors above go out of scope
 
-        plans[k].launch_iter = [=](int par, hipEvent_t e0, hipEvent_t e1) -> pf_status {
-            hipLaunchKernelGGL(pfk::k_batch_active, dim3(1), dim3(pfk::ACT_NT), 0, stream, dscp, (const int *)das,
-                               (const int *)dbs, n, dact, dpa, dpb, dna);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return fail(PF_ERR_DEVICE, "active-member list launch failed: %s", hipGetErrorString(e));
+        // iteration i of a run of launches (parity i & 1); the active-member
+        // list is refreshed every LIST_EVERY iterations: a member that stops
+        // in between keeps its tiles in the launches until the next refresh,
+        // where they leave at their first test of the stop state
+        plans[k].launch_iter = [=](int i, hipEvent_t e0, hipEvent_t e1) -> pf_status {
+            constexpr int LIST_EVERY = 8;
+            const int par = i & 1;
+            hipError_t e = hipSuccess;
+            if (i % LIST_EVERY == 0) {
+                hipLaunchKernelGGL(pfk::k_batch_active, dim3(1), dim3(pfk::ACT_NT), 0, stream, dscp,
+                                   (const int *)das, (const int *)dbs, n, dact, dpa, dpb, dna);
+                e = hipGetLastError();
+                if (e != hipSuccess)
+                    return fail(PF_ERR_DEVICE, "active-member list launch failed: %s", hipGetErrorString(e));
+            }
             e = launch_batch_form<pfk::OP_BA, T>(form, ca, dA[par], dact, dpa, dna, stream, e0, e1);
             if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
             e = launch_batch_form<pfk::OP_BB, T>(form, cb, dB[par], dact, dpb, dna, stream);
@@ -1565,7 +1575,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         hipGraph_t graph;
         HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
         pf_status st = PF_OK;
-        for (int i = 0; i < m && st == PF_OK; ++i) st = plans[k].launch_iter(i & 1, nullptr, nullptr);
+        for (int i = 0; i < m && st == PF_OK; ++i) st = plans[k].launch_iter(i, nullptr, nullptr);
         plans[k].gather();
         hipError_t e = hipStreamEndCapture(stream, &graph);
         if (st != PF_OK) return st;
@@ -1610,12 +1620,12 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         constexpr int WARM = 2, TRIAL = 4;
         std::vector<double> &t = *trials;
         for (int k = 0; k < NPOLICY && running(); ++k) {
-            for (int i = 0; i < WARM; ++i) PFCHK(plans[k].launch_iter(i & 1, nullptr, nullptr));
+            for (int i = 0; i < WARM; ++i) PFCHK(plans[k].launch_iter(i, nullptr, nullptr));
             plans[k].gather();
             PFCHK(read_status());
             for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
             const auto t0 = std::chrono::steady_clock::now();
-            for (int i = 0; i < TRIAL; ++i) PFCHK(plans[k].launch_iter(i & 1, nullptr, nullptr));
+            for (int i = 0; i < TRIAL; ++i) PFCHK(plans[k].launch_iter(i, nullptr, nullptr));
             plans[k].gather();
             PFCHK(read_status());
             const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1646,7 +1656,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
                 g_batch.ev.push_back(ev);
             }
             for (int i = 0; i < m; ++i)
-                PFCHK(plans[use].launch_iter(i & 1, g_batch.ev[2 * i], g_batch.ev[2 * i + 1]));
+                PFCHK(plans[use].launch_iter(i, g_batch.ev[2 * i], g_batch.ev[2 * i + 1]));
             plans[use].gather();
             e = hipGetLastError();
         } else {
