@@ -957,6 +957,16 @@ int chunk_len(const pf_grid *g, const pf_lin_opts *o)
 // writes the scalar block, whose host copy is set to the same values.  The
 // first step A reads r^ from s^ (r^ = s^ - omega t^ with t^ = 0) and
 // p^ = v^ = 0.
+// A Krylov start recorded instead of launched (batched solves launch every
+// member's start together, in one kernel on the batch's stream).
+struct StartRec {
+    pf_grid *g;
+    int elem;
+    void *p, *v, *t, *xz;
+    Scalars init;
+};
+std::vector<StartRec> *g_defer_start = nullptr;   // set while a batch decides its next runs
+
 template <typename T>
 pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter, int maxit, bool zero_x = false)
 {
@@ -974,6 +984,10 @@ pf_status krylov_start(pf_grid *g, Work<T> &w, double rr, double tol2, int iter,
     h.stop = pfk::ST_RUN;
     h.stop_a = pfk::ST_RUN;
     h.fresh = 1;
+    if (g_defer_start) {
+        g_defer_start->push_back(StartRec{g, (int)sizeof(T), w.p[0], w.v[0], w.t, zero_x ? (void *)w.x : nullptr, h});
+        return PF_OK;
+    }
     hipLaunchKernelGGL((pfk::k_krylov_start<T>), dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, w.p[0],
                        w.v[0], w.t, zero_x ? w.x : (T *)nullptr, h, g->sc);
     HIPCHK(hipGetLastError());
@@ -1243,7 +1257,9 @@ pf_status ls_round_decide(LinSolve &L, bool *run)
 }
 
 // After a Krylov run that ended with device status st (g->hsc is current).
-pf_status ls_after(LinSolve &L, int st)
+// gpu = false: the caller does the copy and correction of every member in
+// one batched launch.
+pf_status ls_after(LinSolve &L, int st, bool gpu = true)
 {
     pf_grid *g = L.g;
     L.iter = g->hsc->iter_done;
@@ -1252,6 +1268,7 @@ pf_status ls_after(LinSolve &L, int st)
         // nothing, so the next true residual equals the last one and the
         // solve falls back to FP64 (ls_round_decide)
         if (st == pfk::ST_RESTART) ++L.restarts;
+        if (!gpu) return PF_OK;
         HIPCHK(hipMemcpyAsync(g->w64.s, g->w64.x, g->N * sizeof(double), hipMemcpyDeviceToDevice, g->stream));
         if (st != pfk::ST_NONFINITE) {
             hipLaunchKernelGGL(pfk::k_correct, dim3(pw_blocks(g->N)), dim3(NT), 0, g->stream, g->N, g->w64.x,
@@ -1414,7 +1431,11 @@ std::map<std::vector<long>, std::vector<double>> g_batch_trials;   // per policy
 struct BatchPlan {
     hipGraphExec_t exec = nullptr;
     std::function<pf_status(int, hipEvent_t, hipEvent_t)> launch_iter;
+    // the first iteration after another plan's: step A from a table (device)
+    // whose partial counts are that plan's step B tile counts
+    std::function<pf_status(int, const void *)> launch_switch;
     std::function<void()> gather;
+    std::vector<int> gB;   // step B tile count per member
     ~BatchPlan()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -1472,7 +1493,7 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
     const size_t szI = sizeof(int) * (n + 1), szP = sizeof(void *) * n, szS = sizeof(Scalars) * n;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t per_pol = 4 * al(szZ) + 4 * al(szI) + al(sizeof(int) * n) + al(sizeof(int));
-    const size_t need = npol * per_pol + al(szP) + al(szS);
+    const size_t need = npol * per_pol + al(szP) + al(szS) + al(szZ);
     if (need > g_batch.bytes) {
         if (g_batch.dev) (void)hipFree(g_batch.dev);
         g_batch.dev = nullptr;
@@ -1495,6 +1516,8 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
     for (int i = 0; i < n; ++i) scp[i] = act[i]->g->sc;
     const Scalars **dscp = (const Scalars **)take(szP);
     Scalars *dgather = (Scalars *)take(szS);
+    pfk::ZArgs<T> *dsw = (pfk::ZArgs<T> *)take(szZ);   // step-A table of a policy switch
+    std::vector<pfk::ZArgs<T>> zas[NPOLICY][2];         // host copies of the step-A tables
     HIPCHK(hipMemcpyAsync(dscp, scp.data(), szP, hipMemcpyHostToDevice, stream));
 
     BatchPlan plans[NPOLICY];
@@ -1543,6 +1566,10 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         HIPCHK(hipMemcpyAsync(das, astart.data(), szI, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(dbs, bstart.data(), szI, hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));   // the host vectors above go out of scope
+        zas[k][0] = za[0];
+        zas[k][1] = za[1];
+        plans[k].gB.resize(n);
+        for (int i = 0; i < n; ++i) plans[k].gB[i] = csb[i].G;
 
         // iteration i of a run of launches (parity i & 1); the active-member
         // list is refreshed every LIST_EVERY iterations: a member that stops
@@ -1565,10 +1592,33 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
             if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
             return PF_OK;
         };
+        plans[k].launch_switch = [=](int i, const void *dAs) -> pf_status {
+            const int par = i & 1;
+            hipLaunchKernelGGL(pfk::k_batch_active, dim3(1), dim3(pfk::ACT_NT), 0, stream, dscp, (const int *)das,
+                               (const int *)dbs, n, dact, dpa, dpb, dna);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return fail(PF_ERR_DEVICE, "active-member list launch failed: %s", hipGetErrorString(e));
+            e = launch_batch_form<pfk::OP_BA, T>(form, ca, (const pfk::ZArgs<T> *)dAs, dact, dpa, dna, stream);
+            if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step A launch failed: %s", hipGetErrorString(e));
+            e = launch_batch_form<pfk::OP_BB, T>(form, cb, dB[par], dact, dpb, dna, stream);
+            if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched step B launch failed: %s", hipGetErrorString(e));
+            return PF_OK;
+        };
         plans[k].gather = [=]() {
             hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
         };
     }
+    // Step A of iteration i sums the partials that step B of iteration i - 1
+    // wrote, one per step-B tile of each member: the first iteration of plan
+    // q after iterations of plan p reads plan p's counts (the policies tile
+    // the members differently).
+    std::vector<pfk::ZArgs<T>> zsw;
+    auto switch_iter = [&](int q, int p, int i) -> pf_status {
+        zsw = zas[q][i & 1];
+        for (int j = 0; j < n; ++j) zsw[j].Gin = plans[p].gB[j];
+        HIPCHK(hipMemcpyAsync(dsw, zsw.data(), szZ, hipMemcpyHostToDevice, stream));
+        return plans[q].launch_switch(i, dsw);
+    };
     // the chunk graph of plan k, captured on first use
     auto capture = [&](int k) -> pf_status {
         if (plans[k].exec) return PF_OK;
@@ -1620,7 +1670,10 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         constexpr int WARM = 2, TRIAL = 4;
         std::vector<double> &t = *trials;
         for (int k = 0; k < NPOLICY && running(); ++k) {
-            for (int i = 0; i < WARM; ++i) PFCHK(plans[k].launch_iter(i, nullptr, nullptr));
+            for (int i = 0; i < WARM; ++i) {
+                if (i == 0 && k > 0) PFCHK(switch_iter(k, k - 1, i));
+                else PFCHK(plans[k].launch_iter(i, nullptr, nullptr));
+            }
             plans[k].gather();
             PFCHK(read_status());
             for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
@@ -1644,6 +1697,15 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
         } else {   // the run ended before every policy was timed: compare again next time
             trials->clear();
         }
+    }
+    if (npol > 1 && next_untried() < 0 && use != NPOLICY - 1 && running()) {
+        // from the last policy timed to the one kept: two iterations (keeping
+        // the chunks' parity), the first with the last policy's counts
+        PFCHK(switch_iter(use, NPOLICY - 1, 0));
+        PFCHK(plans[use].launch_iter(1, nullptr, nullptr));
+        plans[use].gather();
+        PFCHK(read_status());
+        for (int i = 0; i < n; ++i) before[i] = g_batch.hsc[i].iter_done;
     }
     if (running()) PFCHK(capture(use));
     while (running()) {
@@ -1691,7 +1753,206 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
     return PF_OK;
 }
 
+// ------------------------------------------------ batched bookkeeping
+
+// Device tables for the work between a batch's Krylov runs (corrections,
+// true residuals, starts), grown on demand; pinned copies of the gathered
+// scalar blocks.  Each table is reused only after a stream synchronisation.
+struct RoundBuf {
+    void *dev = nullptr;
+    size_t bytes = 0;
+    Scalars *hsc = nullptr;
+    int hcap = 0;
+} g_round;
+
+struct RoundLayout {
+    size_t corr, s64, s32, args, act, pref, na, fin, scp, gather, total;
+};
+
+RoundLayout round_layout(int n)
+{
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    RoundLayout L{};
+    size_t o = 0;
+    L.corr = o; o += al(sizeof(pfk::CorrectMember) * n);
+    L.s64 = o; o += al(sizeof(pfk::StartMember<double>) * n);
+    L.s32 = o; o += al(sizeof(pfk::StartMember<float>) * n);
+    L.args = o; o += al(sizeof(pfk::ZArgs<double>) * n);
+    L.act = o; o += al(sizeof(int) * n);
+    L.pref = o; o += al(sizeof(int) * (n + 1));
+    L.na = o; o += al(sizeof(int));
+    L.fin = o; o += al(sizeof(pfk::FinArgs) * n);
+    L.scp = o; o += al(sizeof(void *) * n);
+    L.gather = o; o += al(sizeof(Scalars) * n);
+    L.total = o;
+    return L;
+}
+
+pf_status round_reserve(int n)
+{
+    const size_t need = round_layout(n).total;
+    if (need > g_round.bytes) {
+        if (g_round.dev) (void)hipFree(g_round.dev);
+        g_round.dev = nullptr;
+        g_round.bytes = 0;
+        if (hipMalloc(&g_round.dev, need) != hipSuccess) return fail(PF_ERR_ALLOC, "batch table allocation failed");
+        g_round.bytes = need;
+    }
+    if (n > g_round.hcap) {
+        if (g_round.hsc) (void)hipHostFree(g_round.hsc);
+        g_round.hsc = nullptr;
+        g_round.hcap = 0;
+        if (hipHostMalloc((void **)&g_round.hsc, sizeof(Scalars) * n, hipHostMallocDefault) != hipSuccess)
+            return fail(PF_ERR_ALLOC, "batch pinned allocation failed");
+        g_round.hcap = n;
+    }
+    return PF_OK;
+}
+
+// Launch shape of a member's true residual in a batched launch: 512 threads,
+// one node per thread, z-chunks of 16 planes, shared by every member.
+ZCfg round_resid_cfg(const pf_grid *g) { return make_cfg(g->nx, g->ny, g->nz, sizeof(double), 512, 1, 16, 1); }
+
+// The batched bookkeeping serves batches whose members all fit that shape
+// without the WIDE form and stop on the relative L2 residual (the max-norm
+// rule adds a reduction per member).
+bool rounds_batchable(const std::vector<LinSolve> &Ls)
+{
+    const char *e = getenv("PF_BATCH_ROUNDS");   // 0: member by member (for comparisons)
+    if (e && e[0] == '0') return false;
+    for (const LinSolve &L : Ls) {
+        if (L.o->stop_rule == PF_STOP_ABS_INF) return false;
+        const ZCfg c = round_resid_cfg(L.g);
+        if (c.wide || c.G > L.g->Gmax || c.lds > LDS_MAX) return false;
+    }
+    return true;
+}
+
+// True FP64 residuals of the members in R (as ls_round_residual), their
+// reductions into red[0], and every member's scalar block read back into
+// its host copy: one launch each and one synchronisation.
+pf_status batch_round_residuals(std::vector<LinSolve *> &R, hipStream_t stream)
+{
+    const int n = (int)R.size();
+    PFCHK(round_reserve(n));
+    const RoundLayout lay = round_layout(n);
+    char *base = (char *)g_round.dev;
+    static std::vector<pfk::ZArgs<double>> za;
+    static std::vector<int> act, pref;
+    static std::vector<pfk::FinArgs> fin;
+    static std::vector<const Scalars *> scp;
+    za.resize(n);
+    act.resize(n);
+    pref.assign(n + 1, 0);
+    fin.resize(n);
+    scp.resize(n);
+    ZCfg comb{};
+    comb.NTZ = 512; comb.PPT = 1; comb.depth = 1; comb.G = 0; comb.lds = 0; comb.wide = false;
+    const bool psi = R[0]->op.psi;
+    for (int i = 0; i < n; ++i) {
+        const LinSolve &L = *R[i];
+        pf_grid *g = L.g;
+        const ZCfg c = round_resid_cfg(g);
+        pfk::ZArgs<double> a = zbase_cfg<double>(g, L.op, c);
+        a.x = g->w64.x;
+        a.out = g->w64.r;
+        a.b = g->b64;
+        a.lift = 0;
+        a.dval = L.op.psi ? nullptr : g->dval;
+        if (L.mixed) {
+            a.rt32 = g->w32.rt;
+            a.rs64 = nullptr;
+            a.rs32 = g->w32.s;
+        } else {
+            a.rt32 = g->w64.rt;
+            a.rs64 = g->w64.s;
+            a.rs32 = nullptr;
+        }
+        za[i] = a;
+        act[i] = i;
+        pref[i + 1] = pref[i] + c.G;
+        fin[i] = pfk::FinArgs{g->sc, g->partials, c.G, 0};
+        scp[i] = g->sc;
+        comb.lds = std::max(comb.lds, c.lds);
+    }
+    comb.G = pref[n];
+    const int na = n;
+    auto *dargs = (pfk::ZArgs<double> *)(base + lay.args);
+    int *dact = (int *)(base + lay.act), *dpref = (int *)(base + lay.pref), *dna = (int *)(base + lay.na);
+    auto *dfin = (pfk::FinArgs *)(base + lay.fin);
+    const Scalars **dscp = (const Scalars **)(base + lay.scp);
+    Scalars *dgather = (Scalars *)(base + lay.gather);
+    HIPCHK(hipMemcpyAsync(dargs, za.data(), sizeof(pfk::ZArgs<double>) * n, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dact, act.data(), sizeof(int) * n, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dpref, pref.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dna, &na, sizeof(int), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dfin, fin.data(), sizeof(pfk::FinArgs) * n, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dscp, scp.data(), sizeof(void *) * n, hipMemcpyHostToDevice, stream));
+    hipError_t e = psi ? launch_batch_k<pfk::OP_RESID, double, true, pfk::SIG_NONE, false, 512, 1, false, 1>(
+                             comb, dargs, dact, dpref, dna, stream, nullptr, nullptr)
+                       : launch_batch_k<pfk::OP_RESID, double, false, pfk::SIG_NONE, false, 512, 1, false, 1>(
+                             comb, dargs, dact, dpref, dna, stream, nullptr, nullptr);
+    if (e != hipSuccess) return fail(PF_ERR_DEVICE, "batched residual launch failed: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL((pfk::k_finalize_batch<pfk::FIN_SUM>), dim3(n), dim3(256), 0, stream, (const pfk::FinArgs *)dfin);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(pfk::k_gather_scalars, dim3((n + 63) / 64), dim3(64), 0, stream, dscp, dgather, n);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(g_round.hsc, dgather, sizeof(Scalars) * n, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int i = 0; i < n; ++i) *R[i]->g->hsc = g_round.hsc[i];
+    return PF_OK;
+}
+
+// After the FP32 runs of the members in M (statuses st): x kept in w64.s and
+// the correction added (as ls_after), one launch for all.
+pf_status batch_round_correct(const std::vector<LinSolve *> &M, const std::vector<int> &st, hipStream_t stream)
+{
+    const int n = (int)M.size();
+    PFCHK(round_reserve(n));
+    const RoundLayout lay = round_layout(n);
+    static std::vector<pfk::CorrectMember> cm;
+    cm.resize(n);
+    size_t nmax = 0;
+    for (int i = 0; i < n; ++i) {
+        pf_grid *g = M[i]->g;
+        cm[i] = pfk::CorrectMember{g->N, g->w64.x, g->w64.s, g->w32.x, g->flags, (int)dirbit(M[i]->op),
+                                   st[i] != pfk::ST_NONFINITE ? 1 : 0};
+        nmax = std::max(nmax, g->N);
+    }
+    auto *dcm = (pfk::CorrectMember *)((char *)g_round.dev + lay.corr);
+    HIPCHK(hipMemcpyAsync(dcm, cm.data(), sizeof(pfk::CorrectMember) * n, hipMemcpyHostToDevice, stream));
+    const int bx = (int)std::min<size_t>(256, (nmax + NT - 1) / NT);
+    hipLaunchKernelGGL(pfk::k_correct_batch, dim3(bx, n), dim3(NT), 0, stream, (const pfk::CorrectMember *)dcm);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
+}
+
+// The recorded Krylov starts, one launch per precision.
+template <typename T>
+pf_status launch_starts(const std::vector<StartRec> &recs, hipStream_t stream, size_t off)
+{
+    static std::vector<pfk::StartMember<T>> sm;
+    sm.clear();
+    size_t nmax = 0;
+    for (const StartRec &r : recs) {
+        if (r.elem != (int)sizeof(T)) continue;
+        sm.push_back(pfk::StartMember<T>{r.g->N, (T *)r.p, (T *)r.v, (T *)r.t, (T *)r.xz, r.g->sc, r.init});
+        nmax = std::max(nmax, r.g->N);
+    }
+    if (sm.empty()) return PF_OK;
+    auto *dsm = (pfk::StartMember<T> *)((char *)g_round.dev + off);
+    HIPCHK(hipMemcpyAsync(dsm, sm.data(), sizeof(pfk::StartMember<T>) * sm.size(), hipMemcpyHostToDevice, stream));
+    const int bx = (int)std::min<size_t>(256, (nmax + NT - 1) / NT);
+    hipLaunchKernelGGL((pfk::k_krylov_start_batch<T>), dim3(bx, (unsigned)sm.size()), dim3(NT), 0, stream,
+                       (const pfk::StartMember<T> *)dsm);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
+}
+
 // Solve several systems (same operator kind and options) as one batch.
+// Between Krylov runs, the members' corrections, true residuals and restarts
+// run as batched launches on the batch's stream with one status read per
+// round (rounds_batchable), else member by member.
 pf_status solve_batch(std::vector<LinSolve> &Ls)
 {
     const int n = (int)Ls.size();
@@ -1700,37 +1961,60 @@ pf_status solve_batch(std::vector<LinSolve> &Ls)
     for (auto &L : Ls) PFCHK(sync(L.g));
     for (auto &L : Ls) PFCHK(ls_init_decide(L));
     hipStream_t bs = Ls[0].g->stream;
+    const bool batched = rounds_batchable(Ls);
+    if (batched) PFCHK(round_reserve(n));
     int m = 16;
     for (auto &L : Ls) m = std::max(m, chunk_len(L.g, L.o));
     std::vector<long> members;
     for (auto &L : Ls) members.push_back(((long)L.g->nx * 4096 + L.g->ny) * 4096 + L.g->nz);
     std::sort(members.begin(), members.end());
+    std::vector<StartRec> starts;
     for (bool first = true;; first = false) {
         if (!first) {   // the first true residuals came with the init read
-            for (auto &L : Ls)
-                if (!L.done) PFCHK(ls_round_launch(L));
-            for (auto &L : Ls) PFCHK(sync(L.g));
+            if (batched) {
+                std::vector<LinSolve *> R;
+                for (auto &L : Ls)
+                    if (!L.done) R.push_back(&L);
+                if (!R.empty()) PFCHK(batch_round_residuals(R, bs));
+            } else {
+                for (auto &L : Ls)
+                    if (!L.done) PFCHK(ls_round_launch(L));
+                for (auto &L : Ls) PFCHK(sync(L.g));
+            }
         }
         std::vector<LinSolve *> act;
+        starts.clear();
+        if (batched) g_defer_start = &starts;
+        pf_status dst = PF_OK;
         for (auto &L : Ls) {
             if (L.done) continue;
             bool run = false;
-            PFCHK(ls_round_decide(L, &run));
+            dst = ls_round_decide(L, &run);
+            if (dst != PF_OK) break;
             if (run) act.push_back(&L);
         }
+        g_defer_start = nullptr;
+        if (dst != PF_OK) return dst;
+        if (batched) {
+            const RoundLayout lay = round_layout(n);
+            PFCHK(launch_starts<double>(starts, bs, lay.s64));
+            PFCHK(launch_starts<float>(starts, bs, lay.s32));
+        }
         if (act.empty()) break;
-        for (LinSolve *L : act) PFCHK(sync(L->g));   // Krylov starts written
+        if (!batched)
+            for (LinSolve *L : act) PFCHK(sync(L->g));   // Krylov starts written
         // members that fell back to FP64 run apart from those still refining in FP32
         std::vector<LinSolve *> a32, a64;
         for (LinSolve *L : act) (L->mixed ? a32 : a64).push_back(L);
         std::vector<int> st;
         if (!a32.empty()) {
             PFCHK(batch_krylov_run<float>(a32, members, bs, m, st));
-            for (size_t i = 0; i < a32.size(); ++i) PFCHK(ls_after(*a32[i], st[i]));
+            for (size_t i = 0; i < a32.size(); ++i) PFCHK(ls_after(*a32[i], st[i], !batched));
+            if (batched) PFCHK(batch_round_correct(a32, st, bs));
         }
         if (!a64.empty()) {
             PFCHK(batch_krylov_run<double>(a64, members, bs, m, st));
-            for (size_t i = 0; i < a64.size(); ++i) PFCHK(ls_after(*a64[i], st[i]));
+            for (size_t i = 0; i < a64.size(); ++i) PFCHK(ls_after(*a64[i], st[i], !batched));
         }
     }
     for (auto &L : Ls) PFCHK(sync(L.g));

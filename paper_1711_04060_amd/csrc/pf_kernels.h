@@ -1241,6 +1241,13 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f)
     finalize_block<KIND>(f);
 }
 
+// One finalize per member of a batch (member = blockIdx.x).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_finalize_batch(const FinArgs *f)
+{
+    finalize_block<KIND>(f[blockIdx.x]);
+}
+
 // Copy the scalar blocks of n systems into one array (one host read per chunk).
 __global__ void k_gather_scalars(const Scalars *const *src, Scalars *dst, int n)
 {
@@ -1389,6 +1396,56 @@ __global__ void k_correct(size_t N, double *x, const float *d, const uint8_t *fl
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
          n += (size_t)gridDim.x * blockDim.x)
         if (!(flags[n] & dirbit)) x[n] += (double)d[n];
+}
+
+// ---------------------------------------------- batched solve bookkeeping
+// One launch for every member of a batch between its Krylov runs (member =
+// blockIdx.y); each does what the single-system kernels above do.
+
+// After an FP32 run: keep x (copy into s), then x += d on free rows unless
+// the run ended non-finite (apply = 0).
+struct CorrectMember {
+    size_t N;
+    double *x, *s;
+    const float *d;
+    const uint8_t *flags;
+    int dirbit, apply;
+};
+
+__global__ void k_correct_batch(const CorrectMember *m)
+{
+    const CorrectMember c = m[blockIdx.y];
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < c.N; n += (size_t)gridDim.x * blockDim.x) {
+        const double x = c.x[n];
+        c.s[n] = x;
+        if (c.apply && !(c.flags[n] & c.dirbit)) c.x[n] = x + (double)c.d[n];
+    }
+}
+
+// Start of a Krylov run (k_krylov_start) for every member.
+template <typename T>
+struct StartMember {
+    size_t N;
+    T *p, *v, *t, *xz;
+    Scalars *sc;
+    Scalars init;
+};
+
+template <typename T>
+__global__ void k_krylov_start_batch(const StartMember<T> *m)
+{
+    const StartMember<T> &c = m[blockIdx.y];
+    const size_t N = c.N;
+    T *p = c.p, *v = c.v, *t = c.t, *xz = c.xz;
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        p[n] = T(0);
+        v[n] = T(0);
+        t[n] = T(0);
+        if (xz) xz[n] = T(0);
+    }
+    constexpr unsigned W = sizeof(Scalars) / 4;
+    if (blockIdx.x == 0 && threadIdx.x < W)
+        reinterpret_cast<unsigned *>(c.sc)[threadIdx.x] = reinterpret_cast<const unsigned *>(&c.init)[threadIdx.x];
 }
 
 }  // namespace pfk
