@@ -785,6 +785,8 @@ def main():
                          "autotuner's (for counter runs, whose serialised launches distort the tuner)")
     ap.add_argument("--pmc-summary-193", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs of --linear193-only 1 --copy-ref 1 and exit")
+    ap.add_argument("--spmv-only", type=int, default=0,
+                    help="run only the isolated cold 193^3 product (for counters) and exit")
     ap.add_argument("--linear193-only", type=int, default=0,
                     help="run only the 193^3 FP64 and mixed linear solves (for traces and counters) and exit")
     ap.add_argument("--cpu-sample-job", type=str, default="", help=argparse.SUPPRESS)
@@ -823,6 +825,9 @@ def main():
         pf.pf_set_launch(strip, kz, nt, depth)
     if args.linear193_only:
         print(json.dumps({"linear_193": linear193_only(pf, torch, inputs)}), flush=True)
+        return
+    if args.spmv_only:
+        print(json.dumps({"spmv_cold_193": forms_spmv_cold(pf, torch, inputs)}), flush=True)
         return
     if args.pmc_run:
         args.sample, args.forms, args.cpu, args.bias_sweep = 1, 0, 0, 0
