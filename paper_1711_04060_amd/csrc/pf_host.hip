@@ -1359,9 +1359,12 @@ struct BatchBuf {
 //      below a chunk on the small members, fewer tiles once few members are
 //      left);
 //   6: as 5 for step A; step B with 512 threads x two nodes (its lighter
-//      work per node favours longer strips).
+//      work per node favours longer strips);
+//   7: as 5 for step A; step B with z-chunks of 32 planes;
+//   8: as 5 for step A; step B as 6 with z-chunks of 32 planes.
+// Step B with z-chunks of 64 planes was slower than 7 and dropped.
 // step: 0 = A, 1 = B.
-constexpr int NPOLICY = 7;
+constexpr int NPOLICY = 9;
 
 template <typename T>
 std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int policy, ZCfg &combined)
@@ -1370,7 +1373,7 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
     const bool own_kz = policy == 0 || policy == 2;
     if (policy == 2) depth = 1;
     if (policy == 3) { ntz = 256; depth = 1; }
-    if (policy == 6 && step == 1) { ppt = 2; depth = default_depth(sizeof(T), 2); }
+    if ((policy == 6 || policy == 8) && step == 1) { ppt = 2; depth = default_depth(sizeof(T), 2); }
     if (policy == 0) {
         std::map<std::tuple<int, int, int>, double> weight;
         for (const LinSolve *L : act) {
@@ -1395,7 +1398,8 @@ std::vector<ZCfg> batch_shapes(const std::vector<LinSolve *> &act, int step, int
         if (own_kz) {
             kz = (step == 0 ? cfg_ref<T>(L->g) : cfgb_ref<T>(L->g)).KZ;
         } else if (policy >= 4) {
-            kz = policy == 4 ? 32 : 16;   // 5, 6: 16
+            kz = 16;   // 5, 6, and step A of 7 and 8
+            if (policy == 4 || ((policy == 7 || policy == 8) && step == 1)) kz = 32;
         } else {
             const long S = (long)ntz * ppt;
             const long strips = ((long)g->nx * g->ny + S - 1) / S;
@@ -1691,9 +1695,9 @@ pf_status batch_krylov_run(std::vector<LinSolve *> &act, const std::vector<long>
             use = (int)(std::max_element(t.begin(), t.end()) - t.begin());
             g_batch_policy[key] = use;
             if (getenv("PF_LOG"))
-                fprintf(stderr, "[pf] batch of %d: policies 0..6 at %.3g %.3g %.3g %.3g %.3g %.3g %.3g "
+                fprintf(stderr, "[pf] batch of %d: policies 0..8 at %.3g %.3g %.3g %.3g %.3g %.3g %.3g %.3g %.3g "
                                 "node-iterations/s over %d iterations each; keeping policy %d\n", n, t[0], t[1], t[2],
-                        t[3], t[4], t[5], t[6], TRIAL, use);
+                        t[3], t[4], t[5], t[6], t[7], t[8], TRIAL, use);
         } else {   // the run ended before every policy was timed: compare again next time
             trials->clear();
         }

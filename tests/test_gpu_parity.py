@@ -558,7 +558,7 @@ def small_batch_refs():
     return probs, [oracle.linear_solve(p, p.sigma, p.b, tol=1e-13)[0] for p in probs]
 
 
-@pytest.mark.parametrize("policy", range(7))
+@pytest.mark.parametrize("policy", range(9))
 def test_every_batch_launch_policy_matches_oracle(policy, small_batch_refs):
     """Each of the batched launch policies (kernel instance, z-chunk length,
     step-B strip) the library may keep, pinned through PF_BATCH_POLICY, gives
